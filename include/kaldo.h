@@ -1,0 +1,225 @@
+/*
+ * kaldo.h -- C ABI of the MI355X (gfx950) three-phonon linewidth library.
+ *
+ * The library computes, on one GPU, the hot path of anharmonic lattice
+ * dynamics described in the kALDo 2.0 paper (arXiv 2602.23728):
+ *
+ *   phonons     harmonic frequencies, eigenvectors and group velocities from
+ *               second-order force constants (paper: Eq. dynmat,
+ *               Eq. dynmat_reciprocal, Eq. eigenvalue_crystal, Eq. groupvel);
+ *   linewidths  three-phonon linewidths Gamma(q,s) from the sparse (COO)
+ *               third-order force constants projected on three eigenvectors
+ *               with Bloch phases, squared, and summed against Bose-Einstein
+ *               populations and a smeared energy delta (Eq. phi3_proj,
+ *               Eq. gamma with its Delta terms, Eq. broadening, Eq. bose,
+ *               Eq. lifetime; the "Computational Implementation" list);
+ *   kappa_rta   the RTA thermal conductivity tensor (Eq. heatcap, Eq. rta).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Units in: eV, Angstrom, amu, K.  Units out: omega and Gamma in rad/ps,
+ * velocities in Angstrom/ps, kappa in W/(m K).  Cyclic widths (THz) are
+ * converted with omega = 2 pi nu.
+ *
+ * Modes: mu = (q, s).  The q-mesh is Gamma-centred, q_n = sum_c (n_c/N_c) b_c,
+ * flattened in C order over (n1, n2, n3): q = (n1*N2 + n2)*N3 + n3.  With
+ * N_b basis atoms, nb3 = 3 N_b branches.
+ *
+ * Memory: every array argument documented "device" is a pointer into HBM of
+ * the current HIP device (e.g. a torch CUDA tensor's data_ptr()); "host"
+ * arguments are ordinary CPU memory read during the call only.  The library
+ * keeps no pointer to caller memory past the call (or, for enqueued work,
+ * past completion of that work on the caller's stream).  Device work is
+ * enqueued on the caller's stream (hipStream_t passed as void*; NULL = the
+ * legacy default stream) and the call returns after enqueueing; results are
+ * valid after the stream is synchronised.
+ *
+ * Errors: every call returns a kaldo_status; no exception crosses the ABI.
+ * Arguments are validated before anything is enqueued (KALDO_EINVAL);
+ * device-runtime failures return KALDO_EDEVICE.  kaldo_last_error() returns
+ * a thread-local description of the last failure in the calling thread.
+ *
+ * Determinism: all reductions run in a fixed order; identical inputs give
+ * bit-identical outputs.
+ */
+#ifndef KALDO_H
+#define KALDO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KALDO_OK = 0,
+  KALDO_EINVAL = -1,      /* bad argument: shape, range, NULL, NaN        */
+  KALDO_ENOMEM = -2,      /* allocation failed (handle creation only)     */
+  KALDO_EDEVICE = -3,     /* HIP runtime error                            */
+  KALDO_ENUMERIC = -4,    /* numerical failure (e.g. no eigen convergence)*/
+  KALDO_EUNSUPPORTED = -5 /* valid request this build does not implement  */
+} kaldo_status;
+
+/* Arithmetic of the vertex contraction (projection of Phi3 on eigenvectors).
+ * Frequencies, widths, the 2-sigma cut, populations, |V|^2 weights and all
+ * accumulations are FP64 in every mode. */
+typedef enum {
+  KALDO_FP64 = 0,   /* contraction in FP64                                  */
+  KALDO_FP32 = 1,   /* operands rounded to FP32, FP32 products and sums     */
+  KALDO_BF16X3 = 2  /* operands split x = hi + lo (bf16 each); products
+                       hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+} kaldo_precision;
+
+typedef enum { KALDO_GAUSS = 0, KALDO_LORENTZ = 1 } kaldo_shape;
+
+/* Energy-conservation smearing (paper: Eq. broadening and the text after it).
+ * shape      Gaussian exp(-x^2/s^2)/(sqrt(pi) s) or Lorentzian
+ *            (s/2)/(pi (x^2 + s^2/4)); both are 0 unless |x| < 2 s.
+ * adaptive   0: s = 2 pi sigma_thz.  1: per scattering pair
+ *            s = max(2 pi sigma_floor_thz, |dv| h / sqrt(12)), with h^2 the
+ *            mean of |b_c/N_c|^2 over the three mesh axes and dv the velocity
+ *            difference of the two partner phonons of that process.
+ * nu_min_thz modes with cyclic frequency below it get Gamma = 0 and take no
+ *            part as scattering partners (the paper's min_frequency).       */
+typedef struct {
+  int32_t shape;
+  int32_t adaptive;
+  double sigma_thz;
+  double sigma_floor_thz;
+  double nu_min_thz;
+} kaldo_broadening;
+
+/* Opaque handle: one crystal (or one Gamma-point cell) with its force
+ * constants resident in device memory. */
+typedef struct kaldo_crystal_s kaldo_crystal;
+
+/* kaldo_crystal_create -- upload a cell and its force constants.
+ * (paper: "Interatomic Force Constants": FC2 dense 3N_b x 3N, FC3 sparse COO
+ *  3N_b x (3N)^2 with the first index in the home cell.)
+ *   n_basis     N_b >= 1
+ *   lattice     host double[9], rows a1, a2, a3 in Angstrom
+ *   mass        host double[N_b], amu, > 0
+ *   n_rep       number of replicas (cells) the FCs reach, >= 1
+ *   rep         host int32[n_rep][3] integer replica coordinates, rep[0] must
+ *               be (0,0,0) (a Gamma-point solid passes n_rep = 1)
+ *   fc2         host double[3N_b][n_rep][3N_b], eV/A^2:
+ *               fc2[3i+a][l][3j+b] = Phi(0 i a, l j b)
+ *   nnz, fc3_i, fc3_j, fc3_k, fc3_val
+ *               host COO: fc3_i in [0, 3N_b) is 3*basis+alpha of the home
+ *               atom; fc3_j, fc3_k in [0, 3 N_b n_rep) are
+ *               (rep*N_b + basis)*3 + beta; values eV/A^3.  Any order;
+ *               duplicates are summed.
+ *   out         receives the handle.
+ * Allocates device memory on the current device (KALDO_ENOMEM on failure);
+ * the handle owns it until kaldo_crystal_destroy.  Synchronous. */
+int kaldo_crystal_create(int32_t n_basis, const double* lattice, const double* mass,
+                         int32_t n_rep, const int32_t* rep, const double* fc2,
+                         int64_t nnz, const int32_t* fc3_i, const int32_t* fc3_j,
+                         const int32_t* fc3_k, const double* fc3_val,
+                         kaldo_crystal** out);
+
+/* Frees the handle and its device memory.  NULL is a no-op. */
+int kaldo_crystal_destroy(kaldo_crystal* c);
+
+/* kaldo_phonons -- harmonic phonons on a Gamma-centred mesh, FP64 on the GPU.
+ * (paper: Eq. dynmat_reciprocal with phase e^{-i q.R_l}, Eq. eigenvalue_crystal,
+ *  Eq. groupvel with the analytic dD/dq.)  One Hermitian eigenproblem per q.
+ *   mesh    host int32[3], each >= 1
+ *   omega   device double[N_q][nb3]   rad/ps, ascending per q;
+ *           omega = sign(lambda) sqrt(|lambda|) for eigenvalue lambda of D
+ *   evec    device double[N_q][nb3][nb3][2] complex, [q][component][mode]:
+ *           unit columns; within a cluster of frequencies closer than
+ *           1e-4 THz the basis diagonalises sum_c chat_c dD/dq_c with
+ *           chat = (1,2,3)/sqrt(14); each column's largest-modulus component
+ *           is real positive
+ *   vel     device double[N_q][nb3][3]  Angstrom/ps, diagonal Hellmann-Feynman
+ *           elements; 0 where |nu| < 1e-3 THz
+ * Requires nb3 <= 32 (one workgroup per q, matrices held in LDS); larger
+ * cells at the Gamma point use kaldo_phonons_gamma.  Cyclic Jacobi, at most
+ * 60 sweeps (converged to off-diagonal norm <= 1e-16 of the total). */
+int kaldo_phonons(const kaldo_crystal* c, const int32_t* mesh, double* omega,
+                  double* evec, double* vel, void* stream);
+
+/* kaldo_phonons_gamma -- Gamma-point phonons of one cell: the real symmetric
+ * D = sum_l Phi(0, l)/sqrt(m m) (paper: Eq. dynmat, Eq. eigenvalue),
+ * diagonalised in FP64 on the host (Householder tridiagonalisation and the
+ * implicit QL method).  Synchronous; needs no GPU.
+ *   n_basis, mass, n_rep, fc2   host, layouts of kaldo_crystal_create
+ *   omega   host double[nb3] rad/ps ascending, sign(lambda) sqrt(|lambda|)
+ *   evec    host double[nb3][nb3] real, [component][mode], unit columns, each
+ *           column's largest-modulus component positive
+ * KALDO_ENUMERIC if the QL iteration does not converge. */
+int kaldo_phonons_gamma(int32_t n_basis, const double* mass, int32_t n_rep, const double* fc2,
+                        double* omega, double* evec);
+
+/* Device workspace bytes kaldo_linewidths needs for this crystal, mesh and
+ * precision. */
+size_t kaldo_linewidths_workspace(const kaldo_crystal* c, const int32_t* mesh,
+                                  int32_t precision);
+
+/* kaldo_linewidths -- three-phonon linewidths of a crystal on a mesh.
+ * (paper: Eq. phi3_proj with Bloch phases, all-incoming momenta
+ *  q + q1 + q2 = G; Eq. gamma with populations paired as
+ *  coalescence (n1 - n2) delta(w + w1 - w2) and decay
+ *  1/2 (n1 + n2 + 1) delta(w - w1 - w2); 1/N_q Bloch normalisation;
+ *  Eq. broadening with the |x| < 2 sigma cut; Eq. bose.)
+ *   Gamma(q,s) = pi hbar U^3/(8 N_q) sum_{q1,s',s''} m |V|^2/(w w1 w2)
+ *                [(n1 - n2) g(x+) + 1/2 (n1 + n2 + 1) g(x-)]
+ *   with x+ = (w + w1) - w2, x- = (w - w1) - w2 in FP64, q2 = -q - q1.
+ *   mesh           host int32[3]
+ *   omega, evec, vel   device, layouts of kaldo_phonons
+ *   temperature    K, > 0
+ *   broadening     host struct
+ *   precision      kaldo_precision
+ *   modes_subset   device int32[n_subset] flat mode indices q*nb3 + s, or NULL
+ *                  for all modes; only those entries of gamma are written
+ *   workspace      device buffer of kaldo_linewidths_workspace() bytes
+ *   gamma          device double[N_q*nb3] rad/ps
+ * Requires nb3 <= 16. */
+int kaldo_linewidths(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                     const double* evec, const double* vel, double temperature,
+                     const kaldo_broadening* broadening, int32_t precision,
+                     const int32_t* modes_subset, int64_t n_subset, void* workspace,
+                     size_t workspace_bytes, double* gamma, void* stream);
+
+/* Device workspace bytes kaldo_linewidths_gamma needs. */
+size_t kaldo_linewidths_gamma_workspace(const kaldo_crystal* c, int32_t precision);
+
+/* kaldo_linewidths_gamma -- linewidths of a Gamma-point solid (N_q = 1, real
+ * eigenvectors): V_mu = E^T A_mu E with A_mu[b][c] = sum_a Phi3_abc E_a,mu /
+ * sqrt(m_a m_b m_c); same rate formula with N_q = 1 and fixed-width smearing
+ * (paper: Eq. phi3_proj, Eq. gamma; the Gamma-point QHGK setting).
+ *   omega       device double[nb3] rad/ps
+ *   evec        device double[nb3][nb3] real [component][mode]
+ *   modes_subset device int32[n_subset] or NULL
+ *   gamma       device double[nb3]
+ * broadening->adaptive must be 0. */
+int kaldo_linewidths_gamma(const kaldo_crystal* c, const double* omega, const double* evec,
+                           double temperature, const kaldo_broadening* broadening,
+                           int32_t precision, const int32_t* modes_subset, int64_t n_subset,
+                           void* workspace, size_t workspace_bytes, double* gamma,
+                           void* stream);
+
+/* kaldo_kappa_rta -- RTA conductivity (paper: Eq. heatcap, Eq. rta, with
+ * tau = 1/(2 Gamma) of Eq. lifetime):
+ *   kappa_ab = 1/(N_q V_cell) sum_mu c_mu v_mu,a v_mu,b / (2 Gamma_mu)
+ * over modes with nu >= nu_min_thz and Gamma_mu > 1e-8 max(Gamma).
+ *   omega, vel, gamma  device, layouts of kaldo_phonons / kaldo_linewidths
+ *   n_modes            N_q * nb3
+ *   kappa              device double[9] W/(m K), row-major
+ * Fixed-order single-workgroup reduction. */
+int kaldo_kappa_rta(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                    const double* vel, const double* gamma, double temperature,
+                    double nu_min_thz, double* kappa, void* stream);
+
+/* Thread-local message for the last failing call in this thread. */
+const char* kaldo_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int kaldo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KALDO_H */

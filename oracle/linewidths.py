@@ -183,8 +183,9 @@ def crystal_linewidths(model, mesh, omega, evec, vel, T, broadening, q_list=None
         gm = smearing(xm, np.broadcast_to(sm, xm.shape), broadening.shape)
         safe = np.where(m12, w1 * w2, 1.0)
         pop = (n1 - n2) * gp + 0.5 * (n1 + n2 + 1.0) * gm
-        term = np.where(m12, (np.abs(V) ** 2) * pop / (w * safe), 0.0)
-        g = PREFACTOR / nq * term.sum(axis=(0, 2, 3))
+        with np.errstate(divide="ignore", invalid="ignore"):  # rows of masked modes
+            term = np.where(m12, (np.abs(V) ** 2) * pop / (w * safe), 0.0)
+            g = PREFACTOR / nq * term.sum(axis=(0, 2, 3))
         g[~phys[q]] = 0.0
         out[q] = g
         if stats is not None:

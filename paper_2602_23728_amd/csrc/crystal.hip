@@ -1,0 +1,234 @@
+// Crystal handle: validation, host-side index planning of the FC3 COO, and
+// upload of every table the kernels read.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <tuple>
+
+#include "common.h"
+
+namespace kaldo {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void reciprocal(const double* a, double* b) {
+  // b_c = 2 pi (a_{c+1} x a_{c+2}) / (a_0 . (a_1 x a_2))
+  auto cross = [](const double* u, const double* v, double* w) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+  };
+  double c[3];
+  cross(a + 3, a + 6, c);
+  double vol = a[0] * c[0] + a[1] * c[1] + a[2] * c[2];
+  for (int r = 0; r < 3; ++r) {
+    double w[3];
+    cross(a + 3 * ((r + 1) % 3), a + 3 * ((r + 2) % 3), w);
+    for (int k = 0; k < 3; ++k) b[3 * r + k] = kTwoPi * w[k] / vol;
+  }
+}
+
+template <typename T>
+static int upload(kaldo_crystal* c, T** dst, const std::vector<T>& src) {
+  size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    set_error("hipMalloc failed for " + std::to_string(bytes) + " bytes");
+    return KALDO_ENOMEM;
+  }
+  c->allocations.push_back(p);
+  if (!src.empty()) KALDO_HIP(hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dst = static_cast<T*>(p);
+  return KALDO_OK;
+}
+
+static void free_all(kaldo_crystal* c) {
+  for (void* p : c->allocations) (void)hipFree(p);
+  c->allocations.clear();
+}
+
+static int build_bloch(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const int32_t* fj,
+                       const int32_t* fk, const double* fv) {
+  const int nb = c->nb;
+  struct Contrib { int32_t i, l2; double coef; int64_t order; };
+  // key: (d0, d1, d2, jc, kc)
+  std::map<std::array<int32_t, 5>, std::vector<Contrib>> groups;
+  for (int64_t t = 0; t < nnz; ++t) {
+    int32_t jr = (fj[t] / 3) / nb, jb = (fj[t] / 3) % nb, kr = (fk[t] / 3) / nb,
+            kb = (fk[t] / 3) % nb, ib = fi[t] / 3;
+    std::array<int32_t, 5> key = {c->rep[3 * jr] - c->rep[3 * kr],
+                                  c->rep[3 * jr + 1] - c->rep[3 * kr + 1],
+                                  c->rep[3 * jr + 2] - c->rep[3 * kr + 2],
+                                  jb * 3 + fj[t] % 3, kb * 3 + fk[t] % 3};
+    double coef = fv[t] / std::sqrt(c->mass[ib] * c->mass[jb] * c->mass[kb]);
+    groups[key].push_back({fi[t], kr, coef, t});
+  }
+  std::vector<int32_t> dvec, d_ptr, e_jc, e_kc, t_ptr, t_i, t_l2;
+  std::vector<double> t_coef;
+  std::array<int32_t, 3> cur = {INT32_MIN, INT32_MIN, INT32_MIN};
+  t_ptr.push_back(0);
+  for (auto& kv : groups) {
+    const auto& key = kv.first;
+    std::array<int32_t, 3> d = {key[0], key[1], key[2]};
+    if (d != cur) {
+      cur = d;
+      dvec.insert(dvec.end(), d.begin(), d.end());
+      d_ptr.push_back(static_cast<int32_t>(e_jc.size()));
+    }
+    e_jc.push_back(key[3]);
+    e_kc.push_back(key[4]);
+    auto v = kv.second;
+    std::sort(v.begin(), v.end(), [](const Contrib& a, const Contrib& b) {
+      return std::tie(a.i, a.l2, a.order) < std::tie(b.i, b.l2, b.order);
+    });
+    for (auto& x : v) {
+      t_i.push_back(x.i);
+      t_l2.push_back(x.l2);
+      t_coef.push_back(x.coef);
+    }
+    t_ptr.push_back(static_cast<int32_t>(t_i.size()));
+  }
+  d_ptr.push_back(static_cast<int32_t>(e_jc.size()));
+  Fc3Bloch& b = c->bloch;
+  b.n_d = static_cast<int>(dvec.size() / 3);
+  b.n_e = static_cast<int>(e_jc.size());
+  b.n_t = static_cast<int>(t_i.size());
+  int rc;
+  if ((rc = upload(c, &b.dvec, dvec))) return rc;
+  if ((rc = upload(c, &b.d_ptr, d_ptr))) return rc;
+  if ((rc = upload(c, &b.e_jc, e_jc))) return rc;
+  if ((rc = upload(c, &b.e_kc, e_kc))) return rc;
+  if ((rc = upload(c, &b.t_ptr, t_ptr))) return rc;
+  if ((rc = upload(c, &b.t_i, t_i))) return rc;
+  if ((rc = upload(c, &b.t_l2, t_l2))) return rc;
+  if ((rc = upload(c, &b.t_coef, t_coef))) return rc;
+  return KALDO_OK;
+}
+
+static int build_gamma(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const int32_t* fj,
+                       const int32_t* fk, const double* fv) {
+  const int nb3 = c->nb3;
+  std::vector<int64_t> idx(nnz);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+    return std::make_tuple(fj[a], fk[a], fi[a], a) < std::make_tuple(fj[b], fk[b], fi[b], b);
+  });
+  std::vector<int32_t> row_ptr(nb3 + 1, 0), col, t_ptr, t_a;
+  std::vector<double> t_coef;
+  t_ptr.push_back(0);
+  int32_t pb = -1, pc = -1;
+  for (int64_t n = 0; n < nnz; ++n) {
+    int64_t t = idx[n];
+    int32_t b = fj[t], cc = fk[t];
+    if (b != pb || cc != pc) {
+      if (pb >= 0) t_ptr.push_back(static_cast<int32_t>(t_a.size()));
+      col.push_back(cc);
+      row_ptr[b + 1]++;
+      pb = b;
+      pc = cc;
+    }
+    int32_t a = fi[t];
+    t_a.push_back(a);
+    t_coef.push_back(fv[t] / std::sqrt(c->mass[a / 3] * c->mass[b / 3] * c->mass[cc / 3]));
+  }
+  if (pb >= 0) t_ptr.push_back(static_cast<int32_t>(t_a.size()));
+  for (int r = 0; r < nb3; ++r) row_ptr[r + 1] += row_ptr[r];
+  Fc3Gamma& g = c->gamma;
+  g.n_bc = static_cast<int>(col.size());
+  g.n_t = static_cast<int>(t_a.size());
+  int rc;
+  if ((rc = upload(c, &g.row_ptr, row_ptr))) return rc;
+  if ((rc = upload(c, &g.col, col))) return rc;
+  if ((rc = upload(c, &g.t_ptr, t_ptr))) return rc;
+  if ((rc = upload(c, &g.t_a, t_a))) return rc;
+  if ((rc = upload(c, &g.t_coef, t_coef))) return rc;
+  return KALDO_OK;
+}
+
+}  // namespace kaldo
+
+using namespace kaldo;
+
+extern "C" const char* kaldo_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int kaldo_version(void) { return 100; }
+
+extern "C" int kaldo_crystal_create(int32_t n_basis, const double* lattice, const double* mass,
+                                    int32_t n_rep, const int32_t* rep, const double* fc2,
+                                    int64_t nnz, const int32_t* fc3_i, const int32_t* fc3_j,
+                                    const int32_t* fc3_k, const double* fc3_val,
+                                    kaldo_crystal** out) {
+  KALDO_REQUIRE(out != nullptr, "kaldo_crystal_create: out is NULL");
+  *out = nullptr;
+  KALDO_REQUIRE(n_basis >= 1 && n_rep >= 1 && nnz >= 0, "kaldo_crystal_create: bad sizes");
+  KALDO_REQUIRE(lattice && mass && rep && fc2, "kaldo_crystal_create: NULL array");
+  KALDO_REQUIRE(nnz == 0 || (fc3_i && fc3_j && fc3_k && fc3_val),
+                "kaldo_crystal_create: NULL FC3 array");
+  KALDO_REQUIRE(rep[0] == 0 && rep[1] == 0 && rep[2] == 0,
+                "kaldo_crystal_create: rep[0] must be (0,0,0)");
+  const int nb3 = 3 * n_basis;
+  double vol = lattice[0] * (lattice[4] * lattice[8] - lattice[5] * lattice[7]) -
+               lattice[1] * (lattice[3] * lattice[8] - lattice[5] * lattice[6]) +
+               lattice[2] * (lattice[3] * lattice[7] - lattice[4] * lattice[6]);
+  KALDO_REQUIRE(std::isfinite(vol) && std::fabs(vol) > 1e-12,
+                "kaldo_crystal_create: singular lattice");
+  for (int i = 0; i < n_basis; ++i)
+    KALDO_REQUIRE(std::isfinite(mass[i]) && mass[i] > 0, "kaldo_crystal_create: mass <= 0");
+  const size_t n2 = static_cast<size_t>(nb3) * n_rep * nb3;
+  for (size_t k = 0; k < n2; ++k)
+    KALDO_REQUIRE(std::isfinite(fc2[k]), "kaldo_crystal_create: non-finite FC2");
+  const int32_t jmax = 3 * n_basis * n_rep;
+  for (int64_t t = 0; t < nnz; ++t) {
+    KALDO_REQUIRE(fc3_i[t] >= 0 && fc3_i[t] < nb3, "kaldo_crystal_create: fc3_i out of range");
+    KALDO_REQUIRE(fc3_j[t] >= 0 && fc3_j[t] < jmax, "kaldo_crystal_create: fc3_j out of range");
+    KALDO_REQUIRE(fc3_k[t] >= 0 && fc3_k[t] < jmax, "kaldo_crystal_create: fc3_k out of range");
+    KALDO_REQUIRE(std::isfinite(fc3_val[t]), "kaldo_crystal_create: non-finite FC3 value");
+  }
+  auto* c = new (std::nothrow) kaldo_crystal_s();
+  if (!c) {
+    set_error("kaldo_crystal_create: host allocation failed");
+    return KALDO_ENOMEM;
+  }
+  c->nb = n_basis;
+  c->nb3 = nb3;
+  c->n_rep = n_rep;
+  std::copy(lattice, lattice + 9, c->lattice);
+  c->volume = std::fabs(vol);
+  c->mass.assign(mass, mass + n_basis);
+  c->rep.assign(rep, rep + 3 * n_rep);
+  c->fc2.assign(fc2, fc2 + n2);
+  std::vector<double> scaled(n2), repcart(3 * n_rep);
+  for (int a = 0; a < nb3; ++a)
+    for (int l = 0; l < n_rep; ++l)
+      for (int b = 0; b < nb3; ++b) {
+        size_t k = (static_cast<size_t>(a) * n_rep + l) * nb3 + b;
+        scaled[k] = fc2[k] / std::sqrt(mass[a / 3] * mass[b / 3]);
+      }
+  for (int l = 0; l < n_rep; ++l)
+    for (int x = 0; x < 3; ++x)
+      repcart[3 * l + x] = rep[3 * l] * lattice[x] + rep[3 * l + 1] * lattice[3 + x] +
+                           rep[3 * l + 2] * lattice[6 + x];
+  int rc = upload(c, &c->d_fc2, scaled);
+  if (!rc) rc = upload(c, &c->d_rep, c->rep);
+  if (!rc) rc = upload(c, &c->d_repcart, repcart);
+  if (!rc) rc = build_bloch(c, nnz, fc3_i, fc3_j, fc3_k, fc3_val);
+  if (!rc && n_rep == 1) rc = build_gamma(c, nnz, fc3_i, fc3_j, fc3_k, fc3_val);
+  if (rc) {
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return KALDO_OK;
+}
+
+extern "C" int kaldo_crystal_destroy(kaldo_crystal* c) {
+  if (!c) return KALDO_OK;
+  free_all(c);
+  delete c;
+  return KALDO_OK;
+}

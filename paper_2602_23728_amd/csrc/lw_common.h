@@ -1,0 +1,117 @@
+// Device helpers shared by the crystal and Gamma-point linewidth kernels:
+// the FP64 energy cut, smearing and population weight of one partner pair,
+// adaptive widths, and a fixed-order wave reduction.
+#pragma once
+
+#include <cmath>
+
+#include "common.h"
+
+namespace kaldo {
+
+// pi hbar U^3 / 8: turns sum |V|^2 [eV^2/(A^6 amu^3)] w^-3 g [ps^4] into rad/ps.
+constexpr double kPrefactor = kPi * kHbar * kU * kU * kU / 8.0;
+
+template <typename T>
+struct Cx;
+template <>
+struct Cx<float> {
+  using type = float2;
+  __host__ __device__ static float2 make(float x, float y) { return make_float2(x, y); }
+};
+template <>
+struct Cx<double> {
+  using type = double2;
+  __host__ __device__ static double2 make(double x, double y) { return make_double2(x, y); }
+};
+
+struct LwParams {
+  int nb3, nq, n_d, n_e;
+  int N[3];
+  int shape, adaptive;
+  double sig_fixed, sig_floor, h2;  // rad/ps, rad/ps, 1/A^2
+};
+
+inline int check_broadening(const kaldo_broadening* b, bool allow_adaptive) {
+  KALDO_REQUIRE(b->shape == KALDO_GAUSS || b->shape == KALDO_LORENTZ, "broadening: unknown shape");
+  KALDO_REQUIRE(b->adaptive == 0 || b->adaptive == 1, "broadening: adaptive must be 0 or 1");
+  KALDO_REQUIRE(allow_adaptive || b->adaptive == 0,
+                "broadening: adaptive widths need group velocities (crystal path only)");
+  if (b->adaptive)
+    KALDO_REQUIRE(std::isfinite(b->sigma_floor_thz) && b->sigma_floor_thz > 0,
+                  "broadening: sigma_floor_thz must be > 0");
+  else
+    KALDO_REQUIRE(std::isfinite(b->sigma_thz) && b->sigma_thz > 0, "broadening: sigma_thz must be > 0");
+  KALDO_REQUIRE(std::isfinite(b->nu_min_thz) && b->nu_min_thz >= 0, "broadening: nu_min_thz < 0");
+  return KALDO_OK;
+}
+
+inline LwParams make_params(const kaldo_crystal* c, const int32_t* mesh, double T,
+                            const kaldo_broadening* b) {
+  LwParams p;
+  p.nb3 = c->nb3;
+  p.nq = mesh[0] * mesh[1] * mesh[2];
+  p.n_d = c->bloch.n_d;
+  p.n_e = c->bloch.n_e;
+  for (int i = 0; i < 3; ++i) p.N[i] = mesh[i];
+  p.shape = b->shape;
+  p.adaptive = b->adaptive;
+  p.sig_fixed = kTwoPi * b->sigma_thz;
+  p.sig_floor = kTwoPi * b->sigma_floor_thz;
+  double rc[9];
+  reciprocal(c->lattice, rc);
+  double h2 = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      double x = rc[3 * r + k] / mesh[r];
+      h2 += x * x;
+    }
+  p.h2 = h2 / 3.0;
+  (void)T;
+  return p;
+}
+
+// sigma+ for coalescence (dv = v1 + v2), sigma- for decay (dv = -v1 + v2).
+__device__ __forceinline__ void widths(const LwParams& p, const double* __restrict__ vel, int m1,
+                                       int m2, double& sp, double& sm) {
+  if (!p.adaptive) {
+    sp = sm = p.sig_fixed;
+    return;
+  }
+  const double* v1 = vel + 3 * (size_t)m1;
+  const double* v2 = vel + 3 * (size_t)m2;
+  double ax = v1[0] + v2[0], ay = v1[1] + v2[1], az = v1[2] + v2[2];
+  double bx = -v1[0] + v2[0], by = -v1[1] + v2[1], bz = -v1[2] + v2[2];
+  double Sa = ax * ax + ay * ay + az * az;
+  double Sb = bx * bx + by * by + bz * bz;
+  sp = fmax(sqrt(Sa * p.h2 / 12.0), p.sig_floor);
+  sm = fmax(sqrt(Sb * p.h2 / 12.0), p.sig_floor);
+}
+
+__device__ __forceinline__ double smear(int shape, double x, double s) {
+  if (shape == KALDO_GAUSS) return exp(-(x * x) / (s * s)) / (kSqrtPi * s);
+  return (0.5 * s) / (kPi * (x * x + 0.25 * s * s));
+}
+
+// [(n1 - n2) g(x+) + 1/2 (n1 + n2 + 1) g(x-)] / (w w1 w2), zero unless a
+// process passes |x| < 2 sigma; x+ = (w + w1) - w2, x- = (w - w1) - w2.
+__device__ __forceinline__ double pair_weight(const LwParams& p, double w, double w1, double w2,
+                                              double n1, double n2, double sp, double sm) {
+  const double xp = (w + w1) - w2;
+  const double xm = (w - w1) - w2;
+  const bool pp = fabs(xp) < 2.0 * sp;
+  const bool pm = fabs(xm) < 2.0 * sm;
+  if (!(pp || pm)) return 0.0;
+  const double gp = pp ? smear(p.shape, xp, sp) : 0.0;
+  const double gm = pm ? smear(p.shape, xm, sm) : 0.0;
+  const double pop = (n1 - n2) * gp + 0.5 * (n1 + n2 + 1.0) * gm;
+  return pop / (w * (w1 * w2));
+}
+
+// Sum over a wave64 in a fixed butterfly order; lane 0 holds the result.
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace kaldo

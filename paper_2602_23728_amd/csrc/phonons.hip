@@ -1,0 +1,327 @@
+// Harmonic phonons on a Gamma-centred mesh: one workgroup (one wave64) per
+// q-point builds the Bloch dynamical matrix in LDS, diagonalises it with a
+// cyclic complex Jacobi method in FP64, sorts, fixes degenerate bases and
+// phases, and evaluates Hellmann-Feynman group velocities.
+//
+// Paper: Eq. dynmat (mass scaling), Eq. dynmat_reciprocal (phase e^{-i q.R_l}),
+// Eq. eigenvalue_crystal, Eq. groupvel (analytic dD/dq).
+#include <cmath>
+
+#include "common.h"
+
+namespace kaldo {
+
+struct cplx {
+  double x, y;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ cplx cconj(cplx a) { return {a.x, -a.y}; }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.x * s, a.y * s}; }
+
+// Cyclic Jacobi on the Hermitian n x n matrix A (row-major, leading dim ld) in
+// LDS; accumulates the unitary V (initialised here to I).  For pivot (p,q)
+// with a_pq = |a| e^{i phi}, the rotation J = [[c, s e^{i phi}],
+// [-s e^{-i phi}, c]] with t = tan(theta) the smaller root of
+// t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp)/(2|a|), annihilates a_pq.
+// All 64 lanes of the workgroup call it; control flow is uniform.
+__device__ void jacobi_hermitian(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
+  for (int k = lane; k < n * n; k += 64) {
+    int r = k / n, c = k % n;
+    V[r * ld + c] = {r == c ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  __shared__ double red[64];
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // off-diagonal and total Frobenius norms
+    double off = 0.0, tot = 0.0;
+    for (int k = lane; k < n * n; k += 64) {
+      int r = k / n, c = k % n;
+      cplx a = A[r * ld + c];
+      double m2 = a.x * a.x + a.y * a.y;
+      tot += m2;
+      if (r != c) off += m2;
+    }
+    red[lane] = off;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+      if (lane < w) red[lane] += red[lane + w];
+      __syncthreads();
+    }
+    off = red[0];
+    __syncthreads();
+    red[lane] = tot;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+      if (lane < w) red[lane] += red[lane + w];
+      __syncthreads();
+    }
+    tot = red[0];
+    __syncthreads();
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        double app = A[p * ld + p].x, aqq = A[q * ld + q].x;
+        cplx apq = A[p * ld + q];
+        double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+        if (!(mag > 1e-300)) continue;
+        cplx e = {apq.x / mag, apq.y / mag};
+        double tau = (aqq - app) / (2.0 * mag);
+        double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        double c = 1.0 / sqrt(1.0 + t * t);
+        double s = t * c;
+        cplx se = cscale(e, s), sec = cscale(cconj(e), s);
+        __syncthreads();
+        if (lane < n && lane != p && lane != q) {
+          cplx akp = A[lane * ld + p], akq = A[lane * ld + q];
+          cplx nkp = {c * akp.x - (sec.x * akq.x - sec.y * akq.y),
+                      c * akp.y - (sec.x * akq.y + sec.y * akq.x)};
+          cplx nkq = {se.x * akp.x - se.y * akp.y + c * akq.x,
+                      se.x * akp.y + se.y * akp.x + c * akq.y};
+          A[lane * ld + p] = nkp;
+          A[lane * ld + q] = nkq;
+          A[p * ld + lane] = cconj(nkp);
+          A[q * ld + lane] = cconj(nkq);
+        }
+        if (lane < n) {
+          cplx vkp = V[lane * ld + p], vkq = V[lane * ld + q];
+          V[lane * ld + p] = {c * vkp.x - (sec.x * vkq.x - sec.y * vkq.y),
+                              c * vkp.y - (sec.x * vkq.y + sec.y * vkq.x)};
+          V[lane * ld + q] = {se.x * vkp.x - se.y * vkp.y + c * vkq.x,
+                              se.x * vkp.y + se.y * vkp.x + c * vkq.y};
+        }
+        if (lane == 0) {
+          A[p * ld + p] = {app - t * mag, 0.0};
+          A[q * ld + q] = {aqq + t * mag, 0.0};
+          A[p * ld + q] = {0.0, 0.0};
+          A[q * ld + p] = {0.0, 0.0};
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Sort eigenpairs ascending: lam[k] with columns V[:,k] -> sorted into
+// lam_out / V (via scratch W).  Stable on ties.
+__device__ void sort_eigen(const double* lam_in, double* lam_out, cplx* V, cplx* W, int n,
+                           int ld, int lane) {
+  __syncthreads();
+  if (lane < n) {
+    double l = lam_in[lane];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      double m = lam_in[j];
+      rank += (m < l) || (m == l && j < lane);
+    }
+    lam_out[rank] = l;
+    for (int a = 0; a < n; ++a) W[a * ld + rank] = V[a * ld + lane];
+  }
+  __syncthreads();
+  for (int k = lane; k < n * n; k += 64) {
+    int r = k / n, c = k % n;
+    V[r * ld + c] = W[r * ld + c];
+  }
+  __syncthreads();
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const double* __restrict__ fc2s,
+                                                     const int32_t* __restrict__ rep,
+                                                     const double* __restrict__ repcart, int N0,
+                                                     int N1, int N2, double* __restrict__ omega,
+                                                     double* __restrict__ evec,
+                                                     double* __restrict__ vel) {
+  constexpr int LD = NMAX;
+  __shared__ cplx A[NMAX * LD];
+  __shared__ cplx V[NMAX * LD];
+  __shared__ cplx W[NMAX * LD];
+  __shared__ cplx Z[NMAX * LD];
+  __shared__ double lam[NMAX], lsort[NMAX];
+  __shared__ int cl_start[NMAX + 1];
+  __shared__ int n_cl;
+  __shared__ double zl[NMAX], zs[NMAX];
+  const int lane = threadIdx.x;
+  const int q = blockIdx.x;
+  const int n = nb3;
+  const int nq0 = q / (N1 * N2), nq1 = (q / N2) % N1, nq2 = q % N2;
+  const double chat[3] = {1.0 / sqrt(14.0), 2.0 / sqrt(14.0), 3.0 / sqrt(14.0)};
+
+  // D(q)[a][b] = sum_l e^{-i q.R_l} K[a][l][b] / sqrt(m_a m_b), Hermitised.
+  auto phase = [&](int l) {
+    const int* r = rep + 3 * l;
+    int m0 = ((nq0 * r[0]) % N0 + N0) % N0, m1 = ((nq1 * r[1]) % N1 + N1) % N1,
+        m2 = ((nq2 * r[2]) % N2 + N2) % N2;
+    double f = (double)m0 / N0 + (double)m1 / N1 + (double)m2 / N2;
+    double sn, cs;
+    sincospi(-2.0 * f, &sn, &cs);
+    return cplx{cs, sn};
+  };
+  for (int k = lane; k < n * n; k += 64) {
+    int a = k / n, b = k % n;
+    cplx d1 = {0, 0}, d2 = {0, 0};
+    for (int l = 0; l < n_rep; ++l) {
+      cplx ph = phase(l);
+      d1 = cadd(d1, cscale(ph, fc2s[((size_t)a * n_rep + l) * n + b]));
+      d2 = cadd(d2, cscale(ph, fc2s[((size_t)b * n_rep + l) * n + a]));
+    }
+    // (D + D^H)/2
+    A[a * LD + b] = {0.5 * (d1.x + d2.x), 0.5 * (d1.y - d2.y)};
+  }
+  __syncthreads();
+  jacobi_hermitian(A, V, n, LD, lane, 60);
+  if (lane < n) lam[lane] = A[lane * LD + lane].x;
+  sort_eigen(lam, lsort, V, W, n, LD, lane);
+
+  // Degenerate clusters on nu = omega / 2 pi.
+  if (lane == 0) {
+    int nc = 0;
+    cl_start[nc++] = 0;
+    double prev = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double l = lsort[k];
+      double nu = (l >= 0 ? sqrt(l * kU) : -sqrt(-l * kU)) / kTwoPi;
+      if (k > 0 && !(nu - prev < kDegTolThz)) cl_start[nc++] = k;
+      prev = nu;
+    }
+    cl_start[nc] = n;
+    n_cl = nc;
+  }
+  __syncthreads();
+  // dD_chat = sum_c chat_c dD/dq_c = sum_l (-i chat.R_l) e^{-i q.R_l} K_l, into A.
+  bool any_deg = false;
+  for (int k = 0; k < n_cl; ++k) any_deg |= (cl_start[k + 1] - cl_start[k]) > 1;
+  if (any_deg) {
+    for (int k = lane; k < n * n; k += 64) {
+      int a = k / n, b = k % n;
+      cplx d = {0, 0};
+      for (int l = 0; l < n_rep; ++l) {
+        cplx ph = phase(l);
+        double cr = chat[0] * repcart[3 * l] + chat[1] * repcart[3 * l + 1] + chat[2] * repcart[3 * l + 2];
+        // -i * cr * ph
+        d = cadd(d, cscale(cplx{ph.y * cr, -ph.x * cr}, fc2s[((size_t)a * n_rep + l) * n + b]));
+      }
+      A[a * LD + b] = d;
+    }
+    __syncthreads();
+    for (int k = 0; k < n_cl; ++k) {
+      const int c0 = cl_start[k], m = cl_start[k + 1] - c0;
+      if (m < 2) continue;
+      // W = dD P  (n x m), then Z = P^H W (m x m), Hermitised
+      for (int idx = lane; idx < n * m; idx += 64) {
+        int a = idx / m, j = idx % m;
+        cplx s = {0, 0};
+        for (int b = 0; b < n; ++b) s = cadd(s, cmul(A[a * LD + b], V[b * LD + c0 + j]));
+        W[a * LD + j] = s;
+      }
+      __syncthreads();
+      for (int idx = lane; idx < m * m; idx += 64) {
+        int i = idx / m, j = idx % m;
+        cplx s = {0, 0}, s2 = {0, 0};
+        for (int a = 0; a < n; ++a) {
+          s = cadd(s, cmul(cconj(V[a * LD + c0 + i]), W[a * LD + j]));
+          s2 = cadd(s2, cmul(cconj(V[a * LD + c0 + j]), W[a * LD + i]));
+        }
+        Z[i * LD + j] = {0.5 * (s.x + s2.x), 0.5 * (s.y - s2.y)};
+      }
+      __syncthreads();
+      // eigenvectors of the m x m block into W (as V), Z diagonalised in place
+      jacobi_hermitian(Z, W, m, LD, lane, 60);
+      if (lane < m) zl[lane] = Z[lane * LD + lane].x;
+      sort_eigen(zl, zs, W, Z, m, LD, lane);
+      // P <- P W: rows a of V's cluster columns
+      if (lane < n) {
+        cplx row[NMAX];
+        for (int j = 0; j < m; ++j) {
+          cplx s = {0, 0};
+          for (int i = 0; i < m; ++i) s = cadd(s, cmul(V[lane * LD + c0 + i], W[i * LD + j]));
+          row[j] = s;
+        }
+        for (int j = 0; j < m; ++j) V[lane * LD + c0 + j] = row[j];
+      }
+      __syncthreads();
+    }
+  }
+  // Phase fix: largest-modulus component (first on ties) real positive.
+  if (lane < n) {
+    int best = 0;
+    double bm = -1.0;
+    for (int a = 0; a < n; ++a) {
+      cplx v = V[a * LD + lane];
+      double m2 = v.x * v.x + v.y * v.y;
+      if (m2 > bm) {
+        bm = m2;
+        best = a;
+      }
+    }
+    cplx piv = V[best * LD + lane];
+    double pm = sqrt(bm);
+    cplx f = {piv.x / pm, -piv.y / pm};
+    for (int a = 0; a < n; ++a) V[a * LD + lane] = cmul(V[a * LD + lane], f);
+  }
+  __syncthreads();
+  // Outputs: omega, eta, and v_c = Re(eta^H dD/dq_c eta) U / (2 omega).
+  double om_l = 0.0;
+  if (lane < n) {
+    double l = lsort[lane];
+    om_l = l >= 0 ? sqrt(l * kU) : -sqrt(-l * kU);
+    omega[(size_t)q * n + lane] = om_l;
+  }
+  for (int k = lane; k < n * n; k += 64) {
+    int a = k / n, mu = k % n;
+    cplx v = V[a * LD + mu];
+    size_t o = (((size_t)q * n + a) * n + mu) * 2;
+    evec[o] = v.x;
+    evec[o + 1] = v.y;
+  }
+  for (int c = 0; c < 3; ++c) {
+    __syncthreads();
+    for (int k = lane; k < n * n; k += 64) {
+      int a = k / n, b = k % n;
+      cplx d = {0, 0};
+      for (int l = 0; l < n_rep; ++l) {
+        cplx ph = phase(l);
+        double cr = repcart[3 * l + c];
+        d = cadd(d, cscale(cplx{ph.y * cr, -ph.x * cr}, fc2s[((size_t)a * n_rep + l) * n + b]));
+      }
+      A[a * LD + b] = d;
+    }
+    __syncthreads();
+    if (lane < n) {
+      double re = 0.0;
+      for (int a = 0; a < n; ++a) {
+        cplx s = {0, 0};
+        for (int b = 0; b < n; ++b) s = cadd(s, cmul(A[a * LD + b], V[b * LD + lane]));
+        cplx va = V[a * LD + lane];
+        re += va.x * s.x + va.y * s.y;
+      }
+      double nu = om_l / kTwoPi;
+      double v = fabs(nu) >= kNuVelFloorThz ? re * kU / (2.0 * om_l) : 0.0;
+      vel[((size_t)q * n + lane) * 3 + c] = v;
+    }
+  }
+}
+
+}  // namespace kaldo
+
+using namespace kaldo;
+
+extern "C" int kaldo_phonons(const kaldo_crystal* c, const int32_t* mesh, double* omega,
+                             double* evec, double* vel, void* stream) {
+  KALDO_REQUIRE(c && mesh && omega && evec && vel, "kaldo_phonons: NULL argument");
+  KALDO_REQUIRE(mesh[0] >= 1 && mesh[1] >= 1 && mesh[2] >= 1, "kaldo_phonons: mesh must be >= 1");
+  KALDO_REQUIRE(c->nb3 <= kMaxNb3Phonons, "kaldo_phonons: nb3 > 32 (use kaldo_phonons_gamma)");
+  const long nq = (long)mesh[0] * mesh[1] * mesh[2];
+  KALDO_REQUIRE(nq <= (1L << 24), "kaldo_phonons: mesh too large");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (c->nb3 <= 16) {
+    hipLaunchKernelGGL(phonons_kernel<16>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
+                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
+  } else {
+    hipLaunchKernelGGL(phonons_kernel<32>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
+                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
+  }
+  KALDO_HIP(hipGetLastError());
+  return KALDO_OK;
+}

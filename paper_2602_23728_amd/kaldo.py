@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libkaldo.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels (or, for the Gamma-point
+eigenproblem, its host C++); this module only moves arguments: numpy arrays
+for host inputs, torch CUDA tensors for device buffers, and the current torch
+stream as the HIP stream.  It fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkaldo.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+GAUSS, LORENTZ = 0, 1
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
+
+
+class KaldoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Broadening(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("adaptive", ctypes.c_int32),
+                ("sigma_thz", ctypes.c_double), ("sigma_floor_thz", ctypes.c_double),
+                ("nu_min_thz", ctypes.c_double)]
+
+    @classmethod
+    def of(cls, b):
+        """From any object with shape/adaptive/sigma_thz/sigma_floor_thz/nu_min_thz."""
+        return cls(int(b.shape), int(bool(b.adaptive)), float(b.sigma_thz),
+                   float(b.sigma_floor_thz), float(b.nu_min_thz))
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I32P = ctypes.POINTER(ctypes.c_int32)
+F64P = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2602_23728_amd.build "
+                              "(there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.kaldo_last_error.restype = ctypes.c_char_p
+        L.kaldo_version.restype = ctypes.c_int
+        L.kaldo_crystal_create.argtypes = [ctypes.c_int32, F64P, F64P, ctypes.c_int32, I32P, F64P,
+                                           ctypes.c_int64, I32P, I32P, I32P, F64P,
+                                           ctypes.POINTER(P)]
+        L.kaldo_crystal_destroy.argtypes = [P]
+        L.kaldo_phonons.argtypes = [P, I32P, P, P, P, P]
+        L.kaldo_phonons_gamma.argtypes = [ctypes.c_int32, F64P, ctypes.c_int32, F64P, F64P, F64P]
+        L.kaldo_linewidths_workspace.argtypes = [P, I32P, ctypes.c_int32]
+        L.kaldo_linewidths_workspace.restype = ctypes.c_size_t
+        L.kaldo_linewidths.argtypes = [P, I32P, P, P, P, ctypes.c_double,
+                                       ctypes.POINTER(Broadening), ctypes.c_int32, P,
+                                       ctypes.c_int64, P, ctypes.c_size_t, P, P]
+        L.kaldo_linewidths_gamma_workspace.argtypes = [P, ctypes.c_int32]
+        L.kaldo_linewidths_gamma_workspace.restype = ctypes.c_size_t
+        L.kaldo_linewidths_gamma.argtypes = [P, P, P, ctypes.c_double, ctypes.POINTER(Broadening),
+                                             ctypes.c_int32, P, ctypes.c_int64, P,
+                                             ctypes.c_size_t, P, P]
+        L.kaldo_kappa_rta.argtypes = [P, I32P, P, P, P, ctypes.c_double, ctypes.c_double, P, P]
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
+            "kaldo_phonons_gamma", "kaldo_linewidths_workspace", "kaldo_linewidths",
+            "kaldo_linewidths_gamma_workspace", "kaldo_linewidths_gamma", "kaldo_kappa_rta",
+            "kaldo_last_error", "kaldo_version"]
+
+
+def _check(rc):
+    if rc != 0:
+        raise KaldoError(rc, lib().kaldo_last_error().decode())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _dev(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensor expected"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _mesh(mesh):
+    m = _i32(mesh)
+    assert m.shape == (3,)
+    return m
+
+
+class Crystal:
+    """A cell with FC2 / FC3 uploaded to the current device."""
+
+    def __init__(self, n_basis, lattice, mass, rep, fc2, fc3_i, fc3_j, fc3_k, fc3_val):
+        self._keep = [_f64(lattice).reshape(9), _f64(mass), _i32(rep).reshape(-1), _f64(fc2).reshape(-1),
+                      _i32(fc3_i), _i32(fc3_j), _i32(fc3_k), _f64(fc3_val)]
+        lat, m, r, f2, fi, fj, fk, fv = self._keep
+        self.n_basis = int(n_basis)
+        self.nb3 = 3 * self.n_basis
+        self.volume = float(abs(np.linalg.det(_f64(lattice).reshape(3, 3))))
+        h = P()
+        _check(lib().kaldo_crystal_create(self.n_basis, _ptr(lat, F64P), _ptr(m, F64P),
+                                          int(len(r) // 3), _ptr(r, I32P), _ptr(f2, F64P),
+                                          int(len(fv)), _ptr(fi, I32P), _ptr(fj, I32P),
+                                          _ptr(fk, I32P), _ptr(fv, F64P), ctypes.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_model(cls, m):
+        return cls(m.n_basis, m.lattice, m.mass, m.rep, m.fc2, m.fc3_i, m.fc3_j, m.fc3_k, m.fc3_val)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().kaldo_crystal_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def phonons(c: Crystal, mesh, out=None):
+    """omega [N_q, nb3], evec [N_q, nb3, nb3] complex128, vel [N_q, nb3, 3] on cuda."""
+    m = _mesh(mesh)
+    nq = int(np.prod(m))
+    if out is None:
+        dev = torch.device("cuda")
+        out = (torch.empty(nq, c.nb3, dtype=torch.float64, device=dev),
+               torch.empty(nq, c.nb3, c.nb3, 2, dtype=torch.float64, device=dev),
+               torch.empty(nq, c.nb3, 3, dtype=torch.float64, device=dev))
+    om, ev, ve = out
+    _check(lib().kaldo_phonons(c.handle, _ptr(m, I32P), _dev(om), _dev(ev), _dev(ve), _stream()))
+    return om, torch.view_as_complex(ev), ve
+
+
+def phonons_gamma(n_basis, mass, fc2):
+    """Host FP64 Gamma-point eigenproblem: omega [nb3], E [nb3, nb3] (numpy).
+    fc2: [3N_b][n_rep][3N_b]."""
+    m = _f64(mass)
+    f2 = _f64(fc2)
+    nb3 = 3 * int(n_basis)
+    n_rep = f2.size // (nb3 * nb3)
+    om = np.empty(nb3)
+    E = np.empty((nb3, nb3))
+    _check(lib().kaldo_phonons_gamma(int(n_basis), _ptr(m, F64P), int(n_rep), _ptr(f2.reshape(-1), F64P),
+                                     _ptr(om, F64P), _ptr(E, F64P)))
+    return om, E
+
+
+def linewidths_workspace(c: Crystal, mesh, precision):
+    return int(lib().kaldo_linewidths_workspace(c.handle, _ptr(_mesh(mesh), I32P), int(precision)))
+
+
+def _as_real(evec):
+    if evec.is_complex():
+        return torch.view_as_real(evec)
+    return evec
+
+
+def linewidths(c: Crystal, mesh, omega, evec, vel, temperature, broadening, precision=FP32,
+               subset=None, workspace=None, out=None):
+    """Gamma [N_q, nb3] (rad/ps) on cuda."""
+    m = _mesh(mesh)
+    nq = int(np.prod(m))
+    ws_bytes = linewidths_workspace(c, m, precision)
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda")
+    if out is None:
+        out = torch.zeros(nq, c.nb3, dtype=torch.float64, device="cuda")
+    ev = _as_real(evec).contiguous()
+    b = Broadening.of(broadening)
+    sub = None if subset is None else subset.to(torch.int32).contiguous()
+    _check(lib().kaldo_linewidths(c.handle, _ptr(m, I32P), _dev(omega), _dev(ev), _dev(vel),
+                                  float(temperature), ctypes.byref(b), int(precision), _dev(sub),
+                                  0 if sub is None else int(sub.numel()), _dev(workspace),
+                                  int(workspace.numel()), _dev(out), _stream()))
+    return out
+
+
+def linewidths_gamma(c: Crystal, omega, evec, temperature, broadening, precision=FP32,
+                     subset=None, workspace=None, out=None):
+    """Gamma [nb3] (rad/ps) of a Gamma-point solid, on cuda."""
+    ws_bytes = int(lib().kaldo_linewidths_gamma_workspace(c.handle, int(precision)))
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device="cuda")
+    if out is None:
+        out = torch.zeros(c.nb3, dtype=torch.float64, device="cuda")
+    b = Broadening.of(broadening)
+    sub = None if subset is None else subset.to(torch.int32).contiguous()
+    _check(lib().kaldo_linewidths_gamma(c.handle, _dev(omega), _dev(evec.contiguous()),
+                                        float(temperature), ctypes.byref(b), int(precision),
+                                        _dev(sub), 0 if sub is None else int(sub.numel()),
+                                        _dev(workspace), int(workspace.numel()), _dev(out),
+                                        _stream()))
+    return out
+
+
+def kappa_rta(c: Crystal, mesh, omega, vel, gamma, temperature, nu_min_thz, out=None):
+    """kappa [3, 3] W/(m K) on cuda."""
+    m = _mesh(mesh)
+    if out is None:
+        out = torch.empty(3, 3, dtype=torch.float64, device="cuda")
+    _check(lib().kaldo_kappa_rta(c.handle, _ptr(m, I32P), _dev(omega), _dev(vel), _dev(gamma),
+                                 float(temperature), float(nu_min_thz), _dev(out), _stream()))
+    return out

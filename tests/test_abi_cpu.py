@@ -1,0 +1,80 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments before touching the device, and its host
+Gamma-point eigensolver agrees with LAPACK."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import phonons as oph
+from synthetic import configs, models
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kaldo.h")
+
+K = pytest.importorskip("paper_2602_23728_amd.kaldo")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kaldo_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = K.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(K.EXPORTED)
+    assert lib.kaldo_version() >= 100
+
+
+def test_argument_validation_without_device():
+    lib = K.lib()
+    mesh = (ctypes.c_int32 * 3)(2, 2, 2)
+    rc = lib.kaldo_phonons(None, mesh, None, None, None, None)
+    assert rc == -1 and b"NULL" in lib.kaldo_last_error()
+    b = K.Broadening(0, 0, 0.1, 0.01, 0.1)
+    rc = lib.kaldo_linewidths(None, mesh, None, None, None, 300.0, ctypes.byref(b), 1, None, 0,
+                              None, 0, None, None)
+    assert rc == -1
+    # rep[0] must be the home cell: rejected before any device allocation
+    m = models.diamond()
+    rep = np.ascontiguousarray(m.rep[::-1], np.int32)
+    with pytest.raises(K.KaldoError) as e:
+        K.Crystal(m.n_basis, m.lattice, m.mass, rep, m.fc2, m.fc3_i, m.fc3_j, m.fc3_k, m.fc3_val)
+    assert e.value.status == -1
+    bad = m.fc3_j.copy()
+    bad[3] = 10_000
+    with pytest.raises(K.KaldoError):
+        K.Crystal(m.n_basis, m.lattice, m.mass, m.rep, m.fc2, m.fc3_i, bad, m.fc3_k, m.fc3_val)
+    with pytest.raises(K.KaldoError):
+        K.phonons_gamma(2, np.array([1.0, -1.0]), np.zeros((6, 1, 6)))
+
+
+@pytest.mark.parametrize("which", ["supercell", "rglass", "glass"])
+def test_host_gamma_eigensolver_matches_lapack(which):
+    if which == "supercell":
+        m = models.supercell_gamma(models.diamond(), (3, 3, 3))
+    elif which == "rglass":
+        m = models.random_cluster_glass(3, 12)
+    else:
+        m = configs.build_model("glass")
+    om, E = K.phonons_gamma(m.n_basis, m.mass, m.fc2)
+    oo, oE = oph.phonons_gamma_real(m)
+    n = len(om)
+    big = np.abs(oo) > 2 * np.pi * 0.05
+    assert np.max(np.abs(om[big] - oo[big])) <= 1e-10 * oo.max()
+    assert np.max(np.abs(E.T @ E - np.eye(n))) < 1e-12
+    D = m.fc2.sum(axis=1) / np.sqrt(np.outer(np.repeat(m.mass, 3), np.repeat(m.mass, 3)))
+    lam = np.sign(om) * om ** 2 / oph.U
+    assert np.max(np.abs(D @ E - E * lam[None, :])) < 1e-12 * np.abs(D).max()
+    nu = oo / (2 * np.pi)
+    for j in range(n):
+        iso = (j == 0 or nu[j] - nu[j - 1] > 1e-4) and (j == n - 1 or nu[j + 1] - nu[j] > 1e-4)
+        if iso and big[j]:
+            assert np.max(np.abs(E[:, j] - oE[:, j])) < 1e-9

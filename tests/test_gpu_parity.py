@@ -1,0 +1,253 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Both sides take the same seeded inputs; linewidth tests feed both the same
+(omega, eta, v) arrays because inside a degenerate subspace per-mode values
+depend on the basis.  Tolerances: Gamma relative error <= 1e-5 for modes with
+Gamma > 1e-3 max Gamma in the FP32 form, <= 1e-10 (relative to max Gamma) in
+the FP64 form; kappa <= 1e-4 (trace/3 and max component, relative to trace/3).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import kappa as okappa
+from oracle import linewidths as olw
+from oracle import phonons as oph
+from oracle.constants import TWO_PI
+from synthetic import configs, models
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2602_23728_amd import kaldo as K  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+B_FIXED = configs.Broadening(adaptive=False)
+B_ADAPT = configs.Broadening(adaptive=True)
+B_LOR = configs.Broadening(shape=configs.LORENTZ, adaptive=False, sigma_thz=0.2)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def clusters(nu, tol=1e-4):
+    out, start = [], 0
+    for k in range(1, len(nu) + 1):
+        if k == len(nu) or nu[k] - nu[k - 1] >= tol:
+            out.append(slice(start, k))
+            start = k
+    return out
+
+
+def gamma_close(g_gpu, g_ref, rel=1e-5, floor=1e-3):
+    g_gpu = np.asarray(g_gpu).reshape(-1)
+    g_ref = np.asarray(g_ref).reshape(-1)
+    big = g_ref > floor * g_ref.max()
+    err = np.abs(g_gpu[big] - g_ref[big]) / g_ref[big]
+    return float(err.max()) if big.any() else 0.0
+
+
+def kappa_close(k_gpu, k_ref):
+    kbar = np.trace(k_ref) / 3
+    return max(abs(np.trace(k_gpu) / 3 - kbar) / kbar, np.max(np.abs(k_gpu - k_ref)) / kbar)
+
+
+@pytest.fixture(scope="module")
+def diamond():
+    m = models.diamond()
+    return m, K.Crystal.from_model(m)
+
+
+# ------------------------------------------------------------------ phonons
+
+@pytest.mark.parametrize("name,mesh", [("diamond", (5, 5, 5)), ("perovskite", (3, 3, 3)),
+                                       ("random", (2, 3, 4))])
+def test_phonons_match_oracle(name, mesh):
+    m = models.random_cell(7, 2) if name == "random" else configs.build_model(name)
+    c = K.Crystal.from_model(m)
+    om, ev, ve = K.phonons(c, mesh)
+    om, ev, ve = host(om), host(ev), host(ve)
+    oo, oe, ov = oph.phonons(m, mesh)
+    nu, onu = om / TWO_PI, oo / TWO_PI
+    big = np.abs(onu) > 0.05
+    assert np.max(np.abs(om[big] - oo[big])) <= 1e-9 * np.abs(oo).max()
+    assert np.all(np.abs(nu[~big]) < 0.01)
+    for q in range(om.shape[0]):
+        assert np.allclose(ev[q].conj().T @ ev[q], np.eye(m.n_basis * 3), atol=1e-12)
+        for cl in clusters(onu[q]):
+            if onu[q][cl][0] < 0.05:
+                continue
+            P1 = ev[q][:, cl] @ ev[q][:, cl].conj().T
+            P2 = oe[q][:, cl] @ oe[q][:, cl].conj().T
+            assert np.max(np.abs(P1 - P2)) < 1e-8
+            # trace of the velocity operator over the cluster is basis-free
+            assert np.allclose(ve[q][cl].sum(0), ov[q][cl].sum(0), atol=1e-7 * max(1, np.abs(ov).max()))
+
+
+# ------------------------------------------------------------------ crystal linewidths
+
+def _oracle_inputs(m, mesh):
+    return oph.phonons(m, mesh)
+
+
+@pytest.mark.parametrize("broad", [B_FIXED, B_ADAPT, B_LOR], ids=["fixed", "adaptive", "lorentz"])
+def test_linewidths_fp64_c1(diamond, broad):
+    m, c = diamond
+    mesh = (5, 5, 5)
+    om, ev, ve = _oracle_inputs(m, mesh)
+    G = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, broad, K.FP64))
+    Go = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, broad)
+    assert np.max(np.abs(G - Go)) <= 1e-10 * Go.max()
+
+
+@pytest.mark.parametrize("broad", [B_FIXED, B_ADAPT], ids=["fixed", "adaptive"])
+def test_linewidths_fp32_c1(diamond, broad):
+    m, c = diamond
+    mesh = (5, 5, 5)
+    om, ev, ve = _oracle_inputs(m, mesh)
+    G = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, broad, K.FP32))
+    Go = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, broad)
+    assert gamma_close(G, Go) <= 1e-5
+    kg = host(K.kappa_rta(c, mesh, dev(om), dev(ve), dev(G), 300.0, 0.1))
+    ko = okappa.kappa_rta(om, ve, Go, 300.0, m.volume, 125, 0.1)
+    assert kappa_close(kg, ko) <= 1e-4
+
+
+def test_kappa_kernel_matches_oracle(diamond):
+    m, c = diamond
+    mesh = (5, 5, 5)
+    om, ev, ve = _oracle_inputs(m, mesh)
+    Go = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_ADAPT)
+    kg = host(K.kappa_rta(c, mesh, dev(om), dev(ve), dev(Go), 300.0, 0.1))
+    ko = okappa.kappa_rta(om, ve, Go, 300.0, m.volume, 125, 0.1)
+    assert np.max(np.abs(kg - ko)) <= 1e-12 * np.abs(ko).max()
+
+
+def test_end_to_end_c1_gpu_phonons(diamond):
+    """GPU phonons -> GPU linewidths -> GPU kappa vs the oracle's own chain."""
+    m, c = diamond
+    mesh = (5, 5, 5)
+    om, ev, ve = K.phonons(c, mesh)
+    G = K.linewidths(c, mesh, om, ev, ve, 300.0, B_ADAPT, K.FP32)
+    kg = host(K.kappa_rta(c, mesh, om, ve, G, 300.0, 0.1))
+    G, om_h = host(G), host(om)
+    oo, oe, ov = _oracle_inputs(m, mesh)
+    Go = olw.crystal_linewidths(m, mesh, oo, oe, ov, 300.0, B_ADAPT)
+    ko = okappa.kappa_rta(oo, ov, Go, 300.0, m.volume, 125, 0.1)
+    onu = oo / TWO_PI
+    for q in range(oo.shape[0]):
+        for cl in clusters(onu[q]):
+            a, b = G[q][cl].sum(), Go[q][cl].sum()
+            if b > 1e-3 * Go.max():
+                assert abs(a - b) <= 1e-5 * b
+    assert kappa_close(kg, ko) <= 1e-4
+
+
+def test_linewidths_ragged_mesh_random_cell():
+    m = models.random_cell(11, 2)
+    mesh = (2, 3, 5)
+    c = K.Crystal.from_model(m)
+    om, ev, ve = _oracle_inputs(m, mesh)
+    for prec, tol in ((K.FP64, 1e-10), (K.FP32, 1e-5)):
+        G = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, prec))
+        Go = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_ADAPT)
+        if prec == K.FP64:
+            assert np.max(np.abs(G - Go)) <= tol * Go.max()
+        else:
+            assert gamma_close(G, Go) <= tol
+
+
+def test_c2_full_size_golden(diamond):
+    path = os.path.join(GOLDEN, "c2_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py C2")
+    g = np.load(path)
+    m, c = diamond
+    cfg = configs.CONFIGS["C2"]
+    G = host(K.linewidths(c, cfg.mesh, dev(g["omega"]), dev(g["evec"]), dev(g["vel"]), 300.0,
+                          cfg.broadening, K.FP32))
+    assert gamma_close(G, g["gamma"]) <= 1e-5
+    kg = host(K.kappa_rta(c, cfg.mesh, dev(g["omega"]), dev(g["vel"]), dev(G), 300.0, 0.1))
+    assert kappa_close(kg, g["kappa"]) <= 1e-4
+
+
+def test_c3_sampled_q_points():
+    cfg = configs.CONFIGS["C3"]
+    m = configs.model_for(cfg)
+    c = K.Crystal.from_model(m)
+    om, ev, ve = _oracle_inputs(m, cfg.mesh)
+    G = host(K.linewidths(c, cfg.mesh, dev(om), dev(ev), dev(ve), 300.0, cfg.broadening, K.FP32))
+    qs = [0, 1, 777, 1727]
+    Go = olw.crystal_linewidths(m, cfg.mesh, om, ev, ve, 300.0, cfg.broadening, q_list=qs)
+    assert gamma_close(G[qs], Go[qs]) <= 1e-5
+
+
+def test_subset_writes_only_selected(diamond):
+    m, c = diamond
+    mesh = (3, 3, 3)
+    om, ev, ve = _oracle_inputs(m, mesh)
+    out = torch.full((27, 6), -7.0, dtype=torch.float64, device="cuda")
+    sel = np.array([0, 5, 13, 60, 161], np.int32)
+    K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, K.FP64, subset=dev(sel), out=out)
+    G = host(out).reshape(-1)
+    Gall = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, K.FP64)).reshape(-1)
+    mask = np.zeros(162, bool)
+    mask[sel] = True
+    assert np.all(G[~mask] == -7.0)
+    assert np.array_equal(G[mask], Gall[mask])
+
+
+def test_bitwise_deterministic(diamond):
+    m, c = diamond
+    mesh = (5, 5, 5)
+    om, ev, ve = _oracle_inputs(m, mesh)
+    a = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, K.FP32))
+    b = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, K.FP32))
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ Gamma point
+
+def test_gamma_point_supercell_and_zone_folding(diamond):
+    m, _ = diamond
+    sc = models.supercell_gamma(m, (3, 3, 3))
+    c = K.Crystal.from_model(sc)
+    om, E = oph.phonons_gamma_real(sc)
+    Go = olw.gamma_point_linewidths(sc, om, E, 300.0, B_FIXED)
+    for prec, tol in ((K.FP64, 1e-10), (K.FP32, 1e-5)):
+        G = host(K.linewidths_gamma(c, dev(om), dev(E), 300.0, B_FIXED, prec))
+        if prec == K.FP64:
+            assert np.max(np.abs(G - Go)) <= tol * Go.max()
+        else:
+            assert gamma_close(G, Go) <= tol
+
+
+def test_gamma_point_random_glass():
+    g = models.random_cluster_glass(seed=9, n_atoms=20, box=8.0)
+    c = K.Crystal.from_model(g)
+    om, E = oph.phonons_gamma_real(g)
+    Go = olw.gamma_point_linewidths(g, om, E, 300.0, B_LOR)
+    G = host(K.linewidths_gamma(c, dev(om), dev(E), 300.0, B_LOR, K.FP64))
+    assert np.max(np.abs(G - Go)) <= 1e-10 * Go.max()
+
+
+def test_glass_c4_sampled_modes():
+    cfg = configs.CONFIGS["C4"]
+    gl = configs.model_for(cfg)
+    c = K.Crystal.from_model(gl)
+    om, E = K.phonons_gamma(gl.n_basis, gl.mass, gl.fc2)
+    G = host(K.linewidths_gamma(c, dev(om), dev(E), 300.0, cfg.broadening, K.FP32))
+    modes = [600, 900, 1200, 1535]
+    Go = olw.gamma_point_linewidths(gl, om, E, 300.0, cfg.broadening, modes=modes)
+    assert gamma_close(G[modes], Go[modes]) <= 1e-5
+    assert np.all(G[om / TWO_PI < 0.1] == 0.0)
