@@ -213,6 +213,20 @@ int kaldo_kappa_rta(const kaldo_crystal* c, const int32_t* mesh, const double* o
                     const double* vel, const double* gamma, double temperature,
                     double nu_min_thz, double* kappa, void* stream);
 
+/* Per-kernel timing.  kaldo_profile_begin() makes every later kernel launch
+ * of the library record a HIP event before and after it on its launch
+ * stream; kaldo_profile_end() waits for those events, writes up to
+ * `capacity` records (one per kernel name, in first-launch order) and sets
+ * *n_out to the number of distinct kernels, then switches timing off.
+ * Process-wide; calls from several threads are serialised. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} kaldo_kernel_time;
+int kaldo_profile_begin(void);
+int kaldo_profile_end(kaldo_kernel_time* out, int32_t capacity, int32_t* n_out);
+
 /* Thread-local message for the last failing call in this thread. */
 const char* kaldo_last_error(void);
 

@@ -71,6 +71,13 @@ struct Fc3Bloch {
   int32_t* t_i = nullptr;    // [n_t] home-cell dof
   int32_t* t_l2 = nullptr;   // [n_t] replica index of the third index
   double* t_coef = nullptr;  // [n_t]
+  // Atom-block view of the same entries: block = (jb, kb, d) with its 3x3
+  // Cartesian (beta, gamma) sub-block; blocks sorted by (jb, kb, d).
+  int n_blk = 0;
+  int32_t* e_blk = nullptr;     // [n_e] block of entry e
+  int32_t* e_bg = nullptr;      // [n_e] 3*beta + gamma of entry e
+  int32_t* blk_d = nullptr;     // [n_blk] d index of each block
+  int32_t* pair_ptr = nullptr;  // [N_b*N_b + 1] block ranges per (jb, kb)
 };
 
 // Gamma-point FC3: CSR over the (b, c) pattern of A_mu[b][c],
@@ -104,4 +111,17 @@ struct kaldo_crystal_s {
 namespace kaldo {
 // Reciprocal rows b_c (with 2 pi) of a lattice given by rows a_i.
 void reciprocal(const double* lattice, double* recip);
+
+// Per-kernel event timing (see kaldo_profile_begin).
+bool prof_on();
+void prof_mark(const char* name, hipStream_t st, bool start);
 }  // namespace kaldo
+
+// Launch a kernel, bracketed by timing events when profiling is enabled.
+#define KALDO_LAUNCH(name, kernel, grid, block, shmem, stream, ...)            \
+  do {                                                                         \
+    const bool p_ = ::kaldo::prof_on();                                        \
+    if (p_) ::kaldo::prof_mark(name, stream, true);                            \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);       \
+    if (p_) ::kaldo::prof_mark(name, stream, false);                           \
+  } while (0)

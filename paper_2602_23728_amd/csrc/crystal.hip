@@ -93,7 +93,26 @@ static int build_bloch(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
     t_ptr.push_back(static_cast<int32_t>(t_i.size()));
   }
   d_ptr.push_back(static_cast<int32_t>(e_jc.size()));
+  // atom blocks (jb, kb, d), sorted by (jb, kb, d)
+  const int n_d = static_cast<int>(dvec.size() / 3);
+  std::map<std::array<int32_t, 3>, int32_t> blocks;
+  for (int d = 0; d < n_d; ++d)
+    for (int e = d_ptr[d]; e < d_ptr[d + 1]; ++e) blocks[{e_jc[e] / 3, e_kc[e] / 3, d}] = 0;
+  std::vector<int32_t> blk_d, pair_ptr(nb * nb + 1, 0), e_blk(e_jc.size()), e_bg(e_jc.size());
+  int32_t nblk = 0;
+  for (auto& kv : blocks) {
+    kv.second = nblk++;
+    blk_d.push_back(kv.first[2]);
+    pair_ptr[kv.first[0] * nb + kv.first[1] + 1]++;
+  }
+  for (int k = 0; k < nb * nb; ++k) pair_ptr[k + 1] += pair_ptr[k];
+  for (int d = 0; d < n_d; ++d)
+    for (int e = d_ptr[d]; e < d_ptr[d + 1]; ++e) {
+      e_blk[e] = blocks[{e_jc[e] / 3, e_kc[e] / 3, d}];
+      e_bg[e] = (e_jc[e] % 3) * 3 + e_kc[e] % 3;
+    }
   Fc3Bloch& b = c->bloch;
+  b.n_blk = nblk;
   b.n_d = static_cast<int>(dvec.size() / 3);
   b.n_e = static_cast<int>(e_jc.size());
   b.n_t = static_cast<int>(t_i.size());
@@ -106,6 +125,10 @@ static int build_bloch(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
   if ((rc = upload(c, &b.t_i, t_i))) return rc;
   if ((rc = upload(c, &b.t_l2, t_l2))) return rc;
   if ((rc = upload(c, &b.t_coef, t_coef))) return rc;
+  if ((rc = upload(c, &b.e_blk, e_blk))) return rc;
+  if ((rc = upload(c, &b.e_bg, e_bg))) return rc;
+  if ((rc = upload(c, &b.blk_d, blk_d))) return rc;
+  if ((rc = upload(c, &b.pair_ptr, pair_ptr))) return rc;
   return KALDO_OK;
 }
 

@@ -225,26 +225,26 @@ static int run_gamma(const kaldo_crystal* c, const double* omega, const double* 
   T* av = reinterpret_cast<T*>(ws + g.off_av);
   T* W = reinterpret_cast<T*>(ws + g.off_w);
   double* partial = reinterpret_cast<double*>(ws + g.off_partial);
-  hipLaunchKernelGGL(gp_prepare, dim3((n + 255) / 256), dim3(256), 0, st, n, omega,
+  KALDO_LAUNCH("gp_prepare", gp_prepare, dim3((n + 255) / 256), dim3(256), 0, st, n, omega,
                      kHbar / (kKb * Tk), b->nu_min_thz, occ, phys, sel, subset ? 0 : 1);
   if (subset && n_subset > 0)
-    hipLaunchKernelGGL(gp_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
+    KALDO_LAUNCH("gp_select", gp_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
                        (long)n_subset, n, sel);
   long nn = (long)n * n;
-  hipLaunchKernelGGL(gp_round<T>, dim3((nn + 255) / 256), dim3(256), 0, st, nn, evec, Et);
+  KALDO_LAUNCH("gp_round", gp_round<T>, dim3((nn + 255) / 256), dim3(256), 0, st, nn, evec, Et);
   int32_t mesh1[3] = {1, 1, 1};
   LwParams p = make_params(c, mesh1, Tk, b);
   for (int m0 = 0; m0 < n; m0 += kGpBatch) {
     int nb = std::min(kGpBatch, n - m0);
     long na = (long)c->gamma.n_bc * nb;
-    hipLaunchKernelGGL(gp_avals<T>, dim3((na + 255) / 256), dim3(256), 0, st, n, c->gamma.n_bc, m0,
+    KALDO_LAUNCH("gp_avals", gp_avals<T>, dim3((na + 255) / 256), dim3(256), 0, st, n, c->gamma.n_bc, m0,
                        nb, c->gamma.t_ptr, c->gamma.t_a, c->gamma.t_coef, evec, av);
-    hipLaunchKernelGGL(gp_spmm<T>, dim3(n, nb), dim3(256), 0, st, n, c->gamma.n_bc, nb,
+    KALDO_LAUNCH("gp_spmm", gp_spmm<T>, dim3(n, nb), dim3(256), 0, st, n, c->gamma.n_bc, nb,
                        c->gamma.row_ptr, c->gamma.col, av, Et, W);
-    hipLaunchKernelGGL(gp_gemm<T>, dim3(nt, nt, nb), dim3(256), 0, st, p, n, m0, Et, W, omega, occ,
+    KALDO_LAUNCH("gp_gemm", gp_gemm<T>, dim3(nt, nt, nb), dim3(256), 0, st, p, n, m0, Et, W, omega, occ,
                        phys, sel, partial, nt);
   }
-  hipLaunchKernelGGL(gp_finish, dim3((n + 255) / 256), dim3(256), 0, st, n, nt * nt, partial, phys,
+  KALDO_LAUNCH("gp_finish", gp_finish, dim3((n + 255) / 256), dim3(256), 0, st, n, nt * nt, partial, phys,
                      sel, gamma);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;

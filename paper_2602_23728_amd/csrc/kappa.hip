@@ -67,7 +67,7 @@ extern "C" int kaldo_kappa_rta(const kaldo_crystal* c, const int32_t* mesh, cons
   const long nq = (long)mesh[0] * mesh[1] * mesh[2];
   const long n_modes = nq * c->nb3;
   const double scale = kKappaUnit / ((double)nq * c->volume);
-  hipLaunchKernelGGL(kappa_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), n_modes,
+  KALDO_LAUNCH("kappa_kernel", kappa_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), n_modes,
                      omega, vel, gamma, kHbar / (kKb * temperature), nu_min_thz, scale, kappa);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;

@@ -16,6 +16,7 @@
 //   lw_crystal       per (q, q1): FP64 cut and weights for every (s,s',s''),
 //                    projection of the passing ones, wave-ordered partial sums
 //   lw_finish        per mode: fixed-order sum of the partials, prefactor
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -185,7 +186,7 @@ __global__ void lw_finish(int nq, int nb3, int nblk, double scale, const double*
 }
 
 struct CrystalWs {
-  size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, total;
+  size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, off_phase, off_list, total;
 };
 
 static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
@@ -205,6 +206,8 @@ static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
   w.off_eta = take(cs * nq * nb3 * nb3);
   w.off_at = take(cs * nq * (size_t)c->bloch.n_e * nb3);
   w.off_partial = take(sizeof(double) * nq * nblk * nb3);
+  w.off_phase = take(cs * nq * (size_t)std::max(1, c->bloch.n_d));
+  w.off_list = take(sizeof(int32_t) * (nq * nb3 + 1));
   w.total = o;
   return w;
 }
@@ -225,24 +228,30 @@ static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double
   C* at = reinterpret_cast<C*>(ws + w.off_at);
   double* partial = reinterpret_cast<double*>(ws + w.off_partial);
   const double inv_kt_hbar = kHbar / (kKb * T_k);
-  hipLaunchKernelGGL(lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes, nb3,
+  KALDO_LAUNCH("lw_prepare", lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes, nb3,
                      omega, evec, inv_kt_hbar, b->nu_min_thz, occ, phys, sel, subset ? 0 : 1);
   if (subset && n_subset > 0)
-    hipLaunchKernelGGL(lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
+    KALDO_LAUNCH("lw_select", lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
                        (long)n_subset, n_modes, sel);
+  LwParams p = make_params(c, mesh, T_k, b);
+  if (fused_supported(c, sizeof(T) == 8 ? KALDO_FP64 : KALDO_FP32)) {
+    C* phase_tab = reinterpret_cast<C*>(ws + w.off_phase);
+    int32_t* list = reinterpret_cast<int32_t*>(ws + w.off_list);
+    return launch_fused<T>(c, p, omega, vel, occ, phys, sel, evec, eta, phase_tab, list,
+                           kPrefactor / (double)nq, gamma, st);
+  }
   long ne = nq * nb3 * nb3;
-  hipLaunchKernelGGL(lw_round_evec<T>, dim3((ne + 255) / 256), dim3(256), 0, st, ne, evec, eta);
+  KALDO_LAUNCH("lw_round_evec", lw_round_evec<T>, dim3((ne + 255) / 256), dim3(256), 0, st, ne, evec, eta);
   long na = nq * (long)c->bloch.n_e * nb3;
-  hipLaunchKernelGGL(lw_atilde<T>, dim3((na + 255) / 256), dim3(256), 0, st, (int)nq, nb3,
+  KALDO_LAUNCH("lw_atilde", lw_atilde<T>, dim3((na + 255) / 256), dim3(256), 0, st, (int)nq, nb3,
                      c->bloch.n_e, mesh[0], mesh[1], mesh[2], c->d_rep, c->bloch.t_ptr,
                      c->bloch.t_i, c->bloch.t_l2, c->bloch.t_coef, evec, at);
-  LwParams p = make_params(c, mesh, T_k, b);
   const int nblk = (nq + 63) / 64;
   size_t shmem = sizeof(C) * 64 * std::max(1, c->bloch.n_d);
-  hipLaunchKernelGGL(lw_crystal<T>, dim3(nblk, nq), dim3(64), shmem, st, p, omega, vel, occ, phys,
+  KALDO_LAUNCH("lw_crystal", lw_crystal<T>, dim3(nblk, nq), dim3(64), shmem, st, p, omega, vel, occ, phys,
                      sel, eta, at, c->bloch.dvec, c->bloch.d_ptr, c->bloch.e_jc, c->bloch.e_kc,
                      partial);
-  hipLaunchKernelGGL(lw_finish, dim3((n_modes + 255) / 256), dim3(256), 0, st, (int)nq, nb3, nblk,
+  KALDO_LAUNCH("lw_finish", lw_finish, dim3((n_modes + 255) / 256), dim3(256), 0, st, (int)nq, nb3, nblk,
                      kPrefactor / (double)nq, partial, phys, sel, gamma);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;

@@ -26,7 +26,7 @@ struct Cx<double> {
 };
 
 struct LwParams {
-  int nb3, nq, n_d, n_e;
+  int nb3, nq, n_d, n_e, n_blk;
   int N[3];
   int shape, adaptive;
   double sig_fixed, sig_floor, h2;  // rad/ps, rad/ps, 1/A^2
@@ -53,6 +53,7 @@ inline LwParams make_params(const kaldo_crystal* c, const int32_t* mesh, double 
   p.nq = mesh[0] * mesh[1] * mesh[2];
   p.n_d = c->bloch.n_d;
   p.n_e = c->bloch.n_e;
+  p.n_blk = c->bloch.n_blk;
   for (int i = 0; i < 3; ++i) p.N[i] = mesh[i];
   p.shape = b->shape;
   p.adaptive = b->adaptive;
@@ -113,5 +114,13 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
+
+// Fused one-workgroup-per-q crystal kernel (lw_fused.hip).
+bool fused_supported(const kaldo_crystal* c, int prec);
+template <typename T>
+int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* vel,
+                 const double* occ, const uint8_t* phys, const uint8_t* sel, const double* evec,
+                 typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab, int32_t* phys_list,
+                 double scale, double* gamma, hipStream_t st);
 
 }  // namespace kaldo

@@ -316,10 +316,10 @@ extern "C" int kaldo_phonons(const kaldo_crystal* c, const int32_t* mesh, double
   KALDO_REQUIRE(nq <= (1L << 24), "kaldo_phonons: mesh too large");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (c->nb3 <= 16) {
-    hipLaunchKernelGGL(phonons_kernel<16>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
+    KALDO_LAUNCH("phonons_kernel", phonons_kernel<16>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
                        c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
   } else {
-    hipLaunchKernelGGL(phonons_kernel<32>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
+    KALDO_LAUNCH("phonons_kernel", phonons_kernel<32>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
                        c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
   }
   KALDO_HIP(hipGetLastError());

@@ -27,6 +27,11 @@ class KaldoError(RuntimeError):
         self.status = status
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
 class Broadening(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_int32), ("adaptive", ctypes.c_int32),
                 ("sigma_thz", ctypes.c_double), ("sigma_floor_thz", ctypes.c_double),
@@ -72,6 +77,9 @@ def lib():
                                              ctypes.c_int32, P, ctypes.c_int64, P,
                                              ctypes.c_size_t, P, P]
         L.kaldo_kappa_rta.argtypes = [P, I32P, P, P, P, ctypes.c_double, ctypes.c_double, P, P]
+        L.kaldo_profile_begin.argtypes = []
+        L.kaldo_profile_end.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]
         _lib = L
     return _lib
 
@@ -79,7 +87,7 @@ def lib():
 EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
             "kaldo_phonons_gamma", "kaldo_linewidths_workspace", "kaldo_linewidths",
             "kaldo_linewidths_gamma_workspace", "kaldo_linewidths_gamma", "kaldo_kappa_rta",
-            "kaldo_last_error", "kaldo_version"]
+            "kaldo_last_error", "kaldo_version", "kaldo_profile_begin", "kaldo_profile_end"]
 
 
 def _check(rc):
