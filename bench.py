@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C2")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-q", type=int, default=48)
     return ap.parse_args()
@@ -75,6 +75,46 @@ def cpu_baseline(cfg, model, nq_sample, seed=0):
                 est_total_s=est), stats
 
 
+def bench_gamma_point(a, cfg, model, c, prec, K, torch):
+    """Gamma-point solid: host FP64 eigenproblem once (setup), then the GPU
+    linewidth pass timed."""
+    t0 = time.perf_counter()
+    om_h, E_h = K.phonons_gamma(model.n_basis, model.mass, model.fc2)
+    t_eig = time.perf_counter() - t0
+    om = torch.as_tensor(om_h).cuda()
+    E = torch.as_tensor(E_h).cuda()
+    n = len(om_h)
+    ws = torch.empty(int(K.lib().kaldo_linewidths_gamma_workspace(c.handle, prec)),
+                     dtype=torch.uint8, device="cuda")
+    gam = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def step():
+        K.linewidths_gamma(c, om, E, cfg.temperature, cfg.broadening, prec, workspace=ws, out=gam)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    K.lib().kaldo_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = profile_read(K)
+    ms = 1e3 * elapsed / a.steps
+    print(f"bench: {ms:.3f} ms/step; kernels: " +
+          ", ".join(f"{k} {v[1] / v[0]:.3f} ms x{v[0] // a.steps}" for k, v in prof.items()),
+          file=sys.stderr, flush=True)
+    print(json.dumps({"metric": METRIC, "value": n / (ms * 1e-3), "unit": "modes/s",
+                      "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": a.precision, "data": "synthetic",
+                      "config": {"workload": f"{cfg.name}: {cfg.description}", "modes": n,
+                                 "precision": a.precision},
+                      "host_eigensolver_s": t_eig,
+                      "kernels_ms_per_step": {k: v[1] / a.steps for k, v in prof.items()}}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -89,9 +129,11 @@ def main():
 
     cfg = configs.CONFIGS[a.config]
     model = configs.model_for(cfg)
-    prec = K.FP32 if a.precision == "fp32" else K.FP64
+    prec = {"fp32": K.FP32, "fp64": K.FP64, "bf16x3": K.BF16X3}[a.precision]
     torch.cuda.set_device(0)
     c = K.Crystal.from_model(model)
+    if cfg.mesh == (1, 1, 1):
+        return bench_gamma_point(a, cfg, model, c, prec, K, torch)
     mesh = cfg.mesh
     nq = int(np.prod(mesh))
     nb3 = c.nb3

@@ -160,7 +160,25 @@ static int build_gamma(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
   }
   if (pb >= 0) t_ptr.push_back(static_cast<int32_t>(t_a.size()));
   for (int r = 0; r < nb3; ++r) row_ptr[r + 1] += row_ptr[r];
+  const int n_rt = (nb3 + kSpmmRows - 1) / kSpmmRows;
+  std::vector<int32_t> tile_u_ptr(1, 0), tile_u, col_local(col.size());
+  int max_u = 0, g_max_entries = 0;
+  for (int t = 0; t < n_rt; ++t) {
+    const int r0 = t * kSpmmRows, r1 = std::min(nb3, r0 + kSpmmRows);
+    std::vector<int32_t> u(col.begin() + row_ptr[r0], col.begin() + row_ptr[r1]);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    for (int k = row_ptr[r0]; k < row_ptr[r1]; ++k)
+      col_local[k] = static_cast<int32_t>(std::lower_bound(u.begin(), u.end(), col[k]) - u.begin());
+    tile_u.insert(tile_u.end(), u.begin(), u.end());
+    tile_u_ptr.push_back(static_cast<int32_t>(tile_u.size()));
+    max_u = std::max<int>(max_u, static_cast<int>(u.size()));
+    g_max_entries = std::max(g_max_entries, row_ptr[r1] - row_ptr[r0]);
+  }
   Fc3Gamma& g = c->gamma;
+  g.n_rtiles = n_rt;
+  g.max_u = max_u;
+  g.max_tile_entries = g_max_entries;
   g.n_bc = static_cast<int>(col.size());
   g.n_t = static_cast<int>(t_a.size());
   int rc;
@@ -169,6 +187,9 @@ static int build_gamma(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
   if ((rc = upload(c, &g.t_ptr, t_ptr))) return rc;
   if ((rc = upload(c, &g.t_a, t_a))) return rc;
   if ((rc = upload(c, &g.t_coef, t_coef))) return rc;
+  if ((rc = upload(c, &g.tile_u_ptr, tile_u_ptr))) return rc;
+  if ((rc = upload(c, &g.tile_u, tile_u))) return rc;
+  if ((rc = upload(c, &g.col_local, col_local))) return rc;
   return KALDO_OK;
 }
 

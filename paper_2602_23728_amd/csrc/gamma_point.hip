@@ -16,6 +16,7 @@
 //   gp_finish  fixed-order sum of the tile partials per mode
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "common.h"
 #include "lw_common.h"
@@ -187,8 +188,22 @@ __global__ void gp_finish(int n, int n_tiles2, const double* __restrict__ partia
 }
 
 struct GammaWs {
-  size_t off_occ, off_phys, off_sel, off_et, off_av, off_w, off_partial, total;
+  size_t off_occ, off_phys, off_sel, off_et, off_av, off_w, off_partial, off_rest, total;
 };
+
+size_t gm_workspace_bytes(const kaldo_crystal* c, int prec);
+int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* evec,
+           const double* occ, const uint8_t* phys, const uint8_t* sel, unsigned char* ws,
+           int prec, double* gamma, hipStream_t st);
+
+bool gm_supported(const kaldo_crystal* c);
+
+static bool use_mfma(const kaldo_crystal* c, int prec) {
+  if (prec == KALDO_FP64 || !gm_supported(c)) return false;
+  if (prec == KALDO_BF16X3) return true;
+  const char* f = std::getenv("KALDO_FORCE_GENERIC");
+  return !(f && f[0] == '1');
+}
 
 static GammaWs gamma_ws(const kaldo_crystal* c, int prec) {
   const size_t n = c->nb3;
@@ -204,18 +219,22 @@ static GammaWs gamma_ws(const kaldo_crystal* c, int prec) {
   w.off_occ = take(8 * n);
   w.off_phys = take(n);
   w.off_sel = take(n);
+  w.off_rest = o;
   w.off_et = take(es * n * n);
   w.off_av = take(es * (size_t)c->gamma.n_bc * kGpBatch);
   w.off_w = take(es * n * n * kGpBatch);
   w.off_partial = take(8 * n * nt * nt);
   w.total = o;
+  if (prec != KALDO_FP64 && gm_supported(c))
+    w.total = std::max(w.total, w.off_rest + gm_workspace_bytes(c, prec));
   return w;
 }
 
 template <typename T>
 static int run_gamma(const kaldo_crystal* c, const double* omega, const double* evec, double Tk,
                      const kaldo_broadening* b, const int32_t* subset, int64_t n_subset,
-                     unsigned char* ws, const GammaWs& g, double* gamma, hipStream_t st) {
+                     unsigned char* ws, const GammaWs& g, int prec, double* gamma,
+                     hipStream_t st) {
   const int n = c->nb3;
   const int nt = (n + kGpTile - 1) / kGpTile;
   double* occ = reinterpret_cast<double*>(ws + g.off_occ);
@@ -230,10 +249,12 @@ static int run_gamma(const kaldo_crystal* c, const double* omega, const double* 
   if (subset && n_subset > 0)
     KALDO_LAUNCH("gp_select", gp_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
                        (long)n_subset, n, sel);
-  long nn = (long)n * n;
-  KALDO_LAUNCH("gp_round", gp_round<T>, dim3((nn + 255) / 256), dim3(256), 0, st, nn, evec, Et);
   int32_t mesh1[3] = {1, 1, 1};
   LwParams p = make_params(c, mesh1, Tk, b);
+  if (use_mfma(c, prec))
+    return run_gm(c, p, omega, evec, occ, phys, sel, ws + g.off_rest, prec, gamma, st);
+  long nn = (long)n * n;
+  KALDO_LAUNCH("gp_round", gp_round<T>, dim3((nn + 255) / 256), dim3(256), 0, st, nn, evec, Et);
   for (int m0 = 0; m0 < n; m0 += kGpBatch) {
     int nb = std::min(kGpBatch, n - m0);
     long na = (long)c->gamma.n_bc * nb;
@@ -273,18 +294,20 @@ extern "C" int kaldo_linewidths_gamma(const kaldo_crystal* c, const double* omeg
   if (rc) return rc;
   KALDO_REQUIRE(precision == KALDO_FP64 || precision == KALDO_FP32 || precision == KALDO_BF16X3,
                 "kaldo_linewidths_gamma: unknown precision");
-  if (precision == KALDO_BF16X3) {
-    set_error("kaldo_linewidths_gamma: BF16X3 is not available yet");
-    return KALDO_EUNSUPPORTED;
-  }
   KALDO_REQUIRE(n_subset >= 0 && (n_subset == 0 || modes_subset),
                 "kaldo_linewidths_gamma: bad subset");
+  if (precision == KALDO_BF16X3 && !gm_supported(c)) {
+    set_error("kaldo_linewidths_gamma: BF16X3 needs the MFMA path, whose SpMM tile does not fit LDS here");
+    return KALDO_EUNSUPPORTED;
+  }
   GammaWs g = gamma_ws(c, precision);
   KALDO_REQUIRE(workspace && workspace_bytes >= g.total, "kaldo_linewidths_gamma: workspace too small");
   if (modes_subset && n_subset == 0) return KALDO_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto* ws = static_cast<unsigned char*>(workspace);
   if (precision == KALDO_FP64)
-    return run_gamma<double>(c, omega, evec, temperature, b, modes_subset, n_subset, ws, g, gamma, st);
-  return run_gamma<float>(c, omega, evec, temperature, b, modes_subset, n_subset, ws, g, gamma, st);
+    return run_gamma<double>(c, omega, evec, temperature, b, modes_subset, n_subset, ws, g,
+                             precision, gamma, st);
+  return run_gamma<float>(c, omega, evec, temperature, b, modes_subset, n_subset, ws, g, precision,
+                          gamma, st);
 }

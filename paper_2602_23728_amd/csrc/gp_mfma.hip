@@ -1,0 +1,422 @@
+// Gamma-point projection on the matrix cores.
+//
+// For each mode mu the vertex matrix is V_mu = E^T W_mu with W_mu = A_mu E
+// (paper: Eq. phi3_proj with real eigenvectors).  V_mu is symmetric, so only
+// tiles (I, J) with I <= J of the 128 x 128 tiling are computed; an
+// off-diagonal tile stands for both orders of the partner pair, and its
+// epilogue adds w(mu', mu'') + w(mu'', mu').  Tiles whose partner
+// frequencies cannot meet the 2-sigma cut in either order exit before any
+// load (exact interval test).
+//
+// Operands live in HBM transposed, k-contiguous: ET[m][k] = E[k][m] and
+// WT[n][k] = W_mu[k][n], padded to a multiple of 128 with zeros.
+//   FP32 form:  v_mfma_f32_16x16x4_f32 on FP32 operands.
+//   BF16x3:     x = hi + lo with hi = bf16(x), lo = bf16(x - hi); each product
+//               is hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with
+//               FP32 accumulation (lo*lo dropped).
+// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement, each wave owning a
+// 64 x 64 block of the tile as 4 x 4 MFMA 16 x 16 accumulators.  The K loop
+// stages 128 x KT slices of both operands through LDS.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "lw_common.h"
+
+namespace kaldo {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+
+constexpr int kMT = 128;   // output tile edge
+constexpr int kMBatch = 256;  // modes per launch
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// ET (FP32 or bf16 hi/lo) from E (FP64, [k][m]); zero padding beyond n.
+__global__ void gm_prep_et(int n, int np, const double* __restrict__ E, float* __restrict__ et32,
+                           __bf16* __restrict__ eth, __bf16* __restrict__ etl) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)np * np) return;
+  const int m = idx / np, k = idx % np;
+  const float v = (m < n && k < n) ? (float)E[(size_t)k * n + m] : 0.0f;
+  if (et32) et32[idx] = v;
+  if (eth) {
+    __bf16 h, l;
+    split_bf16(v, h, l);
+    eth[idx] = h;
+    etl[idx] = l;
+  }
+}
+
+// A_mu values on the fixed (b, c) pattern, FP32, for modes m0 .. m0 + nb - 1,
+// stored mode-contiguous: avT[e][j] (kMBatch columns).
+__global__ void gm_avals(int n, int n_bc, int m0, int nb, const int32_t* __restrict__ t_ptr,
+                         const int32_t* __restrict__ t_a, const double* __restrict__ t_coef,
+                         const double* __restrict__ E, float* __restrict__ avT) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long)n_bc * kMBatch) return;
+  const int e = k / kMBatch, j = k % kMBatch;
+  double s = 0.0;
+  if (j < nb)
+    for (int t = t_ptr[e]; t < t_ptr[e + 1]; ++t) s += t_coef[t] * E[(size_t)t_a[t] * n + m0 + j];
+  avT[k] = (float)s;
+}
+
+// WT[j][c'][b] = sum_{k in row b} av[j][k] E[col_k][c'] for a tile of
+// kSpmmRows rows b and 64 columns c', all modes j of the batch.  The E rows
+// the tile touches (its unique column list) are staged once in LDS; each
+// mode's 32 x 64 result is transposed through LDS so WT rows are written
+// contiguously.  FP32 products and sums; the BF16x3 form stores hi/lo.
+constexpr int kSpmmCols = 64;            // columns c' per workgroup
+constexpr int kSpmmModes = 16;           // modes per workgroup
+// WT[j][c'][b] = sum_{k in row b} A_mu_j[b][col_k] E[col_k][c'], for a tile of
+// kSpmmRows rows (one per lane), kSpmmCols columns (16 per wave) and
+// kSpmmModes modes.  The tile's E rows are staged in LDS (FP32); each lane
+// walks its row's entries once per group of 4 columns and updates 4 x 16
+// accumulators per entry.  Writes are contiguous along b.
+__global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtiles,
+                                               const int32_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col_local,
+                                               const int32_t* __restrict__ tile_u_ptr,
+                                               const int32_t* __restrict__ tile_u,
+                                               const float* __restrict__ avT,
+                                               const double* __restrict__ E,
+                                               float* __restrict__ wt32, __bf16* __restrict__ wth,
+                                               __bf16* __restrict__ wtl) {
+  extern __shared__ float4 es4[];
+  float* es = reinterpret_cast<float*>(es4);  // [n_u][kSpmmCols]
+  const int rt = blockIdx.x, c0 = blockIdx.y * kSpmmCols, j0 = blockIdx.z * kSpmmModes;
+  const int b0 = rt * kSpmmRows;
+  const bool has_rows = rt < n_rtiles;  // row tiles past the last row of A are zero
+  const int u0 = has_rows ? tile_u_ptr[rt] : 0;
+  const int n_u = has_rows ? tile_u_ptr[rt + 1] - u0 : 0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int idx = tid; idx < n_u * kSpmmCols; idx += 256) {
+    const int u = idx / kSpmmCols, x = idx % kSpmmCols;
+    es[idx] = (c0 + x < n) ? (float)E[(size_t)tile_u[u0 + u] * n + c0 + x] : 0.0f;
+  }
+  __syncthreads();
+  const int b = b0 + lane;
+  const int k_lo = (has_rows && b < n) ? row_ptr[b] : 0;
+  const int k_hi = (has_rows && b < n) ? row_ptr[b + 1] : 0;
+  for (int xc = 0; xc < kSpmmCols / 4 / 4; ++xc) {
+    const int x0 = wv * (kSpmmCols / 4) + 4 * xc;
+    float acc[4][kSpmmModes];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int j = 0; j < kSpmmModes; ++j) acc[x][j] = 0.0f;
+    for (int k = k_lo; k < k_hi; ++k) {
+      const float4 e = *reinterpret_cast<const float4*>(&es[col_local[k] * kSpmmCols + x0]);
+      const float4* ap = reinterpret_cast<const float4*>(avT + (size_t)k * kMBatch + j0);
+      float a[kSpmmModes];
+#pragma unroll
+      for (int q = 0; q < kSpmmModes / 4; ++q) {
+        const float4 v = ap[q];
+        a[4 * q] = v.x;
+        a[4 * q + 1] = v.y;
+        a[4 * q + 2] = v.z;
+        a[4 * q + 3] = v.w;
+      }
+#pragma unroll
+      for (int j = 0; j < kSpmmModes; ++j) {
+        acc[0][j] += a[j] * e.x;
+        acc[1][j] += a[j] * e.y;
+        acc[2][j] += a[j] * e.z;
+        acc[3][j] += a[j] * e.w;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSpmmModes; ++j) {
+      if (j0 + j >= nb) break;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const size_t g = ((size_t)(j0 + j) * np + c0 + x0 + x) * np + b;
+        const float v = acc[x][j];
+        if (wt32) wt32[g] = v;
+        if (wth) {
+          __bf16 h, l;
+          split_bf16(v, h, l);
+          wth[g] = h;
+          wtl[g] = l;
+        }
+      }
+    }
+  }
+}
+
+struct GmTileInfo {
+  int ti, tj;
+};
+
+__device__ __forceinline__ GmTileInfo tri_tile(int t, int nt) {
+  // t-th tile of the upper triangle (ti <= tj), row-major
+  int ti = 0, rem = t;
+  while (rem >= nt - ti) {
+    rem -= nt - ti;
+    ++ti;
+  }
+  return {ti, ti + rem};
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0, int n_tri,
+                                               const float* __restrict__ et32,
+                                               const __bf16* __restrict__ eth,
+                                               const __bf16* __restrict__ etl,
+                                               const float* __restrict__ wt32,
+                                               const __bf16* __restrict__ wth,
+                                               const __bf16* __restrict__ wtl,
+                                               const double* __restrict__ omega,
+                                               const double* __restrict__ occ,
+                                               const uint8_t* __restrict__ phys,
+                                               const uint8_t* __restrict__ sel,
+                                               double* __restrict__ partial) {
+  constexpr int KT = SPLIT ? 32 : 16;
+  // LDS rows padded to stagger banks
+  constexpr int LDA32 = KT + 1;        // floats
+  constexpr int LDA16 = KT + 8;        // bf16 elements (row = 80 bytes)
+  __shared__ __attribute__((aligned(16))) float sA32[SPLIT ? 1 : kMT * LDA32];
+  __shared__ __attribute__((aligned(16))) float sB32[SPLIT ? 1 : kMT * LDA32];
+  __shared__ __attribute__((aligned(16))) __bf16 sAh[SPLIT ? kMT * LDA16 : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sAl[SPLIT ? kMT * LDA16 : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sBh[SPLIT ? kMT * LDA16 : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 sBl[SPLIT ? kMT * LDA16 : 8];
+  __shared__ double red[256];
+  __shared__ int skip;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nt = np / kMT;
+  const GmTileInfo tt = tri_tile(blockIdx.x, nt);
+  const int jb = blockIdx.y;
+  const int mu = m0 + jb;
+  const int i0 = tt.ti * kMT, j0 = tt.tj * kMT;
+  double* out = partial + (size_t)mu * n_tri + blockIdx.x;
+  if (!sel[mu] || !phys[mu]) {
+    if (tid == 0) *out = 0.0;
+    return;
+  }
+  const double w = omega[mu];
+  if (tid == 0) {
+    double lo1 = 1e300, hi1 = -1e300, lo2 = 1e300, hi2 = -1e300;
+    for (int k = 0; k < kMT; ++k) {
+      const int a = i0 + k, b = j0 + k;
+      if (a < n && phys[a]) { lo1 = fmin(lo1, omega[a]); hi1 = fmax(hi1, omega[a]); }
+      if (b < n && phys[b]) { lo2 = fmin(lo2, omega[b]); hi2 = fmax(hi2, omega[b]); }
+    }
+    int sk = 1;
+    if (lo1 <= hi1 && lo2 <= hi2) {
+      const double reach = 2.0 * p.sig_fixed * (1.0 + 1e-12) + 1e-9;
+      auto can = [&](double l1, double h1, double l2, double h2) {
+        const bool cp = (w + l1 - h2) < reach && (w + h1 - l2) > -reach;
+        const bool cm = (w - h1 - h2) < reach && (w - l1 - l2) > -reach;
+        return cp || cm;
+      };
+      sk = !(can(lo1, hi1, lo2, hi2) || (tt.ti != tt.tj && can(lo2, hi2, lo1, hi1)));
+    }
+    skip = sk;
+  }
+  __syncthreads();
+  if (skip) {
+    if (tid == 0) *out = 0.0;
+    return;
+  }
+
+  const size_t wbase = (size_t)jb * np * np;
+  const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;  // wave block inside the tile
+  const int lr = lane & 15, lg = lane >> 4;
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < np; k0 += KT) {
+    // stage 128 x KT of ET (rows i0..) and WT (rows j0..)
+    if constexpr (!SPLIT) {
+      for (int idx = tid; idx < kMT * KT; idx += 256) {
+        const int r = idx / KT, c = idx % KT;
+        sA32[r * LDA32 + c] = et32[(size_t)(i0 + r) * np + k0 + c];
+        sB32[r * LDA32 + c] = wt32[wbase + (size_t)(j0 + r) * np + k0 + c];
+      }
+    } else {
+      // 8 bf16 (16 bytes) per copy
+      for (int idx = tid; idx < kMT * (KT / 8); idx += 256) {
+        const int r = idx / (KT / 8), c = (idx % (KT / 8)) * 8;
+        const size_t ga = (size_t)(i0 + r) * np + k0 + c;
+        const size_t gb = wbase + (size_t)(j0 + r) * np + k0 + c;
+        *reinterpret_cast<uint4*>(&sAh[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&eth[ga]);
+        *reinterpret_cast<uint4*>(&sAl[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&etl[ga]);
+        *reinterpret_cast<uint4*>(&sBh[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&wth[gb]);
+        *reinterpret_cast<uint4*>(&sBl[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&wtl[gb]);
+      }
+    }
+    __syncthreads();
+    if constexpr (!SPLIT) {
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += 4) {
+        float a[4], b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a[t] = sA32[(wm + 16 * t + lr) * LDA32 + kk + lg];
+          b[t] = sB32[(wn + 16 * t + lr) * LDA32 + kk + lg];
+        }
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < 4; ++tb)
+            acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+      }
+    } else {
+      bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int ra = (wm + 16 * t + lr) * LDA16 + 8 * lg;
+        const int rb = (wn + 16 * t + lr) * LDA16 + 8 * lg;
+        ah[t] = *reinterpret_cast<const bf16x8*>(&sAh[ra]);
+        al[t] = *reinterpret_cast<const bf16x8*>(&sAl[ra]);
+        bh[t] = *reinterpret_cast<const bf16x8*>(&sBh[rb]);
+        bl[t] = *reinterpret_cast<const bf16x8*>(&sBl[rb]);
+      }
+#pragma unroll
+      for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 4; ++tb) {
+          acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ta], bh[tb], acc[ta][tb], 0, 0, 0);
+          acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ta], bl[tb], acc[ta][tb], 0, 0, 0);
+          acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ta], bh[tb], acc[ta][tb], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds V[m = row0 + 4*lg + r][n = col0 + lr] of each 16 x 16 tile.
+  const bool offdiag = tt.ti != tt.tj;
+  const double s2 = 2.0 * p.sig_fixed;
+  double sum = 0.0;
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) {
+    const int jn = j0 + wn + 16 * tb + lr;
+    if (jn >= n || !phys[jn]) continue;
+    const double w2 = omega[jn], n2 = occ[jn];
+#pragma unroll
+    for (int ta = 0; ta < 4; ++ta) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int im = i0 + wm + 16 * ta + 4 * lg + r;
+        if (im >= n || !phys[im]) continue;
+        const double w1 = omega[im];
+        // quick reject: neither order of the pair is near the energy shell
+        const double d1 = fabs(w + w1 - w2), d2 = fabs(w - w1 - w2);
+        const double d3 = fabs(w + w2 - w1);
+        const double lim = s2 * (1.0 + 1e-9) + 1e-9;
+        if (d1 >= lim && d2 >= lim && (!offdiag || d3 >= lim)) continue;
+        const double n1 = occ[im];
+        double wt = pair_weight(p, w, w1, w2, n1, n2, p.sig_fixed, p.sig_fixed);
+        if (offdiag) wt += pair_weight(p, w, w2, w1, n2, n1, p.sig_fixed, p.sig_fixed);
+        if (wt == 0.0) continue;
+        const double v = (double)acc[ta][tb][r];
+        sum += v * v * wt;
+      }
+    }
+  }
+  red[tid] = sum;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) *out = red[0];
+}
+
+__global__ void gm_finish(int n, int n_tri, const double* __restrict__ partial,
+                          const uint8_t* __restrict__ phys, const uint8_t* __restrict__ sel,
+                          double* __restrict__ gamma) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n || !sel[m]) return;
+  double acc = 0.0;
+  for (int t = 0; t < n_tri; ++t) acc += partial[(size_t)m * n_tri + t];
+  gamma[m] = phys[m] ? kPrefactor * acc : 0.0;
+}
+
+// The SpMM stages max_u rows of 64 floats in LDS.
+bool gm_supported(const kaldo_crystal* c) {
+  return (size_t)c->gamma.max_u * kSpmmCols * sizeof(float) <= 96 * 1024;
+}
+
+size_t gm_workspace_bytes(const kaldo_crystal* c, int prec) {
+  const size_t n = c->nb3;
+  const size_t np = (n + kMT - 1) / kMT * kMT;
+  const size_t nt = np / kMT, n_tri = nt * (nt + 1) / 2;
+  const bool split = prec == KALDO_BF16X3;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { o += (bytes + 255) / 256 * 256; };
+  take(np * np * 4);                       // et32 (needed by the SpMM in both forms)
+  if (split) take(np * np * 2 * 2);         // eth, etl
+  take((size_t)c->gamma.n_bc * kMBatch * 4);  // avals
+  take(split ? np * np * kMBatch * 2 * 2 : np * np * kMBatch * 4);  // W
+  take(n * n_tri * 8);                     // partials
+  return o;
+}
+
+int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* evec,
+           const double* occ, const uint8_t* phys, const uint8_t* sel, unsigned char* ws,
+           int prec, double* gamma, hipStream_t st) {
+  const int n = c->nb3;
+  const int np = (n + kMT - 1) / kMT * kMT;
+  const int nt = np / kMT, n_tri = nt * (nt + 1) / 2;
+  const bool split = prec == KALDO_BF16X3;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* r = ws + o;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  float* et32 = reinterpret_cast<float*>(take((size_t)np * np * 4));
+  __bf16* eth = nullptr;
+  __bf16* etl = nullptr;
+  if (split) {
+    eth = reinterpret_cast<__bf16*>(take((size_t)np * np * 2 * 2));  // hi and lo
+    etl = eth + (size_t)np * np;
+  }
+  float* av = reinterpret_cast<float*>(take((size_t)c->gamma.n_bc * kMBatch * 4));
+  float* wt32 = nullptr;
+  __bf16* wth = nullptr;
+  __bf16* wtl = nullptr;
+  if (split) {
+    wth = reinterpret_cast<__bf16*>(take((size_t)np * np * kMBatch * 4));
+    wtl = wth + (size_t)np * np * kMBatch;
+  } else {
+    wt32 = reinterpret_cast<float*>(take((size_t)np * np * kMBatch * 4));
+  }
+  double* partial = reinterpret_cast<double*>(take((size_t)n * n_tri * 8));
+  const long nn = (long)np * np;
+  KALDO_LAUNCH("gm_prep_et", gm_prep_et, dim3((nn + 255) / 256), dim3(256), 0, st, n, np, evec,
+               et32, eth, etl);
+  for (int m0 = 0; m0 < n; m0 += kMBatch) {
+    const int nb = std::min(kMBatch, n - m0);
+    const long na = (long)c->gamma.n_bc * kMBatch;
+    KALDO_LAUNCH("gm_avals", gm_avals, dim3((na + 255) / 256), dim3(256), 0, st, n, c->gamma.n_bc,
+                 m0, nb, c->gamma.t_ptr, c->gamma.t_a, c->gamma.t_coef, evec, av);
+    const size_t spmm_lds = (size_t)c->gamma.max_u * kSpmmCols * sizeof(float);
+    KALDO_LAUNCH("gm_spmm", gm_spmm, dim3(np / kSpmmRows, np / kSpmmCols, (nb + kSpmmModes - 1) / kSpmmModes),
+                 dim3(256), spmm_lds, st, n, np, nb, c->gamma.n_rtiles, c->gamma.row_ptr,
+                 c->gamma.col_local, c->gamma.tile_u_ptr, c->gamma.tile_u, av, evec, wt32, wth, wtl);
+    if (split)
+      KALDO_LAUNCH("gm_gemm_bf16x3", gm_gemm<true>, dim3(n_tri, nb), dim3(256), 0, st, p, n, np,
+                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, partial);
+    else
+      KALDO_LAUNCH("gm_gemm_fp32", gm_gemm<false>, dim3(n_tri, nb), dim3(256), 0, st, p, n, np,
+                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, partial);
+  }
+  KALDO_LAUNCH("gm_finish", gm_finish, dim3((n + 255) / 256), dim3(256), 0, st, n, n_tri, partial,
+               phys, sel, gamma);
+  KALDO_HIP(hipGetLastError());
+  return KALDO_OK;
+}
+
+}  // namespace kaldo

@@ -280,3 +280,34 @@ def test_perovskite_small_mesh_fused_fp32():
     Go = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_ADAPT)
     G = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, K.FP32))
     assert gamma_close(G, Go) <= 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-4)])
+def test_gamma_point_mfma_forms(diamond, prec, tol):
+    """MFMA Gamma-point projection (FP32 and BF16x3 split) on the zone-folded
+    54-atom supercell (162 modes: a ragged tile of the 128-wide tiling)."""
+    m, _ = diamond
+    sc = models.supercell_gamma(m, (3, 3, 3))
+    c = K.Crystal.from_model(sc)
+    om, E = oph.phonons_gamma_real(sc)
+    Go = olw.gamma_point_linewidths(sc, om, E, 300.0, B_FIXED)
+    P = K.FP32 if prec == "fp32" else K.BF16X3
+    G = host(K.linewidths_gamma(c, dev(om), dev(E), 300.0, B_FIXED, P))
+    err = gamma_close(G, Go)
+    print(f"{prec}: max rel err {err:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-4)])
+def test_glass_c4_mfma_sampled(prec, tol):
+    cfg = configs.CONFIGS["C4"]
+    gl = configs.model_for(cfg)
+    c = K.Crystal.from_model(gl)
+    om, E = K.phonons_gamma(gl.n_basis, gl.mass, gl.fc2)
+    P = K.FP32 if prec == "fp32" else K.BF16X3
+    G = host(K.linewidths_gamma(c, dev(om), dev(E), 300.0, cfg.broadening, P))
+    modes = [520, 700, 1100, 1400]
+    Go = olw.gamma_point_linewidths(gl, om, E, 300.0, cfg.broadening, modes=modes)
+    err = gamma_close(G[modes], Go[modes])
+    print(f"C4 {prec}: max rel err {err:.3e}")
+    assert err <= tol
