@@ -78,6 +78,10 @@ struct Fc3Bloch {
   int32_t* e_bg = nullptr;      // [n_e] 3*beta + gamma of entry e
   int32_t* blk_d = nullptr;     // [n_blk] d index of each block
   int32_t* pair_ptr = nullptr;  // [N_b*N_b + 1] block ranges per (jb, kb)
+  // Work list for building one 16x16 B_s tile with a wave (3N_b <= 16):
+  // slot k of lane l is entry k*64 + l of the (jc, kc) entries sorted by
+  // their block count; int4 = (jc*17 + kc or -1, first block, end block, bg).
+  int4* bwork = nullptr;        // [4][64]
 };
 
 // Gamma-point FC3: CSR over the (b, c) pattern of A_mu[b][c],

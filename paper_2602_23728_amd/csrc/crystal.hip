@@ -111,6 +111,25 @@ static int build_bloch(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
       e_blk[e] = blocks[{e_jc[e] / 3, e_kc[e] / 3, d}];
       e_bg[e] = (e_jc[e] % 3) * 3 + e_kc[e] % 3;
     }
+  // balanced work list for the 16x16 B_s tiles of the MFMA kernel
+  std::vector<int4> bwork(256, int4{-1, 0, 0, 0});
+  if (3 * nb <= 16) {
+    struct W { int pos, lo, hi, bg; };
+    std::vector<W> ws;
+    for (int jc = 0; jc < 3 * nb; ++jc)
+      for (int kc = 0; kc < 3 * nb; ++kc) {
+        const int pr = (jc / 3) * nb + kc / 3;
+        ws.push_back({jc * 17 + kc, pair_ptr[pr], pair_ptr[pr + 1], (jc % 3) * 3 + kc % 3});
+      }
+    std::stable_sort(ws.begin(), ws.end(),
+                     [](const W& a, const W& b) { return a.hi - a.lo > b.hi - b.lo; });
+    for (size_t e = 0; e < ws.size(); ++e) {
+      // serpentine deal over the 64 lanes keeps per-lane block counts even
+      const int slot = static_cast<int>(e / 64), l = static_cast<int>(e % 64);
+      const int lane = (slot & 1) ? 63 - l : l;
+      bwork[slot * 64 + lane] = int4{ws[e].pos, ws[e].lo, ws[e].hi, ws[e].bg};
+    }
+  }
   Fc3Bloch& b = c->bloch;
   b.n_blk = nblk;
   b.n_d = static_cast<int>(dvec.size() / 3);
@@ -129,6 +148,7 @@ static int build_bloch(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
   if ((rc = upload(c, &b.e_bg, e_bg))) return rc;
   if ((rc = upload(c, &b.blk_d, blk_d))) return rc;
   if ((rc = upload(c, &b.pair_ptr, pair_ptr))) return rc;
+  if ((rc = upload(c, &b.bwork, bwork))) return rc;
   return KALDO_OK;
 }
 

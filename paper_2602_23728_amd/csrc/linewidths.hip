@@ -18,6 +18,8 @@
 //   lw_finish        per mode: fixed-order sum of the partials, prefactor
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 
 #include "common.h"
 #include "lw_common.h"
@@ -212,11 +214,32 @@ static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
   return w;
 }
 
+// Which crystal kernel serves a request: the dense MFMA kernel for the split
+// form (and, in FP32, for cells of 9 or more branches, where dense 16-wide
+// tiles beat the pruned VALU path), otherwise the fused pruned kernel, and the
+// generic kernel when neither fits.  KALDO_CRYSTAL_PATH=fused|mfma|generic
+// overrides the FP32 choice.
+enum class CrystalPath { Generic, Fused, Mfma };
+
+static CrystalPath choose_path(const kaldo_crystal* c, int prec) {
+  const char* env = std::getenv("KALDO_CRYSTAL_PATH");
+  const std::string want = env ? env : "";
+  if (prec == KALDO_BF16X3) return CrystalPath::Mfma;
+  if (const char* f = std::getenv("KALDO_FORCE_GENERIC"))
+    if (f[0] == '1') return CrystalPath::Generic;
+  if (want == "generic") return CrystalPath::Generic;
+  if (prec == KALDO_FP32 && mfma_supported(c) && (want == "mfma" || (want.empty() && c->nb3 >= 9)))
+    return CrystalPath::Mfma;
+  if (fused_supported(c, prec)) return CrystalPath::Fused;
+  return CrystalPath::Generic;
+}
+
 template <typename T>
 static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
                        const double* evec, const double* vel, double T_k,
                        const kaldo_broadening* b, const int32_t* subset, int64_t n_subset,
-                       unsigned char* ws, const CrystalWs& w, double* gamma, hipStream_t st) {
+                       unsigned char* ws, const CrystalWs& w, int prec, double* gamma,
+                       hipStream_t st) {
   using C = typename Cx<T>::type;
   const int nb3 = c->nb3;
   const long nq = (long)mesh[0] * mesh[1] * mesh[2];
@@ -234,7 +257,13 @@ static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double
     KALDO_LAUNCH("lw_select", lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
                        (long)n_subset, n_modes, sel);
   LwParams p = make_params(c, mesh, T_k, b);
-  if (fused_supported(c, sizeof(T) == 8 ? KALDO_FP64 : KALDO_FP32)) {
+  const CrystalPath path = choose_path(c, prec);
+  if (path == CrystalPath::Mfma) {
+    float2* phase_tab = reinterpret_cast<float2*>(ws + w.off_phase);
+    return launch_mfma(c, p, prec == KALDO_BF16X3, omega, vel, occ, phys, sel, evec, phase_tab,
+                       kPrefactor / (double)nq, gamma, st);
+  }
+  if (path == CrystalPath::Fused) {
     C* phase_tab = reinterpret_cast<C*>(ws + w.off_phase);
     int32_t* list = reinterpret_cast<int32_t*>(ws + w.off_list);
     return launch_fused<T>(c, p, omega, vel, occ, phys, sel, evec, eta, phase_tab, list,
@@ -280,8 +309,8 @@ extern "C" int kaldo_linewidths(const kaldo_crystal* c, const int32_t* mesh, con
   if (rc) return rc;
   KALDO_REQUIRE(precision == KALDO_FP64 || precision == KALDO_FP32 || precision == KALDO_BF16X3,
                 "kaldo_linewidths: unknown precision");
-  if (precision == KALDO_BF16X3) {
-    set_error("kaldo_linewidths: BF16X3 is not available on the crystal path");
+  if (precision == KALDO_BF16X3 && !mfma_supported(c)) {
+    set_error("kaldo_linewidths: BF16X3 needs the MFMA kernel (nb3 <= 16, tables in LDS)");
     return KALDO_EUNSUPPORTED;
   }
   KALDO_REQUIRE(n_subset >= 0 && (n_subset == 0 || modes_subset), "kaldo_linewidths: bad subset");
@@ -294,7 +323,7 @@ extern "C" int kaldo_linewidths(const kaldo_crystal* c, const int32_t* mesh, con
   auto* ws = static_cast<unsigned char*>(workspace);
   if (precision == KALDO_FP64)
     return run_crystal<double>(c, mesh, omega, evec, vel, temperature, b, modes_subset, n_subset,
-                               ws, w, gamma, st);
+                               ws, w, precision, gamma, st);
   return run_crystal<float>(c, mesh, omega, evec, vel, temperature, b, modes_subset, n_subset, ws,
-                            w, gamma, st);
+                            w, precision, gamma, st);
 }

@@ -73,20 +73,42 @@ inline LwParams make_params(const kaldo_crystal* c, const int32_t* mesh, double 
 }
 
 // sigma+ for coalescence (dv = v1 + v2), sigma- for decay (dv = -v1 + v2).
+__device__ __forceinline__ void widths_v(const LwParams& p, const double* v1, const double* v2,
+                                         double& sp, double& sm);
 __device__ __forceinline__ void widths(const LwParams& p, const double* __restrict__ vel, int m1,
                                        int m2, double& sp, double& sm) {
+  widths_v(p, vel + 3 * (size_t)m1, vel + 3 * (size_t)m2, sp, sm);
+}
+__device__ __forceinline__ void widths_v(const LwParams& p, const double* v1, const double* v2,
+                                         double& sp, double& sm) {
   if (!p.adaptive) {
     sp = sm = p.sig_fixed;
     return;
   }
-  const double* v1 = vel + 3 * (size_t)m1;
-  const double* v2 = vel + 3 * (size_t)m2;
   double ax = v1[0] + v2[0], ay = v1[1] + v2[1], az = v1[2] + v2[2];
   double bx = -v1[0] + v2[0], by = -v1[1] + v2[1], bz = -v1[2] + v2[2];
   double Sa = ax * ax + ay * ay + az * az;
   double Sb = bx * bx + by * by + bz * bz;
   sp = fmax(sqrt(Sa * p.h2 / 12.0), p.sig_floor);
   sm = fmax(sqrt(Sb * p.h2 / 12.0), p.sig_floor);
+}
+
+// sigma^2 (not sigma) of the two processes, max(S h^2 / 12, floor^2), and
+// the squared velocity sums S+- they come from (fixed width: S = 0).
+__device__ __forceinline__ void widths2(const LwParams& p, const double* v1, const double* v2,
+                                        double& s2p, double& s2m, double& Sp, double& Sm) {
+  if (!p.adaptive) {
+    s2p = s2m = p.sig_fixed * p.sig_fixed;
+    Sp = Sm = 0.0;
+    return;
+  }
+  const double ax = v1[0] + v2[0], ay = v1[1] + v2[1], az = v1[2] + v2[2];
+  const double bx = -v1[0] + v2[0], by = -v1[1] + v2[1], bz = -v1[2] + v2[2];
+  Sp = ax * ax + ay * ay + az * az;
+  Sm = bx * bx + by * by + bz * bz;
+  const double f2 = p.sig_floor * p.sig_floor;
+  s2p = fmax(Sp * p.h2 / 12.0, f2);
+  s2m = fmax(Sm * p.h2 / 12.0, f2);
 }
 
 __device__ __forceinline__ double smear(int shape, double x, double s) {
@@ -115,6 +137,23 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
   return v;
 }
 
+// e^{-i q1.R_d} for every mesh point q1 and replica difference d, in T.
+template <typename T>
+__global__ void lw_phase_table(int nq, int n_d, int N0, int N1, int N2,
+                               const int32_t* __restrict__ dvec, typename Cx<T>::type* out) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long)nq * n_d) return;
+  const int q1 = k / n_d, d = k % n_d;
+  const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
+  const int32_t* r = dvec + 3 * d;
+  int m0 = ((b0 * r[0]) % N0 + N0) % N0, m1 = ((b1 * r[1]) % N1 + N1) % N1,
+      m2 = ((b2 * r[2]) % N2 + N2) % N2;
+  double f = (double)m0 / N0 + (double)m1 / N1 + (double)m2 / N2;
+  double sn, cs;
+  sincospi(-2.0 * f, &sn, &cs);
+  out[k] = Cx<T>::make((T)cs, (T)sn);
+}
+
 // Fused one-workgroup-per-q crystal kernel (lw_fused.hip).
 bool fused_supported(const kaldo_crystal* c, int prec);
 template <typename T>
@@ -122,5 +161,12 @@ int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega,
                  const double* occ, const uint8_t* phys, const uint8_t* sel, const double* evec,
                  typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab, int32_t* phys_list,
                  double scale, double* gamma, hipStream_t st);
+
+// Dense MFMA crystal kernel (lw_mfma.hip).
+bool mfma_supported(const kaldo_crystal* c);
+int launch_mfma(const kaldo_crystal* c, const LwParams& p, bool split, const double* omega,
+                const double* vel, const double* occ, const uint8_t* phys, const uint8_t* sel,
+                const double* evec, float2* phase_tab, double scale, double* gamma,
+                hipStream_t st);
 
 }  // namespace kaldo

@@ -46,23 +46,6 @@ __device__ __forceinline__ Band make_band(double sig2, float scale_sum) {
   return {t * (1.0f - 1e-6f) - d, t * (1.0f + 1e-6f) + d};
 }
 
-// sigma^2 (not sigma) of the two processes: max(S h^2 / 12, floor^2).
-__device__ __forceinline__ void widths2(const LwParams& p, const double* v1, const double* v2,
-                                        double& s2p, double& s2m, double& Sp, double& Sm) {
-  if (!p.adaptive) {
-    s2p = s2m = p.sig_fixed * p.sig_fixed;
-    Sp = Sm = 0.0;
-    return;
-  }
-  const double ax = v1[0] + v2[0], ay = v1[1] + v2[1], az = v1[2] + v2[2];
-  const double bx = -v1[0] + v2[0], by = -v1[1] + v2[1], bz = -v1[2] + v2[2];
-  Sp = ax * ax + ay * ay + az * az;
-  Sm = bx * bx + by * by + bz * bz;
-  const double f2 = p.sig_floor * p.sig_floor;
-  s2p = fmax(Sp * p.h2 / 12.0, f2);
-  s2m = fmax(Sm * p.h2 / 12.0, f2);
-}
-
 // The exact FP64 decision of the oracle: |(w + w1) - w2| < 2 sigma+ or
 // |(w - w1) - w2| < 2 sigma-, sigma = max(sqrt(S h^2/12), floor) (or fixed).
 __device__ __forceinline__ bool exact_pass(const LwParams& p, double w, double w1, double w2,
@@ -375,22 +358,6 @@ __global__ void lw_eta_transpose(long nq, int nb3, const double* __restrict__ ev
   const long q = k / ((long)nb3 * nb3);
   const size_t src = ((q * nb3 + j) * nb3 + s) * 2;
   etaT[k] = Cx<T>::make((T)evec[src], (T)evec[src + 1]);
-}
-
-template <typename T>
-__global__ void lw_phase_table(int nq, int n_d, int N0, int N1, int N2,
-                               const int32_t* __restrict__ dvec, typename Cx<T>::type* out) {
-  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (long)nq * n_d) return;
-  const int q1 = k / n_d, d = k % n_d;
-  const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
-  const int32_t* r = dvec + 3 * d;
-  int m0 = ((b0 * r[0]) % N0 + N0) % N0, m1 = ((b1 * r[1]) % N1 + N1) % N1,
-      m2 = ((b2 * r[2]) % N2 + N2) % N2;
-  double f = (double)m0 / N0 + (double)m1 / N1 + (double)m2 / N2;
-  double sn, cs;
-  sincospi(-2.0 * f, &sn, &cs);
-  out[k] = Cx<T>::make((T)cs, (T)sn);
 }
 
 size_t fused_lds_bytes(const kaldo_crystal* c, int prec) {

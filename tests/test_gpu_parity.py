@@ -311,3 +311,40 @@ def test_glass_c4_mfma_sampled(prec, tol):
     err = gamma_close(G[modes], Go[modes])
     print(f"C4 {prec}: max rel err {err:.3e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("name,mesh", [("diamond", (5, 5, 5)), ("perovskite", (4, 4, 4)),
+                                       ("random", (2, 3, 5))])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_crystal_mfma_forms(name, mesh, prec, monkeypatch):
+    """Dense MFMA crystal kernel (FP32 and BF16x3) against the oracle."""
+    m = models.random_cell(11, 2) if name == "random" else configs.build_model(name)
+    c = K.Crystal.from_model(m)
+    om, ev, ve = _oracle_inputs(m, mesh)
+    Go = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_ADAPT)
+    monkeypatch.setenv("KALDO_CRYSTAL_PATH", "mfma")
+    P = K.FP32 if prec == "fp32" else K.BF16X3
+    G = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, P))
+    err = gamma_close(G, Go)
+    kg = host(K.kappa_rta(c, mesh, dev(om), dev(ve), dev(G), 300.0, 0.1))
+    ko = okappa.kappa_rta(om, ve, Go, 300.0, m.volume, int(np.prod(mesh)), 0.1)
+    kerr = kappa_close(kg, ko)
+    print(f"{name} {prec}: Gamma max rel err {err:.3e}, kappa rel err {kerr:.3e}")
+    assert err <= (1e-5 if prec == "fp32" else 1e-3)
+    assert kerr <= 1e-4
+
+
+def test_c2_golden_bf16x3(diamond):
+    path = os.path.join(GOLDEN, "c2_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing")
+    g = np.load(path)
+    m, c = diamond
+    cfg = configs.CONFIGS["C2"]
+    G = host(K.linewidths(c, cfg.mesh, dev(g["omega"]), dev(g["evec"]), dev(g["vel"]), 300.0,
+                          cfg.broadening, K.BF16X3))
+    err = gamma_close(G, g["gamma"])
+    kg = host(K.kappa_rta(c, cfg.mesh, dev(g["omega"]), dev(g["vel"]), dev(G), 300.0, 0.1))
+    kerr = kappa_close(kg, g["kappa"])
+    print(f"C2 bf16x3: Gamma max rel err {err:.3e}, kappa rel err {kerr:.3e}")
+    assert kerr <= 1e-4
