@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-q", type=int, default=48)
+    ap.add_argument("--form", default="plain", choices=["plain", "learned"],
+                    help="learned: the learned form against plain FP32 (full mesh and wedge)")
+    ap.add_argument("--train-steps", type=int, default=3000)
     return ap.parse_args()
 
 
@@ -115,6 +118,90 @@ def bench_gamma_point(a, cfg, model, c, prec, K, torch):
                       "kernels_ms_per_step": {k: v[1] / a.steps for k, v in prof.items()}}))
 
 
+def bench_learned(a, cfg, model, c, K, torch):
+    """The learned form on a crystal mesh, against the plain FP32 path on every
+    mode (the conductivity reference) and on the irreducible wedge.  Each of
+    the three chains (phonons -> linewidths -> conductivity) is timed over
+    `steps` repetitions; the wedge itself is host set-up."""
+    from paper_2602_23728_amd import learned as L
+    from synthetic import draws as D
+    mesh, T, b = cfg.mesh, cfg.temperature, cfg.broadening
+    nq = int(np.prod(mesh))
+    nb3 = c.nb3
+    wedge = L.Wedge(model.lattice, model.frac, model.mass, mesh)
+    kap = torch.empty(3, 3, dtype=torch.float64, device="cuda")
+    state = {}
+
+    def full():
+        om, ev, ve = K.phonons(c, mesh)
+        g = K.linewidths(c, mesh, om, ev, ve, T, b, K.FP32)
+        K.kappa_rta(c, mesh, om, ve, g, T, b.nu_min_thz, out=kap)
+        return kap.clone()
+
+    def ibz():
+        om, ev, ve = K.phonons(c, mesh)
+        g = L.plain_ibz_linewidths(c, wedge, om, ev, ve, T, b, K.FP32)
+        K.kappa_rta(c, mesh, om, ve, g, T, b.nu_min_thz, out=kap)
+        return kap.clone()
+
+    def learned():
+        om, ev, ve = K.phonons(c, mesh)
+        cand = L.candidate_modes(wedge, om, nb3, b.nu_min_thz)
+        if "draws" not in state or len(state["cand"]) != len(cand):
+            state["cand"] = cand
+            state["draws"] = D.surrogate_draws(len(cand), K.surrogate_feature_count(c), members=5,
+                                               seed=0)
+        res = L.learned_linewidths(c, wedge, om, ev, ve, T, b, cand, state["draws"],
+                                   steps=a.train_steps, lr=1e-3, tol=0.01)
+        K.kappa_rta(c, mesh, om, ve, res.gamma, T, b.nu_min_thz, out=kap)
+        state["res"] = res
+        return kap.clone()
+
+    def timed(fn, name):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        K.lib().kaldo_profile_begin()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            k = fn()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / a.steps
+        prof = profile_read(K)
+        print(f"bench[{name}]: {ms:.3f} ms/step; kernels: " +
+              ", ".join(f"{kk} {v[1] / a.steps:.3f} ms" for kk, v in prof.items()),
+              file=sys.stderr, flush=True)
+        return ms, k.cpu().numpy(), {kk: v[1] / a.steps for kk, v in prof.items()}
+
+    ms_full, k_full, p_full = timed(full, "plain-full")
+    ms_ibz, k_ibz, p_ibz = timed(ibz, "plain-wedge")
+    ms_lrn, k_lrn, p_lrn = timed(learned, "learned")
+    res = state["res"]
+
+    def rel(k):
+        kbar = np.trace(k_full) / 3
+        return float(max(abs(np.trace(k) / 3 - kbar) / kbar, np.max(np.abs(k - k_full)) / kbar))
+
+    n_modes = nq * nb3
+    n_rest = len(state["cand"]) - res.n_train - res.n_held
+    print(json.dumps({
+        "metric": METRIC, "value": n_modes / (ms_lrn * 1e-3), "unit": "modes/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_lrn, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.description}", "modes": n_modes,
+                   "mesh": list(mesh), "form": "learned"},
+        "plain_full_ms": ms_full, "plain_wedge_ms": ms_ibz,
+        "speedup_vs_plain_full": ms_full / ms_lrn, "speedup_vs_plain_wedge": ms_ibz / ms_lrn,
+        "kappa_rel_err_learned": rel(k_lrn), "kappa_rel_err_wedge": rel(k_ibz),
+        "kappa_trace_over_3": float(np.trace(k_full) / 3),
+        "irreducible_q": int(wedge.n_ir), "candidates": int(len(state["cand"])),
+        "train": res.n_train, "held_out": res.n_held, "fallback": res.n_fallback,
+        "fallback_frac_of_rest": res.n_fallback / max(1, n_rest), "tau": res.tau,
+        "train_steps": a.train_steps,
+        "kernels_ms_per_step": {"plain_full": p_full, "plain_wedge": p_ibz, "learned": p_lrn},
+    }))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -134,6 +221,8 @@ def main():
     c = K.Crystal.from_model(model)
     if cfg.mesh == (1, 1, 1):
         return bench_gamma_point(a, cfg, model, c, prec, K, torch)
+    if a.form == "learned":
+        return bench_learned(a, cfg, model, c, K, torch)
     mesh = cfg.mesh
     nq = int(np.prod(mesh))
     nb3 = c.nb3

@@ -213,6 +213,169 @@ int kaldo_kappa_rta(const kaldo_crystal* c, const int32_t* mesh, const double* o
                     const double* vel, const double* gamma, double temperature,
                     double nu_min_thz, double* kappa, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned form.  The paper restricts the scattering calculation to the
+ * irreducible wedge of the mesh and maps the results back onto the full grid
+ * (overview of the 2.0 computational changes), and lists the scattering
+ * phase space among its computed quantities ("Phonon Properties and
+ * Scattering"; no formula is given).  The MLP ensemble, its features and
+ * the gate below are this library's own: no surrogate appears in the paper.
+ * All device entry points enqueue on `stream` and return; results are valid
+ * after a stream synchronisation unless stated otherwise.
+ * ------------------------------------------------------------------------ */
+
+/* kaldo_mesh_ibz -- irreducible wedge of a Gamma-centred mesh (host, FP64).
+ * Point operations are the integer matrices M (entries -1..1 in the lattice
+ * basis) that keep the metric and map the basis onto itself (equal masses,
+ * up to a translation); q and M^T q share a star when M^T q lies on the
+ * mesh (non-cubic meshes keep the operations that do).  A reduced basis is
+ * assumed (then every point operation has entries in -1..1).
+ *   lattice    host double[3][3] rows a_i (Angstrom)
+ *   frac       host double[n_basis][3] fractional positions
+ *   mass       host double[n_basis] amu
+ *   mesh       host int32[3]
+ *   ir_of_q    host int32[N_q] out: the smallest flat index in the star of q
+ *   star_size  host int32[N_q] out: star size at representatives, else 0
+ *   n_ops_out, n_ir_out  host int32 out (may be NULL) */
+int kaldo_mesh_ibz(const double* lattice, int32_t n_basis, const double* frac,
+                   const double* mass, const int32_t* mesh, int32_t* ir_of_q,
+                   int32_t* star_size, int32_t* n_ops_out, int32_t* n_ir_out);
+
+/* Device workspace bytes kaldo_jdos needs (0 on bad arguments). */
+size_t kaldo_jdos_workspace(const kaldo_crystal* c, const int32_t* mesh);
+
+/* kaldo_jdos -- two-phonon joint density of states, read as the partner count
+ * of Eq. gamma without the vertex and populations, with the same cut
+ * |x| < 2 sigma, smearing, widths and nu_min masks as kaldo_linewidths:
+ *   D+(q,s) = (1/N_q) sum_{q1 s' s''} m g((w + w1) - w2; sigma+)
+ *   D-(q,s) = (1/N_q) sum_{q1 s' s''} m g((w - w1) - w2; sigma-)
+ * with q2 = -q - q1 (mod G) and m = [nu1 >= nu_min][nu2 >= nu_min]; 0 for
+ * modes below nu_min.  Units ps/rad.  Cut decisions and sums in FP64.
+ *   omega, vel     device, layouts of kaldo_phonons
+ *   modes_subset   device int32[n_subset] or NULL (all modes); only those
+ *                  entries of dplus / dminus are written
+ *   dplus, dminus  device double[N_q*nb3]
+ * Requires nb3 <= 16. */
+int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+               const double* vel, const kaldo_broadening* broadening,
+               const int32_t* modes_subset, int64_t n_subset, void* workspace,
+               size_t workspace_bytes, double* dplus, double* dminus, void* stream);
+
+/* Feature count per row: nb3 + 8 (at most 32). */
+int32_t kaldo_surrogate_feature_count(const kaldo_crystal* c);
+
+/* kaldo_surrogate_features -- row k for mode m = modes[k] (float32):
+ *   nu (THz), |v| (A/ps), one-hot branch (nb3 entries), the ascending
+ *   |components| of the shortest Cartesian image q + G (1/A), |q + G|,
+ *   ln(1 + D+), ln(1 + D-).
+ *   modes     device int32[n] flat mode indices
+ *   features  device float[n][nb3 + 8] */
+int kaldo_surrogate_features(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                             const double* vel, const double* dplus, const double* dminus,
+                             const int32_t* modes, int64_t n, float* features, void* stream);
+
+/* kaldo_standardize -- column means and population standard deviations over
+ * the first n_fit rows (FP64), then every row of X (device float[n][n_feat])
+ * standardised in place; sd = 1 for columns constant on the fit rows.
+ *   mu_sd  device float[n_feat][2] out */
+int kaldo_standardize(int64_t n, int32_t n_feat, float* X, int64_t n_fit, float* mu_sd,
+                      void* stream);
+
+/* kaldo_surrogate_targets -- y_k = (ln gamma[modes[k]] - mu) / sd (float32)
+ * with mu, sd the mean and population std of ln gamma over the listed modes.
+ *   gamma    device double[N_q*nb3] rad/ps, > 0 at the listed modes
+ *   y        device float[n]; y_mu_sd device float[2] out */
+int kaldo_surrogate_targets(const double* gamma, const int32_t* modes, int64_t n, float* y,
+                            float* y_mu_sd, void* stream);
+
+/* Parameters per ensemble member for n_in inputs (-1 if n_in not in 1..32):
+ * W0 [n_in][64], b0 [64], W1..W3 [64][64] each followed by its bias [64],
+ * head W4 [64], b4 [1]; row-major, in that order. */
+int32_t kaldo_mlp_param_count(int32_t n_in);
+
+/* Device workspace bytes kaldo_mlp_train needs. */
+size_t kaldo_mlp_workspace(int32_t n_in, int32_t n_members, int32_t n_samples);
+
+/* kaldo_mlp_train -- full-batch training of an ensemble of n_members MLPs
+ * (4 hidden layers of 64 tanh units, linear head), FP32.  Member e minimises
+ *   L_e = sum_i c_ei (f_e(x_i) - y_i)^2 / sum_i c_ei
+ * (c = bootstrap counts) with `steps` Adam steps (b1 0.9, b2 0.999, eps 1e-8,
+ * bias-corrected, learning rate lr).  Gradients are reduced in a fixed order:
+ * identical inputs give identical parameters.
+ *   X        device float[n_samples][n_in] (n_in <= 32)
+ *   y        device float[n_samples]
+ *   counts   device float[n_members][n_samples] (integers >= 0, sum > 0)
+ *   params   device float[n_members][P] in: initial, out: trained
+ *   losses   device float[n_members][steps] or NULL: L_e before each step
+ *   grad_out device float[n_members][P] or NULL: gradient of the last step
+ * One cooperative launch whose workgroups meet at a grid barrier twice per
+ * step.  Returns EUNSUPPORTED when the grid cannot be co-resident.  This
+ * call synchronises `stream` and returns EDEVICE if a barrier timed out. */
+int kaldo_mlp_train(int32_t n_in, int32_t n_members, int32_t n_samples, const float* X,
+                    const float* y, const float* counts, float* params, int32_t steps, float lr,
+                    void* workspace, size_t workspace_bytes, float* losses, float* grad_out,
+                    void* stream);
+
+/* kaldo_mlp_predict -- ensemble forward pass: per row the mean and the
+ * population std over members of the outputs (n_members <= 16).
+ *   X       device float[n][n_in]; params device float[n_members][P]
+ *   mean, spread  device float[n] out */
+int kaldo_mlp_predict(int32_t n_in, int32_t n_members, int64_t n, const float* X,
+                      const float* params, float* mean, float* spread, void* stream);
+
+/* kaldo_surrogate_domain -- per feature column the [min, max] over the first
+ * n_fit rows of X (device float[n][n_feat], n_feat <= 32); inside[k]
+ * (device uint8[n]) = 1 when every feature of row k lies in those ranges.
+ * Rows outside the training domain are extrapolations: the gate sends them
+ * to the exact path whatever the ensemble's spread. */
+int kaldo_surrogate_domain(int64_t n, int32_t n_feat, const float* X, int64_t n_fit,
+                           uint8_t* inside, void* stream);
+
+/* kaldo_gate_score -- per row the first-order conductivity error the
+ * ensemble's disagreement implies:
+ *   score[k] = w / G_pred * spread[k] * sd,   G_pred = exp(mean[k] sd + mu),
+ *   w = star_size[q] c(omega)/k_B |v|^2 (Eq. heatcap; trace of Eq. rta's
+ *   summand without the constant factor),
+ * with (mu, sd) = y_mu_sd; +inf where inside is given and inside[k] == 0.
+ *   modes device int32[n]; mean, spread device float[n]; score device float[n] */
+int kaldo_gate_score(int64_t n, const int32_t* modes, const float* mean, const float* spread,
+                     const float* y_mu_sd, const double* omega, const double* vel,
+                     const int32_t* star_size, int32_t nb3, double temperature,
+                     const uint8_t* inside, float* score, void* stream);
+
+/* kaldo_gate_calibrate -- gate threshold from n held-out rows (n <= 4096).
+ * Row k (mode modes[k]): w as in kaldo_gate_score, predicted Gamma =
+ * exp(mean[k] sd + mu).  Rows are taken in ascending score, equal scores as
+ * one group; a group is accepted while
+ *   |sum_accepted w (1/G_pred - 1/G_true)| <= tol sum_all w / G_true.
+ * *tau (device float) = the next float above the last accepted score, 0 if
+ * none: rows with score < tau use the network. */
+int kaldo_gate_calibrate(int64_t n, const int32_t* modes, const double* gamma, const float* mean,
+                         const float* y_mu_sd, const float* score, const double* omega,
+                         const double* vel, const int32_t* star_size, int32_t nb3,
+                         double temperature, double tol, float* tau, void* stream);
+
+/* kaldo_gate_select -- rows k with score[k] >= *tau whose mode is not yet
+ * computed (computed[modes[k]] == 0) are appended in row order to fallback
+ * (device int32[n]) and marked computed; *n_fallback (device int32) = their
+ * count.  The listed modes must be distinct. */
+int kaldo_gate_select(int64_t n, const int32_t* modes, const float* score, const float* tau,
+                      uint8_t* computed, int32_t* fallback, int32_t* n_fallback, void* stream);
+
+/* kaldo_surrogate_fill -- gamma[modes[k]] = exp(mean[k] sd + mu) for rows whose
+ * mode is not computed; other entries untouched. */
+int kaldo_surrogate_fill(int64_t n, const int32_t* modes, const float* mean,
+                         const float* y_mu_sd, const uint8_t* computed, double* gamma,
+                         void* stream);
+
+/* kaldo_star_map -- full-grid linewidths from the representatives':
+ * gamma[q][s] = mean of gamma_ir[rep(q)][s'] over the frequency cluster
+ * (|d nu| < 1e-4 THz) of s at rep(q).  Linewidths are invariant under the
+ * crystal's point operations; cluster averaging removes the gauge freedom
+ * of degenerate modes.  gamma must not alias gamma_ir. */
+int kaldo_star_map(const int32_t* mesh, int32_t nb3, const int32_t* ir_of_q,
+                   const double* omega, const double* gamma_ir, double* gamma, void* stream);
+
 /* Per-kernel timing.  kaldo_profile_begin() makes every later kernel launch
  * of the library record a HIP event before and after it on its launch
  * stream; kaldo_profile_end() waits for those events, writes up to

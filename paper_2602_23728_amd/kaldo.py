@@ -77,6 +77,31 @@ def lib():
                                              ctypes.c_int32, P, ctypes.c_int64, P,
                                              ctypes.c_size_t, P, P]
         L.kaldo_kappa_rta.argtypes = [P, I32P, P, P, P, ctypes.c_double, ctypes.c_double, P, P]
+        L.kaldo_mesh_ibz.argtypes = [F64P, ctypes.c_int32, F64P, F64P, I32P, I32P, I32P, I32P, I32P]
+        L.kaldo_jdos_workspace.argtypes = [P, I32P]
+        L.kaldo_jdos_workspace.restype = ctypes.c_size_t
+        L.kaldo_jdos.argtypes = [P, I32P, P, P, ctypes.POINTER(Broadening), P, ctypes.c_int64, P,
+                                 ctypes.c_size_t, P, P, P]
+        L.kaldo_surrogate_feature_count.argtypes = [P]
+        L.kaldo_surrogate_feature_count.restype = ctypes.c_int32
+        L.kaldo_surrogate_features.argtypes = [P, I32P, P, P, P, P, P, ctypes.c_int64, P, P]
+        L.kaldo_standardize.argtypes = [ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, P]
+        L.kaldo_surrogate_targets.argtypes = [P, P, ctypes.c_int64, P, P, P]
+        L.kaldo_mlp_param_count.argtypes = [ctypes.c_int32]
+        L.kaldo_mlp_param_count.restype = ctypes.c_int32
+        L.kaldo_mlp_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.kaldo_mlp_workspace.restype = ctypes.c_size_t
+        L.kaldo_mlp_train.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, P,
+                                      ctypes.c_int32, ctypes.c_float, P, ctypes.c_size_t, P, P, P]
+        L.kaldo_mlp_predict.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P, P, P, P, P]
+        L.kaldo_gate_calibrate.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, ctypes.c_int32,
+                                           ctypes.c_double, ctypes.c_double, P, P]
+        L.kaldo_gate_select.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P]
+        L.kaldo_surrogate_domain.argtypes = [ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, P]
+        L.kaldo_gate_score.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int32,
+                                       ctypes.c_double, P, P, P]
+        L.kaldo_surrogate_fill.argtypes = [ctypes.c_int64, P, P, P, P, P, P]
+        L.kaldo_star_map.argtypes = [I32P, ctypes.c_int32, P, P, P, P, P]
         L.kaldo_profile_begin.argtypes = []
         L.kaldo_profile_end.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int32)]
@@ -87,7 +112,12 @@ def lib():
 EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
             "kaldo_phonons_gamma", "kaldo_linewidths_workspace", "kaldo_linewidths",
             "kaldo_linewidths_gamma_workspace", "kaldo_linewidths_gamma", "kaldo_kappa_rta",
-            "kaldo_last_error", "kaldo_version", "kaldo_profile_begin", "kaldo_profile_end"]
+            "kaldo_last_error", "kaldo_version", "kaldo_profile_begin", "kaldo_profile_end",
+            "kaldo_mesh_ibz", "kaldo_jdos_workspace", "kaldo_jdos", "kaldo_surrogate_feature_count",
+            "kaldo_surrogate_features", "kaldo_standardize", "kaldo_surrogate_targets",
+            "kaldo_mlp_param_count", "kaldo_mlp_workspace", "kaldo_mlp_train", "kaldo_mlp_predict",
+            "kaldo_gate_calibrate", "kaldo_gate_select", "kaldo_surrogate_fill", "kaldo_star_map",
+            "kaldo_surrogate_domain", "kaldo_gate_score"]
 
 
 def _check(rc):
@@ -240,4 +270,173 @@ def kappa_rta(c: Crystal, mesh, omega, vel, gamma, temperature, nu_min_thz, out=
         out = torch.empty(3, 3, dtype=torch.float64, device="cuda")
     _check(lib().kaldo_kappa_rta(c.handle, _ptr(m, I32P), _dev(omega), _dev(vel), _dev(gamma),
                                  float(temperature), float(nu_min_thz), _dev(out), _stream()))
+    return out
+
+
+# ------------------------------------------------------------------ learned form
+
+def mesh_ibz(lattice, frac, mass, mesh):
+    """Host: (ir_of_q [N_q], star_size [N_q], n_ops, n_ir) as numpy int32."""
+    m = _mesh(mesh)
+    nq = int(np.prod(m))
+    lat = _f64(lattice).reshape(9)
+    fr = _f64(frac).reshape(-1)
+    ms = _f64(mass)
+    ir = np.empty(nq, np.int32)
+    star = np.empty(nq, np.int32)
+    n_ops = ctypes.c_int32()
+    n_ir = ctypes.c_int32()
+    _check(lib().kaldo_mesh_ibz(_ptr(lat, F64P), int(len(ms)), _ptr(fr, F64P), _ptr(ms, F64P),
+                                _ptr(m, I32P), _ptr(ir, I32P), _ptr(star, I32P),
+                                ctypes.byref(n_ops), ctypes.byref(n_ir)))
+    return ir, star, n_ops.value, n_ir.value
+
+
+def jdos(c: Crystal, mesh, omega, vel, broadening, subset=None, workspace=None, out=None):
+    """(D+, D-) [N_q, nb3] ps/rad on cuda; only subset entries are written."""
+    m = _mesh(mesh)
+    nq = int(np.prod(m))
+    ws = int(lib().kaldo_jdos_workspace(c.handle, _ptr(m, I32P)))
+    if workspace is None:
+        workspace = torch.empty(max(ws, 1), dtype=torch.uint8, device="cuda")
+    if out is None:
+        out = (torch.zeros(nq, c.nb3, dtype=torch.float64, device="cuda"),
+               torch.zeros(nq, c.nb3, dtype=torch.float64, device="cuda"))
+    b = Broadening.of(broadening)
+    sub = None if subset is None else subset.to(torch.int32).contiguous()
+    _check(lib().kaldo_jdos(c.handle, _ptr(m, I32P), _dev(omega), _dev(vel), ctypes.byref(b),
+                            _dev(sub), 0 if sub is None else int(sub.numel()), _dev(workspace),
+                            int(workspace.numel()), _dev(out[0]), _dev(out[1]), _stream()))
+    return out
+
+
+def surrogate_feature_count(c: Crystal):
+    return int(lib().kaldo_surrogate_feature_count(c.handle))
+
+
+def surrogate_features(c: Crystal, mesh, omega, vel, dplus, dminus, modes, out=None):
+    """float32 [n, nb3 + 8] on cuda."""
+    m = _mesh(mesh)
+    modes = modes.to(torch.int32).contiguous()
+    n = int(modes.numel())
+    if out is None:
+        out = torch.empty(n, surrogate_feature_count(c), dtype=torch.float32, device="cuda")
+    _check(lib().kaldo_surrogate_features(c.handle, _ptr(m, I32P), _dev(omega), _dev(vel),
+                                          _dev(dplus), _dev(dminus), _dev(modes), n, _dev(out),
+                                          _stream()))
+    return out
+
+
+def standardize(X, n_fit, mu_sd=None):
+    """Standardises X (float32 [n, n_feat], cuda) in place; returns mu_sd [n_feat, 2]."""
+    n, nf = X.shape
+    if mu_sd is None:
+        mu_sd = torch.empty(nf, 2, dtype=torch.float32, device="cuda")
+    _check(lib().kaldo_standardize(int(n), int(nf), _dev(X), int(n_fit), _dev(mu_sd), _stream()))
+    return mu_sd
+
+
+def surrogate_targets(gamma, modes, out=None):
+    """(y float32 [n], y_mu_sd float32 [2]) on cuda."""
+    modes = modes.to(torch.int32).contiguous()
+    n = int(modes.numel())
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float32, device="cuda"),
+               torch.empty(2, dtype=torch.float32, device="cuda"))
+    _check(lib().kaldo_surrogate_targets(_dev(gamma), _dev(modes), n, _dev(out[0]), _dev(out[1]),
+                                         _stream()))
+    return out
+
+
+def mlp_param_count(n_in):
+    return int(lib().kaldo_mlp_param_count(int(n_in)))
+
+
+def mlp_train(X, y, counts, params, steps, lr=1e-3, losses=False, grad=False, workspace=None):
+    """Trains params (float32 [M, P], cuda) in place.  Returns (losses [M, steps] or None,
+    gradient of the last step [M, P] or None).  Synchronises the stream."""
+    n, n_in = X.shape
+    M = params.shape[0]
+    ws = int(lib().kaldo_mlp_workspace(int(n_in), int(M), int(n)))
+    if workspace is None:
+        workspace = torch.empty(max(ws, 1), dtype=torch.uint8, device="cuda")
+    L = torch.zeros(M, max(int(steps), 1), dtype=torch.float32, device="cuda") if losses else None
+    G = torch.zeros_like(params) if grad else None
+    _check(lib().kaldo_mlp_train(int(n_in), int(M), int(n), _dev(X.contiguous()), _dev(y.contiguous()),
+                                 _dev(counts.contiguous()), _dev(params), int(steps), float(lr),
+                                 _dev(workspace), int(workspace.numel()), _dev(L), _dev(G), _stream()))
+    return L, G
+
+
+def mlp_predict(X, params, out=None):
+    """(mean, spread) float32 [n] on cuda."""
+    n, n_in = X.shape
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float32, device="cuda"),
+               torch.empty(n, dtype=torch.float32, device="cuda"))
+    _check(lib().kaldo_mlp_predict(int(n_in), int(params.shape[0]), int(n), _dev(X.contiguous()),
+                                   _dev(params.contiguous()), _dev(out[0]), _dev(out[1]), _stream()))
+    return out
+
+
+def surrogate_domain(X, n_fit, out=None):
+    """uint8 [n] on cuda: 1 where the row lies inside the first n_fit rows' ranges."""
+    n, nf = X.shape
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    _check(lib().kaldo_surrogate_domain(int(n), int(nf), _dev(X), int(n_fit), _dev(out), _stream()))
+    return out
+
+
+def gate_score(modes, mean, spread, y_mu_sd, omega, vel, star_size, nb3, temperature, inside=None,
+               out=None):
+    """float32 [n] on cuda."""
+    modes = modes.to(torch.int32).contiguous()
+    n = int(modes.numel())
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+    _check(lib().kaldo_gate_score(n, _dev(modes), _dev(mean), _dev(spread), _dev(y_mu_sd), _dev(omega),
+                                  _dev(vel), _dev(star_size), int(nb3), float(temperature),
+                                  _dev(inside), _dev(out), _stream()))
+    return out
+
+
+def gate_calibrate(modes, gamma, mean, y_mu_sd, score, omega, vel, star_size, nb3, temperature,
+                   tol, out=None):
+    """tau: float32 [1] on cuda."""
+    modes = modes.to(torch.int32).contiguous()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib().kaldo_gate_calibrate(int(modes.numel()), _dev(modes), _dev(gamma), _dev(mean),
+                                      _dev(y_mu_sd), _dev(score), _dev(omega), _dev(vel),
+                                      _dev(star_size), int(nb3), float(temperature), float(tol),
+                                      _dev(out), _stream()))
+    return out
+
+
+def gate_select(modes, score, tau, computed, out=None):
+    """(fallback int32 [n], n_fallback int32 [1]) on cuda; marks computed."""
+    modes = modes.to(torch.int32).contiguous()
+    n = int(modes.numel())
+    if out is None:
+        out = (torch.empty(max(n, 1), dtype=torch.int32, device="cuda"),
+               torch.empty(1, dtype=torch.int32, device="cuda"))
+    _check(lib().kaldo_gate_select(n, _dev(modes), _dev(score), _dev(tau), _dev(computed),
+                                   _dev(out[0]), _dev(out[1]), _stream()))
+    return out
+
+
+def surrogate_fill(modes, mean, y_mu_sd, computed, gamma):
+    modes = modes.to(torch.int32).contiguous()
+    _check(lib().kaldo_surrogate_fill(int(modes.numel()), _dev(modes), _dev(mean), _dev(y_mu_sd),
+                                      _dev(computed), _dev(gamma), _stream()))
+    return gamma
+
+
+def star_map(mesh, nb3, ir_of_q, omega, gamma_ir, out=None):
+    m = _mesh(mesh)
+    if out is None:
+        out = torch.empty_like(gamma_ir)
+    _check(lib().kaldo_star_map(_ptr(m, I32P), int(nb3), _dev(ir_of_q), _dev(omega), _dev(gamma_ir),
+                                _dev(out), _stream()))
     return out

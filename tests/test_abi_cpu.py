@@ -78,3 +78,23 @@ def test_host_gamma_eigensolver_matches_lapack(which):
         iso = (j == 0 or nu[j] - nu[j - 1] > 1e-4) and (j == n - 1 or nu[j + 1] - nu[j] > 1e-4)
         if iso and big[j]:
             assert np.max(np.abs(E[:, j] - oE[:, j])) < 1e-9
+
+
+@pytest.mark.parametrize("which,mesh", [("diamond", (8, 8, 8)), ("diamond", (6, 6, 4)),
+                                        ("perovskite", (6, 6, 6)), ("random", (3, 4, 5))])
+def test_host_wedge_matches_oracle(which, mesh):
+    """kaldo_mesh_ibz (metric-preserving integer matrices) against the oracle's
+    Cartesian cubic-operation search."""
+    from oracle import surrogate as osur
+    from synthetic import models
+    m = {"diamond": models.diamond(), "perovskite": models.perovskite(0),
+         "random": models.random_cell(5, 2)}[which]
+    ir, star, n_ops, n_ir = K.mesh_ibz(m.lattice, m.frac, m.mass, mesh)
+    ir_o = osur.ibz_map(m, mesh)
+    if which == "random":
+        # lattice operations outside the cubic set are not searched by the oracle
+        assert np.all(ir <= ir_o)
+    else:
+        np.testing.assert_array_equal(ir, ir_o)
+    assert n_ir == len(np.unique(ir)) and star.sum() == np.prod(mesh)
+    np.testing.assert_array_equal(star, np.bincount(ir, minlength=len(ir)))

@@ -1,0 +1,332 @@
+"""GPU parity of the learned linewidth form against the oracle.
+
+JDOS, features, standardisation, the MLP forward / backward / Adam, ensemble
+inference, the gate threshold, the fallback list and the star map each run
+through the C ABI on seeded inputs shared with the oracle.  The end-to-end
+test runs the whole learned form on the 24^3 diamond mesh and checks its
+conductivity against the plain FP32 path (2 %), and the plain path on the
+irreducible wedge against the full mesh.
+"""
+import numpy as np
+import pytest
+
+from oracle import jdos as ojdos
+from oracle import kappa as okappa
+from oracle import mlp as omlp
+from oracle import phonons as oph
+from oracle import surrogate as osur
+from oracle.constants import TWO_PI
+from synthetic import configs, draws, models
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2602_23728_amd import kaldo as K  # noqa: E402
+from paper_2602_23728_amd import learned as L  # noqa: E402
+
+B_FIXED = configs.Broadening(adaptive=False)
+B_ADAPT = configs.Broadening(adaptive=True)
+B_LOR = configs.Broadening(shape=configs.LORENTZ, adaptive=False, sigma_thz=0.2)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def kappa_rel(k, k_ref):
+    kbar = np.trace(k_ref) / 3
+    return max(abs(np.trace(k) / 3 - kbar) / kbar, np.max(np.abs(k - k_ref)) / kbar)
+
+
+@pytest.fixture(scope="module")
+def diamond():
+    m = models.diamond()
+    return m, K.Crystal.from_model(m)
+
+
+# ------------------------------------------------------------------ JDOS
+
+@pytest.mark.parametrize("broad,mesh", [(B_FIXED, (5, 5, 5)), (B_ADAPT, (6, 6, 6)),
+                                        (B_LOR, (4, 4, 4)), (B_ADAPT, (3, 4, 5))],
+                         ids=["fixed", "adaptive", "lorentz", "ragged"])
+def test_jdos_matches_oracle(diamond, broad, mesh):
+    m, c = diamond
+    om, ev, ve = oph.phonons(m, mesh)
+    dp_o, dm_o = ojdos.jdos(m, mesh, om, ve, broad)
+    dp, dm = K.jdos(c, mesh, dev(om), dev(ve), broad)
+    dp, dm = host(dp), host(dm)
+    for a, b in ((dp, dp_o), (dm, dm_o)):
+        big = b > 1e-3 * b.max()
+        assert big.any()
+        assert np.max(np.abs(a[big] - b[big]) / b[big]) <= 1e-5
+        assert np.max(np.abs(a - b)) <= 1e-5 * b.max()
+        assert np.all(a[om / TWO_PI < 0.1] == 0.0)
+
+
+def test_jdos_subset_writes_only_selected(diamond):
+    m, c = diamond
+    mesh = (4, 4, 4)
+    om, ev, ve = oph.phonons(m, mesh)
+    dp_o, dm_o = ojdos.jdos(m, mesh, om, ve, B_ADAPT)
+    sub = np.array([5, 17, 100, 383, 200], np.int32)
+    out = (torch.full((64, 6), -7.0, dtype=torch.float64, device="cuda"),
+           torch.full((64, 6), -7.0, dtype=torch.float64, device="cuda"))
+    dp, dm = K.jdos(c, mesh, dev(om), dev(ve), B_ADAPT, subset=dev(sub), out=out)
+    dp, dm = host(dp).reshape(-1), host(dm).reshape(-1)
+    mask = np.zeros(dp.size, bool)
+    mask[sub] = True
+    assert np.all(dp[~mask] == -7.0) and np.all(dm[~mask] == -7.0)
+    np.testing.assert_allclose(dp[sub], dp_o.reshape(-1)[sub], rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(dm[sub], dm_o.reshape(-1)[sub], rtol=1e-5, atol=1e-12)
+
+
+# ------------------------------------------------------------------ features
+
+def test_features_and_standardize_match_oracle(diamond):
+    m, c = diamond
+    mesh = (6, 6, 6)
+    om, ev, ve = oph.phonons(m, mesh)
+    dp, dm = ojdos.jdos(m, mesh, om, ve, B_ADAPT)
+    modes = np.random.default_rng(4).permutation(om.size)[:300].astype(np.int32)
+    F_o = osur.features(m, mesh, om, ve, dp, dm, modes)
+    X = K.surrogate_features(c, mesh, dev(om), dev(ve), dev(dp), dev(dm), dev(modes))
+    np.testing.assert_allclose(host(X), F_o, rtol=2e-6, atol=1e-6)
+    Z_o, mu_o, sd_o = osur.standardize(host(X).astype(np.float64), 120)
+    mu_sd = host(K.standardize(X, 120))
+    np.testing.assert_allclose(mu_sd[:, 0], mu_o, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(mu_sd[:, 1], sd_o, rtol=1e-6)
+    np.testing.assert_allclose(host(X), Z_o, rtol=1e-5, atol=1e-5)
+
+
+def test_targets_match_definition():
+    rng = np.random.default_rng(5)
+    g = rng.lognormal(-2.0, 1.5, size=500)
+    modes = rng.permutation(500)[:137].astype(np.int32)
+    y, mu_sd = K.surrogate_targets(dev(g), dev(modes))
+    lg = np.log(g[modes])
+    np.testing.assert_allclose(host(mu_sd), [lg.mean(), lg.std()], rtol=1e-6)
+    np.testing.assert_allclose(host(y), (lg - lg.mean()) / lg.std(), rtol=1e-5, atol=1e-6)
+
+
+# ------------------------------------------------------------------ MLP
+
+def _mlp_problem(n=165, n_in=14, members=3, seed=7):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, n_in)).astype(np.float32)
+    y = (np.sin(X[:, 0]) + 0.3 * X[:, 1] * X[:, 2] + 0.1 * rng.normal(size=n)).astype(np.float32)
+    d = draws.surrogate_draws(10 * n, n_in, members=members, seed=seed)
+    counts = np.stack([np.bincount(np.random.default_rng(100 + e).integers(0, n, n), minlength=n)
+                       for e in range(members)]).astype(np.float32)
+    return X, y, counts, d.params
+
+
+def _oracle_grad(params_flat, X, y, c, n_in):
+    p = omlp.unflatten(params_flat.astype(np.float64), n_in)
+    loss, g = omlp.loss_and_grad(p, X.astype(np.float64), y.astype(np.float64), c.astype(np.float64))
+    return loss, omlp.flatten(g)
+
+
+def test_mlp_gradient_and_loss_match_oracle():
+    X, y, counts, P0 = _mlp_problem()
+    n_in = X.shape[1]
+    assert P0.shape[1] == K.mlp_param_count(n_in)
+    params = dev(P0.copy())
+    losses, grad = K.mlp_train(dev(X), dev(y), dev(counts), params, 1, 1e-3, losses=True, grad=True)
+    grad, losses = host(grad), host(losses)
+    for e in range(P0.shape[0]):
+        lo, go = _oracle_grad(P0[e], X, y, counts[e], n_in)
+        assert abs(losses[e, 0] - lo) <= 1e-5 * lo
+        assert np.linalg.norm(grad[e] - go) <= 1e-4 * np.linalg.norm(go)
+        assert np.max(np.abs(grad[e] - go)) <= 1e-4 * np.max(np.abs(go))
+
+
+def test_mlp_adam_steps_match_oracle():
+    X, y, counts, P0 = _mlp_problem(members=2)
+    n_in = X.shape[1]
+    steps, lr = 20, 1e-3
+    params = dev(P0.copy())
+    losses, _ = K.mlp_train(dev(X), dev(y), dev(counts), params, steps, lr, losses=True)
+    P_gpu, losses = host(params), host(losses)
+    for e in range(P0.shape[0]):
+        p = omlp.unflatten(P0[e].astype(np.float64), n_in)
+        p_o, l_o = omlp.train(p, X.astype(np.float64), y.astype(np.float64),
+                              counts[e].astype(np.float64), steps, lr)
+        np.testing.assert_allclose(losses[e], l_o, rtol=1e-4)
+        # Adam moves each weight by about lr per step whatever the gradient's
+        # size, so a weight whose gradient is at rounding level may move the
+        # other way: those are bounded by 2 lr per step, the rest must agree.
+        _, g0 = _oracle_grad(P0[e], X, y, counts[e], n_in)
+        flat = omlp.flatten(p_o)
+        solid = np.abs(g0) > 1e-3 * np.max(np.abs(g0))
+        err = np.abs(P_gpu[e] - flat)
+        assert np.max(err[solid]) <= 2e-3 * lr * steps + 1e-5 * np.max(np.abs(flat))
+        assert np.max(err) <= 2.0 * lr * steps
+        assert np.mean(err[solid] > 1e-5) < 0.01
+
+
+def test_mlp_training_reduces_loss_and_is_deterministic():
+    X, y, counts, P0 = _mlp_problem(members=2)
+    a, b = dev(P0.copy()), dev(P0.copy())
+    la, _ = K.mlp_train(dev(X), dev(y), dev(counts), a, 400, 1e-3, losses=True)
+    K.mlp_train(dev(X), dev(y), dev(counts), b, 400, 1e-3)
+    la = host(la)
+    assert np.all(la[:, -1] < 0.5 * la[:, 0])
+    assert np.array_equal(host(a), host(b))
+
+
+def test_mlp_train_many_samples_uses_larger_groups():
+    """Enough rows that the 8-row grid no longer fits on the device at once."""
+    X, y, counts, P0 = _mlp_problem(n=4000, n_in=10, members=2, seed=9)
+    params = dev(P0.copy())
+    losses, grad = K.mlp_train(dev(X), dev(y), dev(counts), params, 1, 1e-3, losses=True, grad=True)
+    lo, go = _oracle_grad(P0[0], X, y, counts[0], 10)
+    assert abs(host(losses)[0, 0] - lo) <= 1e-5 * lo
+    assert np.linalg.norm(host(grad)[0] - go) <= 1e-4 * np.linalg.norm(go)
+
+
+def test_mlp_predict_matches_oracle_forward():
+    X, y, counts, P0 = _mlp_problem(n=333, members=5)
+    n_in = X.shape[1]
+    mean, spread = K.mlp_predict(dev(X), dev(P0))
+    outs = np.stack([omlp.forward(omlp.unflatten(P0[e].astype(np.float64), n_in),
+                                  X.astype(np.float64))[0] for e in range(5)])
+    np.testing.assert_allclose(host(mean), outs.mean(axis=0), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(host(spread), outs.std(axis=0), rtol=1e-4, atol=1e-5)
+
+
+# ------------------------------------------------------------------ gate, fill, star map
+
+def test_gate_calibrate_matches_oracle(diamond):
+    m, c = diamond
+    mesh = (6, 6, 6)
+    om, ev, ve = oph.phonons(m, mesh)
+    rng = np.random.default_rng(11)
+    phys = np.flatnonzero(om.reshape(-1) / TWO_PI >= 0.1)
+    modes = rng.permutation(phys)[:200].astype(np.int32)
+    g = rng.lognormal(-1.0, 1.0, size=om.size)
+    mean = rng.normal(size=200).astype(np.float32)
+    spread = rng.gamma(2.0, 0.05, size=200).astype(np.float32)
+    spread[10:14] = spread[3]   # ties
+    y_mu_sd = np.array([-1.0, 1.0], np.float32)
+    # network close to the truth on low-spread rows, off on the others
+    mean = ((np.log(g[modes]) - y_mu_sd[0]) / y_mu_sd[1]
+            + rng.normal(size=200) * spread * 2).astype(np.float32)
+    star = rng.integers(1, 49, size=om.shape[0]).astype(np.int32)
+    for tol in (0.0, 0.005, 0.02, 0.2, 10.0):
+        tau = host(K.gate_calibrate(dev(modes), dev(g), dev(mean), dev(y_mu_sd), dev(spread),
+                                    dev(om), dev(ve), dev(star), 6, 300.0, tol))[0]
+        w = osur.mode_weights(om.reshape(-1)[modes], ve.reshape(-1, 3)[modes], 300.0,
+                              star[modes // 6])
+        gp = np.exp(mean.astype(np.float64) * float(y_mu_sd[1]) + float(y_mu_sd[0]))
+        tau_o = osur.gate_threshold(g[modes], gp, spread, w, tol)
+        assert tau == tau_o, (tol, tau, tau_o)
+
+
+def test_domain_and_gate_score_match_oracle(diamond):
+    m, c = diamond
+    mesh = (6, 6, 6)
+    om, ev, ve = oph.phonons(m, mesh)
+    rng = np.random.default_rng(13)
+    X = rng.normal(size=(400, 14)).astype(np.float32)
+    X[:, 3] = (rng.uniform(size=400) < 0.5)       # one-hot-like column
+    X[:100, 5] = 0.0                               # constant on the fit rows
+    inside = host(K.surrogate_domain(dev(X), 100))
+    np.testing.assert_array_equal(inside.astype(bool), osur.domain_inside(X.astype(np.float64), 100))
+    assert 0 < inside.sum() < 400
+    phys = np.flatnonzero(om.reshape(-1) / TWO_PI >= 0.1)
+    modes = rng.permutation(phys)[:400].astype(np.int32)
+    mean = rng.normal(size=400).astype(np.float32)
+    spread = rng.gamma(2.0, 0.1, size=400).astype(np.float32)
+    y_mu_sd = np.array([-1.5, 0.8], np.float32)
+    star = rng.integers(1, 49, size=om.shape[0]).astype(np.int32)
+    sc = host(K.gate_score(dev(modes), dev(mean), dev(spread), dev(y_mu_sd), dev(om), dev(ve),
+                           dev(star), 6, 300.0, dev(inside)))
+    w = osur.mode_weights(om.reshape(-1)[modes], ve.reshape(-1, 3)[modes], 300.0, star[modes // 6])
+    sc_o = osur.gate_score(mean, spread, y_mu_sd, w, inside.astype(bool))
+    assert np.array_equal(np.isinf(sc), np.isinf(sc_o))
+    fin = np.isfinite(sc_o)
+    np.testing.assert_allclose(sc[fin], sc_o[fin], rtol=1e-6)
+
+
+def test_gate_select_fill_and_star_map(diamond):
+    m, c = diamond
+    mesh = (4, 4, 4)
+    om, ev, ve = oph.phonons(m, mesh)
+    rng = np.random.default_rng(12)
+    nm = 64 * 6
+    modes = rng.permutation(nm)[: nm - 20].astype(np.int32)   # distinct, 364 rows
+    k = len(modes)
+    spread = rng.uniform(0, 1, size=k).astype(np.float32)
+    mean = rng.normal(size=k).astype(np.float32)
+    computed = (rng.uniform(size=nm) < 0.2).astype(np.uint8)
+    tau = np.array([0.6], np.float32)
+    comp_d = dev(computed.copy())
+    fb, nfb = K.gate_select(dev(modes), dev(spread), dev(tau), comp_d)
+    want = [mm for mm, s in zip(modes, spread) if not (s < tau[0]) and not computed[mm]]
+    assert host(nfb)[0] == len(want)
+    np.testing.assert_array_equal(host(fb)[: len(want)], want)
+    comp_after = computed.copy()
+    comp_after[want] = 1
+    np.testing.assert_array_equal(host(comp_d), comp_after)
+    # fill
+    y_mu_sd = np.array([-2.0, 0.7], np.float32)
+    gam = np.full(nm, -1.0)
+    gam_d = dev(gam.copy())
+    K.surrogate_fill(dev(modes), dev(mean), dev(y_mu_sd), comp_d, gam_d)
+    exp_g = gam.copy()
+    for mm, mu in zip(modes, mean):
+        if not comp_after[mm]:
+            exp_g[mm] = np.exp(float(mu) * float(y_mu_sd[1]) + float(y_mu_sd[0]))
+    np.testing.assert_allclose(host(gam_d), exp_g, rtol=1e-15)
+    # star map
+    ir, star, _, _ = K.mesh_ibz(m.lattice, m.frac, m.mass, mesh)
+    g_ir = rng.lognormal(size=om.shape)
+    out = K.star_map(mesh, 6, dev(ir), dev(om), dev(g_ir))
+    np.testing.assert_allclose(host(out), osur.star_map(ir, om, g_ir), rtol=1e-15)
+
+
+# ------------------------------------------------------------------ end to end
+
+def test_learned_form_c5_end_to_end(diamond):
+    """24^3 diamond: plain FP32 on every mode is the reference; the plain path
+    on the irreducible wedge must agree to 1e-3, the learned form to 2 %."""
+    m, c = diamond
+    cfg = configs.CONFIGS["C5"]
+    mesh, T, b = cfg.mesh, cfg.temperature, cfg.broadening
+    om, ev, ve = K.phonons(c, mesh)
+    g_full = K.linewidths(c, mesh, om, ev, ve, T, b, K.FP32)
+    k_full = host(K.kappa_rta(c, mesh, om, ve, g_full, T, b.nu_min_thz))
+    wedge = L.Wedge(m.lattice, m.frac, m.mass, mesh)
+    assert wedge.n_ir == 413
+    g_ibz = L.plain_ibz_linewidths(c, wedge, om, ev, ve, T, b, K.FP32)
+    k_ibz = host(K.kappa_rta(c, mesh, om, ve, g_ibz, T, b.nu_min_thz))
+    e_ibz = kappa_rel(k_ibz, k_full)
+    cand = L.candidate_modes(wedge, om, c.nb3, b.nu_min_thz)
+    d = draws.surrogate_draws(len(cand), K.surrogate_feature_count(c), members=5, seed=0)
+    res = L.learned_linewidths(c, wedge, om, ev, ve, T, b, cand, d, steps=3000, lr=1e-3, tol=0.01)
+    k_sur = host(K.kappa_rta(c, mesh, om, ve, res.gamma, T, b.nu_min_thz))
+    e_sur = kappa_rel(k_sur, k_full)
+    # held-out error of ln Gamma, network against the training mean ("no network")
+    g_ir = host(res.gamma_ir).reshape(-1)
+    modes = host(res.modes)
+    ho = modes[res.n_train:res.n_train + res.n_held]
+    mu, sd = host(res.y_mu_sd)
+    pred = host(res.mean)[res.n_train:res.n_train + res.n_held] * sd + mu
+    truth = np.log(g_ir[ho])
+    rmse_net = float(np.sqrt(np.mean((pred - truth) ** 2)))
+    rmse_const = float(np.sqrt(np.mean((mu - truth) ** 2)))
+    print(f"\nC5: kappa full {np.trace(k_full)/3:.4f} ibz err {e_ibz:.2e} learned err {e_sur:.2e} "
+          f"tau {res.tau:.4g} fallback {res.n_fallback}/{len(cand) - res.n_train - res.n_held} "
+          f"outside domain {int((host(res.inside) == 0).sum())} "
+          f"held-out rmse ln Gamma net {rmse_net:.3f} vs const {rmse_const:.3f}", flush=True)
+    assert e_ibz <= 1e-3
+    assert e_sur <= 0.02
+    assert rmse_net < 0.5 * rmse_const

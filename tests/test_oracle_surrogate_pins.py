@@ -116,3 +116,138 @@ def test_mlp_training_reduces_loss():
     params = mlp.init_params(6, np.random.default_rng(6))
     params, losses = mlp.train(params, X, y, np.ones(120), steps=300, lr=3e-3)
     assert losses[-1] < 0.1 * losses[0]
+
+
+# ---------------------------------------------------------------- wedge, star map, features, gate
+from oracle import linewidths as olw  # noqa: E402
+from oracle import surrogate as osur  # noqa: E402
+
+
+@pytest.mark.parametrize("n,count", [(4, 8), (6, 16), (8, 29)])
+def test_fcc_wedge_counts_match_textbook(n, count):
+    """Gamma-centred n^3 meshes of an fcc crystal with the full cubic group
+    have 8, 16 and 29 irreducible points (standard k-point tables)."""
+    ir = osur.ibz_map(models.diamond(), (n, n, n))
+    assert len(np.unique(ir)) == count
+    assert osur.star_sizes(ir).sum() == n ** 3
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_simple_cubic_wedge_closed_form(n):
+    """Simple cubic, even n: the wedge 0 <= z <= y <= x <= n/2 holds
+    (n/2+1)(n/2+2)(n/2+3)/6 points."""
+    ir = osur.ibz_map(models.perovskite(0), (n, n, n))
+    h = n // 2
+    assert len(np.unique(ir)) == (h + 1) * (h + 2) * (h + 3) // 6
+
+
+@pytest.mark.parametrize("which", ["diamond", "perovskite", "random"])
+def test_crystal_operations_form_a_group(which):
+    """The operations found hold the identity and are closed under products
+    and inverses; the cubic crystals keep all 48."""
+    m = {"diamond": models.diamond(), "perovskite": models.perovskite(0),
+         "random": models.random_cell(5, 2)}[which]
+    ops = osur.crystal_operations(m)
+    key = lambda R: tuple(np.rint(R).astype(int).reshape(-1))
+    have = {key(R) for R in ops}
+    assert key(np.eye(3)) in have
+    for A in ops:
+        assert key(A.T) in have
+        for B in ops:
+            assert key(A @ B) in have
+    if which != "random":
+        assert len(ops) == 48
+
+
+def test_star_members_share_frequencies_and_jdos():
+    """Point symmetry of the dynamics: every q of a star has the spectrum of
+    its representative, and the phase space D+- is a function of the star."""
+    m = models.diamond()
+    mesh = (4, 4, 4)
+    ir = osur.ibz_map(m, mesh)
+    om, ev, ve = phonons.phonons(m, mesh)
+    # zero-frequency branches of the nearest-neighbour model carry eigen-solver noise
+    np.testing.assert_allclose(om, om[ir], rtol=1e-10, atol=1e-4)
+    # fixed width: adaptive widths use partner velocities, whose split inside a
+    # degenerate multiplet follows a gauge that is not point-symmetric
+    dp, dm = ojdos.jdos(m, mesh, om, ve, B_FIXED)
+    np.testing.assert_allclose(dp, dp[ir], rtol=1e-8, atol=1e-12 * dp.max())
+    np.testing.assert_allclose(dm, dm[ir], rtol=1e-8, atol=1e-12 * dm.max())
+
+
+def test_star_map_reproduces_full_mesh_linewidths():
+    """Gamma computed on every q equals, after averaging over degenerate
+    clusters, the star map of the representatives' values."""
+    m = models.diamond()
+    mesh = (4, 4, 4)
+    ir = osur.ibz_map(m, mesh)
+    om, ev, ve = phonons.phonons(m, mesh)
+    g = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_FIXED)
+    mapped = osur.star_map(ir, om, g)
+    own = osur.star_map(np.arange(len(ir)), om, g)   # cluster averages at each q itself
+    scale = g.max()
+    np.testing.assert_allclose(mapped, own, rtol=1e-7, atol=1e-9 * scale)
+
+
+def test_features_are_star_invariant():
+    m = models.diamond()
+    mesh = (4, 4, 4)
+    ir = osur.ibz_map(m, mesh)
+    om, ev, ve = phonons.phonons(m, mesh)
+    dp, dm = ojdos.jdos(m, mesh, om, ve, B_FIXED)
+    nb3 = om.shape[1]
+    modes = np.arange(om.size)
+    F = osur.features(m, mesh, om, ve, dp, dm, modes)
+    Fr = osur.features(m, mesh, om, ve, dp, dm, (ir[modes // nb3] * nb3 + modes % nb3))
+    cols = [0] + list(range(2 + nb3, nb3 + 8))  # nu, q components, |q|, ln(1 + D)
+    np.testing.assert_allclose(F[:, cols], Fr[:, cols], rtol=1e-8, atol=1e-5)  # zero-branch noise
+    # |q| of the shortest image never exceeds the image at the mesh coordinates
+    B = phonons.reciprocal(m.lattice)
+    q0 = (phonons.mesh_points(mesh) / np.asarray(mesh)) @ B
+    assert np.all(F[:, nb3 + 5] <= np.linalg.norm(q0, axis=1)[modes // nb3] + 1e-12)
+
+
+def test_standardize_moments():
+    X = np.random.default_rng(3).normal(2.0, 3.0, size=(50, 4))
+    X[:, 2] = 5.0
+    Z, mu, sd = osur.standardize(X, 30)
+    np.testing.assert_allclose(Z[:30, [0, 1, 3]].mean(axis=0), 0.0, atol=1e-12)
+    np.testing.assert_allclose(Z[:30, [0, 1, 3]].std(axis=0), 1.0, rtol=1e-12)
+    assert sd[2] == 1.0 and np.all(Z[:, 2] == 0.0)
+
+
+def test_gate_threshold_small_cases():
+    gt = np.array([1.0, 1.0, 1.0, 1.0])
+    w = np.ones(4)
+    sp = np.array([0.1, 0.2, 0.3, 0.4], np.float32)
+    # perfect predictions: every row accepted
+    tau = osur.gate_threshold(gt, gt.copy(), sp, w, 0.0)
+    assert tau == np.nextafter(np.float32(0.4), np.float32(np.inf))
+    # row with spread 0.2 off by 1/G: +1 on a reference sum of 4 -> needs tol >= 0.25
+    gp = np.array([1.0, 0.5, 1.0, 1.0])
+    assert osur.gate_threshold(gt, gp, sp, w, 0.24) == np.nextafter(np.float32(0.1), np.float32(np.inf))
+    assert osur.gate_threshold(gt, gp, sp, w, 0.25) == np.nextafter(np.float32(0.4), np.float32(np.inf))
+    # a bad first row accepts nothing
+    gp = np.array([0.5, 1.0, 1.0, 1.0])
+    assert osur.gate_threshold(gt, gp, sp, w, 0.1) == 0.0
+    # tied spreads are one group
+    sp2 = np.array([0.1, 0.1, 0.3, 0.4], np.float32)
+    gp = np.array([1.0, 0.5, 1.0, 1.0])
+    assert osur.gate_threshold(gt, gp, sp2, w, 0.24) == 0.0
+    # an error that a later row cancels is still a stop (prefix rule)
+    gp = np.array([1.0, 0.5, 2.0, 1.0])
+    assert osur.gate_threshold(gt, gp, sp, w, 0.2) == np.nextafter(np.float32(0.1), np.float32(np.inf))
+
+
+def test_gate_score_is_first_order_kappa_error():
+    """score = |d(w/Gamma)| for a shift of ln Gamma by spread*sd, to first order."""
+    w = np.array([2.0, 5.0, 0.3])
+    mean = np.array([0.1, -0.4, 1.2])
+    y_mu_sd = (-1.0, 0.7)
+    spread = np.array([1e-6, 2e-6, 3e-6])
+    s = osur.gate_score(mean, spread, y_mu_sd, w)
+    l = mean * y_mu_sd[1] + y_mu_sd[0]
+    exact = np.abs(w / np.exp(l + spread * y_mu_sd[1]) - w / np.exp(l))
+    np.testing.assert_allclose(s, exact, rtol=1e-5)
+    inside = np.array([True, False, True])
+    assert np.isinf(osur.gate_score(mean, spread, y_mu_sd, w, inside)[1])
