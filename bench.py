@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-q", type=int, default=48)
+    ap.add_argument("--cpu-sample-q", type=int, default=200)
     ap.add_argument("--form", default="plain", choices=["plain", "learned"],
                     help="learned: the learned form against plain FP32 (full mesh and wedge)")
     ap.add_argument("--train-steps", type=int, default=1000)

@@ -59,8 +59,17 @@ __device__ __forceinline__ bool exact_pass(const LwParams& p, double w, double w
   return fabs(x) < 2.0 * s;
 }
 
+// Waves per SIMD the register allocation targets: four for the small FP32
+// cells (measured: the latency of the gathers needs the extra wave), the
+// compiler's choice otherwise.
 template <int NB, typename T>
-__global__ __launch_bounds__(kFusedThreads) void lw_fused(
+constexpr int fused_waves_per_eu() {
+  return (NB <= 2 && sizeof(T) == 4) ? 4 : 1;
+}
+
+template <int NB, typename T>
+__global__ __launch_bounds__(kFusedThreads)
+__attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     LwParams p, int n_rep, const int32_t* __restrict__ rep, const double* __restrict__ omega,
     const double* __restrict__ vel, const double* __restrict__ occ,
     const uint8_t* __restrict__ phys, const uint8_t* __restrict__ sel,
@@ -79,7 +88,6 @@ __global__ __launch_bounds__(kFusedThreads) void lw_fused(
   C* at = reinterpret_cast<C*>(smem);  // [n_blk][9][NB3]
   __shared__ int rq_q1[CAP];
   __shared__ int rq_code[CAP];
-  __shared__ double rq_w[CAP];
   __shared__ int wave_tot[BS / 64];
   __shared__ double2 phq[64];
   __shared__ double wq64[NB3];
@@ -147,11 +155,15 @@ __global__ __launch_bounds__(kFusedThreads) void lw_fused(
       const int q1 = rq_q1[r];
       const int code = rq_code[r];
       const int s = code & 255, s1 = (code >> 8) & 255, s2 = code >> 16;
-      const double w = rq_w[r];
       const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
       const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
                 c2 = ((-a2 - b2) % N2 + N2) % N2;
       const int q2 = (c0 * N1 + c1) * N2 + c2;
+      // FP64 weight of the entry (here, where every lane has an entry)
+      const int m1 = q1 * NB3 + s1, m2 = q2 * NB3 + s2;
+      double sp, sm;
+      widths(p, vel, m1, m2, sp, sm);
+      const double w = pair_weight(p, wq64[s], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
       C x[NB3], y[NB3];
       const C* xs = etaT + ((size_t)q1 * NB3 + s1) * NB3;
       const C* ys = etaT + ((size_t)q2 * NB3 + s2) * NB3;
@@ -265,16 +277,9 @@ __global__ __launch_bounds__(kFusedThreads) void lw_fused(
       const int take = min(CAP - fill, total - written);
       if (count > 0 && my_off < written + take && my_off + count > written) {
         int rank = my_off;
-        const int m1 = q1 * NB3 + s1;
-        const double w1 = omega[m1], n1 = occ[m1];
 #pragma unroll
         for (int s2 = 0; s2 < NB3; ++s2) {
           unsigned b = bits[s2];
-          if (!b) continue;
-          const int m2 = q2 * NB3 + s2;
-          const double w2 = omega[m2], n2 = occ[m2];
-          double sp, sm;
-          widths(p, vel, m1, m2, sp, sm);
           while (b) {
             const int s = __ffs(b) - 1;
             b &= b - 1;
@@ -282,7 +287,6 @@ __global__ __launch_bounds__(kFusedThreads) void lw_fused(
               const int slot = fill + rank - written;
               rq_q1[slot] = q1;
               rq_code[slot] = s | (s1 << 8) | (s2 << 16);
-              rq_w[slot] = pair_weight(p, wq64[s], w1, w2, n1, n2, sp, sm);
             }
             ++rank;
           }
@@ -374,7 +378,7 @@ bool fused_supported(const kaldo_crystal* c, int prec) {
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return false;
   // dynamic LDS plus the static queue / scan / reduction buffers
-  const size_t stat = kFusedCap * 16 + kFusedThreads * 8 + 64 * 16 + 64;
+  const size_t stat = kFusedCap * 8 + kFusedThreads * 8 + 64 * 16 + 64;
   return fused_lds_bytes(c, prec) + stat <= (size_t)lds_max;
 }
 

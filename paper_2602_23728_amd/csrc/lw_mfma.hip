@@ -14,7 +14,8 @@
 //   FP32 form:  v_mfma_f32_16x16x4_f32, 8 per real product.
 //   BF16x3:     v_mfma_f32_16x16x32_bf16 on x = hi + lo splits,
 //               hi*hi + hi*lo + lo*hi per real product, FP32 accumulation.
-// One workgroup per q (4 waves); each wave takes its own q1 values.
+// One workgroup per q (8 waves sharing A~_q in LDS, two per SIMD); each wave
+// takes its own q1 values.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -27,9 +28,10 @@ namespace kaldo {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 
-constexpr int kMfmaThreads = 256;
+constexpr int kMfmaWaves = 8;
+constexpr int kMfmaThreads = 64 * kMfmaWaves;
 constexpr int kMfmaMaxBlocks = 128;  // atom blocks (jb, kb, d) of the FC3 tables
-constexpr int kCandCap = 64 + 4 * 64;  // a full batch plus one branch's worth
+constexpr int kCandCap = 2 * 64;     // a full batch plus one row's worth
 
 // Order LDS traffic between the lanes of one wave (no workgroup barrier:
 // the waves of a workgroup run different numbers of q1 iterations).
@@ -59,16 +61,16 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
   const int NB3 = p.nb3;
   extern __shared__ double2 smem[];
   float2* at = reinterpret_cast<float2*>(smem);  // [n_blk][9][NB3]
-  __shared__ float2 tsc[4][16 * 17];             // per-wave T scratch [row jc][col s'']
-  __shared__ float2 bsc[4][16 * 17];             // per-wave B_s tile [row jc][col kc]
-  __shared__ float2 phb[4][kMfmaMaxBlocks];      // per-wave e^{-i q1.R_d(blk)} per block
-  __shared__ int cq_code[4][kCandCap];           // per-wave near-shell candidates:
-  __shared__ int cq_q1[4][kCandCap];             //   s | s' << 8 | s'' << 16, q1,
-  __shared__ double cq_v2[4][kCandCap];          //   |V|^2
+  __shared__ float2 tsc[kMfmaWaves][16 * 17];         // per-wave T scratch [row jc][col s'']
+  __shared__ float2 bsc[kMfmaWaves][16 * 17];         // per-wave B_s tile [row jc][col kc]
+  __shared__ float2 phb[kMfmaWaves][kMfmaMaxBlocks];  // per-wave e^{-i q1.R_d(blk)} per block
+  __shared__ int cq_code[kMfmaWaves][kCandCap];       // per-wave near-shell candidates:
+  __shared__ int cq_q1[kMfmaWaves][kCandCap];         //   s | s' << 8 | s'' << 16, q1,
+  __shared__ double cq_v2[kMfmaWaves][kCandCap];      //   |V|^2
   __shared__ double2 phq[64];
   __shared__ double wq64[16];
-  __shared__ double accl[16][kMfmaThreads];      // per-thread, per-branch sums
   __shared__ double red[kMfmaThreads];
+  double acc[16];  // this thread's per-branch sums (registers)
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
@@ -89,8 +91,9 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
     return;
   }
   if (tid < NB3) wq64[tid] = omega[q * NB3 + tid];
-  for (int k = 0; k < 16; ++k) accl[k][tid] = 0.0;
-  for (int k = tid; k < 4 * 16 * 17; k += kMfmaThreads) (&bsc[0][0])[k] = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  for (int k = tid; k < kMfmaWaves * 16 * 17; k += kMfmaThreads) (&bsc[0][0])[k] = make_float2(0.f, 0.f);
   for (int l = tid; l < n_rep; l += kMfmaThreads) {
     const int32_t* r = rep + 3 * l;
     int m0 = ((a0 * r[0]) % N0 + N0) % N0, m1 = ((a1 * r[1]) % N1 + N1) % N1,
@@ -122,9 +125,14 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
   constexpr int NF = SPLIT ? 8 : 4;
   auto kc_of = [&](int i) { return SPLIT ? 8 * (lg & 1) + i : 4 * i + lg; };
   // this lane's share of every B_s tile (fixed for the whole kernel)
-  int4 wk[4];
+  // packed as pos | lo << 9 | hi << 17 | bg << 25 (pos < 272, block indices
+  // <= 128, bg < 9), -1 for no item
+  int wk[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) wk[k] = bwork[k * 64 + lane];
+  for (int k = 0; k < 4; ++k) {
+    const int4 w = bwork[k * 64 + lane];
+    wk[k] = w.x < 0 ? -1 : (w.x | (w.y << 9) | (w.z << 17) | (w.w << 25));
+  }
 
   // Exact FP64 cut and weight of queued candidates, one per lane, in queue
   // order; the contribution goes to this lane's sum of the candidate's branch.
@@ -142,14 +150,17 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
         double sp, sm;
         widths(p, vel, m1, m2, sp, sm);
         const double wt = pair_weight(p, wq64[cs_], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
-        accl[cs_][tid] += wt * cq_v2[wv][e];
+        const double c = wt * cq_v2[wv][e];
+        // register accumulators need a static index: add to the selected one
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] += (k == cs_) ? c : 0.0;
       }
     }
     n_cand = 0;
     wave_sync();
   };
 
-  for (int q1 = wv; q1 < p.nq; q1 += 4) {
+  for (int q1 = wv; q1 < p.nq; q1 += kMfmaWaves) {
     const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
     const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
               c2 = ((-a2 - b2) % N2 + N2) % N2;
@@ -232,15 +243,34 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
       float2* Bt = bsc[wv];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (wk[k].x < 0) continue;
+        if (wk[k] < 0) continue;
+        const int pos = wk[k] & 511, lo = (wk[k] >> 9) & 255, end = (wk[k] >> 17) & 255,
+                  bg = (wk[k] >> 25) & 15;
         float2 v = make_float2(0.f, 0.f);
-        for (int blk = wk[k].y; blk < wk[k].z; ++blk) {
-          const float2 a = at[(blk * 9 + wk[k].w) * NB3 + s];
+        const int stride = 9 * NB3;
+        const float2* ap = at + (lo * 9 + bg) * NB3 + s;
+        int blk = lo;
+        // four blocks per round: their LDS loads are issued together
+        for (; blk + 4 <= end; blk += 4, ap += 4 * stride) {
+          float2 a[4], f[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            a[j] = ap[j * stride];
+            f[j] = phb[wv][blk + j];
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            v.x += f[j].x * a[j].x - f[j].y * a[j].y;
+            v.y += f[j].x * a[j].y + f[j].y * a[j].x;
+          }
+        }
+        for (; blk < end; ++blk, ap += stride) {
+          const float2 a = *ap;
           const float2 f = phb[wv][blk];
           v.x += f.x * a.x - f.y * a.y;
           v.y += f.x * a.y + f.y * a.x;
         }
-        Bt[wk[k].x] = v;
+        Bt[pos] = v;
       }
       wave_sync();
       float2 bv[NF];
@@ -326,15 +356,20 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
           cq_v2[wv][slot] = (double)vr[r] * (double)vr[r] + (double)vi[r] * (double)vi[r];
         }
         n_cand += __popcll(mask);
+        if (n_cand >= 64) {
+          wave_sync();
+          resolve();
+        }
       }
       wave_sync();
-      if (n_cand >= 64) resolve();
     }
   }
   resolve();
-  for (int s = 0; s < NB3; ++s) {
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    if (s >= NB3) break;
     __syncthreads();
-    red[tid] = accl[s][tid];
+    red[tid] = acc[s];
     __syncthreads();
     for (int w = kMfmaThreads / 2; w > 0; w >>= 1) {
       if (tid < w) red[tid] += red[tid + w];
@@ -352,8 +387,8 @@ bool mfma_supported(const kaldo_crystal* c) {
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return false;
   const size_t dyn = (size_t)c->bloch.n_blk * 9 * c->nb3 * 8;
-  const size_t stat = 2 * 4 * 16 * 17 * 8 + 4 * kMfmaMaxBlocks * 8 + 4 * kCandCap * 16 +
-                      64 * 16 + 16 * 8 + 17 * kMfmaThreads * 8;
+  const size_t stat = 2 * kMfmaWaves * 16 * 17 * 8 + kMfmaWaves * kMfmaMaxBlocks * 8 +
+                      kMfmaWaves * kCandCap * 16 + 64 * 16 + 16 * 8 + kMfmaThreads * 8;
   return dyn + stat <= (size_t)lds_max;
 }
 
