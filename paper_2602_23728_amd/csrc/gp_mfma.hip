@@ -71,6 +71,55 @@ __global__ void gm_avals(int n, int n_bc, int m0, int nb, const int32_t* __restr
 // the tile touches (its unique column list) are staged once in LDS; each
 // mode's 32 x 64 result is transposed through LDS so WT rows are written
 // contiguously.  FP32 products and sums; the BF16x3 form stores hi/lo.
+// Frequency range [lo, hi] of the physical modes of each 128-wide block
+// (lo > hi for a block without any).
+__global__ void gm_block_ranges(int n, int nt, const double* __restrict__ omega,
+                                const uint8_t* __restrict__ phys, double* __restrict__ brange) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nt) return;
+  double lo = 1e300, hi = -1e300;
+  for (int k = 0; k < kMT; ++k) {
+    const int a = I * kMT + k;
+    if (a < n && phys[a]) {
+      lo = fmin(lo, omega[a]);
+      hi = fmax(hi, omega[a]);
+    }
+  }
+  brange[2 * I] = lo;
+  brange[2 * I + 1] = hi;
+}
+
+// Whether tile (I, J), I <= J, of mode frequency w can hold a pair that meets
+// the 2-sigma cut in either order (exact interval test on the block ranges).
+__device__ __forceinline__ bool gm_tile_live(const LwParams& p, double w, const double* brange,
+                                             int I, int J) {
+  const double lo1 = brange[2 * I], hi1 = brange[2 * I + 1];
+  const double lo2 = brange[2 * J], hi2 = brange[2 * J + 1];
+  if (!(lo1 <= hi1 && lo2 <= hi2)) return false;
+  const double reach = 2.0 * p.sig_fixed * (1.0 + 1e-12) + 1e-9;
+  auto can = [&](double l1, double h1, double l2, double h2) {
+    const bool cp = (w + l1 - h2) < reach && (w + h1 - l2) > -reach;
+    const bool cm = (w - h1 - h2) < reach && (w - l1 - l2) > -reach;
+    return cp || cm;
+  };
+  return can(lo1, hi1, lo2, hi2) || (I != J && can(lo2, hi2, lo1, hi1));
+}
+
+// need[jb][J] = 1 when some live tile (I <= J) of mode m0 + jb reads the W
+// columns of block J.
+__global__ void gm_need(LwParams p, int nt, int m0, int nb, const double* __restrict__ omega,
+                        const uint8_t* __restrict__ phys, const uint8_t* __restrict__ sel,
+                        const double* __restrict__ brange, uint8_t* __restrict__ need) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nb * nt) return;
+  const int jb = k / nt, J = k % nt;
+  const int mu = m0 + jb;
+  bool any = false;
+  if (sel[mu] && phys[mu])
+    for (int I = 0; I <= J; ++I) any = any || gm_tile_live(p, omega[mu], brange, I, J);
+  need[k] = any ? 1 : 0;
+}
+
 constexpr int kSpmmCols = 64;            // columns c' per workgroup
 constexpr int kSpmmModes = 16;           // modes per workgroup
 // WT[j][c'][b] = sum_{k in row b} A_mu_j[b][col_k] E[col_k][c'], for a tile of
@@ -86,10 +135,17 @@ __global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtil
                                                const float* __restrict__ avT,
                                                const double* __restrict__ E,
                                                float* __restrict__ wt32, __bf16* __restrict__ wth,
-                                               __bf16* __restrict__ wtl) {
+                                               __bf16* __restrict__ wtl, int nt,
+                                               const uint8_t* __restrict__ need) {
   extern __shared__ float4 es4[];
   float* es = reinterpret_cast<float*>(es4);  // [n_u][kSpmmCols]
   const int rt = blockIdx.x, c0 = blockIdx.y * kSpmmCols, j0 = blockIdx.z * kSpmmModes;
+  {
+    // columns no live GEMM tile of these modes reads are not computed
+    bool any = false;
+    for (int j = 0; j < kSpmmModes && j0 + j < nb; ++j) any = any || need[(j0 + j) * nt + c0 / kMT];
+    if (!any) return;
+  }
   const int b0 = rt * kSpmmRows;
   const bool has_rows = rt < n_rtiles;  // row tiles past the last row of A are zero
   const int u0 = has_rows ? tile_u_ptr[rt] : 0;
@@ -175,6 +231,7 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
                                                const double* __restrict__ occ,
                                                const uint8_t* __restrict__ phys,
                                                const uint8_t* __restrict__ sel,
+                                               const double* __restrict__ brange,
                                                double* __restrict__ partial) {
   constexpr int KT = SPLIT ? 32 : 16;
   // LDS rows padded to stagger banks
@@ -187,7 +244,6 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
   __shared__ __attribute__((aligned(16))) __bf16 sBh[SPLIT ? kMT * LDA16 : 8];
   __shared__ __attribute__((aligned(16))) __bf16 sBl[SPLIT ? kMT * LDA16 : 8];
   __shared__ double red[256];
-  __shared__ int skip;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nt = np / kMT;
@@ -195,33 +251,13 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
   const int jb = blockIdx.y;
   const int mu = m0 + jb;
   const int i0 = tt.ti * kMT, j0 = tt.tj * kMT;
+  const double w = omega[mu];
   double* out = partial + (size_t)mu * n_tri + blockIdx.x;
   if (!sel[mu] || !phys[mu]) {
     if (tid == 0) *out = 0.0;
     return;
   }
-  const double w = omega[mu];
-  if (tid == 0) {
-    double lo1 = 1e300, hi1 = -1e300, lo2 = 1e300, hi2 = -1e300;
-    for (int k = 0; k < kMT; ++k) {
-      const int a = i0 + k, b = j0 + k;
-      if (a < n && phys[a]) { lo1 = fmin(lo1, omega[a]); hi1 = fmax(hi1, omega[a]); }
-      if (b < n && phys[b]) { lo2 = fmin(lo2, omega[b]); hi2 = fmax(hi2, omega[b]); }
-    }
-    int sk = 1;
-    if (lo1 <= hi1 && lo2 <= hi2) {
-      const double reach = 2.0 * p.sig_fixed * (1.0 + 1e-12) + 1e-9;
-      auto can = [&](double l1, double h1, double l2, double h2) {
-        const bool cp = (w + l1 - h2) < reach && (w + h1 - l2) > -reach;
-        const bool cm = (w - h1 - h2) < reach && (w - l1 - l2) > -reach;
-        return cp || cm;
-      };
-      sk = !(can(lo1, hi1, lo2, hi2) || (tt.ti != tt.tj && can(lo2, hi2, lo1, hi1)));
-    }
-    skip = sk;
-  }
-  __syncthreads();
-  if (skip) {
+  if (!gm_tile_live(p, omega[mu], brange, tt.ti, tt.tj)) {  // uniform over the workgroup
     if (tid == 0) *out = 0.0;
     return;
   }
@@ -360,6 +396,8 @@ size_t gm_workspace_bytes(const kaldo_crystal* c, int prec) {
   take((size_t)c->gamma.n_bc * kMBatch * 4);  // avals
   take(split ? np * np * kMBatch * 2 * 2 : np * np * kMBatch * 4);  // W
   take(n * n_tri * 8);                     // partials
+  take(nt * 2 * 8);                        // block frequency ranges
+  take((size_t)kMBatch * nt);              // W column blocks needed per mode
   return o;
 }
 
@@ -394,7 +432,11 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
     wt32 = reinterpret_cast<float*>(take((size_t)np * np * kMBatch * 4));
   }
   double* partial = reinterpret_cast<double*>(take((size_t)n * n_tri * 8));
+  double* brange = reinterpret_cast<double*>(take((size_t)nt * 2 * 8));
+  uint8_t* need = reinterpret_cast<uint8_t*>(take((size_t)kMBatch * nt));
   const long nn = (long)np * np;
+  KALDO_LAUNCH("gm_block_ranges", gm_block_ranges, dim3((nt + 63) / 64), dim3(64), 0, st, n, nt, omega,
+               phys, brange);
   KALDO_LAUNCH("gm_prep_et", gm_prep_et, dim3((nn + 255) / 256), dim3(256), 0, st, n, np, evec,
                et32, eth, etl);
   for (int m0 = 0; m0 < n; m0 += kMBatch) {
@@ -402,16 +444,18 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
     const long na = (long)c->gamma.n_bc * kMBatch;
     KALDO_LAUNCH("gm_avals", gm_avals, dim3((na + 255) / 256), dim3(256), 0, st, n, c->gamma.n_bc,
                  m0, nb, c->gamma.t_ptr, c->gamma.t_a, c->gamma.t_coef, evec, av);
+    KALDO_LAUNCH("gm_need", gm_need, dim3((nb * nt + 255) / 256), dim3(256), 0, st, p, nt, m0, nb, omega,
+                 phys, sel, brange, need);
     const size_t spmm_lds = (size_t)c->gamma.max_u * kSpmmCols * sizeof(float);
     KALDO_LAUNCH("gm_spmm", gm_spmm, dim3(np / kSpmmRows, np / kSpmmCols, (nb + kSpmmModes - 1) / kSpmmModes),
                  dim3(256), spmm_lds, st, n, np, nb, c->gamma.n_rtiles, c->gamma.row_ptr,
-                 c->gamma.col_local, c->gamma.tile_u_ptr, c->gamma.tile_u, av, evec, wt32, wth, wtl);
+                 c->gamma.col_local, c->gamma.tile_u_ptr, c->gamma.tile_u, av, evec, wt32, wth, wtl, nt, need);
     if (split)
       KALDO_LAUNCH("gm_gemm_bf16x3", gm_gemm<true>, dim3(n_tri, nb), dim3(256), 0, st, p, n, np,
-                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, partial);
+                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, brange, partial);
     else
       KALDO_LAUNCH("gm_gemm_fp32", gm_gemm<false>, dim3(n_tri, nb), dim3(256), 0, st, p, n, np,
-                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, partial);
+                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, brange, partial);
   }
   KALDO_LAUNCH("gm_finish", gm_finish, dim3((n + 255) / 256), dim3(256), 0, st, n, n_tri, partial,
                phys, sel, gamma);

@@ -126,6 +126,8 @@ __device__ void sort_eigen(const double* lam_in, double* lam_out, cplx* V, cplx*
   __syncthreads();
 }
 
+constexpr int kPhaseCache = 128;  // replica phases kept in LDS per q
+
 template <int NMAX>
 __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const double* __restrict__ fc2s,
                                                      const int32_t* __restrict__ rep,
@@ -149,7 +151,9 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
   const double chat[3] = {1.0 / sqrt(14.0), 2.0 / sqrt(14.0), 3.0 / sqrt(14.0)};
 
   // D(q)[a][b] = sum_l e^{-i q.R_l} K[a][l][b] / sqrt(m_a m_b), Hermitised.
-  auto phase = [&](int l) {
+  // The replica phases are computed once per q (exact integer phase index)
+  // and kept in LDS for every matrix built below.
+  auto phase_of = [&](int l) {
     const int* r = rep + 3 * l;
     int m0 = ((nq0 * r[0]) % N0 + N0) % N0, m1 = ((nq1 * r[1]) % N1 + N1) % N1,
         m2 = ((nq2 * r[2]) % N2 + N2) % N2;
@@ -158,6 +162,10 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
     sincospi(-2.0 * f, &sn, &cs);
     return cplx{cs, sn};
   };
+  __shared__ cplx phl[kPhaseCache];
+  for (int l = lane; l < n_rep && l < kPhaseCache; l += 64) phl[l] = phase_of(l);
+  __syncthreads();
+  auto phase = [&](int l) { return l < kPhaseCache ? phl[l] : phase_of(l); };
   for (int k = lane; k < n * n; k += 64) {
     int a = k / n, b = k % n;
     cplx d1 = {0, 0}, d2 = {0, 0};
