@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
                                                double* __restrict__ partial) {
   constexpr int KT = SPLIT ? 32 : 16;
   // LDS rows padded to stagger banks
-  constexpr int LDA32 = KT + 1;        // floats
+  constexpr int LDA32 = KT + 4;        // floats (rows 16-byte aligned, reads conflict-free)
   constexpr int LDA16 = KT + 8;        // bf16 elements (row = 80 bytes)
   __shared__ __attribute__((aligned(16))) float sA32[SPLIT ? 1 : kMT * LDA32];
   __shared__ __attribute__((aligned(16))) float sB32[SPLIT ? 1 : kMT * LDA32];
@@ -271,14 +271,38 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // FP32 form: each thread moves two 16-byte pieces of both operands per
+  // slice, and the pieces of slice k0 + KT are loaded into registers while
+  // slice k0 is multiplied out of LDS.
+  constexpr int PPR = KT / 4;  // 16-byte pieces per row (FP32 form)
+  static_assert(SPLIT || kMT * PPR == 2 * 256, "two pieces per thread");
+  uint4 pa[2], pb[2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = tid + 256 * h;
+      const int r = idx / PPR, c = (idx % PPR) * 4;
+      pa[h] = *reinterpret_cast<const uint4*>(&et32[(size_t)(i0 + r) * np + k0 + c]);
+      pb[h] = *reinterpret_cast<const uint4*>(&wt32[wbase + (size_t)(j0 + r) * np + k0 + c]);
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = tid + 256 * h;
+      const int r = idx / PPR, c = (idx % PPR) * 4;
+      *reinterpret_cast<uint4*>(&sA32[r * LDA32 + c]) = pa[h];
+      *reinterpret_cast<uint4*>(&sB32[r * LDA32 + c]) = pb[h];
+    }
+  };
+  // (FP32 form only: with the four bf16 operands the extra registers cost
+  // more occupancy than the prefetch gains)
+  if constexpr (!SPLIT) fetch(0);
   for (int k0 = 0; k0 < np; k0 += KT) {
-    // stage 128 x KT of ET (rows i0..) and WT (rows j0..)
     if constexpr (!SPLIT) {
-      for (int idx = tid; idx < kMT * KT; idx += 256) {
-        const int r = idx / KT, c = idx % KT;
-        sA32[r * LDA32 + c] = et32[(size_t)(i0 + r) * np + k0 + c];
-        sB32[r * LDA32 + c] = wt32[wbase + (size_t)(j0 + r) * np + k0 + c];
-      }
+      stage();
+      __syncthreads();
+      if (k0 + KT < np) fetch(k0 + KT);
     } else {
       // 8 bf16 (16 bytes) per copy
       for (int idx = tid; idx < kMT * (KT / 8); idx += 256) {
@@ -290,8 +314,8 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
         *reinterpret_cast<uint4*>(&sBh[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&wth[gb]);
         *reinterpret_cast<uint4*>(&sBl[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&wtl[gb]);
       }
+      __syncthreads();
     }
-    __syncthreads();
     if constexpr (!SPLIT) {
 #pragma unroll
       for (int kk = 0; kk < KT; kk += 4) {
