@@ -120,6 +120,71 @@ __global__ void gm_need(LwParams p, int nt, int m0, int nb, const double* __rest
   need[k] = any ? 1 : 0;
 }
 
+struct GmTileInfo {
+  int ti, tj;
+};
+
+__device__ __forceinline__ GmTileInfo tri_tile(int t, int nt) {
+  // t-th tile of the upper triangle (ti <= tj), row-major
+  int ti = 0, rem = t;
+  while (rem >= nt - ti) {
+    rem -= nt - ti;
+    ++ti;
+  }
+  return {ti, ti + rem};
+}
+
+// Compacted list of the live (mode, tile) pairs of a batch, in (mode, tile)
+// order: list[k] = jb * n_tri + t.  One workgroup, fixed-order scan.
+__global__ __launch_bounds__(1024) void gm_live_list(LwParams p, int nt, int n_tri, int m0, int nb,
+                                                     const double* __restrict__ omega,
+                                                     const uint8_t* __restrict__ phys,
+                                                     const uint8_t* __restrict__ sel,
+                                                     const double* __restrict__ brange,
+                                                     int32_t* __restrict__ list,
+                                                     int32_t* __restrict__ count) {
+  __shared__ int wave_tot[16];
+  __shared__ int carry;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  const int total = nb * n_tri;
+  for (int base = 0; base < total; base += 1024) {
+    const int k = base + tid;
+    int f = 0;
+    if (k < total) {
+      const int jb = k / n_tri, t = k % n_tri;
+      const int mu = m0 + jb;
+      if (sel[mu] && phys[mu]) {
+        const GmTileInfo tt = tri_tile(t, nt);
+        f = gm_tile_live(p, omega[mu], brange, tt.ti, tt.tj) ? 1 : 0;
+      }
+    }
+    int incl = f;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wave_tot[wv] = incl;
+    __syncthreads();
+    int o = carry, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      o += (w < wv) ? wave_tot[w] : 0;
+      tot += wave_tot[w];
+    }
+    if (f) list[o + incl - 1] = k;
+    __syncthreads();
+    if (tid == 0) carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) *count = carry;
+}
+
+__global__ void gm_zero(long n, double* __restrict__ x) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) x[k] = 0.0;
+}
+
 constexpr int kSpmmCols = 64;            // columns c' per workgroup
 constexpr int kSpmmModes = 16;           // modes per workgroup
 // WT[j][c'][b] = sum_{k in row b} A_mu_j[b][col_k] E[col_k][c'], for a tile of
@@ -205,20 +270,6 @@ __global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtil
   }
 }
 
-struct GmTileInfo {
-  int ti, tj;
-};
-
-__device__ __forceinline__ GmTileInfo tri_tile(int t, int nt) {
-  // t-th tile of the upper triangle (ti <= tj), row-major
-  int ti = 0, rem = t;
-  while (rem >= nt - ti) {
-    rem -= nt - ti;
-    ++ti;
-  }
-  return {ti, ti + rem};
-}
-
 template <bool SPLIT>
 __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0, int n_tri,
                                                const float* __restrict__ et32,
@@ -232,6 +283,8 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
                                                const uint8_t* __restrict__ phys,
                                                const uint8_t* __restrict__ sel,
                                                const double* __restrict__ brange,
+                                               const int32_t* __restrict__ live_list,
+                                               const int32_t* __restrict__ live_count,
                                                double* __restrict__ partial) {
   constexpr int KT = SPLIT ? 32 : 16;
   // LDS rows padded to stagger banks
@@ -247,20 +300,16 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nt = np / kMT;
-  const GmTileInfo tt = tri_tile(blockIdx.x, nt);
-  const int jb = blockIdx.y;
+  // workgroup k takes the k-th live (mode, tile) pair; the rest of the grid
+  // (sized for every pair) exits at once
+  if ((int)blockIdx.x >= *live_count) return;
+  const int pair = live_list[blockIdx.x];
+  const int jb = pair / n_tri, t = pair % n_tri;
+  const GmTileInfo tt = tri_tile(t, nt);
   const int mu = m0 + jb;
   const int i0 = tt.ti * kMT, j0 = tt.tj * kMT;
   const double w = omega[mu];
-  double* out = partial + (size_t)mu * n_tri + blockIdx.x;
-  if (!sel[mu] || !phys[mu]) {
-    if (tid == 0) *out = 0.0;
-    return;
-  }
-  if (!gm_tile_live(p, omega[mu], brange, tt.ti, tt.tj)) {  // uniform over the workgroup
-    if (tid == 0) *out = 0.0;
-    return;
-  }
+  double* out = partial + (size_t)mu * n_tri + t;
 
   const size_t wbase = (size_t)jb * np * np;
   const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;  // wave block inside the tile
@@ -271,15 +320,16 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // FP32 form: each thread moves two 16-byte pieces of both operands per
+  // FP32 form: each thread moves NP 16-byte pieces of both operands per
   // slice, and the pieces of slice k0 + KT are loaded into registers while
   // slice k0 is multiplied out of LDS.
   constexpr int PPR = KT / 4;  // 16-byte pieces per row (FP32 form)
-  static_assert(SPLIT || kMT * PPR == 2 * 256, "two pieces per thread");
-  uint4 pa[2], pb[2];
+  constexpr int NP = kMT * PPR / 256;  // pieces per thread
+  static_assert(SPLIT || kMT * PPR == NP * 256, "whole pieces per thread");
+  uint4 pa[NP], pb[NP];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NP; ++h) {
       const int idx = tid + 256 * h;
       const int r = idx / PPR, c = (idx % PPR) * 4;
       pa[h] = *reinterpret_cast<const uint4*>(&et32[(size_t)(i0 + r) * np + k0 + c]);
@@ -288,7 +338,7 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
   };
   auto stage = [&]() {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NP; ++h) {
       const int idx = tid + 256 * h;
       const int r = idx / PPR, c = (idx % PPR) * 4;
       *reinterpret_cast<uint4*>(&sA32[r * LDA32 + c]) = pa[h];
@@ -422,6 +472,7 @@ size_t gm_workspace_bytes(const kaldo_crystal* c, int prec) {
   take(n * n_tri * 8);                     // partials
   take(nt * 2 * 8);                        // block frequency ranges
   take((size_t)kMBatch * nt);              // W column blocks needed per mode
+  take((size_t)kMBatch * n_tri * 4 + 4);   // live (mode, tile) list and its count
   return o;
 }
 
@@ -458,6 +509,10 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
   double* partial = reinterpret_cast<double*>(take((size_t)n * n_tri * 8));
   double* brange = reinterpret_cast<double*>(take((size_t)nt * 2 * 8));
   uint8_t* need = reinterpret_cast<uint8_t*>(take((size_t)kMBatch * nt));
+  int32_t* live_list = reinterpret_cast<int32_t*>(take((size_t)kMBatch * n_tri * 4 + 4));
+  int32_t* live_count = live_list + (size_t)kMBatch * n_tri;
+  const long n_part = (long)n * n_tri;
+  KALDO_LAUNCH("gm_zero", gm_zero, dim3((unsigned)((n_part + 255) / 256)), dim3(256), 0, st, n_part, partial);
   const long nn = (long)np * np;
   KALDO_LAUNCH("gm_block_ranges", gm_block_ranges, dim3((nt + 63) / 64), dim3(64), 0, st, n, nt, omega,
                phys, brange);
@@ -474,12 +529,16 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
     KALDO_LAUNCH("gm_spmm", gm_spmm, dim3(np / kSpmmRows, np / kSpmmCols, (nb + kSpmmModes - 1) / kSpmmModes),
                  dim3(256), spmm_lds, st, n, np, nb, c->gamma.n_rtiles, c->gamma.row_ptr,
                  c->gamma.col_local, c->gamma.tile_u_ptr, c->gamma.tile_u, av, evec, wt32, wth, wtl, nt, need);
+    KALDO_LAUNCH("gm_live_list", gm_live_list, dim3(1), dim3(1024), 0, st, p, nt, n_tri, m0, nb, omega,
+                 phys, sel, brange, live_list, live_count);
     if (split)
-      KALDO_LAUNCH("gm_gemm_bf16x3", gm_gemm<true>, dim3(n_tri, nb), dim3(256), 0, st, p, n, np,
-                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, brange, partial);
+      KALDO_LAUNCH("gm_gemm_bf16x3", gm_gemm<true>, dim3(n_tri * nb), dim3(256), 0, st, p, n, np,
+                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, brange,
+                   live_list, live_count, partial);
     else
-      KALDO_LAUNCH("gm_gemm_fp32", gm_gemm<false>, dim3(n_tri, nb), dim3(256), 0, st, p, n, np,
-                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, brange, partial);
+      KALDO_LAUNCH("gm_gemm_fp32", gm_gemm<false>, dim3(n_tri * nb), dim3(256), 0, st, p, n, np,
+                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, brange,
+                   live_list, live_count, partial);
   }
   KALDO_LAUNCH("gm_finish", gm_finish, dim3((n + 255) / 256), dim3(256), 0, st, n, n_tri, partial,
                phys, sel, gamma);
