@@ -131,6 +131,33 @@ __device__ __forceinline__ double pair_weight(const LwParams& p, double w, doubl
   return pop / (w * (w1 * w2));
 }
 
+// FP32 pre-classification of |x| < T against an FP64 reference: a_f is |x|
+// evaluated in FP32 from FP32-rounded frequencies, whose error is bounded by
+// 2u(|w| + |w1| + |w2|) (u = 2^-24); T_f = 2 sqrt(sigma^2) in FP32 is within
+// a few ulp of 2 sigma.  Candidates outside [lo, hi] are decided here with
+// certainty; the rest get the exact FP64 test.
+struct Band {
+  float lo, hi;
+};
+__device__ __forceinline__ Band make_band(double sig2, float scale_sum) {
+  const float t = 2.0f * sqrtf((float)sig2);
+  const float d = 4e-7f * scale_sum + 1e-9f;
+  return {t * (1.0f - 1e-6f) - d, t * (1.0f + 1e-6f) + d};
+}
+
+// The exact FP64 decision of the oracle: |(w + w1) - w2| < 2 sigma+ or
+// |(w - w1) - w2| < 2 sigma-, sigma = max(sqrt(S h^2/12), floor) (or fixed).
+__device__ __forceinline__ bool exact_pass(const LwParams& p, double w, double w1, double w2,
+                                        double Sp, double Sm, bool plus) {
+  double s;
+  if (!p.adaptive)
+    s = p.sig_fixed;
+  else
+    s = fmax(sqrt((plus ? Sp : Sm) * p.h2 / 12.0), p.sig_floor);
+  const double x = plus ? (w + w1) - w2 : (w - w1) - w2;
+  return fabs(x) < 2.0 * s;
+}
+
 // Sum over a wave64 in a fixed butterfly order; lane 0 holds the result.
 __device__ __forceinline__ double wave_sum_fixed(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -30,72 +30,109 @@ constexpr int kGateMaxRows = 4096;
 constexpr unsigned kSpinCap = 1u << 20;
 
 // ----------------------------------------------------------------- JDOS
-// One workgroup per q: D+-(q, s) = (1/N_q) sum_{q1, s', s''} m g(x+-) with the
-// exact FP64 cut of the linewidths; fixed-order reduction.
+// Workgroup (q, c) sums chunk c of the (q1, s') partners of every branch of q:
+// D+-(q, s) = (1/N_q) sum_{q1, s', s''} m g(x+-) with the exact FP64 cut of
+// the linewidths; fixed-order reductions within the chunk, then over chunks.
+constexpr int kJdosChunks = 8;
+
+template <int NBM>  // branches held per thread: 3 N_b <= NBM
 __global__ __launch_bounds__(kJdosThreads) void jdos_kernel(LwParams p, const double* __restrict__ omega,
                                                             const double* __restrict__ vel,
                                                             const uint8_t* __restrict__ phys,
                                                             const uint8_t* __restrict__ sel,
-                                                            double* __restrict__ dplus,
-                                                            double* __restrict__ dminus) {
+                                                            double* __restrict__ part) {
   __shared__ double red[kJdosThreads];
   const int NB3 = p.nb3;
-  const int q = blockIdx.x, tid = threadIdx.x;
+  const int q = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
   const int N0 = p.N[0], N1 = p.N[1], N2 = p.N[2];
   const int a0 = q / (N1 * N2), a1 = (q / N2) % N1, a2 = q % N2;
-  unsigned live = 0, any_sel = 0;
-  for (int s = 0; s < NB3; ++s) {
-    live |= (phys[q * NB3 + s] && sel[q * NB3 + s]) ? 1u << s : 0u;
-    any_sel |= sel[q * NB3 + s] ? 1u << s : 0u;
+  unsigned live = 0;
+  double wq[NBM];
+  float wqf[NBM];
+  float wq_abs_max = 0.0f;
+#pragma unroll
+  for (int s = 0; s < NBM; ++s) {
+    wq[s] = s < NB3 ? omega[q * NB3 + s] : 0.0;
+    wqf[s] = (float)wq[s];
+    wq_abs_max = fmaxf(wq_abs_max, fabsf(wqf[s]));
+    if (s < NB3) live |= (phys[q * NB3 + s] && sel[q * NB3 + s]) ? 1u << s : 0u;
   }
-  if (!any_sel) return;
-  double ap[16], am[16];
+  if (!live) return;
+  double ap[NBM], am[NBM];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) ap[s] = am[s] = 0.0;
-  if (live) {
-    for (int item = tid; item < p.nq * NB3; item += kJdosThreads) {
-      const int q1 = item / NB3, s1 = item % NB3;
-      const int m1 = q1 * NB3 + s1;
-      if (!phys[m1]) continue;
-      const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
-      const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
-                c2 = ((-a2 - b2) % N2 + N2) % N2;
-      const int q2 = (c0 * N1 + c1) * N2 + c2;
-      const double w1 = omega[m1];
-      for (int s2 = 0; s2 < NB3; ++s2) {
-        const int m2 = q2 * NB3 + s2;
-        if (!phys[m2]) continue;
-        const double w2 = omega[m2];
-        double sp, sm;
-        widths(p, vel, m1, m2, sp, sm);
+  for (int s = 0; s < NBM; ++s) ap[s] = am[s] = 0.0;
+  const int n_items = p.nq * NB3;
+  const int per = (n_items + kJdosChunks - 1) / kJdosChunks;
+  const int lo = chunk * per, hi = min(n_items, lo + per);
+  for (int item = lo + tid; item < hi; item += kJdosThreads) {
+    const int q1 = item / NB3, s1 = item % NB3;
+    const int m1 = q1 * NB3 + s1;
+    if (!phys[m1]) continue;
+    const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
+    const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
+              c2 = ((-a2 - b2) % N2 + N2) % N2;
+    const int q2 = (c0 * N1 + c1) * N2 + c2;
+    const double w1 = omega[m1];
+    const double* v1 = vel + 3 * (size_t)m1;
+    for (int s2 = 0; s2 < NB3; ++s2) {
+      const int m2 = q2 * NB3 + s2;
+      if (!phys[m2]) continue;
+      const double w2 = omega[m2];
+      // FP32 pre-classification (the band of the linewidth kernels); the
+      // exact FP64 cut of the oracle decides inside the band, and g is
+      // evaluated in FP64 for the pairs that pass
+      double s2p, s2m, Sp, Sm;
+      widths2(p, v1, vel + 3 * (size_t)m2, s2p, s2m, Sp, Sm);
+      const float scl = wq_abs_max + fabsf((float)w1) + fabsf((float)w2);
+      const Band bp = make_band(s2p, scl), bm = make_band(s2m, scl);
+      const float cp = (float)(w1 - w2), cm = (float)(-w1 - w2);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          if (s >= NB3 || !(live >> s & 1u)) continue;
-          const double w = omega[q * NB3 + s];
-          const double xp = (w + w1) - w2, xm = (w - w1) - w2;
-          if (fabs(xp) < 2.0 * sp) ap[s] += smear(p.shape, xp, sp);
-          if (fabs(xm) < 2.0 * sm) am[s] += smear(p.shape, xm, sm);
+      for (int s = 0; s < NBM; ++s) {
+        if (s >= NB3 || !(live >> s & 1u)) continue;
+        const float fp = fabsf(wqf[s] + cp), fm = fabsf(wqf[s] + cm);
+        if (fp < bp.hi && (fp < bp.lo || exact_pass(p, wq[s], w1, w2, Sp, Sm, true))) {
+          const double sg = p.adaptive ? fmax(sqrt(Sp * p.h2 / 12.0), p.sig_floor) : p.sig_fixed;
+          ap[s] += smear(p.shape, (wq[s] + w1) - w2, sg);
+        }
+        if (fm < bm.hi && (fm < bm.lo || exact_pass(p, wq[s], w1, w2, Sp, Sm, false))) {
+          const double sg = p.adaptive ? fmax(sqrt(Sm * p.h2 / 12.0), p.sig_floor) : p.sig_fixed;
+          am[s] += smear(p.shape, (wq[s] - w1) - w2, sg);
         }
       }
     }
   }
+  double* out = part + ((size_t)q * kJdosChunks + chunk) * 32;
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
+  for (int s = 0; s < NBM; ++s) {
     if (s >= NB3) break;
-    for (int part = 0; part < 2; ++part) {
+    for (int which = 0; which < 2; ++which) {
       __syncthreads();
-      red[tid] = part ? am[s] : ap[s];
+      red[tid] = which ? am[s] : ap[s];
       __syncthreads();
       for (int w = kJdosThreads / 2; w > 0; w >>= 1) {
         if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
       }
-      if (tid == 0 && (any_sel >> s & 1u)) {
-        const double v = (live >> s & 1u) ? red[0] / p.nq : 0.0;
-        (part ? dminus : dplus)[q * NB3 + s] = v;
-      }
+      if (tid == 0) out[2 * s + which] = red[0];
     }
   }
+}
+
+// D+- of the selected modes: the chunk sums in chunk order, / N_q; 0 below nu_min.
+__global__ void jdos_finish(int n_modes, int nb3, int nq, const uint8_t* __restrict__ phys,
+                            const uint8_t* __restrict__ sel, const double* __restrict__ part,
+                            double* __restrict__ dplus, double* __restrict__ dminus) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_modes || !sel[m]) return;
+  const int q = m / nb3, s = m % nb3;
+  double sp = 0.0, sm = 0.0;
+  if (phys[m])
+    for (int c = 0; c < kJdosChunks; ++c) {
+      sp += part[((size_t)q * kJdosChunks + c) * 32 + 2 * s];
+      sm += part[((size_t)q * kJdosChunks + c) * 32 + 2 * s + 1];
+    }
+  dplus[m] = phys[m] ? sp / nq : 0.0;
+  dminus[m] = phys[m] ? sm / nq : 0.0;
 }
 
 __global__ void jdos_prepare(int n_modes, const double* __restrict__ omega, double nu_min,
@@ -903,8 +940,9 @@ using namespace kaldo;
 
 extern "C" size_t kaldo_jdos_workspace(const kaldo_crystal* c, const int32_t* mesh) {
   if (!c || !mesh || mesh[0] < 1 || mesh[1] < 1 || mesh[2] < 1) return 0;
-  const size_t nm = (size_t)mesh[0] * mesh[1] * mesh[2] * c->nb3;
-  return (nm + 255) / 256 * 256 * 2;
+  const size_t nq = (size_t)mesh[0] * mesh[1] * mesh[2];
+  const size_t nm = nq * c->nb3;
+  return (nm + 255) / 256 * 256 * 2 + nq * kJdosChunks * 32 * sizeof(double);
 }
 
 extern "C" int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
@@ -922,8 +960,10 @@ extern "C" int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const dou
   if (modes_subset && n_subset == 0) return KALDO_OK;
   const int nq = mesh[0] * mesh[1] * mesh[2];
   const int nm = nq * c->nb3;
+  const size_t flags = ((size_t)nm + 255) / 256 * 256;
   auto* phys = static_cast<uint8_t*>(workspace);
-  uint8_t* sel = phys + need / 2;
+  uint8_t* sel = phys + flags;
+  auto* part = reinterpret_cast<double*>(phys + 2 * flags);
   hipStream_t st = static_cast<hipStream_t>(stream);
   KALDO_LAUNCH("jdos_prepare", jdos_prepare, dim3((nm + 255) / 256), dim3(256), 0, st, nm, omega,
                b->nu_min_thz, phys, sel, modes_subset ? 0 : 1);
@@ -931,8 +971,14 @@ extern "C" int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const dou
     KALDO_LAUNCH("jdos_select", jdos_select, dim3((unsigned)((n_subset + 255) / 256)), dim3(256), 0,
                  st, modes_subset, (long)n_subset, nm, sel);
   const LwParams p = make_params(c, mesh, 300.0, b);
-  KALDO_LAUNCH("jdos_kernel", jdos_kernel, dim3(nq), dim3(kJdosThreads), 0, st, p, omega, vel, phys,
-               sel, dplus, dminus);
+  if (c->nb3 <= 8)
+    KALDO_LAUNCH("jdos_kernel", jdos_kernel<8>, dim3(nq, kJdosChunks), dim3(kJdosThreads), 0, st, p,
+                 omega, vel, phys, sel, part);
+  else
+    KALDO_LAUNCH("jdos_kernel", jdos_kernel<16>, dim3(nq, kJdosChunks), dim3(kJdosThreads), 0, st, p,
+                 omega, vel, phys, sel, part);
+  KALDO_LAUNCH("jdos_finish", jdos_finish, dim3((nm + 255) / 256), dim3(256), 0, st, nm, c->nb3, nq, phys,
+               sel, part, dplus, dminus);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
 }
