@@ -224,15 +224,19 @@ __global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtil
   const int b = b0 + lane;
   const int k_lo = (has_rows && b < n) ? row_ptr[b] : 0;
   const int k_hi = (has_rows && b < n) ? row_ptr[b + 1] : 0;
-  for (int xc = 0; xc < kSpmmCols / 4 / 4; ++xc) {
-    const int x0 = wv * (kSpmmCols / 4) + 4 * xc;
-    float acc[4][kSpmmModes];
+  // each wave: 16 columns in two passes of 8 (8 x 16 accumulators), so every
+  // nonzero's 16 mode values are loaded twice per column tile
+  constexpr int XW = 8;
+  for (int xc = 0; xc < kSpmmCols / 4 / XW; ++xc) {
+    const int x0 = wv * (kSpmmCols / 4) + XW * xc;
+    float acc[XW][kSpmmModes];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < XW; ++x)
 #pragma unroll
       for (int j = 0; j < kSpmmModes; ++j) acc[x][j] = 0.0f;
     for (int k = k_lo; k < k_hi; ++k) {
-      const float4 e = *reinterpret_cast<const float4*>(&es[col_local[k] * kSpmmCols + x0]);
+      const float4* ep = reinterpret_cast<const float4*>(&es[col_local[k] * kSpmmCols + x0]);
+      const float4 e0 = ep[0], e1 = ep[1];
       const float4* ap = reinterpret_cast<const float4*>(avT + (size_t)k * kMBatch + j0);
       float a[kSpmmModes];
 #pragma unroll
@@ -245,17 +249,21 @@ __global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtil
       }
 #pragma unroll
       for (int j = 0; j < kSpmmModes; ++j) {
-        acc[0][j] += a[j] * e.x;
-        acc[1][j] += a[j] * e.y;
-        acc[2][j] += a[j] * e.z;
-        acc[3][j] += a[j] * e.w;
+        acc[0][j] += a[j] * e0.x;
+        acc[1][j] += a[j] * e0.y;
+        acc[2][j] += a[j] * e0.z;
+        acc[3][j] += a[j] * e0.w;
+        acc[4][j] += a[j] * e1.x;
+        acc[5][j] += a[j] * e1.y;
+        acc[6][j] += a[j] * e1.z;
+        acc[7][j] += a[j] * e1.w;
       }
     }
 #pragma unroll
     for (int j = 0; j < kSpmmModes; ++j) {
       if (j0 + j >= nb) break;
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
+      for (int x = 0; x < XW; ++x) {
         const size_t g = ((size_t)(j0 + j) * np + c0 + x0 + x) * np + b;
         const float v = acc[x][j];
         if (wt32) wt32[g] = v;
