@@ -298,8 +298,8 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
   // LDS rows padded to stagger banks
   constexpr int LDA32 = KT + 4;        // floats (rows 16-byte aligned, reads conflict-free)
   constexpr int LDA16 = KT + 8;        // bf16 elements (row = 80 bytes)
-  __shared__ __attribute__((aligned(16))) float sA32[SPLIT ? 1 : kMT * LDA32];
-  __shared__ __attribute__((aligned(16))) float sB32[SPLIT ? 1 : kMT * LDA32];
+  __shared__ __attribute__((aligned(16))) float sA32[SPLIT ? 1 : 2 * kMT * LDA32];  // two buffers
+  __shared__ __attribute__((aligned(16))) float sB32[SPLIT ? 1 : 2 * kMT * LDA32];
   __shared__ __attribute__((aligned(16))) __bf16 sAh[SPLIT ? kMT * LDA16 : 8];
   __shared__ __attribute__((aligned(16))) __bf16 sAl[SPLIT ? kMT * LDA16 : 8];
   __shared__ __attribute__((aligned(16))) __bf16 sBh[SPLIT ? kMT * LDA16 : 8];
@@ -329,8 +329,7 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
     for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
   // FP32 form: each thread moves NP 16-byte pieces of both operands per
-  // slice, and the pieces of slice k0 + KT are loaded into registers while
-  // slice k0 is multiplied out of LDS.
+  // slice.
   constexpr int PPR = KT / 4;  // 16-byte pieces per row (FP32 form)
   constexpr int NP = kMT * PPR / 256;  // pieces per thread
   static_assert(SPLIT || kMT * PPR == NP * 256, "whole pieces per thread");
@@ -344,24 +343,47 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
       pb[h] = *reinterpret_cast<const uint4*>(&wt32[wbase + (size_t)(j0 + r) * np + k0 + c]);
     }
   };
-  auto stage = [&]() {
+  auto stage = [&](int buf) {
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
       const int idx = tid + 256 * h;
       const int r = idx / PPR, c = (idx % PPR) * 4;
-      *reinterpret_cast<uint4*>(&sA32[r * LDA32 + c]) = pa[h];
-      *reinterpret_cast<uint4*>(&sB32[r * LDA32 + c]) = pb[h];
+      *reinterpret_cast<uint4*>(&sA32[buf * kMT * LDA32 + r * LDA32 + c]) = pa[h];
+      *reinterpret_cast<uint4*>(&sB32[buf * kMT * LDA32 + r * LDA32 + c]) = pb[h];
     }
   };
-  // (FP32 form only: with the four bf16 operands the extra registers cost
-  // more occupancy than the prefetch gains)
-  if constexpr (!SPLIT) fetch(0);
-  for (int k0 = 0; k0 < np; k0 += KT) {
-    if constexpr (!SPLIT) {
-      stage();
+  if constexpr (!SPLIT) {
+    // two LDS buffers: slice k0 + KT is fetched into registers and staged into
+    // the idle buffer while slice k0 is multiplied; one barrier per slice
+    fetch(0);
+    stage(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < np; k0 += KT) {
+      const bool more = k0 + KT < np;
+      if (more) fetch(k0 + KT);
+      const float* A = sA32 + cur * kMT * LDA32;
+      const float* B = sB32 + cur * kMT * LDA32;
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += 4) {
+        float a[4], b[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a[t] = A[(wm + 16 * t + lr) * LDA32 + kk + lg];
+          b[t] = B[(wn + 16 * t + lr) * LDA32 + kk + lg];
+        }
+#pragma unroll
+        for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+          for (int tb = 0; tb < 4; ++tb)
+            acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
+      }
+      if (more) stage(cur ^ 1);
       __syncthreads();
-      if (k0 + KT < np) fetch(k0 + KT);
-    } else {
+      cur ^= 1;
+    }
+  } else {
+    for (int k0 = 0; k0 < np; k0 += KT) {
       // 8 bf16 (16 bytes) per copy
       for (int idx = tid; idx < kMT * (KT / 8); idx += 256) {
         const int r = idx / (KT / 8), c = (idx % (KT / 8)) * 8;
@@ -373,23 +395,6 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
         *reinterpret_cast<uint4*>(&sBl[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&wtl[gb]);
       }
       __syncthreads();
-    }
-    if constexpr (!SPLIT) {
-#pragma unroll
-      for (int kk = 0; kk < KT; kk += 4) {
-        float a[4], b[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          a[t] = sA32[(wm + 16 * t + lr) * LDA32 + kk + lg];
-          b[t] = sB32[(wn + 16 * t + lr) * LDA32 + kk + lg];
-        }
-#pragma unroll
-        for (int ta = 0; ta < 4; ++ta)
-#pragma unroll
-          for (int tb = 0; tb < 4; ++tb)
-            acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
-      }
-    } else {
       bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -408,8 +413,8 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
           acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ta], bl[tb], acc[ta][tb], 0, 0, 0);
           acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ta], bh[tb], acc[ta][tb], 0, 0, 0);
         }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   // Epilogue: lane holds V[m = row0 + 4*lg + r][n = col0 + lr] of each 16 x 16 tile.
