@@ -212,17 +212,25 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         const float scl = wq_abs_max + fabsf((float)w1) + fabsf((float)w2);
         const Band bp = make_band(s2p, scl), bm = make_band(s2m, scl);
         const float cp = (float)(w1 - w2), cm = (float)(-w1 - w2);
-        unsigned b = 0;
+        // certain passes and the ambiguous band for all branches first
+        // (branch-free); the exact FP64 test only for the rare band members
+        unsigned b = 0, amb_p = 0, amb_m = 0;
 #pragma unroll
         for (int s = 0; s < NB3; ++s) {
           const float ap = fabsf(wqf[s] + cp), am = fabsf(wqf[s] + cm);
-          bool pass = (ap < bp.lo) || (am < bm.lo);
-          if (!pass && ((ap < bp.hi) || (am < bm.hi))) {
-            pass = ((ap < bp.hi) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, true)) ||
-                   ((am < bm.hi) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, false));
-          }
-          b |= (pass && (live >> s & 1u)) ? (1u << s) : 0u;
+          b |= ((ap < bp.lo) || (am < bm.lo)) ? (1u << s) : 0u;
+          amb_p |= (ap < bp.hi) ? (1u << s) : 0u;
+          amb_m |= (am < bm.hi) ? (1u << s) : 0u;
         }
+        unsigned amb = (amb_p | amb_m) & ~b & live;
+        while (amb) {
+          const int s = __ffs(amb) - 1;
+          amb &= amb - 1;
+          const bool pass = ((amb_p >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, true)) ||
+                            ((amb_m >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, false));
+          b |= pass ? (1u << s) : 0u;
+        }
+        b &= live;
         bits[s2] = b;
         count += __popc(b);
       }
