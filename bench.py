@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--cpu-sample-q", type=int, default=200)
     ap.add_argument("--form", default="plain", choices=["plain", "learned"],
                     help="learned: the learned form against plain FP32 (full mesh and wedge)")
-    ap.add_argument("--train-steps", type=int, default=500)
+    ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -208,7 +208,7 @@ def bench_learned(a, cfg, model, c, K, torch):
             state["draws"] = D.surrogate_draws(len(cand), K.surrogate_feature_count(c), members=5,
                                                seed=0)
         res = L.learned_linewidths(c, wedge, om, ev, ve, T, b, cand, state["draws"],
-                                   steps=a.train_steps, lr=1e-2, tol=0.01)
+                                   steps=a.train_steps, lr=2e-2, tol=0.01)
         K.kappa_rta(c, mesh, om, ve, res.gamma, T, b.nu_min_thz, out=kap)
         state["res"] = res
         return kap.clone()

@@ -24,7 +24,8 @@ constexpr int kMlpDepth = 4;
 constexpr int kMlpMaxIn = 32;
 constexpr int kMlpMaxMembers = 16;
 constexpr int kJdosThreads = 256;
-constexpr int kTrainThreads = 256;
+constexpr int kTrainWaves = 8;
+constexpr int kTrainThreads = 64 * kTrainWaves;
 constexpr int kPredRows = 16;
 constexpr int kGateMaxRows = 4096;
 constexpr unsigned kSpinCap = 1u << 20;
@@ -322,18 +323,48 @@ __host__ __device__ inline LdsLayout lds_layout(int n_in) {
   return o;
 }
 
-__device__ inline void load_params_lds(const float* __restrict__ g, float* __restrict__ s, int n_in,
-                                       const MlpLayout& gl, const LdsLayout& sl) {
-  for (int l = 0; l < kMlpDepth; ++l) {
-    const int fan_in = l == 0 ? n_in : kMlpHidden;
-    for (int idx = threadIdx.x; idx < fan_in * kMlpHidden; idx += blockDim.x) {
-      const int k = idx >> 6, j = idx & 63;
-      s[sl.W[l] + k * kRowPad + j] = g[gl.W[l] + idx];
-    }
-    for (int j = threadIdx.x; j < kMlpHidden; j += blockDim.x) s[sl.b[l] + j] = g[gl.b[l] + j];
+// Padded copy of one member's parameters in the training workspace: the
+// flat layout above followed by zeros up to a multiple of 64 floats (and at
+// least 3 past P), so that every float4 of it is aligned and lies inside one
+// weight row or bias of the flat layout.
+__host__ __device__ inline int padded_params(int P) { return (P + 3 + 63) / 64 * 64; }
+constexpr int kMaxParams = (kMlpMaxIn + 1) * kMlpHidden + (kMlpDepth - 1) * (kMlpHidden + 1) * kMlpHidden +
+                           kMlpHidden + 1;
+constexpr int kLoadIters = ((kMaxParams + 3) / 4 + kTrainThreads - 1) / kTrainThreads;
+
+// Padded parameters -> LDS layout.  Every load is issued before the first
+// LDS store, so the whole vector is in flight at once.
+__device__ inline void load_params_lds4(const float* __restrict__ g, float* __restrict__ s,
+                                        const MlpLayout& gl, const LdsLayout& sl) {
+  const int P = gl.P, n4 = (P + 3) >> 2;
+  float4 v[kLoadIters];
+#pragma unroll
+  for (int i = 0; i < kLoadIters; ++i) {
+    const int q = threadIdx.x + i * kTrainThreads;
+    v[i] = q < n4 ? reinterpret_cast<const float4*>(g)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  // the head's weights and bias are contiguous in both layouts
-  for (int k = threadIdx.x; k <= kMlpHidden; k += blockDim.x) s[sl.W[kMlpDepth] + k] = g[gl.W[kMlpDepth] + k];
+#pragma unroll
+  for (int i = 0; i < kLoadIters; ++i) {
+    const int f = 4 * (threadIdx.x + i * kTrainThreads);
+    if (f < P) {
+      int l = 0;
+#pragma unroll
+      for (int t = 1; t <= kMlpDepth; ++t) l += f >= gl.W[t];
+      int dst;
+      if (l == kMlpDepth) {
+        dst = sl.W[kMlpDepth] + (f - gl.W[kMlpDepth]);  // head weights and bias, contiguous
+      } else if (f < gl.b[l]) {
+        const int r = f - gl.W[l];
+        dst = sl.W[l] + (r >> 6) * kRowPad + (r & 63);
+      } else {
+        dst = sl.b[l] + (f - gl.b[l]);
+      }
+      s[dst] = v[i].x;
+      if (f + 1 < P) s[dst + 1] = v[i].y;
+      if (f + 2 < P) s[dst + 2] = v[i].z;
+      if (f + 3 < P) s[dst + 3] = v[i].w;
+    }
+  }
 }
 
 __device__ __forceinline__ float wave_sum_f(float v) {
@@ -383,10 +414,12 @@ struct TrainArgs {
   const float* X;       // [n][n_in]
   const float* y;       // [n]
   const float* counts;  // [M][n]
-  float* params;        // [M][P]
-  float* m1;            // [M][P]
-  float* m2;            // [M][P]
-  float* partial;       // [M][G][P]
+  float* params;        // [M][P] caller's parameters, read at start, written every step
+  int Pp;               // padded parameter stride of the workspace arrays
+  float* wp;            // [M][Pp] padded working copy of the parameters
+  float* m1;            // [M][Pp]
+  float* m2;            // [M][Pp]
+  float* partial;       // [M][G][Pp]
   float* lpart;         // [M][G]
   float* losses;        // [M][steps] or null
   float* grad_out;      // [M][P] or null: reduced gradient of the last step
@@ -397,15 +430,17 @@ struct TrainArgs {
 constexpr int kBarStride = 32;  // 128 bytes between member counters
 constexpr int kMaxGroups = 32;  // partial gradients reduced from registers
 
-// Workgroup (g, mem) holds sample rows [g S, g S + S) of member mem.  Each
-// step: forward and backward of its rows with the parameters in LDS, partial
-// gradient to global, grid barrier; then workgroup g reduces the partial
-// gradients of its parameter slice over the G workgroups (fixed order) and
-// applies Adam; grid barrier.
+// Workgroup (g, mem) holds sample rows [g S, g S + S) of member mem and owns
+// slice g of its padded parameter vector (whole float4s).  Each step: the
+// padded parameters into LDS, forward and backward of its rows, partial
+// gradient to global, member barrier; then workgroup g reduces the partial
+// gradients of its slice over the G workgroups (fixed order, float4 loads
+// all in flight) and applies Adam; member barrier.
 template <int S>
 __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
   constexpr int H = kMlpHidden;
-  constexpr int RPW = S / 4;  // rows per wave
+  constexpr int RPW = S / kTrainWaves;  // rows per wave
+  static_assert(RPW >= 1 && RPW * kTrainWaves == S, "rows per workgroup");
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   __shared__ int ok_s;
@@ -427,9 +462,12 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
   const unsigned nblk = gridDim.x;
   unsigned bar_target = 0;
   const int row0 = g * S;
-  float* gpart = a.partial + ((size_t)mem * G + g) * P;
+  const int Pp = a.Pp;
+  float* gpart = a.partial + ((size_t)mem * G + g) * Pp;
   const float* cnt = a.counts + (size_t)mem * n;
-  float* gp = a.params + (size_t)mem * P;
+  float* wp = a.wp + (size_t)mem * Pp;
+  float* m1 = a.m1 + (size_t)mem * Pp;
+  float* m2 = a.m2 + (size_t)mem * Pp;
 
   // constant inputs of this workgroup and the member's count sum
   for (int idx = tid; idx < S * kMlpMaxIn; idx += kTrainThreads) {
@@ -451,18 +489,27 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
   }
   const float inv_csum = 1.0f / red_s[0];
   __syncthreads();
-  // Adam moments of this workgroup's parameter slice start at zero
-  const int chunk = (P + G - 1) / G;
-  const int p_lo = min(P, g * chunk), p_hi = min(P, p_lo + chunk);
-  for (int p = p_lo + tid; p < p_hi; p += kTrainThreads) {
-    a.m1[(size_t)mem * P + p] = 0.f;
-    a.m2[(size_t)mem * P + p] = 0.f;
+  // this workgroup's slice of float4s: parameters copied in (zero padding),
+  // Adam moments zero; a barrier publishes the whole padded vector
+  const int n4 = Pp / 4, chunk = (n4 + G - 1) / G;
+  const int q_lo = min(n4, g * chunk), q_hi = min(n4, q_lo + chunk);
+  const float* gp = a.params + (size_t)mem * P;
+  for (int q = q_lo + tid; q < q_hi; q += kTrainThreads) {
+    const int p = 4 * q;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 v = make_float4(p < P ? gp[p] : 0.f, p + 1 < P ? gp[p + 1] : 0.f,
+                                 p + 2 < P ? gp[p + 2] : 0.f, p + 3 < P ? gp[p + 3] : 0.f);
+    reinterpret_cast<float4*>(wp)[q] = v;
+    reinterpret_cast<float4*>(m1)[q] = z;
+    reinterpret_cast<float4*>(m2)[q] = z;
   }
+  bar_target += nblk;
+  if (!member_barrier(bar, a.abort_flag, bar_target, &ok_s)) return;
   float b1t = 1.f, b2t = 1.f;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
 
   for (int step = 0; step < a.steps; ++step) {
-    load_params_lds(gp, prm, n_in, gl, sl);
+    load_params_lds4(wp, prm, gl, sl);
     __syncthreads();
     // forward: a_{l+1} = tanh(a_l W_l + b_l); lane = output unit, wave = rows
     for (int l = 0; l < kMlpDepth; ++l) {
@@ -480,7 +527,7 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
         const float w2 = W[(k + 2) * kRowPad + lane], w3 = W[(k + 3) * kRowPad + lane];
 #pragma unroll
         for (int u = 0; u < RPW; ++u) {
-          const float4 av = *reinterpret_cast<const float4*>(A + (wv + 4 * u) * lda + k);
+          const float4 av = *reinterpret_cast<const float4*>(A + (wv + kTrainWaves * u) * lda + k);
           acc[u] += av.x * w0;
           acc[u] += av.y * w1;
           acc[u] += av.z * w2;
@@ -490,11 +537,11 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
       for (; k < K; ++k) {
         const float w = W[k * kRowPad + lane];
 #pragma unroll
-        for (int u = 0; u < RPW; ++u) acc[u] += A[(wv + 4 * u) * lda + k] * w;
+        for (int u = 0; u < RPW; ++u) acc[u] += A[(wv + kTrainWaves * u) * lda + k] * w;
       }
       float* Z = hs + l * S * H;
 #pragma unroll
-      for (int u = 0; u < RPW; ++u) Z[(wv + 4 * u) * H + lane] = tanhf(acc[u]);
+      for (int u = 0; u < RPW; ++u) Z[(wv + kTrainWaves * u) * H + lane] = tanhf(acc[u]);
       __syncthreads();
     }
     // head, loss and output delta
@@ -504,7 +551,7 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
     float lsum = 0.f;
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
-      const int i = wv + 4 * u;
+      const int i = wv + kTrainWaves * u;
       const float o = wave_sum_f(a4[i * H + lane] * w4) + b4;
       if (lane == 0) {
         const float c = cy[2 * i];
@@ -515,7 +562,12 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
     }
     if (lane == 0) red_s[wv] = lsum;
     __syncthreads();
-    if (tid == 0) a.lpart[(size_t)mem * G + g] = ((red_s[0] + red_s[1]) + red_s[2]) + red_s[3];
+    if (tid == 0) {
+      float t = 0.f;
+#pragma unroll
+      for (int w = 0; w < kTrainWaves; ++w) t += red_s[w];
+      a.lpart[(size_t)mem * G + g] = t;
+    }
     // head gradient, and delta_3 = od W4 (1 - a4^2)
     if (tid < H) {
       float s = 0.f;
@@ -528,7 +580,7 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
     }
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
-      const int i = wv + 4 * u;
+      const int i = wv + kTrainWaves * u;
       const float av = a4[i * H + lane];
       d0[i * H + lane] = od[i] * w4 * (1.f - av * av);
     }
@@ -541,7 +593,7 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
       const int lda = l == 0 ? kMlpMaxIn : H;
       // dW_l[k][j] = sum_i a_l[i][k] delta_l[i][j]   (lane = j; waves take
       // blocks of four k; input columns past K are read but never stored)
-      for (int k0 = 4 * wv; k0 < K; k0 += 16) {
+      for (int k0 = 4 * wv; k0 < K; k0 += 4 * kTrainWaves) {
         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
         for (int i = 0; i < S; ++i) {
           const float dv = dc[i * H + lane];
@@ -573,7 +625,7 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
           const float w2 = W[lane * kRowPad + j + 2], w3 = W[lane * kRowPad + j + 3];
 #pragma unroll
           for (int u = 0; u < RPW; ++u) {
-            const float4 dv = *reinterpret_cast<const float4*>(dc + (wv + 4 * u) * H + j);
+            const float4 dv = *reinterpret_cast<const float4*>(dc + (wv + kTrainWaves * u) * H + j);
             acc[u] += dv.x * w0;
             acc[u] += dv.y * w1;
             acc[u] += dv.z * w2;
@@ -582,7 +634,7 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < RPW; ++u) {
-          const int i = wv + 4 * u;
+          const int i = wv + kTrainWaves * u;
           const float av = A[i * H + lane];
           dn[i * H + lane] = acc[u] * (1.f - av * av);
         }
@@ -595,29 +647,49 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
     bar_target += nblk;
     if (!member_barrier(bar, a.abort_flag, bar_target, &ok_s)) return;
     // reduce the partial gradients of this slice in workgroup order and step
-    // Adam; all loads of one parameter are issued before the sums
+    // Adam; all loads of one float4 are issued before the sums.  Padding
+    // entries (p >= P) keep a zero gradient and stay zero.
     b1t *= b1;
     b2t *= b2;
     const float c1 = 1.f / (1.f - b1t), c2 = 1.f / (1.f - b2t);
-    for (int p = p_lo + tid; p < p_hi; p += kTrainThreads) {
-      const size_t ip = (size_t)mem * P + p;
-      const float mo = a.m1[ip], vo = a.m2[ip], po = a.params[ip];
-      float s = 0.f;
+    for (int q = q_lo + tid; q < q_hi; q += kTrainThreads) {
+      const float4 mo = reinterpret_cast<const float4*>(m1)[q];
+      const float4 vo = reinterpret_cast<const float4*>(m2)[q];
+      const float4 po = reinterpret_cast<const float4*>(wp)[q];
+      float sg[4] = {0.f, 0.f, 0.f, 0.f};
       for (int h0 = 0; h0 < G; h0 += kMaxGroups) {
-        float v[kMaxGroups];
+        float4 v[kMaxGroups];
 #pragma unroll
         for (int j = 0; j < kMaxGroups; ++j)
-          v[j] = h0 + j < G ? a.partial[((size_t)mem * G + h0 + j) * P + p] : 0.f;
+          v[j] = h0 + j < G ? reinterpret_cast<const float4*>(a.partial + ((size_t)mem * G + h0 + j) * Pp)[q]
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int j = 0; j < kMaxGroups; ++j)
-          if (h0 + j < G) s += v[j];
+          if (h0 + j < G) {
+            sg[0] += v[j].x;
+            sg[1] += v[j].y;
+            sg[2] += v[j].z;
+            sg[3] += v[j].w;
+          }
       }
-      const float m = b1 * mo + (1.f - b1) * s;
-      const float v = b2 * vo + (1.f - b2) * s * s;
-      a.m1[ip] = m;
-      a.m2[ip] = v;
-      a.params[ip] = po - a.lr * (m * c1) / (sqrtf(v * c2) + eps);
-      if (a.grad_out) a.grad_out[ip] = s;
+      const float mov[4] = {mo.x, mo.y, mo.z, mo.w}, vov[4] = {vo.x, vo.y, vo.z, vo.w};
+      const float pov[4] = {po.x, po.y, po.z, po.w};
+      float mn[4], vn[4], pn[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int p = 4 * q + e;
+        const float sv = p < P ? sg[e] : 0.f;
+        mn[e] = b1 * mov[e] + (1.f - b1) * sv;
+        vn[e] = b2 * vov[e] + (1.f - b2) * sv * sv;
+        pn[e] = pov[e] - a.lr * (mn[e] * c1) / (sqrtf(vn[e] * c2) + eps);
+        if (p < P) {
+          a.params[(size_t)mem * P + p] = pn[e];
+          if (a.grad_out) a.grad_out[(size_t)mem * P + p] = sv;
+        }
+      }
+      reinterpret_cast<float4*>(m1)[q] = make_float4(mn[0], mn[1], mn[2], mn[3]);
+      reinterpret_cast<float4*>(m2)[q] = make_float4(vn[0], vn[1], vn[2], vn[3]);
+      reinterpret_cast<float4*>(wp)[q] = make_float4(pn[0], pn[1], pn[2], pn[3]);
     }
     if (g == 0 && tid == 0 && a.losses) {
       float s = 0.f;
@@ -1043,9 +1115,9 @@ static size_t train_head_bytes(int32_t n_members) {
 
 extern "C" size_t kaldo_mlp_workspace(int32_t n_in, int32_t n_members, int32_t n_samples) {
   if (n_in <= 0 || n_in > kMlpMaxIn || n_members <= 0 || n_samples <= 0) return 0;
-  const size_t P = mlp_layout(n_in).P;
+  const size_t Pp = padded_params(mlp_layout(n_in).P);
   const size_t G = train_groups(n_samples, 8);  // the largest grid the launcher may choose
-  const size_t floats = 2 * P * n_members + G * P * n_members + G * n_members;
+  const size_t floats = 3 * Pp * n_members + G * Pp * n_members + G * n_members;
   return train_head_bytes(n_members) + (floats * sizeof(float) + 255) / 256 * 256;
 }
 
@@ -1078,8 +1150,11 @@ extern "C" int kaldo_mlp_train(int32_t n_in, int32_t n_members, int32_t n_sample
   a.y = y;
   a.counts = counts;
   a.params = params;
-  a.m1 = f;
-  a.m2 = f + P * n_members;
+  const size_t Pp = padded_params((int)P);
+  a.Pp = (int)Pp;
+  a.wp = f;
+  a.m1 = f + Pp * n_members;
+  a.m2 = f + 2 * Pp * n_members;
   a.losses = losses;
   a.grad_out = grad_out;
   a.bar = bar;
@@ -1089,8 +1164,8 @@ extern "C" int kaldo_mlp_train(int32_t n_in, int32_t n_members, int32_t n_sample
   // fewest rows per workgroup whose grid fits on the device at once
   for (int S : {8, 16, 32}) {
     a.G = (int)train_groups(n_samples, S);
-    a.partial = f + 2 * P * n_members;
-    a.lpart = a.partial + (size_t)a.G * P * n_members;
+    a.partial = f + 3 * Pp * n_members;
+    a.lpart = a.partial + (size_t)a.G * Pp * n_members;
     if (S == 8) rc = launch_train<8>(a, n_members, st, &too_large);
     if (S == 16) rc = launch_train<16>(a, n_members, st, &too_large);
     if (S == 32) rc = launch_train<32>(a, n_members, st, &too_large);

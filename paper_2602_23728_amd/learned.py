@@ -79,7 +79,7 @@ def plain_ibz_linewidths(c, wedge: Wedge, omega, evec, vel, T, broadening, preci
 
 
 def learned_linewidths(c, wedge: Wedge, omega, evec, vel, T, broadening, candidates, draws, *,
-                       steps=500, lr=1e-2, tol=0.01, precision=K.FP32, keep_losses=False):
+                       steps=200, lr=2e-2, tol=0.01, precision=K.FP32, keep_losses=False):
     """Linewidths on the full mesh from the learned form.
 
     candidates: flat mode indices the draws' permutation applies to (normally

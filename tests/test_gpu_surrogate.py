@@ -311,7 +311,7 @@ def test_learned_form_c5_end_to_end(diamond):
     e_ibz = kappa_rel(k_ibz, k_full)
     cand = L.candidate_modes(wedge, om, c.nb3, b.nu_min_thz)
     d = draws.surrogate_draws(len(cand), K.surrogate_feature_count(c), members=5, seed=0)
-    res = L.learned_linewidths(c, wedge, om, ev, ve, T, b, cand, d, steps=500, lr=1e-2, tol=0.01)
+    res = L.learned_linewidths(c, wedge, om, ev, ve, T, b, cand, d, steps=200, lr=2e-2, tol=0.01)
     k_sur = host(K.kappa_rta(c, mesh, om, ve, res.gamma, T, b.nu_min_thz))
     e_sur = kappa_rel(k_sur, k_full)
     # held-out error of ln Gamma, network against the training mean ("no network")
