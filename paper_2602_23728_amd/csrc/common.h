@@ -74,6 +74,7 @@ struct Fc3Bloch {
   // Atom-block view of the same entries: block = (jb, kb, d) with its 3x3
   // Cartesian (beta, gamma) sub-block; blocks sorted by (jb, kb, d).
   int n_blk = 0;
+  int sym_jk = 0;               // Phi3(i, j, k) == Phi3(i, k, j) for every entry
   int32_t* e_blk = nullptr;     // [n_e] block of entry e
   int32_t* e_bg = nullptr;      // [n_e] 3*beta + gamma of entry e
   int32_t* blk_d = nullptr;     // [n_blk] d index of each block

@@ -51,6 +51,25 @@ static void free_all(kaldo_crystal* c) {
   c->allocations.clear();
 }
 
+// Phi3 symmetric in its last two slots: every (i, j, k) carries the value of
+// (i, k, j) (duplicate COO entries summed) to within 1e-12 of the largest
+// |value|.  A derivative tensor is, so the linewidth kernels may then visit
+// each mirrored partner pair once.
+static bool fc3_symmetric_jk(int64_t nnz, const int32_t* fi, const int32_t* fj, const int32_t* fk,
+                             const double* fv) {
+  std::map<std::array<int32_t, 3>, double> m;
+  for (int64_t t = 0; t < nnz; ++t) m[{fi[t], fj[t], fk[t]}] += fv[t];
+  double vmax = 0.0;
+  for (const auto& kv : m) vmax = std::max(vmax, std::fabs(kv.second));
+  const double tol = 1e-12 * vmax;
+  for (const auto& kv : m) {
+    const auto it = m.find({kv.first[0], kv.first[2], kv.first[1]});
+    const double v2 = it == m.end() ? 0.0 : it->second;
+    if (std::fabs(kv.second - v2) > tol) return false;
+  }
+  return true;
+}
+
 static int build_bloch(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const int32_t* fj,
                        const int32_t* fk, const double* fv) {
   const int nb = c->nb;
@@ -132,6 +151,7 @@ static int build_bloch(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
   }
   Fc3Bloch& b = c->bloch;
   b.n_blk = nblk;
+  b.sym_jk = fc3_symmetric_jk(nnz, fi, fj, fk, fv) ? 1 : 0;
   b.n_d = static_cast<int>(dvec.size() / 3);
   b.n_e = static_cast<int>(e_jc.size());
   b.n_t = static_cast<int>(t_i.size());

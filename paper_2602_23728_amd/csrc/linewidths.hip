@@ -26,10 +26,13 @@
 
 namespace kaldo {
 
+// modef[m] = (v, omega) in FP32 for the sweep's pre-classification, omega
+// NaN below the frequency floor so that every comparison against the mode
+// fails, as the physical mask demands.
 __global__ void lw_prepare(int n_modes, int nb3, const double* __restrict__ omega,
-                           const double* __restrict__ evec, double inv_kt_hbar,
+                           const double* __restrict__ vel, double inv_kt_hbar,
                            double nu_min, double* __restrict__ occ, uint8_t* __restrict__ phys,
-                           uint8_t* __restrict__ sel, int sel_all) {
+                           uint8_t* __restrict__ sel, float4* __restrict__ modef, int sel_all) {
   int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_modes) return;
   double w = omega[m];
@@ -37,6 +40,8 @@ __global__ void lw_prepare(int n_modes, int nb3, const double* __restrict__ omeg
   phys[m] = p;
   occ[m] = p ? 1.0 / expm1(w * inv_kt_hbar) : 0.0;
   sel[m] = sel_all ? 1 : 0;
+  modef[m] = make_float4((float)vel[3 * (size_t)m], (float)vel[3 * (size_t)m + 1],
+                         (float)vel[3 * (size_t)m + 2], p ? (float)w : __builtin_nanf(""));
 }
 
 __global__ void lw_select(const int32_t* __restrict__ subset, long n_subset, int n_modes,
@@ -188,7 +193,7 @@ __global__ void lw_finish(int nq, int nb3, int nblk, double scale, const double*
 }
 
 struct CrystalWs {
-  size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, off_phase, off_list, total;
+  size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, off_phase, off_modef, off_qlist, off_fpart, total;
 };
 
 static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
@@ -209,7 +214,9 @@ static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
   w.off_at = take(cs * nq * (size_t)c->bloch.n_e * nb3);
   w.off_partial = take(sizeof(double) * nq * nblk * nb3);
   w.off_phase = take(cs * nq * (size_t)std::max(1, c->bloch.n_d));
-  w.off_list = take(sizeof(int32_t) * (nq * nb3 + 1));
+  w.off_modef = take(sizeof(float4) * nq * nb3);
+  w.off_qlist = take(sizeof(int32_t) * (2 * nq + 1));
+  w.off_fpart = take(sizeof(double) * nq * kFusedMaxChunks * nb3);
   w.total = o;
   return w;
 }
@@ -250,9 +257,10 @@ static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double
   C* eta = reinterpret_cast<C*>(ws + w.off_eta);
   C* at = reinterpret_cast<C*>(ws + w.off_at);
   double* partial = reinterpret_cast<double*>(ws + w.off_partial);
+  float4* modef = reinterpret_cast<float4*>(ws + w.off_modef);
   const double inv_kt_hbar = kHbar / (kKb * T_k);
   KALDO_LAUNCH("lw_prepare", lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes, nb3,
-                     omega, evec, inv_kt_hbar, b->nu_min_thz, occ, phys, sel, subset ? 0 : 1);
+                     omega, vel, inv_kt_hbar, b->nu_min_thz, occ, phys, sel, modef, subset ? 0 : 1);
   if (subset && n_subset > 0)
     KALDO_LAUNCH("lw_select", lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
                        (long)n_subset, n_modes, sel);
@@ -265,9 +273,10 @@ static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double
   }
   if (path == CrystalPath::Fused) {
     C* phase_tab = reinterpret_cast<C*>(ws + w.off_phase);
-    int32_t* list = reinterpret_cast<int32_t*>(ws + w.off_list);
-    return launch_fused<T>(c, p, omega, vel, occ, phys, sel, evec, eta, phase_tab, list,
-                           kPrefactor / (double)nq, gamma, st);
+    int32_t* qlist = reinterpret_cast<int32_t*>(ws + w.off_qlist);
+    double* fpart = reinterpret_cast<double*>(ws + w.off_fpart);
+    return launch_fused<T>(c, p, omega, vel, modef, occ, phys, sel, evec, eta, phase_tab, qlist,
+                           fpart, subset ? n_subset : 0, kPrefactor / (double)nq, gamma, st);
   }
   long ne = nq * nb3 * nb3;
   KALDO_LAUNCH("lw_round_evec", lw_round_evec<T>, dim3((ne + 255) / 256), dim3(256), 0, st, ne, evec, eta);

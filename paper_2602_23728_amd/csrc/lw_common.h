@@ -29,6 +29,7 @@ struct LwParams {
   int nb3, nq, n_d, n_e, n_blk;
   int N[3];
   int shape, adaptive;
+  int half;  // Phi3 symmetric in its last two slots: mirrored partner pairs share V
   double sig_fixed, sig_floor, h2;  // rad/ps, rad/ps, 1/A^2
 };
 
@@ -54,6 +55,7 @@ inline LwParams make_params(const kaldo_crystal* c, const int32_t* mesh, double 
   p.n_d = c->bloch.n_d;
   p.n_e = c->bloch.n_e;
   p.n_blk = c->bloch.n_blk;
+  p.half = c->bloch.sym_jk;
   for (int i = 0; i < 3; ++i) p.N[i] = mesh[i];
   p.shape = b->shape;
   p.adaptive = b->adaptive;
@@ -145,6 +147,39 @@ __device__ __forceinline__ Band make_band(double sig2, float scale_sum) {
   return {t * (1.0f - 1e-6f) - d, t * (1.0f + 1e-6f) + d};
 }
 
+// FP32 twin of make_band for widths computed from the FP32 mode copy (see
+// widths2_f): the interval is widened by e_sig, the bound on how far 2 sigma
+// computed that way can lie from 2 sigma computed in FP64.
+__device__ __forceinline__ Band make_band_f(float sig2, float scale_sum, float e_sig) {
+  const float t = 2.0f * sqrtf(sig2);
+  const float d = 4e-7f * scale_sum + 1e-9f + e_sig;
+  return {t * (1.0f - 1e-6f) - d, t * (1.0f + 1e-6f) + d};
+}
+
+// sigma^2 of both processes from FP32 velocities, and e_sig >= |2 sigma_f -
+// 2 sigma| against sigma from the FP64 velocities.  With u = 2^-24, each
+// component of v1 +- v2 is off by at most 2u (|v1_i| + |v2_i|), so
+// |S_f - S| <= 7.001 u (S+ + S-), using sum_i (|v1_i| + |v2_i|)^2 <=
+// 2 (|v1|^2 + |v2|^2) = S+ + S-; max(., floor^2) is 1-Lipschitz and
+// |sqrt x - sqrt y| <= sqrt|x - y|, hence |2 sigma_f - 2 sigma| <=
+// 2 sqrt(7.001 u (S+ + S-) h^2/12).  e_sig takes twice that; relative
+// rounding of the constants and products is left to make_band_f's 1e-6.
+__device__ __forceinline__ void widths2_f(const LwParams& p, float4 v1, float4 v2, float& s2p,
+                                          float& s2m, float& e_sig) {
+  if (!p.adaptive) {
+    s2p = s2m = (float)(p.sig_fixed * p.sig_fixed);
+    e_sig = 0.0f;
+    return;
+  }
+  const float ax = v1.x + v2.x, ay = v1.y + v2.y, az = v1.z + v2.z;
+  const float bx = v2.x - v1.x, by = v2.y - v1.y, bz = v2.z - v1.z;
+  const float Sp = ax * ax + ay * ay + az * az, Sm = bx * bx + by * by + bz * bz;
+  const float H = (float)(p.h2 / 12.0), F = (float)(p.sig_floor * p.sig_floor);
+  s2p = fmaxf(Sp * H, F);
+  s2m = fmaxf(Sm * H, F);
+  e_sig = 2.0f * sqrtf(1.7e-6f * (Sp + Sm) * H);
+}
+
 // The exact FP64 decision of the oracle: |(w + w1) - w2| < 2 sigma+ or
 // |(w - w1) - w2| < 2 sigma-, sigma = max(sqrt(S h^2/12), floor) (or fixed).
 __device__ __forceinline__ bool exact_pass(const LwParams& p, double w, double w1, double w2,
@@ -181,13 +216,21 @@ __global__ void lw_phase_table(int nq, int n_d, int N0, int N1, int N2,
   out[k] = Cx<T>::make((T)cs, (T)sn);
 }
 
-// Fused one-workgroup-per-q crystal kernel (lw_fused.hip).
+// Fused crystal kernel (lw_fused.hip): one workgroup per (q, chunk) work
+// item, at most kFusedMaxChunks chunks per q, about `target` items in all.
+constexpr int kFusedMaxChunks = 16;
+__host__ __device__ inline int fused_chunks(int n_live, int target) {
+  if (n_live <= 0) return 1;
+  const int c = (target + n_live - 1) / n_live;
+  return c < 1 ? 1 : (c > kFusedMaxChunks ? kFusedMaxChunks : c);
+}
 bool fused_supported(const kaldo_crystal* c, int prec);
 template <typename T>
 int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* vel,
-                 const double* occ, const uint8_t* phys, const uint8_t* sel, const double* evec,
-                 typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab, int32_t* phys_list,
-                 double scale, double* gamma, hipStream_t st);
+                 const float4* modef, const double* occ, const uint8_t* phys, const uint8_t* sel,
+                 const double* evec,
+                 typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab, int32_t* qlist,
+                 double* part, int64_t n_subset, double scale, double* gamma, hipStream_t st);
 
 // Dense MFMA crystal kernel (lw_mfma.hip).
 bool mfma_supported(const kaldo_crystal* c);

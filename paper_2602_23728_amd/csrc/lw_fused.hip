@@ -12,12 +12,19 @@
 //     s'' and s the FP64 energy cut |x+-| < 2 sigma+- of the oracle, with
 //     x+ = (w + w1) - w2, x- = (w - w1) - w2, decides; the passing
 //     (q1, s, s', s'') are compacted in a fixed order (block-wide exclusive
-//     scan) into an LDS queue together with their FP64 weight.
+//     scan) into an LDS queue.  When Phi3 is symmetric in its last two slots
+//     the ordered pair (q1 s', q2 s'') and its mirror (q2 s'', q1 s') have
+//     the same V, so only q1 <_lex q2 is swept (and q1 == q2 once) and an
+//     entry carries the terms of both orderings, each with its own cut.
 //  3. When the queue is full (and at the end) every thread projects queue
 //     entries: V = sum_blocks e^{-i q1.R_d} sum_{beta,gamma}
 //     A~[blk][beta gamma][s] eta_{3jb+beta}(q1,s') eta_{3kb+gamma}(q2,s''),
 //     in the contraction type T, and adds w |V|^2 (FP64) to its per-branch sum.
-//  4. A fixed-order tree reduction over the workgroup gives Gamma(q, s).
+//  4. A fixed-order tree reduction over the workgroup gives this work
+//     item's partial sum; lw_fused_finish adds the chunks of a q in order.
+// A workgroup takes one work item (q, chunk): a live q and a contiguous
+// share of its sweep, so a subset of a few hundred q-points still fills the
+// device.
 // Every order above depends on the inputs only, so results are bitwise
 // reproducible.
 #include <algorithm>
@@ -40,19 +47,167 @@ constexpr int fused_waves_per_eu() {
   return (NB <= 2 && sizeof(T) == 4) ? 4 : 1;
 }
 
+// Partner coordinates of one mesh dimension for a q with coordinate a: with
+// t = (-a) mod N the partner of b is c(b) = (t - b) mod N, and b < c(b)
+// exactly for b in [0, ceil(t/2)) and [t + 1, ceil((t + N)/2)) ("L", nL
+// values), b == c(b) for b = t/2 (t even) and b = (t + N)/2 (t + N even)
+// ("E", nE values).
+struct HalfDim {
+  int t, len1, nL, nE, e0, e1;
+  __device__ int L(int j) const { return j < len1 ? j : t + 1 + (j - len1); }
+  __device__ int E(int j) const { return j == 0 ? e0 : e1; }
+};
+__device__ inline HalfDim half_dim(int a, int N) {
+  HalfDim h;
+  h.t = (N - a) % N;
+  h.len1 = (h.t + 1) / 2;
+  h.nL = h.len1 + (h.t + N + 1) / 2 - h.t - 1;
+  h.nE = 0;
+  h.e0 = h.e1 = 0;
+  if ((h.t & 1) == 0) h.e0 = h.t / 2, h.nE = 1;
+  if (((h.t + N) & 1) == 0) {
+    if (h.nE == 0)
+      h.e0 = (h.t + N) / 2;
+    else
+      h.e1 = (h.t + N) / 2;
+    ++h.nE;
+  }
+  return h;
+}
+
+// The swept partners q1 of one q in a fixed order.  Symmetric Phi3: the mesh
+// points with q1 <_lex q2 (coordinates compared lexicographically, which is
+// the flat order) in three ranges -- b0 in L0; b0 in E0, b1 in L1; b0 in E0,
+// b1 in E1, b2 in L2 -- each doubled, then the points with q1 == q2 (E0 x E1
+// x E2) once.  Otherwise every q1 once, in flat order.
+struct Partners {
+  HalfDim h[3];
+  int nA, nB, nC, n;
+  bool half;
+  __device__ Partners(bool half_, int a0, int a1, int a2, int N0, int N1, int N2) : half(half_) {
+    h[0] = half_dim(a0, N0);
+    h[1] = half_dim(a1, N1);
+    h[2] = half_dim(a2, N2);
+    if (half) {
+      nA = h[0].nL * N1 * N2;
+      nB = h[0].nE * h[1].nL * N2;
+      nC = h[0].nE * h[1].nE * h[2].nL;
+      n = nA + nB + nC + h[0].nE * h[1].nE * h[2].nE;
+    } else {
+      nA = nB = nC = 0;
+      n = N0 * N1 * N2;
+    }
+  }
+  // coordinates of the i-th partner; returns 1 when its terms are doubled
+  __device__ int get(int i, int N1, int N2, int& b0, int& b1, int& b2) const {
+    if (!half) {
+      b0 = i / (N1 * N2);
+      b1 = (i / N2) % N1;
+      b2 = i % N2;
+      return 0;
+    }
+    if (i < nA) {
+      const int j = i / (N1 * N2), r = i - j * (N1 * N2);
+      b0 = h[0].L(j);
+      b1 = r / N2;
+      b2 = r - b1 * N2;
+      return 1;
+    }
+    i -= nA;
+    if (i < nB) {
+      const int per = h[1].nL * N2, j = i / per, r = i - j * per, k = r / N2;
+      b0 = h[0].E(j);
+      b1 = h[1].L(k);
+      b2 = r - k * N2;
+      return 1;
+    }
+    i -= nB;
+    if (i < nC) {
+      const int per = h[1].nE * h[2].nL, j = i / per, r = i - j * per, k = r / h[2].nL;
+      b0 = h[0].E(j);
+      b1 = h[1].E(k);
+      b2 = h[2].L(r - k * h[2].nL);
+      return 1;
+    }
+    i -= nC;
+    const int per = h[1].nE * h[2].nE, j = i / per, r = i - j * per, k = r / h[2].nE;
+    b0 = h[0].E(j);
+    b1 = h[1].E(k);
+    b2 = h[2].E(r - k * h[2].nE);
+    return 0;
+  }
+};
+
+// Live q-points (a selected physical mode) in increasing order, the inverse
+// map (-1 for the others) and their number.  One workgroup.
+__global__ __launch_bounds__(1024) void lw_live_q(int nq, int nb3, const uint8_t* __restrict__ phys,
+                                                  const uint8_t* __restrict__ sel,
+                                                  int32_t* __restrict__ list,
+                                                  int32_t* __restrict__ idx_of_q,
+                                                  int32_t* __restrict__ count) {
+  __shared__ int wave_tot[16];
+  __shared__ int carry;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nq; base += 1024) {
+    const int q = base + tid;
+    int f = 0;
+    if (q < nq)
+      for (int s = 0; s < nb3; ++s) f |= (phys[q * nb3 + s] && sel[q * nb3 + s]) ? 1 : 0;
+    int incl = f;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wave_tot[wv] = incl;
+    __syncthreads();
+    int off = carry, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      off += (k < wv) ? wave_tot[k] : 0;
+      tot += wave_tot[k];
+    }
+    if (q < nq) {
+      idx_of_q[q] = f ? off + incl - 1 : -1;
+      if (f) list[off + incl - 1] = q;
+    }
+    __syncthreads();
+    if (tid == 0) carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) *count = carry;
+}
+
+// Gamma of the selected modes: the chunk sums of their q in chunk order.
+__global__ void lw_fused_finish(int n_modes, int nb3, const uint8_t* __restrict__ phys,
+                                const uint8_t* __restrict__ sel, const int32_t* __restrict__ idx_of_q,
+                                int n_chunk, const double* __restrict__ part, double scale,
+                                double* __restrict__ gamma) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_modes || !sel[m]) return;
+  const int q = m / nb3, s = m - q * nb3, k = idx_of_q[q];
+  if (!phys[m] || k < 0) {
+    gamma[m] = 0.0;
+    return;
+  }
+  double acc = 0.0;
+  for (int c = 0; c < n_chunk; ++c) acc += part[((size_t)k * kFusedMaxChunks + c) * nb3 + s];
+  gamma[m] = scale * acc;
+}
+
 template <int NB, typename T>
 __global__ __launch_bounds__(kFusedThreads)
 __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     LwParams p, int n_rep, const int32_t* __restrict__ rep, const double* __restrict__ omega,
-    const double* __restrict__ vel, const double* __restrict__ occ,
+    const double* __restrict__ vel, const float4* __restrict__ modef, const double* __restrict__ occ,
     const uint8_t* __restrict__ phys, const uint8_t* __restrict__ sel,
-    const int32_t* __restrict__ phys_list, const int32_t* __restrict__ n_phys_ptr,
     const double* __restrict__ evec, const typename Cx<T>::type* __restrict__ etaT,
     const typename Cx<T>::type* __restrict__ phase_tab, const int32_t* __restrict__ t_ptr,
     const int32_t* __restrict__ t_i, const int32_t* __restrict__ t_l2,
     const double* __restrict__ t_coef, const int32_t* __restrict__ e_blk,
     const int32_t* __restrict__ e_bg, const int32_t* __restrict__ blk_d,
-    const int32_t* __restrict__ pair_ptr, double scale, double* __restrict__ gamma) {
+    const int32_t* __restrict__ pair_ptr, const int32_t* __restrict__ live_list,
+    const int32_t* __restrict__ n_live_ptr, int n_chunk, double* __restrict__ part) {
   constexpr int NB3 = 3 * NB;
   constexpr int BS = kFusedThreads;
   constexpr int CAP = kFusedCap;
@@ -68,269 +223,262 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int q = blockIdx.x;
   const int N0 = p.N[0], N1 = p.N[1], N2 = p.N[2];
-  const int a0 = q / (N1 * N2), a1 = (q / N2) % N1, a2 = q % N2;
+  // workgroup = one (live q, chunk) work item; the grid may hold more
+  // workgroups than there are items
+  const int n_work = *n_live_ptr * n_chunk;
+  {
+    const int wk = blockIdx.x;
+    if (wk >= n_work) return;
+    const int kq = wk / n_chunk, chunk = wk - kq * n_chunk;
+    const int q = live_list[kq];
+    const int a0 = q / (N1 * N2), a1 = (q / N2) % N1, a2 = q % N2;
 
-  float wqf[NB3];
-  float wq_abs_max = 0.0f;
-  unsigned live = 0, any_sel = 0;
-#pragma unroll
-  for (int s = 0; s < NB3; ++s) {
-    const double w = omega[q * NB3 + s];
-    wqf[s] = (float)w;
-    wq_abs_max = fmaxf(wq_abs_max, fabsf((float)w));
-    const bool ph = phys[q * NB3 + s], se = sel[q * NB3 + s];
-    live |= (ph && se) ? (1u << s) : 0u;
-    any_sel |= se ? (1u << s) : 0u;
-  }
-  if (live == 0) {
-    if (tid < NB3 && (any_sel >> tid & 1u)) gamma[q * NB3 + tid] = 0.0;
-    return;
-  }
-  if (tid < NB3) wq64[tid] = omega[q * NB3 + tid];
-
-  // 1. A~_q in LDS
-  for (int l = tid; l < n_rep; l += BS) {
-    const int32_t* r = rep + 3 * l;
-    int m0 = ((a0 * r[0]) % N0 + N0) % N0, m1 = ((a1 * r[1]) % N1 + N1) % N1,
-        m2 = ((a2 * r[2]) % N2 + N2) % N2;
-    double f = (double)m0 / N0 + (double)m1 / N1 + (double)m2 / N2;
-    double sn, cs;
-    sincospi(2.0 * f, &sn, &cs);
-    phq[l] = make_double2(cs, sn);
-  }
-  const int n_at = p.n_blk * 9 * NB3;
-  for (int k = tid; k < n_at; k += BS) at[k] = Cx<T>::make((T)0, (T)0);
-  __syncthreads();
-  for (int k = tid; k < p.n_e * NB3; k += BS) {
-    const int e = k / NB3, s = k % NB3;
-    double re = 0.0, im = 0.0;
-    for (int t = t_ptr[e]; t < t_ptr[e + 1]; ++t) {
-      const size_t o = (((size_t)q * NB3 + t_i[t]) * NB3 + s) * 2;
-      const double ex = evec[o], ey = evec[o + 1];
-      const double2 f = phq[t_l2[t]];
-      const double c = t_coef[t];
-      re += c * (ex * f.x - ey * f.y);
-      im += c * (ex * f.y + ey * f.x);
+    float wqf[NB3];
+    float wq_abs_max = 0.0f;
+    unsigned live = 0;
+  #pragma unroll
+    for (int s = 0; s < NB3; ++s) {
+      const double w = omega[q * NB3 + s];
+      wqf[s] = (float)w;
+      wq_abs_max = fmaxf(wq_abs_max, fabsf((float)w));
+      live |= (phys[q * NB3 + s] && sel[q * NB3 + s]) ? (1u << s) : 0u;
     }
-    at[(e_blk[e] * 9 + e_bg[e]) * NB3 + s] = Cx<T>::make((T)re, (T)im);
-  }
-  __syncthreads();
+    if (tid < NB3) wq64[tid] = omega[q * NB3 + tid];
 
-  double acc[NB3];
-#pragma unroll
-  for (int s = 0; s < NB3; ++s) acc[s] = 0.0;
-
-  // 3. projection of queue entries [0, n)
-  auto process = [&](int n) {
-    for (int r = tid; r < n; r += BS) {
-      const int q1 = rq_q1[r];
-      const int code = rq_code[r];
-      const int s = code & 255, s1 = (code >> 8) & 255, s2 = code >> 16;
-      const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
-      const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
-                c2 = ((-a2 - b2) % N2 + N2) % N2;
-      const int q2 = (c0 * N1 + c1) * N2 + c2;
-      // FP64 weight of the entry (here, where every lane has an entry)
-      const int m1 = q1 * NB3 + s1, m2 = q2 * NB3 + s2;
-      double sp, sm;
-      widths(p, vel, m1, m2, sp, sm);
-      const double w = pair_weight(p, wq64[s], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
-      C x[NB3], y[NB3];
-      const C* xs = etaT + ((size_t)q1 * NB3 + s1) * NB3;
-      const C* ys = etaT + ((size_t)q2 * NB3 + s2) * NB3;
-#pragma unroll
-      for (int j = 0; j < NB3; ++j) {
-        x[j] = xs[j];
-        y[j] = ys[j];
+    // 1. A~_q in LDS
+    for (int l = tid; l < n_rep; l += BS) {
+      const int32_t* r = rep + 3 * l;
+      int m0 = ((a0 * r[0]) % N0 + N0) % N0, m1 = ((a1 * r[1]) % N1 + N1) % N1,
+          m2 = ((a2 * r[2]) % N2 + N2) % N2;
+      double f = (double)m0 / N0 + (double)m1 / N1 + (double)m2 / N2;
+      double sn, cs;
+      sincospi(2.0 * f, &sn, &cs);
+      phq[l] = make_double2(cs, sn);
+    }
+    const int n_at = p.n_blk * 9 * NB3;
+    for (int k = tid; k < n_at; k += BS) at[k] = Cx<T>::make((T)0, (T)0);
+    __syncthreads();
+    for (int k = tid; k < p.n_e * NB3; k += BS) {
+      const int e = k / NB3, s = k % NB3;
+      double re = 0.0, im = 0.0;
+      for (int t = t_ptr[e]; t < t_ptr[e + 1]; ++t) {
+        const size_t o = (((size_t)q * NB3 + t_i[t]) * NB3 + s) * 2;
+        const double ex = evec[o], ey = evec[o + 1];
+        const double2 f = phq[t_l2[t]];
+        const double c = t_coef[t];
+        re += c * (ex * f.x - ey * f.y);
+        im += c * (ex * f.y + ey * f.x);
       }
-      const C* ph = phase_tab + (size_t)q1 * p.n_d;
-      T vr = 0, vi = 0;
-#pragma unroll
-      for (int jb = 0; jb < NB; ++jb) {
-#pragma unroll
-        for (int kb = 0; kb < NB; ++kb) {
-          const int b_lo = pair_ptr[jb * NB + kb], b_hi = pair_ptr[jb * NB + kb + 1];
-          if (b_lo == b_hi) continue;
-          C z[9];
-#pragma unroll
-          for (int be = 0; be < 3; ++be)
-#pragma unroll
-            for (int ga = 0; ga < 3; ++ga) {
-              const C u = x[3 * jb + be], v = y[3 * kb + ga];
-              z[be * 3 + ga] = Cx<T>::make(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
+      at[(e_blk[e] * 9 + e_bg[e]) * NB3 + s] = Cx<T>::make((T)re, (T)im);
+    }
+    __syncthreads();
+
+    double acc[NB3];
+  #pragma unroll
+    for (int s = 0; s < NB3; ++s) acc[s] = 0.0;
+
+    // 3. projection of queue entries [0, n)
+    auto process = [&](int n) {
+      for (int r = tid; r < n; r += BS) {
+        const int q1 = rq_q1[r];
+        const int code = rq_code[r];
+        const int s = code & 255, s1 = (code >> 8) & 255, s2 = (code >> 16) & 255, dbl = code >> 24;
+        const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
+        const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
+                  c2 = ((-a2 - b2) % N2 + N2) % N2;
+        const int q2 = (c0 * N1 + c1) * N2 + c2;
+        // FP64 weight of the entry (here, where every lane has an entry)
+        const int m1 = q1 * NB3 + s1, m2 = q2 * NB3 + s2;
+        double sp, sm;
+        widths(p, vel, m1, m2, sp, sm);
+        double w = pair_weight(p, wq64[s], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
+        // the mirrored ordering: same widths (|v1 +- v2| are symmetric), its own cut
+        if (dbl) w += pair_weight(p, wq64[s], omega[m2], omega[m1], occ[m2], occ[m1], sp, sm);
+        C x[NB3], y[NB3];
+        const C* xs = etaT + ((size_t)q1 * NB3 + s1) * NB3;
+        const C* ys = etaT + ((size_t)q2 * NB3 + s2) * NB3;
+  #pragma unroll
+        for (int j = 0; j < NB3; ++j) {
+          x[j] = xs[j];
+          y[j] = ys[j];
+        }
+        const C* ph = phase_tab + (size_t)q1 * p.n_d;
+        T vr = 0, vi = 0;
+  #pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+  #pragma unroll
+          for (int kb = 0; kb < NB; ++kb) {
+            const int b_lo = pair_ptr[jb * NB + kb], b_hi = pair_ptr[jb * NB + kb + 1];
+            if (b_lo == b_hi) continue;
+            C z[9];
+  #pragma unroll
+            for (int be = 0; be < 3; ++be)
+  #pragma unroll
+              for (int ga = 0; ga < 3; ++ga) {
+                const C u = x[3 * jb + be], v = y[3 * kb + ga];
+                z[be * 3 + ga] = Cx<T>::make(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
+              }
+            for (int blk = b_lo; blk < b_hi; ++blk) {
+              const C* ab = at + (size_t)blk * 9 * NB3 + s;
+              T ur = 0, ui = 0;
+  #pragma unroll
+              for (int k = 0; k < 9; ++k) {
+                const C a = ab[k * NB3];
+                ur += a.x * z[k].x - a.y * z[k].y;
+                ui += a.x * z[k].y + a.y * z[k].x;
+              }
+              const C f = ph[blk_d[blk]];
+              vr += f.x * ur - f.y * ui;
+              vi += f.x * ui + f.y * ur;
             }
-          for (int blk = b_lo; blk < b_hi; ++blk) {
-            const C* ab = at + (size_t)blk * 9 * NB3 + s;
-            T ur = 0, ui = 0;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-              const C a = ab[k * NB3];
-              ur += a.x * z[k].x - a.y * z[k].y;
-              ui += a.x * z[k].y + a.y * z[k].x;
-            }
-            const C f = ph[blk_d[blk]];
-            vr += f.x * ur - f.y * ui;
-            vi += f.x * ui + f.y * ur;
           }
         }
+        const double c = w * ((double)vr * (double)vr + (double)vi * (double)vi);
+  #pragma unroll
+        for (int k = 0; k < NB3; ++k) acc[k] += (k == s) ? c : 0.0;
       }
-      const double c = w * ((double)vr * (double)vr + (double)vi * (double)vi);
-#pragma unroll
-      for (int k = 0; k < NB3; ++k) acc[k] += (k == s) ? c : 0.0;
-    }
-  };
+    };
 
-  // 2. sweep of the physical (q1, s') candidates
-  int fill = 0;
-  const int n_items = *n_phys_ptr;
-  for (int base = 0; base < n_items; base += BS) {
-    const int item = base + tid;
-    unsigned bits[NB3];
-#pragma unroll
-    for (int k = 0; k < NB3; ++k) bits[k] = 0;
-    int count = 0;
-    int q1 = 0, s1 = 0, q2 = 0;
-    if (item < n_items) {
-      const int m1 = phys_list[item];
-      q1 = m1 / NB3;
-      s1 = m1 % NB3;
-      const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
-      const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
-                c2 = ((-a2 - b2) % N2 + N2) % N2;
-      q2 = (c0 * N1 + c1) * N2 + c2;
-      const double w1 = omega[m1];
-      const double* v1 = vel + 3 * (size_t)m1;
-#pragma unroll
-      for (int s2 = 0; s2 < NB3; ++s2) {
-        const int m2 = q2 * NB3 + s2;
-        if (!phys[m2]) continue;
-        const double w2 = omega[m2];
-        double s2p, s2m, Sp, Sm;
-        widths2(p, v1, vel + 3 * (size_t)m2, s2p, s2m, Sp, Sm);
-        const float scl = wq_abs_max + fabsf((float)w1) + fabsf((float)w2);
-        const Band bp = make_band(s2p, scl), bm = make_band(s2m, scl);
-        const float cp = (float)(w1 - w2), cm = (float)(-w1 - w2);
-        // certain passes and the ambiguous band for all branches first
-        // (branch-free); the exact FP64 test only for the rare band members
-        unsigned b = 0, amb_p = 0, amb_m = 0;
-#pragma unroll
-        for (int s = 0; s < NB3; ++s) {
-          const float ap = fabsf(wqf[s] + cp), am = fabsf(wqf[s] + cm);
-          b |= ((ap < bp.lo) || (am < bm.lo)) ? (1u << s) : 0u;
-          amb_p |= (ap < bp.hi) ? (1u << s) : 0u;
-          amb_m |= (am < bm.hi) ? (1u << s) : 0u;
-        }
-        unsigned amb = (amb_p | amb_m) & ~b & live;
-        while (amb) {
-          const int s = __ffs(amb) - 1;
-          amb &= amb - 1;
-          const bool pass = ((amb_p >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, true)) ||
-                            ((amb_m >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, false));
-          b |= pass ? (1u << s) : 0u;
-        }
-        b &= live;
-        bits[s2] = b;
-        count += __popc(b);
-      }
-    }
-    // block-wide exclusive scan of count (fixed order)
-    int incl = count;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += v;
-    }
-    if (lane == 63) wave_tot[wv] = incl;
-    __syncthreads();
-    int wave_off = 0, total = 0;
-#pragma unroll
-    for (int k = 0; k < BS / 64; ++k) {
-      const int t = wave_tot[k];
-      wave_off += (k < wv) ? t : 0;
-      total += t;
-    }
-    const int my_off = wave_off + incl - count;
-    __syncthreads();
-    int written = 0;
-    while (written < total) {
-      const int take = min(CAP - fill, total - written);
-      if (count > 0 && my_off < written + take && my_off + count > written) {
-        int rank = my_off;
-#pragma unroll
+    // 2. sweep of the (q1, s') candidates (modes below the floor fail every
+    // comparison through their NaN frequency)
+    int fill = 0;
+    const Partners prt(p.half != 0, a0, a1, a2, N0, N1, N2);
+    // this work item's share: a contiguous range of whole sweep rounds
+    const int n_all = prt.n * NB3;
+    const int per = ((n_all + n_chunk - 1) / n_chunk + BS - 1) / BS * BS;
+    const int i_lo = min(n_all, chunk * per), n_items = min(n_all, i_lo + per);
+    for (int base = i_lo; base < n_items; base += BS) {
+      const int item = base + tid;
+      unsigned bits[NB3];
+  #pragma unroll
+      for (int k = 0; k < NB3; ++k) bits[k] = 0;
+      int count = 0;
+      int q1 = 0, s1 = 0, dbl = 0;
+      if (item < n_items) {
+        const int qi = item / NB3;
+        s1 = item - qi * NB3;
+        int b0, b1, b2;
+        dbl = prt.get(qi, N1, N2, b0, b1, b2);
+        q1 = (b0 * N1 + b1) * N2 + b2;
+        const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
+                  c2 = ((-a2 - b2) % N2 + N2) % N2;
+        const int q2 = (c0 * N1 + c1) * N2 + c2;
+        const int m1 = q1 * NB3 + s1;
+        const unsigned dmask = dbl ? ~0u : 0u;
+        const float4 f1 = modef[m1];
+  #pragma unroll
         for (int s2 = 0; s2 < NB3; ++s2) {
-          unsigned b = bits[s2];
-          while (b) {
-            const int s = __ffs(b) - 1;
-            b &= b - 1;
-            if (rank >= written && rank < written + take) {
-              const int slot = fill + rank - written;
-              rq_q1[slot] = q1;
-              rq_code[slot] = s | (s1 << 8) | (s2 << 16);
-            }
-            ++rank;
+          const int m2 = q2 * NB3 + s2;
+          // FP32 classification from the mode copies (a mode below the floor
+          // carries a NaN frequency and fails every comparison)
+          const float4 f2 = modef[m2];
+          float s2p, s2m, e_sig;
+          widths2_f(p, f1, f2, s2p, s2m, e_sig);
+          const float scl = wq_abs_max + fabsf(f1.w) + fabsf(f2.w);
+          const Band bp = make_band_f(s2p, scl, e_sig), bm = make_band_f(s2m, scl, e_sig);
+          const float cp = f1.w - f2.w, cm = -f1.w - f2.w;
+          // certain passes and the ambiguous band for all branches first
+          // (branch-free); the exact FP64 test only for the rare band members.
+          // ar is the coalescence |x+| of the mirrored ordering, (w + w2) - w1;
+          // the decay |x-| is the same number in FP32 for both orderings.
+          unsigned b = 0, br = 0, amb_p = 0, amb_r = 0, amb_m = 0;
+  #pragma unroll
+          for (int s = 0; s < NB3; ++s) {
+            const float ap = fabsf(wqf[s] + cp), ar = fabsf(wqf[s] - cp), am = fabsf(wqf[s] + cm);
+            b |= ((ap < bp.lo) || (am < bm.lo)) ? (1u << s) : 0u;
+            br |= (ar < bp.lo) ? (1u << s) : 0u;
+            amb_p |= (ap < bp.hi) ? (1u << s) : 0u;
+            amb_r |= (ar < bp.hi) ? (1u << s) : 0u;
+            amb_m |= (am < bm.hi) ? (1u << s) : 0u;
           }
+          b |= br & dmask;
+          amb_r &= dmask;
+          unsigned amb = (amb_p | amb_r | amb_m) & ~b & live;
+          if (amb) {
+            const double w1 = omega[m1], w2 = omega[m2];
+            double s2p64, s2m64, Sp, Sm;
+            widths2(p, vel + 3 * (size_t)m1, vel + 3 * (size_t)m2, s2p64, s2m64, Sp, Sm);
+            while (amb) {
+              const int s = __ffs(amb) - 1;
+              amb &= amb - 1;
+              const bool bm_ = amb_m >> s & 1u;
+              bool pass = ((amb_p >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, true)) ||
+                          (bm_ && exact_pass(p, wq64[s], w1, w2, Sp, Sm, false));
+              if (dbl && !pass)
+                pass = ((amb_r >> s & 1u) && exact_pass(p, wq64[s], w2, w1, Sp, Sm, true)) ||
+                       (bm_ && exact_pass(p, wq64[s], w2, w1, Sp, Sm, false));
+              b |= pass ? (1u << s) : 0u;
+            }
+          }
+          b &= live;
+          bits[s2] = b;
+          count += __popc(b);
         }
       }
-      fill += take;
-      written += take;
+      // block-wide exclusive scan of count (fixed order)
+      int incl = count;
+  #pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+      }
+      if (lane == 63) wave_tot[wv] = incl;
       __syncthreads();
-      if (fill == CAP) {
-        process(fill);
-        fill = 0;
+      int wave_off = 0, total = 0;
+  #pragma unroll
+      for (int k = 0; k < BS / 64; ++k) {
+        const int t = wave_tot[k];
+        wave_off += (k < wv) ? t : 0;
+        total += t;
+      }
+      const int my_off = wave_off + incl - count;
+      __syncthreads();
+      int written = 0;
+      while (written < total) {
+        const int take = min(CAP - fill, total - written);
+        if (count > 0 && my_off < written + take && my_off + count > written) {
+          int rank = my_off;
+  #pragma unroll
+          for (int s2 = 0; s2 < NB3; ++s2) {
+            unsigned b = bits[s2];
+            while (b) {
+              const int s = __ffs(b) - 1;
+              b &= b - 1;
+              if (rank >= written && rank < written + take) {
+                const int slot = fill + rank - written;
+                rq_q1[slot] = q1;
+                rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (dbl << 24);
+              }
+              ++rank;
+            }
+          }
+        }
+        fill += take;
+        written += take;
+        __syncthreads();
+        if (fill == CAP) {
+          process(fill);
+          fill = 0;
+          __syncthreads();
+        }
+      }
+    }
+    process(fill);
+
+    // 4. fixed-order reduction per branch
+  #pragma unroll
+    for (int s = 0; s < NB3; ++s) {
+      __syncthreads();
+      red[tid] = acc[s];
+      __syncthreads();
+      for (int w = BS / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
       }
+      if (tid == 0) part[((size_t)kq * kFusedMaxChunks + chunk) * NB3 + s] = red[0];
     }
   }
-  process(fill);
-
-  // 4. fixed-order reduction per branch
-#pragma unroll
-  for (int s = 0; s < NB3; ++s) {
-    __syncthreads();
-    red[tid] = acc[s];
-    __syncthreads();
-    for (int w = BS / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0 && (any_sel >> s & 1u))
-      gamma[q * NB3 + s] = (live >> s & 1u) ? scale * red[0] : 0.0;
-  }
-}
-
-// Deterministic compaction of the physical modes: list[k] = k-th mode with
-// phys[m] != 0, *count = their number.  One workgroup.
-__global__ __launch_bounds__(1024) void lw_compact_phys(int n_modes, const uint8_t* __restrict__ phys,
-                                                        int32_t* __restrict__ list,
-                                                        int32_t* __restrict__ count) {
-  __shared__ int wave_tot[16];
-  __shared__ int carry;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < n_modes; base += 1024) {
-    const int m = base + tid;
-    const int f = (m < n_modes && phys[m]) ? 1 : 0;
-    int incl = f;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += v;
-    }
-    if (lane == 63) wave_tot[wv] = incl;
-    __syncthreads();
-    int off = carry, tot = 0;
-    for (int k = 0; k < 16; ++k) {
-      off += (k < wv) ? wave_tot[k] : 0;
-      tot += wave_tot[k];
-    }
-    if (f) list[off + incl - 1] = m;
-    __syncthreads();
-    if (tid == 0) carry += tot;
-    __syncthreads();
-  }
-  if (tid == 0) *count = carry;
 }
 
 // eta rounded to T and transposed to [q][mode][component].
@@ -365,28 +513,54 @@ bool fused_supported(const kaldo_crystal* c, int prec) {
 
 template <typename T>
 int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* vel,
-                 const double* occ, const uint8_t* phys, const uint8_t* sel, const double* evec,
-                 typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab, int32_t* phys_list,
-                 double scale, double* gamma, hipStream_t st) {
+                 const float4* modef, const double* occ, const uint8_t* phys, const uint8_t* sel,
+                 const double* evec, typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab,
+                 int32_t* qlist, double* part, int64_t n_subset, double scale, double* gamma,
+                 hipStream_t st) {
   const int nq = p.nq;
   const int n_modes = nq * c->nb3;
   const long ne = (long)n_modes * c->nb3;
   KALDO_LAUNCH("lw_eta_transpose", lw_eta_transpose<T>, dim3((ne + 255) / 256), dim3(256), 0, st,
                (long)nq, c->nb3, evec, eta);
-  KALDO_LAUNCH("lw_compact_phys", lw_compact_phys, dim3(1), dim3(1024), 0, st, n_modes, phys,
-               phys_list + 1, phys_list);
   const long nph = (long)nq * std::max(1, p.n_d);
   KALDO_LAUNCH("lw_phase_table", lw_phase_table<T>, dim3((nph + 255) / 256), dim3(256), 0, st, nq,
                p.n_d, p.N[0], p.N[1], p.N[2], c->bloch.dvec, phase_tab);
+  int32_t* live_list = qlist;
+  int32_t* idx_of_q = qlist + nq;
+  int32_t* n_live = qlist + 2 * nq;
+  KALDO_LAUNCH("lw_live_q", lw_live_q, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel, live_list,
+               idx_of_q, n_live);
   const size_t lds = fused_lds_bytes(c, sizeof(T) == 8 ? KALDO_FP64 : KALDO_FP32);
   const Fc3Bloch& b = c->bloch;
+  int dev = 0, n_cu = 0;
+  KALDO_HIP(hipGetDevice(&dev));
+  KALDO_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  // Chunks per q from the number of live q-points the host can know of: at
+  // most min(N_q, n_subset) (the grid covers that many), estimated as
+  // n_subset / 3N_b (every branch of a q selected) when choosing the chunk
+  // count, so that about four work items fall to each resident workgroup.
+  const long upper = n_subset > 0 ? std::min<long>(nq, n_subset) : nq;
+  const long guess = n_subset > 0 ? std::max<long>(1, n_subset / c->nb3) : nq;
+  // and no chunk shorter than one sweep round (a q sweeps about N_q 3N_b / 2 items)
+  const int max_chunks =
+      (int)std::max<long>(1, std::min<long>(kFusedMaxChunks, (long)nq * c->nb3 / (2 * kFusedThreads)));
 #define KALDO_FUSED_CASE(NBV)                                                                  \
-  case NBV:                                                                                    \
-    KALDO_LAUNCH("lw_fused", (lw_fused<NBV, T>), dim3(nq), dim3(kFusedThreads), lds, st, p,    \
-                 c->n_rep, c->d_rep, omega, vel, occ, phys, sel, phys_list + 1, phys_list, evec, \
-                 eta, phase_tab, b.t_ptr,                                                    \
-                 b.t_i, b.t_l2, b.t_coef, b.e_blk, b.e_bg, b.blk_d, b.pair_ptr, scale, gamma);  \
-    break;
+  case NBV: {                                                                                  \
+    int per_cu = 0;                                                                            \
+    KALDO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lw_fused<NBV, T>,          \
+                                                           kFusedThreads, lds));               \
+    const long slots = (long)std::max(1, per_cu) * n_cu;                                       \
+    const int n_chunk = std::min(fused_chunks((int)std::min<long>(guess, 1l << 30),           \
+                                              (int)std::min<long>(4 * slots, 1l << 30)),       \
+                                 max_chunks);                                                  \
+    KALDO_LAUNCH("lw_fused", (lw_fused<NBV, T>), dim3((unsigned)(upper * n_chunk)),            \
+                 dim3(kFusedThreads), lds, st, p, c->n_rep, c->d_rep, omega, vel, modef, occ,  \
+                 phys, sel, evec, eta, phase_tab, b.t_ptr, b.t_i, b.t_l2, b.t_coef, b.e_blk,   \
+                 b.e_bg, b.blk_d, b.pair_ptr, live_list, n_live, n_chunk, part);               \
+    KALDO_LAUNCH("lw_fused_finish", lw_fused_finish, dim3((n_modes + 255) / 256), dim3(256), 0, \
+                 st, n_modes, c->nb3, phys, sel, idx_of_q, n_chunk, part, scale, gamma);       \
+    break;                                                                                     \
+  }
   switch (c->nb) {
     KALDO_FUSED_CASE(1)
     KALDO_FUSED_CASE(2)
@@ -403,12 +577,12 @@ int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega,
 }
 
 template int launch_fused<float>(const kaldo_crystal*, const LwParams&, const double*,
-                                 const double*, const double*, const uint8_t*, const uint8_t*,
-                                 const double*, float2*, float2*, int32_t*, double, double*,
-                                 hipStream_t);
+                                 const double*, const float4*, const double*, const uint8_t*,
+                                 const uint8_t*, const double*, float2*, float2*, int32_t*,
+                                 double*, int64_t, double, double*, hipStream_t);
 template int launch_fused<double>(const kaldo_crystal*, const LwParams&, const double*,
-                                  const double*, const double*, const uint8_t*, const uint8_t*,
-                                  const double*, double2*, double2*, int32_t*, double, double*,
-                                  hipStream_t);
+                                  const double*, const float4*, const double*, const uint8_t*,
+                                  const uint8_t*, const double*, double2*, double2*, int32_t*,
+                                  double*, int64_t, double, double*, hipStream_t);
 
 }  // namespace kaldo

@@ -45,7 +45,12 @@ __device__ __forceinline__ void wave_sync() {
 //   FP32 16x16x4, 8 MFMAs over the stacked K = 32: MFMA t reads stacked
 //     k = 4 t + g, i.e. complex column kc = 4 (t % 4) + g, part t / 4.
 //   BF16 16x16x32: element i reads stacked k = 8 g + i, i.e. complex column
-//     kc = 8 (g % 2) + i, part g / 2.
+//   kc = 8 (g % 2) + i, part g / 2.
+// The second product V = eta1^T T takes its K order from the accumulator
+// layout of T instead (lane (n, g) holds T rows 4 g + r, r < 4): FP32 MFMA t
+// pairs K slot g with jc = 4 g + t % 4 (part t / 4), BF16 element i with
+// jc = 4 g + i % 4 (part i / 4), so T goes from registers straight into the
+// next product; eta1's fragments follow the same order.
 
 template <bool SPLIT>
 __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
@@ -61,7 +66,6 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
   const int NB3 = p.nb3;
   extern __shared__ double2 smem[];
   float2* at = reinterpret_cast<float2*>(smem);  // [n_blk][9][NB3]
-  __shared__ float2 tsc[kMfmaWaves][16 * 17];         // per-wave T scratch [row jc][col s'']
   __shared__ float2 bsc[kMfmaWaves][16 * 17];         // per-wave B_s tile [row jc][col kc]
   __shared__ float2 phb[kMfmaWaves][kMfmaMaxBlocks];  // per-wave e^{-i q1.R_d(blk)} per block
   __shared__ int cq_code[kMfmaWaves][kCandCap];       // per-wave near-shell candidates:
@@ -170,17 +174,24 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
       phb[wv][blk] = phase_tab[(size_t)q1 * p.n_d + blk_d[blk]];
     wave_sync();
     // eta(q2)[kc][s''] as the B operand of T = B_s eta2 (column n = lr)
-    // and eta(q1)[jc][s'] as A = eta1^T (row m = lr) of V = eta1^T T.
-    float2 e2[NF], e1[NF];
+    // and eta(q1)[jc][s'] (jc = 4 lg + i) as A = eta1^T (row m = lr) of
+    // V = eta1^T T.
+    float2 e2[NF], e1[4];
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
       const int k = kc_of(i);
       e2[i] = make_float2(0.f, 0.f);
-      e1[i] = make_float2(0.f, 0.f);
       if (k < NB3 && lr < NB3) {
         const size_t o2 = (((size_t)q2 * NB3 + k) * NB3 + lr) * 2;
-        const size_t o1 = (((size_t)q1 * NB3 + k) * NB3 + lr) * 2;
         e2[i] = make_float2((float)evec[o2], (float)evec[o2 + 1]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * lg + i;
+      e1[i] = make_float2(0.f, 0.f);
+      if (k < NB3 && lr < NB3) {
+        const size_t o1 = (((size_t)q1 * NB3 + k) * NB3 + lr) * 2;
         e1[i] = make_float2((float)evec[o1], (float)evec[o1 + 1]);
       }
     }
@@ -218,8 +229,8 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
       for (int i = 0; i < 8; ++i) {
         // B' = [Re eta2 ; Im eta2]; A'(eta1^T) = [Re | -Im], A'' = [Im | Re]
         const float b = (lg < 2) ? e2[i].x : e2[i].y;
-        const float a1 = (lg < 2) ? e1[i].x : -e1[i].y;
-        const float a2 = (lg < 2) ? e1[i].y : e1[i].x;
+        const float a1 = (i < 4) ? e1[i & 3].x : -e1[i & 3].y;
+        const float a2 = (i < 4) ? e1[i & 3].y : e1[i & 3].x;
         e2h[i] = (__bf16)b;
         e2l[i] = (__bf16)(b - (float)e2h[i]);
         e1ah[i] = (__bf16)a1;
@@ -304,18 +315,13 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
           ti = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, e2f[t], ti, 0, 0, 0);
         }
       }
-      // T rows 4 lg + r of column lr -> LDS, then read as the B operand
-      float2* T = tsc[wv];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) T[(4 * lg + r) * 17 + lr] = make_float2(tr[r], ti[r]);
-      wave_sync();
+      // T (rows 4 lg + r of column lr, in registers) is the B operand of V
       f4 vr = {0, 0, 0, 0}, vi = {0, 0, 0, 0};
       if constexpr (SPLIT) {
         bf16x8 th, tl;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const float2 x = T[(8 * (lg & 1) + i) * 17 + lr];
-          const float b = (lg < 2) ? x.x : x.y;
+          const float b = (i < 4) ? tr[i & 3] : ti[i & 3];
           th[i] = (__bf16)b;
           tl[i] = (__bf16)(b - (float)th[i]);
         }
@@ -328,13 +334,11 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
       } else {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-          const float2 x = T[(4 * (t & 3) + lg) * 17 + lr];
-          const float b = (t < 4) ? x.x : x.y;
+          const float b = (t < 4) ? tr[t & 3] : ti[t & 3];
           vr = __builtin_amdgcn_mfma_f32_16x16x4f32(e1af[t], b, vr, 0, 0, 0);
           vi = __builtin_amdgcn_mfma_f32_16x16x4f32(e1bf[t], b, vi, 0, 0, 0);
         }
       }
-      wave_sync();
       // epilogue: V[s' = 4 lg + r][s'' = lr].  The FP32 pre-classification
       // drops candidates certainly outside the cut; the rest are queued with
       // their |V|^2 for the exact FP64 decision and weight.
@@ -387,7 +391,7 @@ bool mfma_supported(const kaldo_crystal* c) {
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return false;
   const size_t dyn = (size_t)c->bloch.n_blk * 9 * c->nb3 * 8;
-  const size_t stat = 2 * kMfmaWaves * 16 * 17 * 8 + kMfmaWaves * kMfmaMaxBlocks * 8 +
+  const size_t stat = kMfmaWaves * 16 * 17 * 8 + kMfmaWaves * kMfmaMaxBlocks * 8 +
                       kMfmaWaves * kCandCap * 16 + 64 * 16 + 16 * 8 + kMfmaThreads * 8;
   return dyn + stat <= (size_t)lds_max;
 }

@@ -208,6 +208,30 @@ def test_subset_writes_only_selected(diamond):
     assert np.allclose(G[mask], Gall[mask], rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fc3_not_mirror_symmetric_sweeps_every_partner(diamond, prec):
+    """With Phi3 symmetric in its last two slots the crystal kernel visits
+    each mirrored partner pair (q1, q2) once; an FC3 without that symmetry
+    (entries with j < k scaled by 1.3) must switch back to every ordered
+    partner and still match the oracle, which sums all ordered pairs."""
+    import dataclasses
+    m, _ = diamond
+    val = np.where(m.fc3_j < m.fc3_k, 1.3, 1.0) * m.fc3_val
+    ma = dataclasses.replace(m, fc3_val=val)
+    c = K.Crystal.from_model(ma)
+    mesh = (4, 3, 5)
+    om, ev, ve = _oracle_inputs(m, mesh)
+    p = K.FP32 if prec == "fp32" else K.FP64
+    G = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, p))
+    Go = olw.crystal_linewidths(ma, mesh, om, ev, ve, 300.0, B_ADAPT)
+    Gs = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_ADAPT)
+    assert np.max(np.abs(Go - Gs)) > 1e-2 * Gs.max()  # the perturbation matters
+    if prec == "fp32":
+        assert gamma_close(G, Go) <= 1e-5
+    else:
+        assert np.max(np.abs(G - Go)) <= 1e-10 * Go.max()
+
+
 def test_bitwise_deterministic(diamond):
     m, c = diamond
     mesh = (5, 5, 5)
