@@ -255,7 +255,10 @@ size_t kaldo_jdos_workspace(const kaldo_crystal* c, const int32_t* mesh);
  *   modes_subset   device int32[n_subset] or NULL (all modes); only those
  *                  entries of dplus / dminus are written
  *   dplus, dminus  device double[N_q*nb3]
- * Requires nb3 <= 16. */
+ * Requires nb3 <= 16 and N_q <= 65535 (KALDO_EINVAL otherwise).  Each
+ * unordered partner pair {q1, q2} is visited once and contributes the terms
+ * of both orderings, each with its own cut; sums are in a fixed order, so
+ * results are bitwise reproducible. */
 int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
                const double* vel, const kaldo_broadening* broadening,
                const int32_t* modes_subset, int64_t n_subset, void* workspace,

@@ -47,137 +47,6 @@ constexpr int fused_waves_per_eu() {
   return (NB <= 2 && sizeof(T) == 4) ? 4 : 1;
 }
 
-// Partner coordinates of one mesh dimension for a q with coordinate a: with
-// t = (-a) mod N the partner of b is c(b) = (t - b) mod N, and b < c(b)
-// exactly for b in [0, ceil(t/2)) and [t + 1, ceil((t + N)/2)) ("L", nL
-// values), b == c(b) for b = t/2 (t even) and b = (t + N)/2 (t + N even)
-// ("E", nE values).
-struct HalfDim {
-  int t, len1, nL, nE, e0, e1;
-  __device__ int L(int j) const { return j < len1 ? j : t + 1 + (j - len1); }
-  __device__ int E(int j) const { return j == 0 ? e0 : e1; }
-};
-__device__ inline HalfDim half_dim(int a, int N) {
-  HalfDim h;
-  h.t = (N - a) % N;
-  h.len1 = (h.t + 1) / 2;
-  h.nL = h.len1 + (h.t + N + 1) / 2 - h.t - 1;
-  h.nE = 0;
-  h.e0 = h.e1 = 0;
-  if ((h.t & 1) == 0) h.e0 = h.t / 2, h.nE = 1;
-  if (((h.t + N) & 1) == 0) {
-    if (h.nE == 0)
-      h.e0 = (h.t + N) / 2;
-    else
-      h.e1 = (h.t + N) / 2;
-    ++h.nE;
-  }
-  return h;
-}
-
-// The swept partners q1 of one q in a fixed order.  Symmetric Phi3: the mesh
-// points with q1 <_lex q2 (coordinates compared lexicographically, which is
-// the flat order) in three ranges -- b0 in L0; b0 in E0, b1 in L1; b0 in E0,
-// b1 in E1, b2 in L2 -- each doubled, then the points with q1 == q2 (E0 x E1
-// x E2) once.  Otherwise every q1 once, in flat order.
-struct Partners {
-  HalfDim h[3];
-  int nA, nB, nC, n;
-  bool half;
-  __device__ Partners(bool half_, int a0, int a1, int a2, int N0, int N1, int N2) : half(half_) {
-    h[0] = half_dim(a0, N0);
-    h[1] = half_dim(a1, N1);
-    h[2] = half_dim(a2, N2);
-    if (half) {
-      nA = h[0].nL * N1 * N2;
-      nB = h[0].nE * h[1].nL * N2;
-      nC = h[0].nE * h[1].nE * h[2].nL;
-      n = nA + nB + nC + h[0].nE * h[1].nE * h[2].nE;
-    } else {
-      nA = nB = nC = 0;
-      n = N0 * N1 * N2;
-    }
-  }
-  // coordinates of the i-th partner; returns 1 when its terms are doubled
-  __device__ int get(int i, int N1, int N2, int& b0, int& b1, int& b2) const {
-    if (!half) {
-      b0 = i / (N1 * N2);
-      b1 = (i / N2) % N1;
-      b2 = i % N2;
-      return 0;
-    }
-    if (i < nA) {
-      const int j = i / (N1 * N2), r = i - j * (N1 * N2);
-      b0 = h[0].L(j);
-      b1 = r / N2;
-      b2 = r - b1 * N2;
-      return 1;
-    }
-    i -= nA;
-    if (i < nB) {
-      const int per = h[1].nL * N2, j = i / per, r = i - j * per, k = r / N2;
-      b0 = h[0].E(j);
-      b1 = h[1].L(k);
-      b2 = r - k * N2;
-      return 1;
-    }
-    i -= nB;
-    if (i < nC) {
-      const int per = h[1].nE * h[2].nL, j = i / per, r = i - j * per, k = r / h[2].nL;
-      b0 = h[0].E(j);
-      b1 = h[1].E(k);
-      b2 = h[2].L(r - k * h[2].nL);
-      return 1;
-    }
-    i -= nC;
-    const int per = h[1].nE * h[2].nE, j = i / per, r = i - j * per, k = r / h[2].nE;
-    b0 = h[0].E(j);
-    b1 = h[1].E(k);
-    b2 = h[2].E(r - k * h[2].nE);
-    return 0;
-  }
-};
-
-// Live q-points (a selected physical mode) in increasing order, the inverse
-// map (-1 for the others) and their number.  One workgroup.
-__global__ __launch_bounds__(1024) void lw_live_q(int nq, int nb3, const uint8_t* __restrict__ phys,
-                                                  const uint8_t* __restrict__ sel,
-                                                  int32_t* __restrict__ list,
-                                                  int32_t* __restrict__ idx_of_q,
-                                                  int32_t* __restrict__ count) {
-  __shared__ int wave_tot[16];
-  __shared__ int carry;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nq; base += 1024) {
-    const int q = base + tid;
-    int f = 0;
-    if (q < nq)
-      for (int s = 0; s < nb3; ++s) f |= (phys[q * nb3 + s] && sel[q * nb3 + s]) ? 1 : 0;
-    int incl = f;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += v;
-    }
-    if (lane == 63) wave_tot[wv] = incl;
-    __syncthreads();
-    int off = carry, tot = 0;
-    for (int k = 0; k < 16; ++k) {
-      off += (k < wv) ? wave_tot[k] : 0;
-      tot += wave_tot[k];
-    }
-    if (q < nq) {
-      idx_of_q[q] = f ? off + incl - 1 : -1;
-      if (f) list[off + incl - 1] = q;
-    }
-    __syncthreads();
-    if (tid == 0) carry += tot;
-    __syncthreads();
-  }
-  if (tid == 0) *count = carry;
-}
-
 // Gamma of the selected modes: the chunk sums of their q in chunk order.
 __global__ void lw_fused_finish(int n_modes, int nb3, const uint8_t* __restrict__ phys,
                                 const uint8_t* __restrict__ sel, const int32_t* __restrict__ idx_of_q,
@@ -528,7 +397,7 @@ int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega,
   int32_t* live_list = qlist;
   int32_t* idx_of_q = qlist + nq;
   int32_t* n_live = qlist + 2 * nq;
-  KALDO_LAUNCH("lw_live_q", lw_live_q, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel, live_list,
+  KALDO_LAUNCH("lw_live_q", lw_live_q<>, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel, live_list,
                idx_of_q, n_live);
   const size_t lds = fused_lds_bytes(c, sizeof(T) == 8 ? KALDO_FP64 : KALDO_FP32);
   const Fc3Bloch& b = c->bloch;

@@ -31,86 +31,203 @@ constexpr int kGateMaxRows = 4096;
 constexpr unsigned kSpinCap = 1u << 20;
 
 // ----------------------------------------------------------------- JDOS
-// Workgroup (q, c) sums chunk c of the (q1, s') partners of every branch of q:
-// D+-(q, s) = (1/N_q) sum_{q1, s', s''} m g(x+-) with the exact FP64 cut of
-// the linewidths; fixed-order reductions within the chunk, then over chunks.
-constexpr int kJdosChunks = 8;
+// Work item (live q, chunk): a share of the partner sweep of q.  Every
+// unordered partner pair {q1, q2 = -q - q1} is visited once and contributes
+// the terms of both orderings (the JDOS has no vertex, so this holds for any
+// crystal): D+ gets g((w + w1) - w2) and g((w + w2) - w1), D- gets
+// g((w - w1) - w2) and g((w - w2) - w1), each with its own exact FP64 cut.
+// The sweep pre-classifies in FP32 (the band of the linewidths, so no term
+// inside the cut is dropped) and queues candidates with a 4-bit term mask;
+// the queue is evaluated densely (cut, smearing in FP64) and summed per
+// branch in queue order; fixed-order reductions within the work item, then
+// over the chunks of a q (jdos_finish).
+constexpr int kJdosCap = 2048;
 
 template <int NBM>  // branches held per thread: 3 N_b <= NBM
-__global__ __launch_bounds__(kJdosThreads) void jdos_kernel(LwParams p, const double* __restrict__ omega,
-                                                            const double* __restrict__ vel,
-                                                            const uint8_t* __restrict__ phys,
-                                                            const uint8_t* __restrict__ sel,
-                                                            double* __restrict__ part) {
-  __shared__ double red[kJdosThreads];
+__global__ __launch_bounds__(kJdosThreads) void jdos_kernel(
+    LwParams p, const double* __restrict__ omega, const double* __restrict__ vel,
+    const float4* __restrict__ modef, const uint8_t* __restrict__ phys,
+    const uint8_t* __restrict__ sel, const int32_t* __restrict__ live_list,
+    const int32_t* __restrict__ n_live_ptr, int n_chunk, double* __restrict__ part) {
+  constexpr int BS = kJdosThreads;
+  __shared__ int rq_q1[kJdosCap];
+  __shared__ int rq_code[kJdosCap];
+  __shared__ int wave_tot[BS / 64];
+  __shared__ double wq64[NBM];
+  __shared__ double red[BS];
   const int NB3 = p.nb3;
-  const int q = blockIdx.x, chunk = blockIdx.y, tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wk = blockIdx.x;
+  if (wk >= *n_live_ptr * n_chunk) return;
+  const int kq = wk / n_chunk, chunk = wk - kq * n_chunk;
+  const int q = live_list[kq];
   const int N0 = p.N[0], N1 = p.N[1], N2 = p.N[2];
   const int a0 = q / (N1 * N2), a1 = (q / N2) % N1, a2 = q % N2;
   unsigned live = 0;
-  double wq[NBM];
   float wqf[NBM];
   float wq_abs_max = 0.0f;
 #pragma unroll
   for (int s = 0; s < NBM; ++s) {
-    wq[s] = s < NB3 ? omega[q * NB3 + s] : 0.0;
-    wqf[s] = (float)wq[s];
+    const double w = s < NB3 ? omega[q * NB3 + s] : 0.0;
+    wqf[s] = (float)w;
     wq_abs_max = fmaxf(wq_abs_max, fabsf(wqf[s]));
     if (s < NB3) live |= (phys[q * NB3 + s] && sel[q * NB3 + s]) ? 1u << s : 0u;
   }
-  if (!live) return;
-  double ap[NBM], am[NBM];
+  if (tid < NB3) wq64[tid] = omega[q * NB3 + tid];
+  __syncthreads();
+
+  double accp[NBM], accm[NBM];
 #pragma unroll
-  for (int s = 0; s < NBM; ++s) ap[s] = am[s] = 0.0;
-  const int n_items = p.nq * NB3;
-  const int per = (n_items + kJdosChunks - 1) / kJdosChunks;
-  const int lo = chunk * per, hi = min(n_items, lo + per);
-  for (int item = lo + tid; item < hi; item += kJdosThreads) {
-    const int q1 = item / NB3, s1 = item % NB3;
-    const int m1 = q1 * NB3 + s1;
-    if (!phys[m1]) continue;
-    const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
-    const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
-              c2 = ((-a2 - b2) % N2 + N2) % N2;
-    const int q2 = (c0 * N1 + c1) * N2 + c2;
-    const double w1 = omega[m1];
-    const double* v1 = vel + 3 * (size_t)m1;
-    for (int s2 = 0; s2 < NB3; ++s2) {
-      const int m2 = q2 * NB3 + s2;
-      if (!phys[m2]) continue;
-      const double w2 = omega[m2];
-      // FP32 pre-classification (the band of the linewidth kernels); the
-      // exact FP64 cut of the oracle decides inside the band, and g is
-      // evaluated in FP64 for the pairs that pass
-      double s2p, s2m, Sp, Sm;
-      widths2(p, v1, vel + 3 * (size_t)m2, s2p, s2m, Sp, Sm);
-      const float scl = wq_abs_max + fabsf((float)w1) + fabsf((float)w2);
-      const Band bp = make_band(s2p, scl), bm = make_band(s2m, scl);
-      const float cp = (float)(w1 - w2), cm = (float)(-w1 - w2);
+  for (int s = 0; s < NBM; ++s) accp[s] = accm[s] = 0.0;
+
+  // queue entries [0, n): exact cuts and smearing of the flagged terms
+  auto process = [&](int n) {
+    for (int r = tid; r < n; r += BS) {
+      const int q1 = rq_q1[r], code = rq_code[r];
+      const int s = code & 255, s1 = (code >> 8) & 255, s2 = (code >> 16) & 255, fl = code >> 24;
+      const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
+      const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
+                c2 = ((-a2 - b2) % N2 + N2) % N2;
+      const int m1 = q1 * NB3 + s1, m2 = ((c0 * N1 + c1) * N2 + c2) * NB3 + s2;
+      const double w = wq64[s], w1 = omega[m1], w2 = omega[m2];
+      double sp, sm;
+      widths(p, vel, m1, m2, sp, sm);
+      double gp = 0.0, gm = 0.0;
+      if (fl & 1) {
+        const double x = (w + w1) - w2;
+        if (fabs(x) < 2.0 * sp) gp += smear(p.shape, x, sp);
+      }
+      if (fl & 4) {
+        const double x = (w + w2) - w1;
+        if (fabs(x) < 2.0 * sp) gp += smear(p.shape, x, sp);
+      }
+      if (fl & 2) {
+        const double x = (w - w1) - w2;
+        if (fabs(x) < 2.0 * sm) gm += smear(p.shape, x, sm);
+      }
+      if (fl & 8) {
+        const double x = (w - w2) - w1;
+        if (fabs(x) < 2.0 * sm) gm += smear(p.shape, x, sm);
+      }
 #pragma unroll
-      for (int s = 0; s < NBM; ++s) {
-        if (s >= NB3 || !(live >> s & 1u)) continue;
-        const float fp = fabsf(wqf[s] + cp), fm = fabsf(wqf[s] + cm);
-        if (fp < bp.hi && (fp < bp.lo || exact_pass(p, wq[s], w1, w2, Sp, Sm, true))) {
-          const double sg = p.adaptive ? fmax(sqrt(Sp * p.h2 / 12.0), p.sig_floor) : p.sig_fixed;
-          ap[s] += smear(p.shape, (wq[s] + w1) - w2, sg);
+      for (int k = 0; k < NBM; ++k) {
+        accp[k] += (k == s) ? gp : 0.0;
+        accm[k] += (k == s) ? gm : 0.0;
+      }
+    }
+  };
+
+  // sweep: this work item's share of the partner points, whole rounds
+  const Partners prt(true, a0, a1, a2, N0, N1, N2);
+  const int n_all = prt.n * NB3;
+  const int per = ((n_all + n_chunk - 1) / n_chunk + BS - 1) / BS * BS;
+  const int i_lo = min(n_all, chunk * per), i_hi = min(n_all, i_lo + per);
+  int fill = 0;
+  for (int base = i_lo; base < i_hi; base += BS) {
+    const int item = base + tid;
+    unsigned bpm[NBM], brr[NBM];  // per s'': D+ | D- << 16 of this ordering; D+ of the mirror
+#pragma unroll
+    for (int k = 0; k < NBM; ++k) bpm[k] = brr[k] = 0;
+    int count = 0, q1 = 0, s1 = 0, dbl = 0;
+    if (item < i_hi) {
+      const int qi = item / NB3;
+      s1 = item - qi * NB3;
+      int b0, b1, b2;
+      dbl = prt.get(qi, N1, N2, b0, b1, b2);
+      q1 = (b0 * N1 + b1) * N2 + b2;
+      const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
+                c2 = ((-a2 - b2) % N2 + N2) % N2;
+      const int q2 = (c0 * N1 + c1) * N2 + c2;
+      const float4 f1 = modef[q1 * NB3 + s1];
+      const unsigned dmask = dbl ? ~0u : 0u;
+#pragma unroll
+      for (int s2 = 0; s2 < NBM; ++s2) {
+        if (s2 >= NB3) break;
+        const float4 f2 = modef[q2 * NB3 + s2];  // NaN frequency below the floor
+        float s2p, s2m, e_sig;
+        widths2_f(p, f1, f2, s2p, s2m, e_sig);
+        const float scl = wq_abs_max + fabsf(f1.w) + fabsf(f2.w);
+        const Band bp = make_band_f(s2p, scl, e_sig), bm = make_band_f(s2m, scl, e_sig);
+        const float cp = f1.w - f2.w, cm = -f1.w - f2.w;
+        unsigned mp = 0, mm = 0, mr = 0;
+#pragma unroll
+        for (int s = 0; s < NBM; ++s) {
+          const float ap = fabsf(wqf[s] + cp), ar = fabsf(wqf[s] - cp), am = fabsf(wqf[s] + cm);
+          mp |= (ap < bp.hi) ? (1u << s) : 0u;
+          mr |= (ar < bp.hi) ? (1u << s) : 0u;
+          mm |= (am < bm.hi) ? (1u << s) : 0u;
         }
-        if (fm < bm.hi && (fm < bm.lo || exact_pass(p, wq[s], w1, w2, Sp, Sm, false))) {
-          const double sg = p.adaptive ? fmax(sqrt(Sm * p.h2 / 12.0), p.sig_floor) : p.sig_fixed;
-          am[s] += smear(p.shape, (wq[s] - w1) - w2, sg);
+        mp &= live;
+        mm &= live;
+        mr &= live & dmask;
+        bpm[s2] = mp | (mm << 16);
+        brr[s2] = mr;
+        count += __popc(mp | mm | mr);
+      }
+    }
+    // block-wide exclusive scan of count (fixed order)
+    int incl = count;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wave_tot[wv] = incl;
+    __syncthreads();
+    int wave_off = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < BS / 64; ++k) {
+      const int t = wave_tot[k];
+      wave_off += (k < wv) ? t : 0;
+      total += t;
+    }
+    const int my_off = wave_off + incl - count;
+    __syncthreads();
+    int written = 0;
+    while (written < total) {
+      const int take = min(kJdosCap - fill, total - written);
+      if (count > 0 && my_off < written + take && my_off + count > written) {
+        int rank = my_off;
+#pragma unroll
+        for (int s2 = 0; s2 < NBM; ++s2) {
+          if (s2 >= NB3) break;
+          const unsigned mp = bpm[s2] & 0xffffu, mm = bpm[s2] >> 16, mr = brr[s2];
+          unsigned any = mp | mm | mr;
+          while (any) {
+            const int s = __ffs(any) - 1;
+            any &= any - 1;
+            if (rank >= written && rank < written + take) {
+              const int fl = (mp >> s & 1u) | (mm >> s & 1u) << 1 | (mr >> s & 1u) << 2 |
+                             ((mm >> s & 1u) & dbl) << 3;
+              const int slot = fill + rank - written;
+              rq_q1[slot] = q1;
+              rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (fl << 24);
+            }
+            ++rank;
+          }
         }
+      }
+      fill += take;
+      written += take;
+      __syncthreads();
+      if (fill == kJdosCap) {
+        process(fill);
+        fill = 0;
+        __syncthreads();
       }
     }
   }
-  double* out = part + ((size_t)q * kJdosChunks + chunk) * 32;
+  process(fill);
+
+  double* out = part + ((size_t)kq * kFusedMaxChunks + chunk) * 32;
 #pragma unroll
   for (int s = 0; s < NBM; ++s) {
     if (s >= NB3) break;
     for (int which = 0; which < 2; ++which) {
       __syncthreads();
-      red[tid] = which ? am[s] : ap[s];
+      red[tid] = which ? accm[s] : accp[s];
       __syncthreads();
-      for (int w = kJdosThreads / 2; w > 0; w >>= 1) {
+      for (int w = BS / 2; w > 0; w >>= 1) {
         if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
       }
@@ -119,29 +236,38 @@ __global__ __launch_bounds__(kJdosThreads) void jdos_kernel(LwParams p, const do
   }
 }
 
-// D+- of the selected modes: the chunk sums in chunk order, / N_q; 0 below nu_min.
+// D+- of the selected modes: the chunk sums of their q in chunk order, / N_q;
+// 0 below nu_min.
 __global__ void jdos_finish(int n_modes, int nb3, int nq, const uint8_t* __restrict__ phys,
-                            const uint8_t* __restrict__ sel, const double* __restrict__ part,
+                            const uint8_t* __restrict__ sel, const int32_t* __restrict__ idx_of_q,
+                            int n_chunk, const double* __restrict__ part,
                             double* __restrict__ dplus, double* __restrict__ dminus) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_modes || !sel[m]) return;
-  const int q = m / nb3, s = m % nb3;
+  const int q = m / nb3, s = m - q * nb3, k = idx_of_q[q];
   double sp = 0.0, sm = 0.0;
-  if (phys[m])
-    for (int c = 0; c < kJdosChunks; ++c) {
-      sp += part[((size_t)q * kJdosChunks + c) * 32 + 2 * s];
-      sm += part[((size_t)q * kJdosChunks + c) * 32 + 2 * s + 1];
+  if (phys[m] && k >= 0)
+    for (int c = 0; c < n_chunk; ++c) {
+      sp += part[((size_t)k * kFusedMaxChunks + c) * 32 + 2 * s];
+      sm += part[((size_t)k * kFusedMaxChunks + c) * 32 + 2 * s + 1];
     }
   dplus[m] = phys[m] ? sp / nq : 0.0;
   dminus[m] = phys[m] ? sm / nq : 0.0;
 }
 
-__global__ void jdos_prepare(int n_modes, const double* __restrict__ omega, double nu_min,
-                             uint8_t* __restrict__ phys, uint8_t* __restrict__ sel, int sel_all) {
+// Flags and the FP32 (v, omega) mode copies of the sweep (omega NaN below
+// nu_min, so that every comparison against such a mode fails).
+__global__ void jdos_prepare(int n_modes, const double* __restrict__ omega,
+                             const double* __restrict__ vel, double nu_min,
+                             uint8_t* __restrict__ phys, uint8_t* __restrict__ sel,
+                             float4* __restrict__ modef, int sel_all) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_modes) return;
-  phys[m] = (omega[m] / kTwoPi) >= nu_min;
+  const bool ph = (omega[m] / kTwoPi) >= nu_min;
+  phys[m] = ph;
   sel[m] = sel_all ? 1 : 0;
+  modef[m] = make_float4((float)vel[3 * (size_t)m], (float)vel[3 * (size_t)m + 1],
+                         (float)vel[3 * (size_t)m + 2], ph ? (float)omega[m] : __builtin_nanf(""));
 }
 
 __global__ void jdos_select(const int32_t* __restrict__ subset, long n, int n_modes,
@@ -1010,11 +1136,32 @@ int launch_train(const TrainArgs& a, int M, hipStream_t st, bool* too_large) {
 
 using namespace kaldo;
 
+// Workspace: phys and sel flags (N_q 3N_b bytes each), the FP32 mode copies,
+// the live-q list, its inverse and count, and the per-(q, chunk) sums.
+struct JdosWs {
+  size_t phys, sel, modef, qlist, part, total;
+};
+static JdosWs jdos_ws(size_t nq, size_t nm) {
+  JdosWs w;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  w.phys = take(nm);
+  w.sel = take(nm);
+  w.modef = take(sizeof(float4) * nm);
+  w.qlist = take(sizeof(int32_t) * (2 * nq + 1));
+  w.part = take(sizeof(double) * nq * kFusedMaxChunks * 32);
+  w.total = o;
+  return w;
+}
+
 extern "C" size_t kaldo_jdos_workspace(const kaldo_crystal* c, const int32_t* mesh) {
   if (!c || !mesh || mesh[0] < 1 || mesh[1] < 1 || mesh[2] < 1) return 0;
   const size_t nq = (size_t)mesh[0] * mesh[1] * mesh[2];
-  const size_t nm = nq * c->nb3;
-  return (nm + 255) / 256 * 256 * 2 + nq * kJdosChunks * 32 * sizeof(double);
+  return jdos_ws(nq, nq * c->nb3).total;
 }
 
 extern "C" int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
@@ -1027,30 +1174,58 @@ extern "C" int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const dou
   const int rc = check_broadening(b, true);
   if (rc) return rc;
   KALDO_REQUIRE(n_subset >= 0 && (n_subset == 0 || modes_subset), "kaldo_jdos: bad subset");
+  const long nq_l = (long)mesh[0] * mesh[1] * mesh[2];
+  KALDO_REQUIRE(nq_l <= 65535L, "kaldo_jdos: mesh too large (N_q > 65535)");
   const size_t need = kaldo_jdos_workspace(c, mesh);
   KALDO_REQUIRE(workspace && workspace_bytes >= need, "kaldo_jdos: workspace too small");
   if (modes_subset && n_subset == 0) return KALDO_OK;
-  const int nq = mesh[0] * mesh[1] * mesh[2];
+  const int nq = (int)nq_l;
   const int nm = nq * c->nb3;
-  const size_t flags = ((size_t)nm + 255) / 256 * 256;
-  auto* phys = static_cast<uint8_t*>(workspace);
-  uint8_t* sel = phys + flags;
-  auto* part = reinterpret_cast<double*>(phys + 2 * flags);
+  const JdosWs w = jdos_ws(nq, nm);
+  auto* base = static_cast<unsigned char*>(workspace);
+  uint8_t* phys = base + w.phys;
+  uint8_t* sel = base + w.sel;
+  auto* modef = reinterpret_cast<float4*>(base + w.modef);
+  auto* qlist = reinterpret_cast<int32_t*>(base + w.qlist);
+  auto* part = reinterpret_cast<double*>(base + w.part);
+  int32_t* live_list = qlist;
+  int32_t* idx_of_q = qlist + nq;
+  int32_t* n_live = qlist + 2 * nq;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  KALDO_LAUNCH("jdos_prepare", jdos_prepare, dim3((nm + 255) / 256), dim3(256), 0, st, nm, omega,
-               b->nu_min_thz, phys, sel, modes_subset ? 0 : 1);
+  KALDO_LAUNCH("jdos_prepare", jdos_prepare, dim3((nm + 255) / 256), dim3(256), 0, st, nm, omega, vel,
+               b->nu_min_thz, phys, sel, modef, modes_subset ? 0 : 1);
   if (modes_subset)
     KALDO_LAUNCH("jdos_select", jdos_select, dim3((unsigned)((n_subset + 255) / 256)), dim3(256), 0,
                  st, modes_subset, (long)n_subset, nm, sel);
+  KALDO_LAUNCH("lw_live_q", lw_live_q<>, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel, live_list,
+               idx_of_q, n_live);
   const LwParams p = make_params(c, mesh, 300.0, b);
+  // work items (live q, chunk) as in the crystal linewidths: the grid covers
+  // min(N_q, n_subset) q-points, the chunk count assumes n_subset / 3N_b
+  const long upper = modes_subset ? std::min<long>(nq, n_subset) : nq;
+  const long guess = modes_subset ? std::max<long>(1, n_subset / c->nb3) : nq;
+  const int max_chunks =
+      (int)std::max<long>(1, std::min<long>(kFusedMaxChunks, (long)nq * c->nb3 / (2 * kJdosThreads)));
+  int dev = 0, n_cu = 0, per_cu = 0;
+  KALDO_HIP(hipGetDevice(&dev));
+  KALDO_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   if (c->nb3 <= 8)
-    KALDO_LAUNCH("jdos_kernel", jdos_kernel<8>, dim3(nq, kJdosChunks), dim3(kJdosThreads), 0, st, p,
-                 omega, vel, phys, sel, part);
+    KALDO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jdos_kernel<8>, kJdosThreads, 0));
   else
-    KALDO_LAUNCH("jdos_kernel", jdos_kernel<16>, dim3(nq, kJdosChunks), dim3(kJdosThreads), 0, st, p,
-                 omega, vel, phys, sel, part);
-  KALDO_LAUNCH("jdos_finish", jdos_finish, dim3((nm + 255) / 256), dim3(256), 0, st, nm, c->nb3, nq, phys,
-               sel, part, dplus, dminus);
+    KALDO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jdos_kernel<16>, kJdosThreads, 0));
+  const long slots = (long)std::max(1, per_cu) * n_cu;
+  const int n_chunk = std::min(fused_chunks((int)std::min<long>(guess, 1l << 30),
+                                            (int)std::min<long>(4 * slots, 1l << 30)),
+                               max_chunks);
+  const dim3 grid((unsigned)(upper * n_chunk));
+  if (c->nb3 <= 8)
+    KALDO_LAUNCH("jdos_kernel", jdos_kernel<8>, grid, dim3(kJdosThreads), 0, st, p, omega, vel, modef,
+                 phys, sel, live_list, n_live, n_chunk, part);
+  else
+    KALDO_LAUNCH("jdos_kernel", jdos_kernel<16>, grid, dim3(kJdosThreads), 0, st, p, omega, vel, modef,
+                 phys, sel, live_list, n_live, n_chunk, part);
+  KALDO_LAUNCH("jdos_finish", jdos_finish, dim3((nm + 255) / 256), dim3(256), 0, st, nm, c->nb3, nq,
+               phys, sel, idx_of_q, n_chunk, part, dplus, dminus);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
 }
