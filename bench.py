@@ -368,6 +368,24 @@ def main():
                     executed_fraction=f_exec, executed_tflops=achieved * f_exec,
                     executed_frac=achieved * f_exec / FP32_VECTOR_PEAK,
                     dense_equiv_tflops=F_blk * n_modes / (avg_ms * 1e-3) / 1e12)
+    if dom.startswith("lw_mfma"):
+        # Dense MFMA kernel: per (q, swept partner q1, live branch s) two complex
+        # 16x16x16 products (T = B_s eta2, V = eta1^T T), each two real 16x16x32
+        # products, i.e. 65,536 FLOP; the BF16x3 form issues three BF16 products
+        # per real product.  Partners: (N_q + 1) / 2 per q on average when the
+        # mirrored pair is visited once, else N_q.
+        om_h = om.cpu().numpy()
+        n_live = int(np.sum(om_h / (2 * np.pi) >= cfg.broadening.nu_min_thz))
+        partners = (nq + 1) / 2.0 if fc3_mirror_symmetric(model) else float(nq)
+        split = prec == K.BF16X3
+        flop = n_live * partners * 65536.0 * (3 if split else 1)
+        achieved = flop / (avg_ms * 1e-3) / 1e12
+        peak = 2500.0 if split else FP32_VECTOR_PEAK
+        roof = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                    traffic=None, kernel=dom, kernel_ms=avg_ms,
+                    work_model="dense 16x16 tiles per (q, partner, live branch)"
+                               + (", three BF16 products counted" if split else ""),
+                    flop_per_launch=flop)
     out = {
         "metric": METRIC,
         "value": n_modes / (ms_per_step * 1e-3),
@@ -379,7 +397,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == K.FP32 else "f64",
+        "dtype": {K.FP32: "f32", K.FP64: "f64", K.BF16X3: "bf16x3"}[prec],
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.description}", "modes": n_modes,
                    "mesh": list(mesh), "precision": a.precision},

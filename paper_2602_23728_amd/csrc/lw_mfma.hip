@@ -15,7 +15,9 @@
 //   BF16x3:     v_mfma_f32_16x16x32_bf16 on x = hi + lo splits,
 //               hi*hi + hi*lo + lo*hi per real product, FP32 accumulation.
 // One workgroup per q (8 waves sharing A~_q in LDS, two per SIMD); each wave
-// takes its own q1 values.
+// takes its own q1 values.  With Phi3 symmetric in its last two slots the
+// tile of the mirrored partner (q2, q1) is V^T, so only q1 <_lex q2 is swept
+// (q1 == q2 once) and each candidate carries the terms of both orderings.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -146,14 +148,17 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
       const int e = base + lane;
       if (e < n_cand) {
         const int code = cq_code[wv][e], c1 = cq_q1[wv][e];
-        const int cs_ = code & 255, cs1 = (code >> 8) & 255, cs2 = code >> 16;
+        const int cs_ = code & 255, cs1 = (code >> 8) & 255, cs2 = (code >> 16) & 255,
+                  cdbl = code >> 24;
         const int d0 = c1 / (N1 * N2), d1 = (c1 / N2) % N1, d2 = c1 % N2;
         const int e0 = ((-a0 - d0) % N0 + N0) % N0, e1_ = ((-a1 - d1) % N1 + N1) % N1,
                   e2_ = ((-a2 - d2) % N2 + N2) % N2;
         const int m1 = c1 * NB3 + cs1, m2 = ((e0 * N1 + e1_) * N2 + e2_) * NB3 + cs2;
         double sp, sm;
         widths(p, vel, m1, m2, sp, sm);
-        const double wt = pair_weight(p, wq64[cs_], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
+        double wt = pair_weight(p, wq64[cs_], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
+        // the mirrored ordering: same |V|^2 and widths, its own cut
+        if (cdbl) wt += pair_weight(p, wq64[cs_], omega[m2], omega[m1], occ[m2], occ[m1], sp, sm);
         const double c = wt * cq_v2[wv][e];
         // register accumulators need a static index: add to the selected one
 #pragma unroll
@@ -164,8 +169,11 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
     wave_sync();
   };
 
-  for (int q1 = wv; q1 < p.nq; q1 += kMfmaWaves) {
-    const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
+  const Partners prt(p.half != 0, a0, a1, a2, N0, N1, N2);
+  for (int pi = wv; pi < prt.n; pi += kMfmaWaves) {
+    int b0, b1, b2;
+    const int dbl = prt.get(pi, N1, N2, b0, b1, b2);  // wave-uniform
+    const int q1 = (b0 * N1 + b1) * N2 + b2;
     const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
               c2 = ((-a2 - b2) % N2 + N2) % N2;
     const int q2 = (c0 * N1 + c1) * N2 + c2;
@@ -348,14 +356,15 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
         bool near = false;
         if (pr_ok >> r & 1u) {
           const float ap = fabsf(wsf + cpv[r]), am = fabsf(wsf + cmv[r]);
-          near = ap < bhi_p[r] || am < bhi_m[r];
+          const float ar = fabsf(wsf - cpv[r]);  // coalescence of the mirrored ordering
+          near = ap < bhi_p[r] || am < bhi_m[r] || (dbl && ar < bhi_p[r]);
         }
         const unsigned long long mask = __ballot(near);
         if (near) {
           const unsigned lo = (unsigned)mask, hi = (unsigned)(mask >> 32);
           const int off = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
           const int slot = n_cand + off;
-          cq_code[wv][slot] = s | ((4 * lg + r) << 8) | (s2 << 16);
+          cq_code[wv][slot] = s | ((4 * lg + r) << 8) | (s2 << 16) | (dbl << 24);
           cq_q1[wv][slot] = q1;
           cq_v2[wv][slot] = (double)vr[r] * (double)vr[r] + (double)vi[r] * (double)vi[r];
         }
