@@ -278,8 +278,16 @@ __global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtil
   }
 }
 
+// Waves per SIMD the register allocation targets: three for the split form
+// (measured 0.41 -> 0.38 ms per batch of C4), the compiler's choice (two) for
+// FP32, which loses with three.
 template <bool SPLIT>
-__global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0, int n_tri,
+constexpr int gemm_waves_per_eu() {
+  return SPLIT ? 3 : 1;
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_per_eu<SPLIT>()))) void gm_gemm(LwParams p, int n, int np, int m0, int n_tri,
                                                const float* __restrict__ et32,
                                                const __bf16* __restrict__ eth,
                                                const __bf16* __restrict__ etl,
@@ -333,6 +341,7 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
   constexpr int PPR = KT / 4;  // 16-byte pieces per row (FP32 form)
   constexpr int NP = kMT * PPR / 256;  // pieces per thread
   static_assert(SPLIT || kMT * PPR == NP * 256, "whole pieces per thread");
+  static_assert(SPLIT || KT == 16, "one 16-byte read per tile row covers the slice");
   uint4 pa[NP], pb[NP];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -364,20 +373,25 @@ __global__ __launch_bounds__(256) void gm_gemm(LwParams p, int n, int np, int m0
       if (more) fetch(k0 + KT);
       const float* A = sA32 + cur * kMT * LDA32;
       const float* B = sB32 + cur * kMT * LDA32;
+      // K order inside the slice: MFMA step j pairs lane group lg with
+      // k = 4 lg + j (the same on both operands), so a lane's four k values
+      // are contiguous and come in one 16-byte LDS read per tile
+      float4 a4[4], b4[4];
 #pragma unroll
-      for (int kk = 0; kk < KT; kk += 4) {
-        float a[4], b[4];
+      for (int t = 0; t < 4; ++t) {
+        a4[t] = *reinterpret_cast<const float4*>(&A[(wm + 16 * t + lr) * LDA32 + 4 * lg]);
+        b4[t] = *reinterpret_cast<const float4*>(&B[(wn + 16 * t + lr) * LDA32 + 4 * lg]);
+      }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          a[t] = A[(wm + 16 * t + lr) * LDA32 + kk + lg];
-          b[t] = B[(wn + 16 * t + lr) * LDA32 + kk + lg];
-        }
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
-          for (int tb = 0; tb < 4; ++tb)
-            acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ta], b[tb], acc[ta][tb], 0, 0, 0);
-      }
+          for (int tb = 0; tb < 4; ++tb) {
+            const float av = j == 0 ? a4[ta].x : j == 1 ? a4[ta].y : j == 2 ? a4[ta].z : a4[ta].w;
+            const float bv = j == 0 ? b4[tb].x : j == 1 ? b4[tb].y : j == 2 ? b4[tb].z : b4[tb].w;
+            acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ta][tb], 0, 0, 0);
+          }
       if (more) stage(cur ^ 1);
       __syncthreads();
       cur ^= 1;

@@ -1,36 +1,39 @@
 // RTA thermal conductivity (paper: Eq. heatcap, Eq. rta; lifetime
-// tau = 1/(2 Gamma) of Eq. lifetime).  One workgroup, fixed-order reduction.
+// tau = 1/(2 Gamma) of Eq. lifetime).  One workgroup of 1024 threads (the
+// call has no workspace for partial sums), fixed-order reduction.
 #include <cmath>
 
 #include "common.h"
 
 namespace kaldo {
 
-__global__ __launch_bounds__(256) void kappa_kernel(long n_modes, const double* __restrict__ omega,
+constexpr int kKappaThreads = 1024;
+
+__global__ __launch_bounds__(kKappaThreads) void kappa_kernel(long n_modes, const double* __restrict__ omega,
                                                     const double* __restrict__ vel,
                                                     const double* __restrict__ gamma,
                                                     double inv_kt_hbar, double nu_min,
                                                     double scale, double* __restrict__ kappa) {
-  __shared__ double red[256][7];
+  __shared__ double red[kKappaThreads][6];
   const int t = threadIdx.x;
   // max Gamma (order-independent)
   double gmax = 0.0;
-  for (long m = t; m < n_modes; m += 256) gmax = fmax(gmax, gamma[m]);
+  for (long m = t; m < n_modes; m += kKappaThreads) gmax = fmax(gmax, gamma[m]);
   red[t][0] = gmax;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kKappaThreads / 2; w > 0; w >>= 1) {
     if (t < w) red[t][0] = fmax(red[t][0], red[t + w][0]);
     __syncthreads();
   }
   const double floor_g = kGammaFloorRel * red[0][0];
   __syncthreads();
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (long m = t; m < n_modes; m += 256) {
+  for (long m = t; m < n_modes; m += kKappaThreads) {
     const double w = omega[m], g = gamma[m];
     if (!(w / kTwoPi >= nu_min) || !(g > floor_g) || !(g > 0.0)) continue;
     const double x = w * inv_kt_hbar;
     const double em = expm1(x);
-    const double c = x * x * exp(x) / (em * em);
+    const double c = x * x * (em + 1.0) / (em * em);  // e^x = expm1(x) + 1
     const double ct = c * (1.0 / (2.0 * g));
     const double* v = vel + 3 * m;
     acc[0] += ct * v[0] * v[0];
@@ -42,7 +45,7 @@ __global__ __launch_bounds__(256) void kappa_kernel(long n_modes, const double* 
   }
   for (int k = 0; k < 6; ++k) red[t][k] = acc[k];
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kKappaThreads / 2; w > 0; w >>= 1) {
     if (t < w)
       for (int k = 0; k < 6; ++k) red[t][k] += red[t + w][k];
     __syncthreads();
@@ -67,7 +70,7 @@ extern "C" int kaldo_kappa_rta(const kaldo_crystal* c, const int32_t* mesh, cons
   const long nq = (long)mesh[0] * mesh[1] * mesh[2];
   const long n_modes = nq * c->nb3;
   const double scale = kKappaUnit / ((double)nq * c->volume);
-  KALDO_LAUNCH("kappa_kernel", kappa_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), n_modes,
+  KALDO_LAUNCH("kappa_kernel", kappa_kernel, dim3(1), dim3(kKappaThreads), 0, static_cast<hipStream_t>(stream), n_modes,
                      omega, vel, gamma, kHbar / (kKb * temperature), nu_min_thz, scale, kappa);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
