@@ -31,7 +31,7 @@ FP32_VECTOR_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 and FP32 MFMA (datasheet
 # here, reported as null once they change.
 MEASURED_TRAFFIC = {
     "lw_fused": {"sources": ["lw_fused.hip", "lw_common.h", "common.h"],
-                 "sha256": "63ec0cd99fef4d1e888aa4e66b609bab37c9d39aa53b4c59bcb30384dfc8a48c",
+                 "sha256": "64754e85e1562ee71024d0694f491ffe951bf371d66cf46a3b86ddd92df7849f",
                  "bytes": 41823842, "config": "C2"},
 }
 

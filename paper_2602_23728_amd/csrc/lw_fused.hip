@@ -106,7 +106,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     float wqf[NB3];
     float wq_abs_max = 0.0f;
     unsigned live = 0;
-  #pragma unroll
+#pragma unroll
     for (int s = 0; s < NB3; ++s) {
       const double w = omega[q * NB3 + s];
       wqf[s] = (float)w;
@@ -144,7 +144,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     __syncthreads();
 
     double acc[NB3];
-  #pragma unroll
+#pragma unroll
     for (int s = 0; s < NB3; ++s) acc[s] = 0.0;
 
     // 3. projection of queue entries [0, n)
@@ -167,23 +167,23 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         C x[NB3], y[NB3];
         const C* xs = etaT + ((size_t)q1 * NB3 + s1) * NB3;
         const C* ys = etaT + ((size_t)q2 * NB3 + s2) * NB3;
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < NB3; ++j) {
           x[j] = xs[j];
           y[j] = ys[j];
         }
         const C* ph = phase_tab + (size_t)q1 * p.n_d;
         T vr = 0, vi = 0;
-  #pragma unroll
+#pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
-  #pragma unroll
+#pragma unroll
           for (int kb = 0; kb < NB; ++kb) {
             const int b_lo = pair_ptr[jb * NB + kb], b_hi = pair_ptr[jb * NB + kb + 1];
             if (b_lo == b_hi) continue;
             C z[9];
-  #pragma unroll
+#pragma unroll
             for (int be = 0; be < 3; ++be)
-  #pragma unroll
+#pragma unroll
               for (int ga = 0; ga < 3; ++ga) {
                 const C u = x[3 * jb + be], v = y[3 * kb + ga];
                 z[be * 3 + ga] = Cx<T>::make(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
@@ -191,7 +191,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
             for (int blk = b_lo; blk < b_hi; ++blk) {
               const C* ab = at + (size_t)blk * 9 * NB3 + s;
               T ur = 0, ui = 0;
-  #pragma unroll
+#pragma unroll
               for (int k = 0; k < 9; ++k) {
                 const C a = ab[k * NB3];
                 ur += a.x * z[k].x - a.y * z[k].y;
@@ -204,7 +204,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           }
         }
         const double c = w * ((double)vr * (double)vr + (double)vi * (double)vi);
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < NB3; ++k) acc[k] += (k == s) ? c : 0.0;
       }
     };
@@ -220,7 +220,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     for (int base = i_lo; base < n_items; base += BS) {
       const int item = base + tid;
       unsigned bits[NB3];
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < NB3; ++k) bits[k] = 0;
       int count = 0;
       int q1 = 0, s1 = 0, dbl = 0;
@@ -236,7 +236,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         const int m1 = q1 * NB3 + s1;
         const unsigned dmask = dbl ? ~0u : 0u;
         const float4 f1 = modef[m1];
-  #pragma unroll
+#pragma unroll
         for (int s2 = 0; s2 < NB3; ++s2) {
           const int m2 = q2 * NB3 + s2;
           // FP32 classification from the mode copies (a mode below the floor
@@ -252,7 +252,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           // ar is the coalescence |x+| of the mirrored ordering, (w + w2) - w1;
           // the decay |x-| is the same number in FP32 for both orderings.
           unsigned b = 0, br = 0, amb_p = 0, amb_r = 0, amb_m = 0;
-  #pragma unroll
+#pragma unroll
           for (int s = 0; s < NB3; ++s) {
             const float ap = fabsf(wqf[s] + cp), ar = fabsf(wqf[s] - cp), am = fabsf(wqf[s] + cm);
             b |= ((ap < bp.lo) || (am < bm.lo)) ? (1u << s) : 0u;
@@ -287,7 +287,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
       }
       // block-wide exclusive scan of count (fixed order)
       int incl = count;
-  #pragma unroll
+#pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         const int v = __shfl_up(incl, off, 64);
         if (lane >= off) incl += v;
@@ -295,7 +295,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
       if (lane == 63) wave_tot[wv] = incl;
       __syncthreads();
       int wave_off = 0, total = 0;
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < BS / 64; ++k) {
         const int t = wave_tot[k];
         wave_off += (k < wv) ? t : 0;
@@ -308,7 +308,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         const int take = min(CAP - fill, total - written);
         if (count > 0 && my_off < written + take && my_off + count > written) {
           int rank = my_off;
-  #pragma unroll
+#pragma unroll
           for (int s2 = 0; s2 < NB3; ++s2) {
             unsigned b = bits[s2];
             while (b) {
@@ -336,7 +336,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     process(fill);
 
     // 4. fixed-order reduction per branch
-  #pragma unroll
+#pragma unroll
     for (int s = 0; s < NB3; ++s) {
       __syncthreads();
       red[tid] = acc[s];
