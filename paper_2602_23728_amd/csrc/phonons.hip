@@ -20,12 +20,13 @@ __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + 
 __device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.x * s, a.y * s}; }
 
 // Cyclic Jacobi on the Hermitian n x n matrix A (row-major, leading dim ld) in
-// LDS; accumulates the unitary V (initialised here to I).  For pivot (p,q)
+// LDS, one pivot at a time in row order; accumulates the unitary V
+// (initialised here to I).  For pivot (p,q)
 // with a_pq = |a| e^{i phi}, the rotation J = [[c, s e^{i phi}],
 // [-s e^{-i phi}, c]] with t = tan(theta) the smaller root of
 // t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp)/(2|a|), annihilates a_pq.
 // All 64 lanes of the workgroup call it; control flow is uniform.
-__device__ void jacobi_hermitian(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
+__device__ void jacobi_hermitian_seq(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
   for (int k = lane; k < n * n; k += 64) {
     int r = k / n, c = k % n;
     V[r * ld + c] = {r == c ? 1.0 : 0.0, 0.0};
@@ -103,6 +104,174 @@ __device__ void jacobi_hermitian(cplx* A, cplx* V, int n, int ld, int lane, int 
   __syncthreads();
 }
 
+// The same rotations, a round at a time: on the Hermitian n x n matrix A
+// (row-major, leading dim ld) in LDS; accumulates the unitary V (initialised
+// here to I).  For pivot (p,q)
+// with a_pq = |a| e^{i phi}, the rotation J = [[c, s e^{i phi}],
+// [-s e^{-i phi}, c]] with t = tan(theta) the smaller root of
+// t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp)/(2|a|), annihilates a_pq.
+// A sweep visits every pivot once in n' - 1 rounds of n'/2 disjoint pairs
+// (n' = n rounded up to even; the round-robin "circle" schedule), and the
+// rotations of one round are applied together: their parameters from the
+// current A, then A <- A J and V <- V J (columns), then A <- J^H A (rows),
+// with each pivot's 2 x 2 block set to its rotated values.  The row updates
+// of a round read A after all of its column updates, so the upper and lower
+// triangles are computed in different orders and are re-paired each sweep.
+// All 64 lanes of the workgroup call it; control flow is uniform.
+template <int NMAX>
+__device__ void jacobi_hermitian_par(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
+  constexpr int HP = (NMAX + 1) / 2;  // pairs per round at most
+  __shared__ int rp[HP], rq[HP];
+  __shared__ double rc[HP], rapp[HP], raqq[HP];
+  __shared__ cplx rse[HP], rsec[HP];
+  __shared__ double red[64];
+  for (int k = lane; k < n * n; k += 64) {
+    int r = k / n, c = k % n;
+    V[r * ld + c] = {r == c ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  const int np2 = (n + 1) & ~1, half = np2 / 2;
+  // this lane's update tasks, the same in every round: column updates
+  // (pair k, row r, matrix A or V) and row updates (pair k, column), packed
+  // as k | r << 8 | matrix << 16 (-1 when the lane has none)
+  constexpr int T2 = (NMAX * NMAX + 63) / 64, T3 = (NMAX * NMAX / 2 + 63) / 64;
+  int t2[T2], t3[T3];
+#pragma unroll
+  for (int i = 0; i < T2; ++i) {
+    const int task = lane + 64 * i;
+    t2[i] = task < 2 * n * half ? (task % half) | ((task / half) % n) << 8 | (task >= n * half) << 16 : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < T3; ++i) {
+    const int task = lane + 64 * i;
+    t3[i] = task < n * half ? (task % half) | (task / half) << 8 : -1;
+  }
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // The two triangles are updated by different rotation orders within a
+    // round, so they drift apart by rounding; the lower one is reset to the
+    // conjugate of the upper before each sweep (otherwise that anti-Hermitian
+    // residue keeps the off-diagonal norm above the stopping threshold).
+    if (sweep > 0) {
+      for (int k = lane; k < n * n; k += 64) {
+        const int r = k / n, c = k % n;
+        if (r > c) A[r * ld + c] = cconj(A[c * ld + r]);
+      }
+      __syncthreads();
+    }
+    // off-diagonal and total Frobenius norms
+    double off = 0.0, tot = 0.0;
+    for (int k = lane; k < n * n; k += 64) {
+      int r = k / n, c = k % n;
+      cplx a = A[r * ld + c];
+      double m2 = a.x * a.x + a.y * a.y;
+      tot += m2;
+      if (r != c) off += m2;
+    }
+    red[lane] = off;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+      if (lane < w) red[lane] += red[lane + w];
+      __syncthreads();
+    }
+    off = red[0];
+    __syncthreads();
+    red[lane] = tot;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+      if (lane < w) red[lane] += red[lane + w];
+      __syncthreads();
+    }
+    tot = red[0];
+    __syncthreads();
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int round = 0; round < np2 - 1; ++round) {
+      // 1. rotation of pair k (-1 for the dummy index or a zero pivot)
+      if (lane < half) {
+        int a, b;
+        if (lane == 0) {
+          a = 0;
+          b = 1 + round % (np2 - 1);
+        } else {
+          a = 1 + (round + lane) % (np2 - 1);
+          b = 1 + (round - lane + (np2 - 1)) % (np2 - 1);
+        }
+        const int p = min(a, b), q = max(a, b);
+        int pp = -1;
+        if (q < n) {
+          const double app = A[p * ld + p].x, aqq = A[q * ld + q].x;
+          const cplx apq = A[p * ld + q];
+          const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+          if (mag > 1e-300) {
+            const cplx e = {apq.x / mag, apq.y / mag};
+            const double tau = (aqq - app) / (2.0 * mag);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            const double s = t * c;
+            pp = p;
+            rc[lane] = c;
+            rse[lane] = cscale(e, s);
+            rsec[lane] = cscale(cconj(e), s);
+            rapp[lane] = app - t * mag;
+            raqq[lane] = aqq + t * mag;
+          }
+        }
+        rp[lane] = pp;
+        rq[lane] = q;
+      }
+      __syncthreads();
+      // 2. columns p, q of A and V: x_p' = c x_p - sec x_q, x_q' = se x_p + c x_q
+#pragma unroll
+      for (int i = 0; i < T2; ++i) {
+        if (t2[i] < 0) break;
+        const int k = t2[i] & 255, r = (t2[i] >> 8) & 255;
+        const int p = rp[k];
+        if (p < 0) continue;
+        const int q = rq[k];
+        cplx* M = (t2[i] >> 16) ? V : A;
+        const double c = rc[k];
+        const cplx se = rse[k], sec = rsec[k];
+        const cplx xp = M[r * ld + p], xq = M[r * ld + q];
+        M[r * ld + p] = {c * xp.x - (sec.x * xq.x - sec.y * xq.y), c * xp.y - (sec.x * xq.y + sec.y * xq.x)};
+        M[r * ld + q] = {se.x * xp.x - se.y * xp.y + c * xq.x, se.x * xp.y + se.y * xp.x + c * xq.y};
+      }
+      __syncthreads();
+      // 3. rows p, q of A: y_p' = c y_p - se y_q, y_q' = sec y_p + c y_q; the
+      //    pivot block takes its rotated values exactly
+#pragma unroll
+      for (int i = 0; i < T3; ++i) {
+        if (t3[i] < 0) break;
+        const int k = t3[i] & 255, col = t3[i] >> 8;
+        const int p = rp[k];
+        if (p < 0) continue;
+        const int q = rq[k];
+        if (col == p || col == q) {
+          A[p * ld + col] = col == p ? cplx{rapp[k], 0.0} : cplx{0.0, 0.0};
+          A[q * ld + col] = col == q ? cplx{raqq[k], 0.0} : cplx{0.0, 0.0};
+          continue;
+        }
+        const double c = rc[k];
+        const cplx se = rse[k], sec = rsec[k];
+        const cplx yp = A[p * ld + col], yq = A[q * ld + col];
+        A[p * ld + col] = {c * yp.x - (se.x * yq.x - se.y * yq.y), c * yp.y - (se.x * yq.y + se.y * yq.x)};
+        A[q * ld + col] = {sec.x * yp.x - sec.y * yp.y + c * yq.x, sec.x * yp.y + sec.y * yp.x + c * yq.y};
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+}
+
+// The round-parallel form for small matrices (measured: 1.5-2x faster for
+// 3N_b = 6), the pivot-by-pivot form for larger ones (2x faster at 3N_b = 15,
+// where the round's update passes cost more than they save).
+template <int NMAX>
+__device__ void jacobi_hermitian(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
+  if constexpr (NMAX <= 8)
+    jacobi_hermitian_par<NMAX>(A, V, n, ld, lane, max_sweeps);
+  else
+    jacobi_hermitian_seq(A, V, n, ld, lane, max_sweeps);
+}
+
 // Sort eigenpairs ascending: lam[k] with columns V[:,k] -> sorted into
 // lam_out / V (via scratch W).  Stable on ties.
 __device__ void sort_eigen(const double* lam_in, double* lam_out, cplx* V, cplx* W, int n,
@@ -178,7 +347,7 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
     A[a * LD + b] = {0.5 * (d1.x + d2.x), 0.5 * (d1.y - d2.y)};
   }
   __syncthreads();
-  jacobi_hermitian(A, V, n, LD, lane, 60);
+  jacobi_hermitian<NMAX>(A, V, n, LD, lane, 60);
   if (lane < n) lam[lane] = A[lane * LD + lane].x;
   sort_eigen(lam, lsort, V, W, n, LD, lane);
 
@@ -235,7 +404,7 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
       }
       __syncthreads();
       // eigenvectors of the m x m block into W (as V), Z diagonalised in place
-      jacobi_hermitian(Z, W, m, LD, lane, 60);
+      jacobi_hermitian<NMAX>(Z, W, m, LD, lane, 60);
       if (lane < m) zl[lane] = Z[lane * LD + lane].x;
       sort_eigen(zl, zs, W, Z, m, LD, lane);
       // P <- P W: rows a of V's cluster columns
@@ -323,7 +492,10 @@ extern "C" int kaldo_phonons(const kaldo_crystal* c, const int32_t* mesh, double
   const long nq = (long)mesh[0] * mesh[1] * mesh[2];
   KALDO_REQUIRE(nq <= (1L << 24), "kaldo_phonons: mesh too large");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (c->nb3 <= 16) {
+  if (c->nb3 <= 8) {
+    KALDO_LAUNCH("phonons_kernel", phonons_kernel<8>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
+                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
+  } else if (c->nb3 <= 16) {
     KALDO_LAUNCH("phonons_kernel", phonons_kernel<16>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
                        c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
   } else {
