@@ -353,6 +353,7 @@ __global__ __launch_bounds__(1024) void lw_live_q(int nq, int nb3, const uint8_t
 // Fused crystal kernel (lw_fused.hip): one workgroup per (q, chunk) work
 // item, at most kFusedMaxChunks chunks per q, about `target` items in all.
 constexpr int kFusedMaxChunks = 16;
+constexpr int kWorkItems = 4096;  // (q, chunk) items a launch aims for
 __host__ __device__ inline int fused_chunks(int n_live, int target) {
   if (n_live <= 0) return 1;
   const int c = (target + n_live - 1) / n_live;

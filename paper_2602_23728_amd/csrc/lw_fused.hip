@@ -401,13 +401,12 @@ int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega,
                idx_of_q, n_live);
   const size_t lds = fused_lds_bytes(c, sizeof(T) == 8 ? KALDO_FP64 : KALDO_FP32);
   const Fc3Bloch& b = c->bloch;
-  int dev = 0, n_cu = 0;
-  KALDO_HIP(hipGetDevice(&dev));
-  KALDO_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   // Chunks per q from the number of live q-points the host can know of: at
   // most min(N_q, n_subset) (the grid covers that many), estimated as
   // n_subset / 3N_b (every branch of a q selected) when choosing the chunk
-  // count, so that about four work items fall to each resident workgroup.
+  // count, for about kWorkItems work items (four per resident workgroup on
+  // a 256-CU device; a fixed count keeps the summation order, and so the
+  // bits of Gamma, the same on every device).
   const long upper = n_subset > 0 ? std::min<long>(nq, n_subset) : nq;
   const long guess = n_subset > 0 ? std::max<long>(1, n_subset / c->nb3) : nq;
   // and no chunk shorter than one sweep round (a q sweeps about N_q 3N_b / 2 items)
@@ -415,13 +414,8 @@ int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega,
       (int)std::max<long>(1, std::min<long>(kFusedMaxChunks, (long)nq * c->nb3 / (2 * kFusedThreads)));
 #define KALDO_FUSED_CASE(NBV)                                                                  \
   case NBV: {                                                                                  \
-    int per_cu = 0;                                                                            \
-    KALDO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lw_fused<NBV, T>,          \
-                                                           kFusedThreads, lds));               \
-    const long slots = (long)std::max(1, per_cu) * n_cu;                                       \
-    const int n_chunk = std::min(fused_chunks((int)std::min<long>(guess, 1l << 30),           \
-                                              (int)std::min<long>(4 * slots, 1l << 30)),       \
-                                 max_chunks);                                                  \
+    const int n_chunk =                                                                        \
+        std::min(fused_chunks((int)std::min<long>(guess, 1l << 30), kWorkItems), max_chunks);  \
     KALDO_LAUNCH("lw_fused", (lw_fused<NBV, T>), dim3((unsigned)(upper * n_chunk)),            \
                  dim3(kFusedThreads), lds, st, p, c->n_rep, c->d_rep, omega, vel, modef, occ,  \
                  phys, sel, evec, eta, phase_tab, b.t_ptr, b.t_i, b.t_l2, b.t_coef, b.e_blk,   \

@@ -554,7 +554,7 @@ struct TrainArgs {
 };
 
 constexpr int kBarStride = 32;  // 128 bytes between member counters
-constexpr int kMaxGroups = 32;  // partial gradients reduced from registers
+constexpr int kMaxGroups = 8;  // partial gradients (float4) in flight per reduction batch
 
 // Workgroup (g, mem) holds sample rows [g S, g S + S) of member mem and owns
 // slice g of its padded parameter vector (whole float4s).  Each step: the
@@ -1206,17 +1206,8 @@ extern "C" int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const dou
   const long guess = modes_subset ? std::max<long>(1, n_subset / c->nb3) : nq;
   const int max_chunks =
       (int)std::max<long>(1, std::min<long>(kFusedMaxChunks, (long)nq * c->nb3 / (2 * kJdosThreads)));
-  int dev = 0, n_cu = 0, per_cu = 0;
-  KALDO_HIP(hipGetDevice(&dev));
-  KALDO_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  if (c->nb3 <= 8)
-    KALDO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jdos_kernel<8>, kJdosThreads, 0));
-  else
-    KALDO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jdos_kernel<16>, kJdosThreads, 0));
-  const long slots = (long)std::max(1, per_cu) * n_cu;
-  const int n_chunk = std::min(fused_chunks((int)std::min<long>(guess, 1l << 30),
-                                            (int)std::min<long>(4 * slots, 1l << 30)),
-                               max_chunks);
+  const int n_chunk =
+      std::min(fused_chunks((int)std::min<long>(guess, 1l << 30), kWorkItems), max_chunks);
   const dim3 grid((unsigned)(upper * n_chunk));
   if (c->nb3 <= 8)
     KALDO_LAUNCH("jdos_kernel", jdos_kernel<8>, grid, dim3(kJdosThreads), 0, st, p, omega, vel, modef,
