@@ -70,9 +70,9 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
   float2* at = reinterpret_cast<float2*>(smem);  // [n_blk][9][NB3]
   __shared__ float2 bsc[kMfmaWaves][16 * 17];         // per-wave B_s tile [row jc][col kc]
   __shared__ float2 phb[kMfmaWaves][kMfmaMaxBlocks];  // per-wave e^{-i q1.R_d(blk)} per block
-  __shared__ int cq_code[kMfmaWaves][kCandCap];       // per-wave near-shell candidates:
-  __shared__ int cq_q1[kMfmaWaves][kCandCap];         //   s | s' << 8 | s'' << 16, q1,
-  __shared__ double cq_v2[kMfmaWaves][kCandCap];      //   |V|^2
+  __shared__ int cq_code[kMfmaWaves][kCandCap];       // per-wave near-shell candidates of the
+  __shared__ double cq_v2[kMfmaWaves][kCandCap];      //   current partner: s | s' << 8 | s'' << 16, |V|^2
+  __shared__ double md[kMfmaWaves][2][16][5];         // per-wave (w, n, v) of the q1 and q2 modes
   __shared__ double2 phq[64];
   __shared__ double wq64[16];
   __shared__ double red[kMfmaThreads];
@@ -141,24 +141,23 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
   }
 
   // Exact FP64 cut and weight of queued candidates, one per lane, in queue
-  // order; the contribution goes to this lane's sum of the candidate's branch.
+  // order, from the partner's mode data staged in LDS (the queue only ever
+  // holds candidates of the current partner); the contribution goes to this
+  // lane's sum of the candidate's branch.
   int n_cand = 0;  // wave-uniform
-  auto resolve = [&]() {
+  auto resolve = [&](int dbl) {
     for (int base = 0; base < n_cand; base += 64) {
       const int e = base + lane;
       if (e < n_cand) {
-        const int code = cq_code[wv][e], c1 = cq_q1[wv][e];
-        const int cs_ = code & 255, cs1 = (code >> 8) & 255, cs2 = (code >> 16) & 255,
-                  cdbl = code >> 24;
-        const int d0 = c1 / (N1 * N2), d1 = (c1 / N2) % N1, d2 = c1 % N2;
-        const int e0 = ((-a0 - d0) % N0 + N0) % N0, e1_ = ((-a1 - d1) % N1 + N1) % N1,
-                  e2_ = ((-a2 - d2) % N2 + N2) % N2;
-        const int m1 = c1 * NB3 + cs1, m2 = ((e0 * N1 + e1_) * N2 + e2_) * NB3 + cs2;
+        const int code = cq_code[wv][e];
+        const int cs_ = code & 255, cs1 = (code >> 8) & 255, cs2 = (code >> 16) & 255;
+        const double* d1 = md[wv][0][cs1];
+        const double* d2 = md[wv][1][cs2];
         double sp, sm;
-        widths(p, vel, m1, m2, sp, sm);
-        double wt = pair_weight(p, wq64[cs_], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
+        widths_v(p, d1 + 2, d2 + 2, sp, sm);
+        double wt = pair_weight(p, wq64[cs_], d1[0], d2[0], d1[1], d2[1], sp, sm);
         // the mirrored ordering: same |V|^2 and widths, its own cut
-        if (cdbl) wt += pair_weight(p, wq64[cs_], omega[m2], omega[m1], occ[m2], occ[m1], sp, sm);
+        if (dbl) wt += pair_weight(p, wq64[cs_], d2[0], d1[0], d2[1], d1[1], sp, sm);
         const double c = wt * cq_v2[wv][e];
         // register accumulators need a static index: add to the selected one
 #pragma unroll
@@ -180,6 +179,15 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
     wave_sync();
     for (int blk = lane; blk < p.n_blk; blk += 64)
       phb[wv][blk] = phase_tab[(size_t)q1 * p.n_d + blk_d[blk]];
+    if ((lane & 15) < NB3 && lane < 32) {
+      const int m = (lane < 16 ? q1 : q2) * NB3 + (lane & 15);
+      double* d = md[wv][lane >> 4][lane & 15];
+      d[0] = omega[m];
+      d[1] = occ[m];
+      d[2] = vel[3 * (size_t)m];
+      d[3] = vel[3 * (size_t)m + 1];
+      d[4] = vel[3 * (size_t)m + 2];
+    }
     wave_sync();
     // eta(q2)[kc][s''] as the B operand of T = B_s eta2 (column n = lr)
     // and eta(q1)[jc][s'] (jc = 4 lg + i) as A = eta1^T (row m = lr) of
@@ -364,20 +372,19 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
           const unsigned lo = (unsigned)mask, hi = (unsigned)(mask >> 32);
           const int off = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
           const int slot = n_cand + off;
-          cq_code[wv][slot] = s | ((4 * lg + r) << 8) | (s2 << 16) | (dbl << 24);
-          cq_q1[wv][slot] = q1;
+          cq_code[wv][slot] = s | ((4 * lg + r) << 8) | (s2 << 16);
           cq_v2[wv][slot] = (double)vr[r] * (double)vr[r] + (double)vi[r] * (double)vi[r];
         }
         n_cand += __popcll(mask);
         if (n_cand >= 64) {
           wave_sync();
-          resolve();
+          resolve(dbl);
         }
       }
       wave_sync();
     }
+    resolve(dbl);  // the queue never carries candidates past their partner
   }
-  resolve();
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     if (s >= NB3) break;
@@ -401,7 +408,7 @@ bool mfma_supported(const kaldo_crystal* c) {
     return false;
   const size_t dyn = (size_t)c->bloch.n_blk * 9 * c->nb3 * 8;
   const size_t stat = kMfmaWaves * 16 * 17 * 8 + kMfmaWaves * kMfmaMaxBlocks * 8 +
-                      kMfmaWaves * kCandCap * 16 + 64 * 16 + 16 * 8 + kMfmaThreads * 8;
+                      kMfmaWaves * kCandCap * 12 + kMfmaWaves * 2 * 16 * 5 * 8 + 64 * 16 + 16 * 8 + kMfmaThreads * 8;
   return dyn + stat <= (size_t)lds_max;
 }
 
