@@ -297,8 +297,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
                                                const double* __restrict__ omega,
                                                const double* __restrict__ occ,
                                                const uint8_t* __restrict__ phys,
-                                               const uint8_t* __restrict__ sel,
-                                               const double* __restrict__ brange,
                                                const int32_t* __restrict__ live_list,
                                                const int32_t* __restrict__ live_count,
                                                double* __restrict__ partial) {
@@ -341,7 +339,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
   constexpr int PPR = KT / 4;  // 16-byte pieces per row (FP32 form)
   constexpr int NP = kMT * PPR / 256;  // pieces per thread
   static_assert(SPLIT || kMT * PPR == NP * 256, "whole pieces per thread");
-  static_assert(SPLIT || KT == 16, "one 16-byte read per tile row covers the slice");
+  static_assert(SPLIT || KT % 16 == 0, "whole 16-byte groups per lane group");
   uint4 pa[NP], pb[NP];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -373,25 +371,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
       if (more) fetch(k0 + KT);
       const float* A = sA32 + cur * kMT * LDA32;
       const float* B = sB32 + cur * kMT * LDA32;
-      // K order inside the slice: MFMA step j pairs lane group lg with
-      // k = 4 lg + j (the same on both operands), so a lane's four k values
-      // are contiguous and come in one 16-byte LDS read per tile
-      float4 a4[4], b4[4];
+      // K order inside the slice: lane group lg owns k in [KPL lg, KPL lg +
+      // KPL) and MFMA step j of a 16-byte group pairs it with the group's
+      // j-th value (the same on both operands), so a lane reads its k values
+      // with one 16-byte LDS load per tile row and group
+      constexpr int KPL = KT / 4;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        a4[t] = *reinterpret_cast<const float4*>(&A[(wm + 16 * t + lr) * LDA32 + 4 * lg]);
-        b4[t] = *reinterpret_cast<const float4*>(&B[(wn + 16 * t + lr) * LDA32 + 4 * lg]);
+      for (int h = 0; h < KPL / 4; ++h) {
+        float4 a4[4], b4[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a4[t] = *reinterpret_cast<const float4*>(&A[(wm + 16 * t + lr) * LDA32 + KPL * lg + 4 * h]);
+          b4[t] = *reinterpret_cast<const float4*>(&B[(wn + 16 * t + lr) * LDA32 + KPL * lg + 4 * h]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int ta = 0; ta < 4; ++ta)
+#pragma unroll
+            for (int tb = 0; tb < 4; ++tb) {
+              const float av = j == 0 ? a4[ta].x : j == 1 ? a4[ta].y : j == 2 ? a4[ta].z : a4[ta].w;
+              const float bv = j == 0 ? b4[tb].x : j == 1 ? b4[tb].y : j == 2 ? b4[tb].z : b4[tb].w;
+              acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ta][tb], 0, 0, 0);
+            }
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int ta = 0; ta < 4; ++ta)
-#pragma unroll
-          for (int tb = 0; tb < 4; ++tb) {
-            const float av = j == 0 ? a4[ta].x : j == 1 ? a4[ta].y : j == 2 ? a4[ta].z : a4[ta].w;
-            const float bv = j == 0 ? b4[tb].x : j == 1 ? b4[tb].y : j == 2 ? b4[tb].z : b4[tb].w;
-            acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ta][tb], 0, 0, 0);
-          }
       if (more) stage(cur ^ 1);
       __syncthreads();
       cur ^= 1;
@@ -560,12 +563,12 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
                  phys, sel, brange, live_list, live_count);
     if (split)
       KALDO_LAUNCH("gm_gemm_bf16x3", gm_gemm<true>, dim3(n_tri * nb), dim3(256), 0, st, p, n, np,
-                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, brange,
-                   live_list, live_count, partial);
+                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, live_list,
+                   live_count, partial);
     else
       KALDO_LAUNCH("gm_gemm_fp32", gm_gemm<false>, dim3(n_tri * nb), dim3(256), 0, st, p, n, np,
-                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, sel, brange,
-                   live_list, live_count, partial);
+                   m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, live_list,
+                   live_count, partial);
   }
   KALDO_LAUNCH("gm_finish", gm_finish, dim3((n + 255) / 256), dim3(256), 0, st, n, n_tri, partial,
                phys, sel, gamma);

@@ -8,9 +8,12 @@
 // only where |x| < 2 sigma), Eq. bose.  Only partner pairs that pass the
 // 2-sigma cut are projected ("Computational Implementation").
 //
-// Kernels, in launch order:
-//   lw_prepare       per mode: populations, physical mask, subset flags;
-//                    eta rounded to the contraction type
+// Every path starts with
+//   lw_prepare       per mode: populations, physical mask, subset flags and
+//                    the FP32 (v, omega) copy the sweeps pre-classify with
+// and then runs the fused kernel (lw_fused.hip), the dense MFMA kernel
+// (lw_mfma.hip) or, when neither fits, the generic kernels below:
+//   lw_round_evec    eta rounded to the contraction type
 //   lw_atilde        per (q, e): A~_q[e][s] = sum_t coef_t eta_{i_t}(q,s)
 //                    e^{+i q.R_{l''_t}}   (sparse COO x eta, first index)
 //   lw_crystal       per (q, q1): FP64 cut and weights for every (s,s',s''),
@@ -29,7 +32,7 @@ namespace kaldo {
 // modef[m] = (v, omega) in FP32 for the sweep's pre-classification, omega
 // NaN below the frequency floor so that every comparison against the mode
 // fails, as the physical mask demands.
-__global__ void lw_prepare(int n_modes, int nb3, const double* __restrict__ omega,
+__global__ void lw_prepare(int n_modes, const double* __restrict__ omega,
                            const double* __restrict__ vel, double inv_kt_hbar,
                            double nu_min, double* __restrict__ occ, uint8_t* __restrict__ phys,
                            uint8_t* __restrict__ sel, float4* __restrict__ modef, int sel_all) {
@@ -259,7 +262,7 @@ static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double
   double* partial = reinterpret_cast<double*>(ws + w.off_partial);
   float4* modef = reinterpret_cast<float4*>(ws + w.off_modef);
   const double inv_kt_hbar = kHbar / (kKb * T_k);
-  KALDO_LAUNCH("lw_prepare", lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes, nb3,
+  KALDO_LAUNCH("lw_prepare", lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes,
                      omega, vel, inv_kt_hbar, b->nu_min_thz, occ, phys, sel, modef, subset ? 0 : 1);
   if (subset && n_subset > 0)
     KALDO_LAUNCH("lw_select", lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,

@@ -56,7 +56,7 @@ __device__ __forceinline__ void wave_sync() {
 
 template <bool SPLIT>
 __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
-    LwParams p, int nb, int n_rep, const int32_t* __restrict__ rep,
+    LwParams p, int n_rep, const int32_t* __restrict__ rep,
     const double* __restrict__ omega, const double* __restrict__ vel,
     const double* __restrict__ occ, const uint8_t* __restrict__ phys,
     const uint8_t* __restrict__ sel, const double* __restrict__ evec,
@@ -423,11 +423,11 @@ int launch_mfma(const kaldo_crystal* c, const LwParams& p, bool split, const dou
   const size_t lds = (size_t)c->bloch.n_blk * 9 * c->nb3 * 8;
   const Fc3Bloch& b = c->bloch;
   if (split)
-    KALDO_LAUNCH("lw_mfma_bf16x3", lw_mfma<true>, dim3(nq), dim3(kMfmaThreads), lds, st, p, c->nb,
+    KALDO_LAUNCH("lw_mfma_bf16x3", lw_mfma<true>, dim3(nq), dim3(kMfmaThreads), lds, st, p,
                  c->n_rep, c->d_rep, omega, vel, occ, phys, sel, evec, phase_tab, b.t_ptr, b.t_i,
                  b.t_l2, b.t_coef, b.e_blk, b.e_bg, b.blk_d, b.bwork, scale, gamma);
   else
-    KALDO_LAUNCH("lw_mfma_fp32", lw_mfma<false>, dim3(nq), dim3(kMfmaThreads), lds, st, p, c->nb,
+    KALDO_LAUNCH("lw_mfma_fp32", lw_mfma<false>, dim3(nq), dim3(kMfmaThreads), lds, st, p,
                  c->n_rep, c->d_rep, omega, vel, occ, phys, sel, evec, phase_tab, b.t_ptr, b.t_i,
                  b.t_l2, b.t_coef, b.e_blk, b.e_bg, b.blk_d, b.bwork, scale, gamma);
   KALDO_HIP(hipGetLastError());
