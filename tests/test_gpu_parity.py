@@ -232,6 +232,23 @@ def test_fc3_not_mirror_symmetric_sweeps_every_partner(diamond, prec):
         assert np.max(np.abs(G - Go)) <= 1e-10 * Go.max()
 
 
+def test_subset_chunking_matches_full_mesh(diamond):
+    """A subset of a few hundred q-points is split into many more (q, chunk)
+    work items than the full C2 mesh; each term is computed the same way, so
+    only the grouping of the FP64 sums may differ."""
+    m, c = diamond
+    cfg = configs.CONFIGS["C2"]
+    mesh = cfg.mesh
+    om, ev, ve = K.phonons(c, mesh)
+    full = host(K.linewidths(c, mesh, om, ev, ve, 300.0, cfg.broadening, K.FP32)).reshape(-1)
+    nq = int(np.prod(mesh))
+    qs = np.random.default_rng(3).choice(nq, size=300, replace=False)
+    sub = (qs[:, None] * 6 + np.arange(6)).reshape(-1)[::2].astype(np.int32)
+    g = host(K.linewidths(c, mesh, om, ev, ve, 300.0, cfg.broadening, K.FP32,
+                          subset=dev(sub))).reshape(-1)
+    np.testing.assert_allclose(g[sub], full[sub], rtol=1e-12, atol=1e-14 * full.max())
+
+
 def test_bitwise_deterministic(diamond):
     m, c = diamond
     mesh = (5, 5, 5)

@@ -88,6 +88,20 @@ def test_jdos_subset_writes_only_selected(diamond):
     np.testing.assert_allclose(dm[sub], dm_o.reshape(-1)[sub], rtol=1e-5, atol=1e-12)
 
 
+def test_jdos_subset_chunking_matches_full_mesh(diamond):
+    """Subsets split into more (q, chunk) work items than the full mesh; only
+    the grouping of the FP64 sums may differ."""
+    m, c = diamond
+    mesh = (12, 12, 12)
+    om, ev, ve = K.phonons(c, mesh)
+    dp_f, dm_f = (host(x).reshape(-1) for x in K.jdos(c, mesh, om, ve, B_ADAPT))
+    qs = np.random.default_rng(4).choice(1728, size=100, replace=False)
+    sub = (qs[:, None] * 6 + np.arange(6)).reshape(-1).astype(np.int32)
+    dp, dm = (host(x).reshape(-1) for x in K.jdos(c, mesh, om, ve, B_ADAPT, subset=dev(sub)))
+    np.testing.assert_allclose(dp[sub], dp_f[sub], rtol=1e-12, atol=1e-14 * dp_f.max())
+    np.testing.assert_allclose(dm[sub], dm_f[sub], rtol=1e-12, atol=1e-14 * dm_f.max())
+
+
 # ------------------------------------------------------------------ features
 
 def test_features_and_standardize_match_oracle(diamond):
