@@ -88,6 +88,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
   __shared__ int wave_tot[BS / 64];
   __shared__ double2 phq[64];
   __shared__ double wq64[NB3];
+  __shared__ float wqs[NB3];  // FP32 frequencies of q, indexed per candidate
   __shared__ double red[BS];
 
   const int tid = threadIdx.x;
@@ -114,6 +115,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
       live |= (phys[q * NB3 + s] && sel[q * NB3 + s]) ? (1u << s) : 0u;
     }
     if (tid < NB3) wq64[tid] = omega[q * NB3 + tid];
+    if (tid < NB3) wqs[tid] = (float)omega[q * NB3 + tid];
 
     // 1. A~_q in LDS
     for (int l = tid; l < n_rep; l += BS) {
@@ -247,37 +249,49 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           const float scl = wq_abs_max + fabsf(f1.w) + fabsf(f2.w);
           const Band bp = make_band_f(s2p, scl, e_sig), bm = make_band_f(s2m, scl, e_sig);
           const float cp = f1.w - f2.w, cm = -f1.w - f2.w;
-          // certain passes and the ambiguous band for all branches first
-          // (branch-free); the exact FP64 test only for the rare band members.
-          // ar is the coalescence |x+| of the mirrored ordering, (w + w2) - w1;
-          // the decay |x-| is the same number in FP32 for both orderings.
-          unsigned b = 0, br = 0, amb_p = 0, amb_r = 0, amb_m = 0;
+          // the upper band edge for all branches first (branch-free): a
+          // candidate is any process with |x| < hi; ar is the coalescence |x+|
+          // of the mirrored ordering, (w + w2) - w1, and the decay |x-| is the
+          // same number in FP32 for both orderings
+          unsigned amb_p = 0, amb_r = 0, amb_m = 0;
 #pragma unroll
           for (int s = 0; s < NB3; ++s) {
             const float ap = fabsf(wqf[s] + cp), ar = fabsf(wqf[s] - cp), am = fabsf(wqf[s] + cm);
-            b |= ((ap < bp.lo) || (am < bm.lo)) ? (1u << s) : 0u;
-            br |= (ar < bp.lo) ? (1u << s) : 0u;
             amb_p |= (ap < bp.hi) ? (1u << s) : 0u;
             amb_r |= (ar < bp.hi) ? (1u << s) : 0u;
             amb_m |= (am < bm.hi) ? (1u << s) : 0u;
           }
-          b |= br & dmask;
           amb_r &= dmask;
-          unsigned amb = (amb_p | amb_r | amb_m) & ~b & live;
-          if (amb) {
-            const double w1 = omega[m1], w2 = omega[m2];
-            double s2p64, s2m64, Sp, Sm;
-            widths2(p, vel + 3 * (size_t)m1, vel + 3 * (size_t)m2, s2p64, s2m64, Sp, Sm);
-            while (amb) {
-              const int s = __ffs(amb) - 1;
-              amb &= amb - 1;
-              const bool bm_ = amb_m >> s & 1u;
-              bool pass = ((amb_p >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, true)) ||
-                          (bm_ && exact_pass(p, wq64[s], w1, w2, Sp, Sm, false));
-              if (dbl && !pass)
-                pass = ((amb_r >> s & 1u) && exact_pass(p, wq64[s], w2, w1, Sp, Sm, true)) ||
-                       (bm_ && exact_pass(p, wq64[s], w2, w1, Sp, Sm, false));
-              b |= pass ? (1u << s) : 0u;
+          unsigned cand = (amb_p | amb_r | amb_m) & live;
+          unsigned b = 0;
+          if (cand) {
+            // the rare candidates: certain passes in FP32, the band members
+            // take the exact FP64 test
+            unsigned amb = 0;
+            for (unsigned c = cand; c; c &= c - 1) {
+              const int s = __ffs(c) - 1;
+              const float w = wqs[s];
+              const bool sure = ((amb_p >> s & 1u) && fabsf(w + cp) < bp.lo) ||
+                                ((amb_m >> s & 1u) && fabsf(w + cm) < bm.lo) ||
+                                ((amb_r >> s & 1u) && fabsf(w - cp) < bp.lo);
+              b |= sure ? (1u << s) : 0u;
+              amb |= sure ? 0u : (1u << s);
+            }
+            if (amb) {
+              const double w1 = omega[m1], w2 = omega[m2];
+              double s2p64, s2m64, Sp, Sm;
+              widths2(p, vel + 3 * (size_t)m1, vel + 3 * (size_t)m2, s2p64, s2m64, Sp, Sm);
+              while (amb) {
+                const int s = __ffs(amb) - 1;
+                amb &= amb - 1;
+                const bool bm_ = amb_m >> s & 1u;
+                bool pass = ((amb_p >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, true)) ||
+                            (bm_ && exact_pass(p, wq64[s], w1, w2, Sp, Sm, false));
+                if (dbl && !pass)
+                  pass = ((amb_r >> s & 1u) && exact_pass(p, wq64[s], w2, w1, Sp, Sm, true)) ||
+                         (bm_ && exact_pass(p, wq64[s], w2, w1, Sp, Sm, false));
+                b |= pass ? (1u << s) : 0u;
+              }
             }
           }
           b &= live;
