@@ -271,8 +271,8 @@ def bench_learned(a, cfg, model, c, K, torch):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); the "
-              "multi-GPU sharding of the path is a design note, not an implementation.",
+        print(f"bench.py: kaldo runs on one GPU (asked for --gpus {a.gpus}); sharding the "
+              "path over several GPUs is described in the design notes, not implemented.",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -58,7 +58,7 @@ typedef enum {
   KALDO_ENOMEM = -2,      /* allocation failed (handle creation only)     */
   KALDO_EDEVICE = -3,     /* HIP runtime error                            */
   KALDO_ENUMERIC = -4,    /* numerical failure (e.g. no eigen convergence)*/
-  KALDO_EUNSUPPORTED = -5 /* valid request this build does not implement  */
+  KALDO_EUNSUPPORTED = -5 /* valid request the library does not implement */
 } kaldo_status;
 
 /* Arithmetic of the vertex contraction (projection of Phi3 on eigenvectors).

@@ -13,7 +13,7 @@ Definitions (paper, "Three-Phonon Scattering" subsection):
   eigenvector products.  Phases are exact: q1.R = 2 pi sum_c n1_c l_c / N_c
   with the integer numerator reduced mod N_c.
 * Rates, Eq. gamma with the population/delta factors of the Delta terms,
-  in the reading fixed for this build:
+  in the reading fixed here:
       Gamma_mu = pi hbar U^3 / (8 N_q) sum_{q1,s',s''} m |V|^2/(w w1 w2)
                  [ (n1 - n2) g(x+, sig+) + 1/2 (n1 + n2 + 1) g(x-, sig-) ]
   with x+ = (w + w1) - w2 (coalescence), x- = (w - w1) - w2 (decay),

@@ -1,7 +1,7 @@
 """FP64 multilayer perceptron of the oracle: forward pass, hand-derived
 backward pass and Adam, for the learned linewidth surrogate.
 
-The paper has no surrogate; the network is a reading fixed for this build:
+The paper has no surrogate; the network is a reading fixed here:
 input -> 4 hidden layers of 64 units with tanh -> linear scalar output, loss
 = weighted mean squared error sum_i c_i (y_hat_i - y_i)^2 / sum_i c_i (c_i are
 bootstrap counts), Adam with bias correction (Kingma & Ba, 2015):
