@@ -308,7 +308,9 @@ struct Partners {
 };
 
 // Live q-points (a selected physical mode) in increasing order, the inverse
-// map (-1 for the others) and their number.  One workgroup.
+// map (-1 for the others) and their number.  One workgroup: thread t reads
+// the flags of q = t + 1024 r for every round r first (coalesced, all loads
+// in flight), then one block-wide scan per round orders the list.
 // (A template only so that every translation unit that launches it may
 // instantiate it from this header.)
 template <int kUnused = 0>
@@ -317,35 +319,38 @@ __global__ __launch_bounds__(1024) void lw_live_q(int nq, int nb3, const uint8_t
                                                   int32_t* __restrict__ list,
                                                   int32_t* __restrict__ idx_of_q,
                                                   int32_t* __restrict__ count) {
-  __shared__ int wave_tot[16];
-  __shared__ int carry;
+  __shared__ int wave_tot[2][16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nq; base += 1024) {
-    const int q = base + tid;
+  const int rounds = (nq + 1023) / 1024;  // <= 64 for N_q <= 65535
+  unsigned long long live = 0;
+  for (int r = 0; r < rounds; ++r) {
+    const int q = tid + 1024 * r;
     int f = 0;
     if (q < nq)
-      for (int s = 0; s < nb3; ++s) f |= (phys[q * nb3 + s] && sel[q * nb3 + s]) ? 1 : 0;
+      for (int s = 0; s < nb3; ++s) f |= phys[q * nb3 + s] & sel[q * nb3 + s];  // 0/1 bytes, no branch
+    live |= (unsigned long long)f << r;
+  }
+  int carry = 0;
+  for (int r = 0; r < rounds; ++r) {
+    const int q = tid + 1024 * r;
+    const int f = (int)(live >> r & 1ull);
     int incl = f;
     for (int off = 1; off < 64; off <<= 1) {
       const int v = __shfl_up(incl, off, 64);
       if (lane >= off) incl += v;
     }
-    if (lane == 63) wave_tot[wv] = incl;
+    if (lane == 63) wave_tot[r & 1][wv] = incl;  // double-buffered: one barrier per round
     __syncthreads();
     int off = carry, tot = 0;
     for (int k = 0; k < 16; ++k) {
-      off += (k < wv) ? wave_tot[k] : 0;
-      tot += wave_tot[k];
+      off += (k < wv) ? wave_tot[r & 1][k] : 0;
+      tot += wave_tot[r & 1][k];
     }
     if (q < nq) {
       idx_of_q[q] = f ? off + incl - 1 : -1;
       if (f) list[off + incl - 1] = q;
     }
-    __syncthreads();
-    if (tid == 0) carry += tot;
-    __syncthreads();
+    carry += tot;
   }
   if (tid == 0) *count = carry;
 }
