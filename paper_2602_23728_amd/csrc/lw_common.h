@@ -355,6 +355,20 @@ __global__ __launch_bounds__(1024) void lw_live_q(int nq, int nb3, const uint8_t
   if (tid == 0) *count = carry;
 }
 
+// Every q taken as live (all modes selected): identity list and map.  A q
+// without a physical mode then gives only zero partial sums, which is what
+// the finish kernels write for it anyway.
+template <int kUnused = 0>
+__global__ void lw_all_q(int nq, int32_t* __restrict__ list, int32_t* __restrict__ idx_of_q,
+                         int32_t* __restrict__ count) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nq) {
+    list[q] = q;
+    idx_of_q[q] = q;
+  }
+  if (q == 0) *count = nq;
+}
+
 // Fused crystal kernel (lw_fused.hip): one workgroup per (q, chunk) work
 // item, at most kFusedMaxChunks chunks per q, about `target` items in all.
 constexpr int kFusedMaxChunks = 16;

@@ -411,8 +411,12 @@ int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega,
   int32_t* live_list = qlist;
   int32_t* idx_of_q = qlist + nq;
   int32_t* n_live = qlist + 2 * nq;
-  KALDO_LAUNCH("lw_live_q", lw_live_q<>, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel, live_list,
-               idx_of_q, n_live);
+  if (n_subset > 0)
+    KALDO_LAUNCH("lw_live_q", lw_live_q<>, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel, live_list,
+                 idx_of_q, n_live);
+  else
+    KALDO_LAUNCH("lw_all_q", lw_all_q<>, dim3((nq + 255) / 256), dim3(256), 0, st, nq, live_list,
+                 idx_of_q, n_live);
   const size_t lds = fused_lds_bytes(c, sizeof(T) == 8 ? KALDO_FP64 : KALDO_FP32);
   const Fc3Bloch& b = c->bloch;
   // Chunks per q from the number of live q-points the host can know of: at

@@ -1200,8 +1200,12 @@ extern "C" int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const dou
   if (modes_subset)
     KALDO_LAUNCH("jdos_select", jdos_select, dim3((unsigned)((n_subset + 255) / 256)), dim3(256), 0,
                  st, modes_subset, (long)n_subset, nm, sel);
-  KALDO_LAUNCH("lw_live_q", lw_live_q<>, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel, live_list,
-               idx_of_q, n_live);
+  if (modes_subset)
+    KALDO_LAUNCH("lw_live_q", lw_live_q<>, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel,
+                 live_list, idx_of_q, n_live);
+  else
+    KALDO_LAUNCH("lw_all_q", lw_all_q<>, dim3((nq + 255) / 256), dim3(256), 0, st, nq, live_list,
+                 idx_of_q, n_live);
   const LwParams p = make_params(c, mesh, 300.0, b);
   // work items (live q, chunk) as in the crystal linewidths: the grid covers
   // min(N_q, n_subset) q-points, the chunk count assumes n_subset / 3N_b
