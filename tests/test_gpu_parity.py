@@ -208,8 +208,8 @@ def test_subset_writes_only_selected(diamond):
     assert np.allclose(G[mask], Gall[mask], rtol=1e-13, atol=0)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_fc3_not_mirror_symmetric_sweeps_every_partner(diamond, prec):
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "mfma_fp32"])
+def test_fc3_not_mirror_symmetric_sweeps_every_partner(diamond, prec, monkeypatch):
     """With Phi3 symmetric in its last two slots the crystal kernel visits
     each mirrored partner pair (q1, q2) once; an FC3 without that symmetry
     (entries with j < k scaled by 1.3) must switch back to every ordered
@@ -221,15 +221,17 @@ def test_fc3_not_mirror_symmetric_sweeps_every_partner(diamond, prec):
     c = K.Crystal.from_model(ma)
     mesh = (4, 3, 5)
     om, ev, ve = _oracle_inputs(m, mesh)
-    p = K.FP32 if prec == "fp32" else K.FP64
+    if prec == "mfma_fp32":
+        monkeypatch.setenv("KALDO_CRYSTAL_PATH", "mfma")  # the dense MFMA kernel
+    p = K.FP64 if prec == "fp64" else K.FP32
     G = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, p))
     Go = olw.crystal_linewidths(ma, mesh, om, ev, ve, 300.0, B_ADAPT)
     Gs = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_ADAPT)
     assert np.max(np.abs(Go - Gs)) > 1e-2 * Gs.max()  # the perturbation matters
-    if prec == "fp32":
-        assert gamma_close(G, Go) <= 1e-5
-    else:
+    if prec == "fp64":
         assert np.max(np.abs(G - Go)) <= 1e-10 * Go.max()
+    else:
+        assert gamma_close(G, Go) <= 1e-5
 
 
 def test_subset_chunking_matches_full_mesh(diamond):

@@ -71,6 +71,21 @@ def test_jdos_matches_oracle(diamond, broad, mesh):
         assert np.all(a[om / TWO_PI < 0.1] == 0.0)
 
 
+def test_jdos_wide_cell_matches_oracle():
+    """3N_b = 15 takes the 16-branch instantiation of the JDOS kernel."""
+    m = configs.build_model("perovskite")
+    c = K.Crystal.from_model(m)
+    mesh = (3, 3, 3)
+    om, ev, ve = oph.phonons(m, mesh)
+    dp_o, dm_o = ojdos.jdos(m, mesh, om, ve, B_ADAPT)
+    dp, dm = (host(x) for x in K.jdos(c, mesh, dev(om), dev(ve), B_ADAPT))
+    for a, b in ((dp, dp_o), (dm, dm_o)):
+        big = b > 1e-3 * b.max()
+        assert big.any()
+        assert np.max(np.abs(a[big] - b[big]) / b[big]) <= 1e-5
+        assert np.max(np.abs(a - b)) <= 1e-5 * b.max()
+
+
 def test_jdos_subset_writes_only_selected(diamond):
     m, c = diamond
     mesh = (4, 4, 4)
