@@ -141,8 +141,14 @@ __device__ __forceinline__ double pair_weight(const LwParams& p, double w, doubl
 struct Band {
   float lo, hi;
 };
+
+// The hardware square root (v_sqrt_f32, within 1 ulp for the normal inputs
+// the bands see: sigma^2 >= floor^2), without the correctly-rounded
+// expansion the compiler emits for sqrtf.  The bands carry a 1e-6 relative
+// margin (about 17 ulp), so the pre-classification stays conservative.
+__device__ __forceinline__ float band_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ Band make_band(double sig2, float scale_sum) {
-  const float t = 2.0f * sqrtf((float)sig2);
+  const float t = 2.0f * band_sqrt((float)sig2);
   const float d = 4e-7f * scale_sum + 1e-9f;
   return {t * (1.0f - 1e-6f) - d, t * (1.0f + 1e-6f) + d};
 }
@@ -151,7 +157,7 @@ __device__ __forceinline__ Band make_band(double sig2, float scale_sum) {
 // widths2_f): the interval is widened by e_sig, the bound on how far 2 sigma
 // computed that way can lie from 2 sigma computed in FP64.
 __device__ __forceinline__ Band make_band_f(float sig2, float scale_sum, float e_sig) {
-  const float t = 2.0f * sqrtf(sig2);
+  const float t = 2.0f * band_sqrt(sig2);
   const float d = 4e-7f * scale_sum + 1e-9f + e_sig;
   return {t * (1.0f - 1e-6f) - d, t * (1.0f + 1e-6f) + d};
 }
@@ -177,7 +183,7 @@ __device__ __forceinline__ void widths2_f(const LwParams& p, float4 v1, float4 v
   const float H = (float)(p.h2 / 12.0), F = (float)(p.sig_floor * p.sig_floor);
   s2p = fmaxf(Sp * H, F);
   s2m = fmaxf(Sm * H, F);
-  e_sig = 2.0f * sqrtf(1.7e-6f * (Sp + Sm) * H);
+  e_sig = 2.0f * band_sqrt(1.7e-6f * (Sp + Sm) * H);
 }
 
 // The exact FP64 decision of the oracle: |(w + w1) - w2| < 2 sigma+ or

@@ -231,8 +231,8 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
         widths2(p, vel + 3 * (size_t)m1, vel + 3 * (size_t)(q2 * NB3 + s2), s2p, s2m, Sp, Sm);
         const float scl = wq_abs_max + fabsf((float)w1) + fabsf((float)w2);
         const float d = 4e-7f * scl + 1e-9f;
-        bhi_p[r] = 2.0f * sqrtf((float)s2p) * (1.0f + 1e-6f) + d;
-        bhi_m[r] = 2.0f * sqrtf((float)s2m) * (1.0f + 1e-6f) + d;
+        bhi_p[r] = 2.0f * band_sqrt((float)s2p) * (1.0f + 1e-6f) + d;
+        bhi_m[r] = 2.0f * band_sqrt((float)s2m) * (1.0f + 1e-6f) + d;
         cpv[r] = (float)(w1 - w2);
         cmv[r] = (float)(-w1 - w2);
       }
