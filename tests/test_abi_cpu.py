@@ -56,6 +56,23 @@ def test_argument_validation_without_device():
         K.phonons_gamma(2, np.array([1.0, -1.0]), np.zeros((6, 1, 6)))
 
 
+def test_learned_form_host_checks_without_device():
+    lib = K.lib()
+    # parameter count of the 4 x 64 tanh network: (n_in + 1) 64 + 3 (65 64) + 65
+    assert lib.kaldo_mlp_param_count(14) == 15 * 64 + 3 * 65 * 64 + 65 == 13505
+    assert lib.kaldo_mlp_param_count(33) == -1 and lib.kaldo_mlp_param_count(0) == -1
+    assert lib.kaldo_mlp_workspace(0, 5, 100) == 0 and lib.kaldo_mlp_workspace(14, 5, 0) == 0
+    ws = lib.kaldo_mlp_workspace(14, 5, 165)
+    assert ws > 4 * 5 * 13505 * 3  # parameters, two Adam moments and the partial gradients
+    rc = lib.kaldo_mlp_train(40, 5, 165, None, None, None, None, 10, ctypes.c_float(1e-2), None, 0,
+                             None, None, None)
+    assert rc == -1 and b"n_in" in lib.kaldo_last_error()
+    mesh = (ctypes.c_int32 * 3)(4, 4, 4)
+    b = K.Broadening(0, 1, 0.0, 0.01, 0.1)
+    rc = lib.kaldo_jdos(None, mesh, None, None, ctypes.byref(b), None, 0, None, 0, None, None, None)
+    assert rc == -1 and b"NULL" in lib.kaldo_last_error()
+
+
 @pytest.mark.parametrize("which", ["supercell", "rglass", "glass"])
 def test_host_gamma_eigensolver_matches_lapack(which):
     if which == "supercell":
