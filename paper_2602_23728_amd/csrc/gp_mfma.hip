@@ -279,8 +279,8 @@ __global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtil
 }
 
 // Waves per SIMD the register allocation targets: three for the split form
-// (measured 0.41 -> 0.38 ms per batch of C4), the compiler's choice (two) for
-// FP32, which loses with three.
+// (measured 0.41 -> 0.38 ms per batch of the 512-atom glass), the compiler's
+// choice (two) for FP32, where three measures the same and four spills.
 template <bool SPLIT>
 constexpr int gemm_waves_per_eu() {
   return SPLIT ? 3 : 1;
@@ -310,7 +310,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
   __shared__ __attribute__((aligned(16))) __bf16 sAl[SPLIT ? kMT * LDA16 : 8];
   __shared__ __attribute__((aligned(16))) __bf16 sBh[SPLIT ? kMT * LDA16 : 8];
   __shared__ __attribute__((aligned(16))) __bf16 sBl[SPLIT ? kMT * LDA16 : 8];
-  __shared__ double red[256];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nt = np / kMT;
@@ -340,35 +339,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
   constexpr int NP = kMT * PPR / 256;  // pieces per thread
   static_assert(SPLIT || kMT * PPR == NP * 256, "whole pieces per thread");
   static_assert(SPLIT || KT % 16 == 0, "whole 16-byte groups per lane group");
-  uint4 pa[NP], pb[NP];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int h = 0; h < NP; ++h) {
-      const int idx = tid + 256 * h;
-      const int r = idx / PPR, c = (idx % PPR) * 4;
-      pa[h] = *reinterpret_cast<const uint4*>(&et32[(size_t)(i0 + r) * np + k0 + c]);
-      pb[h] = *reinterpret_cast<const uint4*>(&wt32[wbase + (size_t)(j0 + r) * np + k0 + c]);
-    }
-  };
-  auto stage = [&](int buf) {
-#pragma unroll
-    for (int h = 0; h < NP; ++h) {
-      const int idx = tid + 256 * h;
-      const int r = idx / PPR, c = (idx % PPR) * 4;
-      *reinterpret_cast<uint4*>(&sA32[buf * kMT * LDA32 + r * LDA32 + c]) = pa[h];
-      *reinterpret_cast<uint4*>(&sB32[buf * kMT * LDA32 + r * LDA32 + c]) = pb[h];
-    }
-  };
+  static_assert(SPLIT || NP == 2, "two 16-byte pieces of each operand per thread");
+  // Staging registers are named scalars, not an array: the compiler moves a
+  // private array indexed in a loop into LDS or scratch before unrolling, and
+  // the prefetch then waits for its loads as soon as they are issued.
   if constexpr (!SPLIT) {
     // two LDS buffers: slice k0 + KT is fetched into registers and staged into
     // the idle buffer while slice k0 is multiplied; one barrier per slice
-    fetch(0);
-    stage(0);
+    uint4 pa0, pa1, pb0, pb1;
+    const int r0 = tid / PPR, r1 = (tid + 256) / PPR, cc = (tid % PPR) * 4;
+    const float* ga0 = et32 + (size_t)(i0 + r0) * np + cc;
+    const float* ga1 = et32 + (size_t)(i0 + r1) * np + cc;
+    const float* gb0 = wt32 + wbase + (size_t)(j0 + r0) * np + cc;
+    const float* gb1 = wt32 + wbase + (size_t)(j0 + r1) * np + cc;
+    const int sa0 = r0 * LDA32 + cc, sa1 = r1 * LDA32 + cc;
+    pa0 = *reinterpret_cast<const uint4*>(ga0);
+    pa1 = *reinterpret_cast<const uint4*>(ga1);
+    pb0 = *reinterpret_cast<const uint4*>(gb0);
+    pb1 = *reinterpret_cast<const uint4*>(gb1);
+    *reinterpret_cast<uint4*>(&sA32[sa0]) = pa0;
+    *reinterpret_cast<uint4*>(&sA32[sa1]) = pa1;
+    *reinterpret_cast<uint4*>(&sB32[sa0]) = pb0;
+    *reinterpret_cast<uint4*>(&sB32[sa1]) = pb1;
     __syncthreads();
     int cur = 0;
     for (int k0 = 0; k0 < np; k0 += KT) {
       const bool more = k0 + KT < np;
-      if (more) fetch(k0 + KT);
+      if (more) {
+        pa0 = *reinterpret_cast<const uint4*>(ga0 + k0 + KT);
+        pa1 = *reinterpret_cast<const uint4*>(ga1 + k0 + KT);
+        pb0 = *reinterpret_cast<const uint4*>(gb0 + k0 + KT);
+        pb1 = *reinterpret_cast<const uint4*>(gb1 + k0 + KT);
+      }
       const float* A = sA32 + cur * kMT * LDA32;
       const float* B = sB32 + cur * kMT * LDA32;
       // K order inside the slice: lane group lg owns k in [KPL lg, KPL lg +
@@ -395,7 +397,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
               acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[ta][tb], 0, 0, 0);
             }
       }
-      if (more) stage(cur ^ 1);
+      if (more) {
+        float* As = sA32 + (cur ^ 1) * kMT * LDA32;
+        float* Bs = sB32 + (cur ^ 1) * kMT * LDA32;
+        *reinterpret_cast<uint4*>(&As[sa0]) = pa0;
+        *reinterpret_cast<uint4*>(&As[sa1]) = pa1;
+        *reinterpret_cast<uint4*>(&Bs[sa0]) = pb0;
+        *reinterpret_cast<uint4*>(&Bs[sa1]) = pb1;
+      }
       __syncthreads();
       cur ^= 1;
     }
@@ -464,6 +473,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
       }
     }
   }
+  // the operand buffers are idle after the K loop's last barrier; the
+  // reduction reuses them (four FP32 workgroups then fit the 160 KB of LDS)
+  double* red = SPLIT ? reinterpret_cast<double*>(sAh) : reinterpret_cast<double*>(sA32);
+  static_assert(SPLIT || 2 * kMT * LDA32 * sizeof(float) >= 256 * sizeof(double), "room for the reduction");
+  static_assert(!SPLIT || kMT * LDA16 * sizeof(__bf16) >= 256 * sizeof(double), "room for the reduction");
   red[tid] = sum;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {

@@ -199,7 +199,15 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
       e2[i] = make_float2(0.f, 0.f);
       if (k < NB3 && lr < NB3) {
         const size_t o2 = (((size_t)q2 * NB3 + k) * NB3 + lr) * 2;
-        e2[i] = make_float2((float)evec[o2], (float)evec[o2 + 1]);
+        if constexpr (SPLIT) {
+          // B' stacks Re eta2 over Im eta2: lane groups 0, 1 take the real
+          // part, 2, 3 the imaginary one.  The lane loads only its own
+          // component; a run-time choice between the two halves of a
+          // register pair would send the whole array to scratch memory.
+          e2[i].x = (float)evec[o2 + (lg < 2 ? 0 : 1)];
+        } else {
+          e2[i] = make_float2((float)evec[o2], (float)evec[o2 + 1]);
+        }
       }
     }
 #pragma unroll
@@ -244,7 +252,7 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         // B' = [Re eta2 ; Im eta2]; A'(eta1^T) = [Re | -Im], A'' = [Im | Re]
-        const float b = (lg < 2) ? e2[i].x : e2[i].y;
+        const float b = e2[i].x;
         const float a1 = (i < 4) ? e1[i & 3].x : -e1[i & 3].y;
         const float a2 = (i < 4) ? e1[i & 3].y : e1[i & 3].x;
         e2h[i] = (__bf16)b;

@@ -406,21 +406,24 @@ __global__ __launch_bounds__(256) void targets_kernel(const double* __restrict__
 // Flat parameters of one member: W0 [n_in][H], b0 [H], W1..W3 [H][H] each
 // followed by its bias, W4 [H] (the head), b4 [1]; row-major.  Hidden
 // activations tanh, linear head.
+// Offsets are closed forms of the layer index rather than tables: a small
+// array indexed by a run-time layer number lives in scratch memory, and every
+// lookup in the training loop then becomes a memory load.
 struct MlpLayout {
-  int W[kMlpDepth + 1], b[kMlpDepth + 1], P;
+  int n_in, P;
+  // layer l < depth maps fan_in -> H (fan_in = n_in for l = 0, else H); the
+  // head (l = depth) maps H -> 1
+  __host__ __device__ int W(int l) const {
+    return l == 0 ? 0 : n_in * kMlpHidden + kMlpHidden + (l - 1) * (kMlpHidden * kMlpHidden + kMlpHidden);
+  }
+  __host__ __device__ int b(int l) const {
+    return W(l) + (l == 0 ? n_in * kMlpHidden : l < kMlpDepth ? kMlpHidden * kMlpHidden : kMlpHidden);
+  }
 };
 __host__ __device__ inline MlpLayout mlp_layout(int n_in) {
   MlpLayout o;
-  int off = 0, fan_in = n_in;
-  for (int l = 0; l <= kMlpDepth; ++l) {
-    const int fan_out = l < kMlpDepth ? kMlpHidden : 1;
-    o.W[l] = off;
-    off += fan_in * fan_out;
-    o.b[l] = off;
-    off += fan_out;
-    fan_in = fan_out;
-  }
-  o.P = off;
+  o.n_in = n_in;
+  o.P = o.b(kMlpDepth) + 1;
   return o;
 }
 
@@ -429,23 +432,16 @@ __host__ __device__ inline MlpLayout mlp_layout(int n_in) {
 // and with lanes over k (backward).
 constexpr int kRowPad = kMlpHidden + 1;
 struct LdsLayout {
-  int W[kMlpDepth + 1], b[kMlpDepth + 1], size;
+  int n_in, size;
+  __host__ __device__ int W(int l) const {
+    return l == 0 ? 0 : n_in * kRowPad + kMlpHidden + (l - 1) * (kMlpHidden * kRowPad + kMlpHidden);
+  }
+  __host__ __device__ int b(int l) const { return W(l) + (l == 0 ? n_in * kRowPad : l < kMlpDepth ? kMlpHidden * kRowPad : kMlpHidden); }
 };
 __host__ __device__ inline LdsLayout lds_layout(int n_in) {
   LdsLayout o;
-  int off = 0;
-  for (int l = 0; l < kMlpDepth; ++l) {
-    const int fan_in = l == 0 ? n_in : kMlpHidden;
-    o.W[l] = off;
-    off += fan_in * kRowPad;
-    o.b[l] = off;
-    off += kMlpHidden;
-  }
-  o.W[kMlpDepth] = off;
-  off += kMlpHidden;
-  o.b[kMlpDepth] = off;
-  off += 1;
-  o.size = (off + 3) & ~3;
+  o.n_in = n_in;
+  o.size = (o.b(kMlpDepth) + 1 + 3) & ~3;
   return o;
 }
 
@@ -475,15 +471,15 @@ __device__ inline void load_params_lds4(const float* __restrict__ g, float* __re
     if (f < P) {
       int l = 0;
 #pragma unroll
-      for (int t = 1; t <= kMlpDepth; ++t) l += f >= gl.W[t];
+      for (int t = 1; t <= kMlpDepth; ++t) l += f >= gl.W(t);
       int dst;
       if (l == kMlpDepth) {
-        dst = sl.W[kMlpDepth] + (f - gl.W[kMlpDepth]);  // head weights and bias, contiguous
-      } else if (f < gl.b[l]) {
-        const int r = f - gl.W[l];
-        dst = sl.W[l] + (r >> 6) * kRowPad + (r & 63);
+        dst = sl.W(kMlpDepth) + (f - gl.W(kMlpDepth));  // head weights and bias, contiguous
+      } else if (f < gl.b(l)) {
+        const int r = f - gl.W(l);
+        dst = sl.W(l) + (r >> 6) * kRowPad + (r & 63);
       } else {
-        dst = sl.b[l] + (f - gl.b[l]);
+        dst = sl.b(l) + (f - gl.b(l));
       }
       s[dst] = v[i].x;
       if (f + 1 < P) s[dst + 1] = v[i].y;
@@ -645,9 +641,9 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
       const int K = l == 0 ? n_in : H;
       const float* A = l == 0 ? xs : hs + (l - 1) * S * H;
       const int lda = l == 0 ? kMlpMaxIn : H;
-      const float* W = prm + sl.W[l];
+      const float* W = prm + sl.W(l);
       float acc[RPW];
-      const float bj = prm[sl.b[l] + lane];
+      const float bj = prm[sl.b(l) + lane];
 #pragma unroll
       for (int u = 0; u < RPW; ++u) acc[u] = bj;
       int k = 0;
@@ -675,8 +671,8 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
     }
     // head, loss and output delta
     const float* a4 = hs + 3 * S * H;
-    const float w4 = prm[sl.W[kMlpDepth] + lane];
-    const float b4 = prm[sl.b[kMlpDepth]];
+    const float w4 = prm[sl.W(kMlpDepth) + lane];
+    const float b4 = prm[sl.b(kMlpDepth)];
     float lsum = 0.f;
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
@@ -701,11 +697,11 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
     if (tid < H) {
       float s = 0.f;
       for (int i = 0; i < S; ++i) s += a4[i * H + tid] * od[i];
-      gpart[gl.W[kMlpDepth] + tid] = s;
+      gpart[gl.W(kMlpDepth) + tid] = s;
     } else if (tid == H) {
       float s = 0.f;
       for (int i = 0; i < S; ++i) s += od[i];
-      gpart[gl.b[kMlpDepth]] = s;
+      gpart[gl.b(kMlpDepth)] = s;
     }
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
@@ -732,7 +728,7 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
           s2 += av.z * dv;
           s3 += av.w * dv;
         }
-        float* gw = gpart + gl.W[l] + k0 * H + lane;
+        float* gw = gpart + gl.W(l) + k0 * H + lane;
         gw[0] = s0;
         if (k0 + 1 < K) gw[H] = s1;
         if (k0 + 2 < K) gw[2 * H] = s2;
@@ -741,11 +737,11 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
       if (tid < H) {
         float s = 0.f;
         for (int i = 0; i < S; ++i) s += dc[i * H + tid];
-        gpart[gl.b[l] + tid] = s;
+        gpart[gl.b(l) + tid] = s;
       }
       if (l > 0) {
         // delta_{l-1}[i][k] = (sum_j delta_l[i][j] W_l[k][j]) (1 - a_l[i][k]^2)   (lane = k)
-        const float* W = prm + sl.W[l];
+        const float* W = prm + sl.W(l);
         float acc[RPW];
 #pragma unroll
         for (int u = 0; u < RPW; ++u) acc[u] = 0.f;
@@ -861,11 +857,11 @@ __global__ __launch_bounds__(64 * kMlpMaxMembers) void mlp_predict_kernel(
     const float* A = l == 0 ? xs : h0;
     const int lda = l == 0 ? kMlpMaxIn : H;
     float acc[R];
-    const float bj = prm[gl.b[l] + lane];
+    const float bj = prm[gl.b(l) + lane];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = bj;
     for (int k = 0; k < K; ++k) {
-      const float w = prm[gl.W[l] + k * H + lane];
+      const float w = prm[gl.W(l) + k * H + lane];
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[r] += A[r * lda + k] * w;
     }
@@ -879,8 +875,8 @@ __global__ __launch_bounds__(64 * kMlpMaxMembers) void mlp_predict_kernel(
     h0 = h1;
     h1 = t;
   }
-  const float w4 = prm[gl.W[kMlpDepth] + lane];
-  const float b4 = prm[gl.b[kMlpDepth]];
+  const float w4 = prm[gl.W(kMlpDepth) + lane];
+  const float b4 = prm[gl.b(kMlpDepth)];
   for (int r = 0; r < R; ++r) {
     const float o = wave_sum_f(h0[r * H + lane] * w4) + b4;
     if (lane == 0) outs[wv][r] = o;
