@@ -227,6 +227,13 @@ __global__ void lw_phase_table(int nq, int n_d, int N0, int N1, int N2,
 // exactly for b in [0, ceil(t/2)) and [t + 1, ceil((t + N)/2)) ("L", nL
 // values), b == c(b) for b = t/2 (t even) and b = (t + N)/2 (t + N even)
 // ("E", nE values).
+// (t - b) mod N for t, b in [0, N): with t = (-a) mod N this is the
+// coordinate of q2 = -q - q1 on the mesh, without an integer division.
+__device__ __forceinline__ int wrap_sub(int t, int b, int N) {
+  const int c = t - b;
+  return c < 0 ? c + N : c;
+}
+
 struct HalfDim {
   int t, len1, nL, nE, e0, e1;
   __device__ int L(int j) const { return j < len1 ? j : t + 1 + (j - len1); }

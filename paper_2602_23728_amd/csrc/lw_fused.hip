@@ -84,6 +84,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
   extern __shared__ double2 smem[];
   C* at = reinterpret_cast<C*>(smem);  // [n_blk][9][NB3]
   __shared__ int rq_q1[CAP];
+  __shared__ int rq_q2[CAP];
   __shared__ int rq_code[CAP];
   __shared__ int wave_tot[BS / 64];
   __shared__ double2 phq[64];
@@ -152,13 +153,9 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     // 3. projection of queue entries [0, n)
     auto process = [&](int n) {
       for (int r = tid; r < n; r += BS) {
-        const int q1 = rq_q1[r];
+        const int q1 = rq_q1[r], q2 = rq_q2[r];
         const int code = rq_code[r];
         const int s = code & 255, s1 = (code >> 8) & 255, s2 = (code >> 16) & 255, dbl = code >> 24;
-        const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
-        const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
-                  c2 = ((-a2 - b2) % N2 + N2) % N2;
-        const int q2 = (c0 * N1 + c1) * N2 + c2;
         // FP64 weight of the entry (here, where every lane has an entry)
         const int m1 = q1 * NB3 + s1, m2 = q2 * NB3 + s2;
         double sp, sm;
@@ -225,16 +222,15 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
 #pragma unroll
       for (int k = 0; k < NB3; ++k) bits[k] = 0;
       int count = 0;
-      int q1 = 0, s1 = 0, dbl = 0;
+      int q1 = 0, q2 = 0, s1 = 0, dbl = 0;
       if (item < n_items) {
         const int qi = item / NB3;
         s1 = item - qi * NB3;
         int b0, b1, b2;
         dbl = prt.get(qi, N1, N2, b0, b1, b2);
         q1 = (b0 * N1 + b1) * N2 + b2;
-        const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
-                  c2 = ((-a2 - b2) % N2 + N2) % N2;
-        const int q2 = (c0 * N1 + c1) * N2 + c2;
+        q2 = (wrap_sub(prt.h[0].t, b0, N0) * N1 + wrap_sub(prt.h[1].t, b1, N1)) * N2 +
+             wrap_sub(prt.h[2].t, b2, N2);
         const int m1 = q1 * NB3 + s1;
         const unsigned dmask = dbl ? ~0u : 0u;
         const float4 f1 = modef[m1];
@@ -331,6 +327,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
               if (rank >= written && rank < written + take) {
                 const int slot = fill + rank - written;
                 rq_q1[slot] = q1;
+                rq_q2[slot] = q2;
                 rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (dbl << 24);
               }
               ++rank;
@@ -390,7 +387,7 @@ bool fused_supported(const kaldo_crystal* c, int prec) {
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return false;
   // dynamic LDS plus the static queue / scan / reduction buffers
-  const size_t stat = kFusedCap * 8 + kFusedThreads * 8 + 64 * 16 + 64;
+  const size_t stat = kFusedCap * 12 + kFusedThreads * 8 + 64 * 16 + 64;
   return fused_lds_bytes(c, prec) + stat <= (size_t)lds_max;
 }
 
