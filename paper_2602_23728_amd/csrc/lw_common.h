@@ -281,41 +281,49 @@ struct Partners {
     }
   }
   // coordinates of the i-th partner; returns 1 when its terms are doubled
-  __device__ int get(int i, int N1, int N2, int& b0, int& b1, int& b2) const {
+  // (unsigned arithmetic: every index and extent here is non-negative, and
+  // unsigned division by a run-time divisor is the shorter instruction
+  // sequence)
+  __device__ int get(int i_, int N1_, int N2_, int& b0, int& b1, int& b2) const {
+    unsigned i = (unsigned)i_;
+    const unsigned N2 = (unsigned)N2_, N12 = (unsigned)N1_ * N2;
     if (!half) {
-      b0 = i / (N1 * N2);
-      b1 = (i / N2) % N1;
-      b2 = i % N2;
+      const unsigned j = i / N12, r = i - j * N12, k = r / N2;
+      b0 = (int)j;
+      b1 = (int)k;
+      b2 = (int)(r - k * N2);
       return 0;
     }
-    if (i < nA) {
-      const int j = i / (N1 * N2), r = i - j * (N1 * N2);
-      b0 = h[0].L(j);
-      b1 = r / N2;
-      b2 = r - b1 * N2;
+    if (i < (unsigned)nA) {
+      const unsigned j = i / N12, r = i - j * N12, k = r / N2;
+      b0 = h[0].L((int)j);
+      b1 = (int)k;
+      b2 = (int)(r - k * N2);
       return 1;
     }
-    i -= nA;
-    if (i < nB) {
-      const int per = h[1].nL * N2, j = i / per, r = i - j * per, k = r / N2;
-      b0 = h[0].E(j);
-      b1 = h[1].L(k);
-      b2 = r - k * N2;
+    i -= (unsigned)nA;
+    if (i < (unsigned)nB) {
+      const unsigned per = (unsigned)h[1].nL * N2, j = i / per, r = i - j * per, k = r / N2;
+      b0 = h[0].E((int)j);
+      b1 = h[1].L((int)k);
+      b2 = (int)(r - k * N2);
       return 1;
     }
-    i -= nB;
-    if (i < nC) {
-      const int per = h[1].nE * h[2].nL, j = i / per, r = i - j * per, k = r / h[2].nL;
-      b0 = h[0].E(j);
-      b1 = h[1].E(k);
-      b2 = h[2].L(r - k * h[2].nL);
+    i -= (unsigned)nB;
+    if (i < (unsigned)nC) {
+      const unsigned nL2 = (unsigned)h[2].nL, per = (unsigned)h[1].nE * nL2, j = i / per,
+                     r = i - j * per, k = r / nL2;
+      b0 = h[0].E((int)j);
+      b1 = h[1].E((int)k);
+      b2 = h[2].L((int)(r - k * nL2));
       return 1;
     }
-    i -= nC;
-    const int per = h[1].nE * h[2].nE, j = i / per, r = i - j * per, k = r / h[2].nE;
-    b0 = h[0].E(j);
-    b1 = h[1].E(k);
-    b2 = h[2].E(r - k * h[2].nE);
+    i -= (unsigned)nC;
+    const unsigned nE2 = (unsigned)h[2].nE, per = (unsigned)h[1].nE * nE2, j = i / per,
+                   r = i - j * per, k = r / nE2;
+    b0 = h[0].E((int)j);
+    b1 = h[1].E((int)k);
+    b2 = h[2].E((int)(r - k * nE2));
     return 0;
   }
 };
