@@ -127,6 +127,23 @@ __device__ __forceinline__ double pair_weight(const LwParams& p, double w, doubl
   const bool pp = fabs(xp) < 2.0 * sp;
   const bool pm = fabs(xm) < 2.0 * sm;
   if (!(pp || pm)) return 0.0;
+  if (p.shape == KALDO_GAUSS) {
+    // the same value with two divisions instead of five: one reciprocal of
+    // sigma+ sigma- gives both 1/sigma, and 1/(sqrt(pi) w w1 w2) is applied
+    // once (the cut decisions above keep their exact form)
+    const double r = 1.0 / (sp * sm);
+    const double ip = sm * r, im = sp * r;
+    double gp = 0.0, gm = 0.0;
+    if (pp) {
+      const double u = xp * ip;
+      gp = exp(-(u * u)) * ip;
+    }
+    if (pm) {
+      const double u = xm * im;
+      gm = exp(-(u * u)) * im;
+    }
+    return ((n1 - n2) * gp + 0.5 * (n1 + n2 + 1.0) * gm) / (kSqrtPi * (w * (w1 * w2)));
+  }
   const double gp = pp ? smear(p.shape, xp, sp) : 0.0;
   const double gm = pm ? smear(p.shape, xm, sm) : 0.0;
   const double pop = (n1 - n2) * gp + 0.5 * (n1 + n2 + 1.0) * gm;

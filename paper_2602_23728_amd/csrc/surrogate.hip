@@ -51,7 +51,6 @@ __global__ __launch_bounds__(kJdosThreads) void jdos_kernel(
     const int32_t* __restrict__ n_live_ptr, int n_chunk, double* __restrict__ part) {
   constexpr int BS = kJdosThreads;
   __shared__ int rq_q1[kJdosCap];
-  __shared__ int rq_q2[kJdosCap];
   __shared__ int rq_code[kJdosCap];
   __shared__ int wave_tot[BS / 64];
   __shared__ double wq64[NBM];
@@ -84,9 +83,12 @@ __global__ __launch_bounds__(kJdosThreads) void jdos_kernel(
   // queue entries [0, n): exact cuts and smearing of the flagged terms
   auto process = [&](int n) {
     for (int r = tid; r < n; r += BS) {
-      const int q1 = rq_q1[r], q2 = rq_q2[r], code = rq_code[r];
+      const int q1 = rq_q1[r], code = rq_code[r];
       const int s = code & 255, s1 = (code >> 8) & 255, s2 = (code >> 16) & 255, fl = code >> 24;
-      const int m1 = q1 * NB3 + s1, m2 = q2 * NB3 + s2;
+      const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
+      const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
+                c2 = ((-a2 - b2) % N2 + N2) % N2;
+      const int m1 = q1 * NB3 + s1, m2 = ((c0 * N1 + c1) * N2 + c2) * NB3 + s2;
       const double w = wq64[s], w1 = omega[m1], w2 = omega[m2];
       double sp, sm;
       widths(p, vel, m1, m2, sp, sm);
@@ -126,15 +128,16 @@ __global__ __launch_bounds__(kJdosThreads) void jdos_kernel(
     unsigned bpm[NBM], brr[NBM];  // per s'': D+ | D- << 16 of this ordering; D+ of the mirror
 #pragma unroll
     for (int k = 0; k < NBM; ++k) bpm[k] = brr[k] = 0;
-    int count = 0, q1 = 0, q2 = 0, s1 = 0, dbl = 0;
+    int count = 0, q1 = 0, s1 = 0, dbl = 0;
     if (item < i_hi) {
       const int qi = item / NB3;
       s1 = item - qi * NB3;
       int b0, b1, b2;
       dbl = prt.get(qi, N1, N2, b0, b1, b2);
       q1 = (b0 * N1 + b1) * N2 + b2;
-      q2 = (wrap_sub(prt.h[0].t, b0, N0) * N1 + wrap_sub(prt.h[1].t, b1, N1)) * N2 +
-           wrap_sub(prt.h[2].t, b2, N2);
+      const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
+                c2 = ((-a2 - b2) % N2 + N2) % N2;
+      const int q2 = (c0 * N1 + c1) * N2 + c2;
       const float4 f1 = modef[q1 * NB3 + s1];
       const unsigned dmask = dbl ? ~0u : 0u;
 #pragma unroll
@@ -198,7 +201,6 @@ __global__ __launch_bounds__(kJdosThreads) void jdos_kernel(
                              ((mm >> s & 1u) & dbl) << 3;
               const int slot = fill + rank - written;
               rq_q1[slot] = q1;
-              rq_q2[slot] = q2;
               rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (fl << 24);
             }
             ++rank;
