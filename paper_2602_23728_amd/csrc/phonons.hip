@@ -297,6 +297,58 @@ __device__ void sort_eigen(const double* lam_in, double* lam_out, cplx* V, cplx*
 
 constexpr int kPhaseCache = 128;  // replica phases kept in LDS per q
 
+// Replica sums over the cached phases with eight replicas' force-constant
+// loads in flight at a time (a loop that loads, then adds, one replica at a
+// time waits for every load); the additions keep replica order, so the sums
+// are those of the plain loop.
+//   d1 += sum_l ph_l ka[l n],  d2 += sum_l ph_l kb[l n],  l in [0, l1)
+__device__ __forceinline__ void rep_sum2(const cplx* phl, const double* __restrict__ ka,
+                                         const double* __restrict__ kb, int n, int l1, cplx& d1,
+                                         cplx& d2) {
+  int l = 0;
+  for (; l + 8 <= l1; l += 8) {
+    double x0 = ka[(size_t)l * n], x1 = ka[(size_t)(l + 1) * n], x2 = ka[(size_t)(l + 2) * n],
+           x3 = ka[(size_t)(l + 3) * n], x4 = ka[(size_t)(l + 4) * n], x5 = ka[(size_t)(l + 5) * n],
+           x6 = ka[(size_t)(l + 6) * n], x7 = ka[(size_t)(l + 7) * n];
+    double y0 = kb[(size_t)l * n], y1 = kb[(size_t)(l + 1) * n], y2 = kb[(size_t)(l + 2) * n],
+           y3 = kb[(size_t)(l + 3) * n], y4 = kb[(size_t)(l + 4) * n], y5 = kb[(size_t)(l + 5) * n],
+           y6 = kb[(size_t)(l + 6) * n], y7 = kb[(size_t)(l + 7) * n];
+    d1 = cadd(d1, cscale(phl[l], x0)), d2 = cadd(d2, cscale(phl[l], y0));
+    d1 = cadd(d1, cscale(phl[l + 1], x1)), d2 = cadd(d2, cscale(phl[l + 1], y1));
+    d1 = cadd(d1, cscale(phl[l + 2], x2)), d2 = cadd(d2, cscale(phl[l + 2], y2));
+    d1 = cadd(d1, cscale(phl[l + 3], x3)), d2 = cadd(d2, cscale(phl[l + 3], y3));
+    d1 = cadd(d1, cscale(phl[l + 4], x4)), d2 = cadd(d2, cscale(phl[l + 4], y4));
+    d1 = cadd(d1, cscale(phl[l + 5], x5)), d2 = cadd(d2, cscale(phl[l + 5], y5));
+    d1 = cadd(d1, cscale(phl[l + 6], x6)), d2 = cadd(d2, cscale(phl[l + 6], y6));
+    d1 = cadd(d1, cscale(phl[l + 7], x7)), d2 = cadd(d2, cscale(phl[l + 7], y7));
+  }
+  for (; l < l1; ++l) {
+    d1 = cadd(d1, cscale(phl[l], ka[(size_t)l * n]));
+    d2 = cadd(d2, cscale(phl[l], kb[(size_t)l * n]));
+  }
+}
+
+// d += sum_l (-i cr_l ph_l) ka[l n] with cr_l = rc[3 l], l in [0, l1), as
+// rep_sum2 (the derivative of D along one Cartesian axis)
+__device__ __forceinline__ void rep_dsum(const cplx* phl, const double* __restrict__ ka,
+                                         const double* __restrict__ rc, int n, int l1, cplx& d) {
+  int l = 0;
+  auto term = [&](int j, double x, double cr) {
+    const cplx ph = phl[j];
+    d = cadd(d, cscale(cplx{ph.y * cr, -ph.x * cr}, x));
+  };
+  for (; l + 8 <= l1; l += 8) {
+    double x0 = ka[(size_t)l * n], x1 = ka[(size_t)(l + 1) * n], x2 = ka[(size_t)(l + 2) * n],
+           x3 = ka[(size_t)(l + 3) * n], x4 = ka[(size_t)(l + 4) * n], x5 = ka[(size_t)(l + 5) * n],
+           x6 = ka[(size_t)(l + 6) * n], x7 = ka[(size_t)(l + 7) * n];
+    double c0 = rc[3 * l], c1 = rc[3 * (l + 1)], c2 = rc[3 * (l + 2)], c3 = rc[3 * (l + 3)],
+           c4 = rc[3 * (l + 4)], c5 = rc[3 * (l + 5)], c6 = rc[3 * (l + 6)], c7 = rc[3 * (l + 7)];
+    term(l, x0, c0), term(l + 1, x1, c1), term(l + 2, x2, c2), term(l + 3, x3, c3);
+    term(l + 4, x4, c4), term(l + 5, x5, c5), term(l + 6, x6, c6), term(l + 7, x7, c7);
+  }
+  for (; l < l1; ++l) term(l, ka[(size_t)l * n], rc[3 * l]);
+}
+
 template <int NMAX>
 __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const double* __restrict__ fc2s,
                                                      const int32_t* __restrict__ rep,
@@ -335,11 +387,13 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
   for (int l = lane; l < n_rep && l < kPhaseCache; l += 64) phl[l] = phase_of(l);
   __syncthreads();
   auto phase = [&](int l) { return l < kPhaseCache ? phl[l] : phase_of(l); };
+  const int n_cached = n_rep < kPhaseCache ? n_rep : kPhaseCache;
   for (int k = lane; k < n * n; k += 64) {
     int a = k / n, b = k % n;
     cplx d1 = {0, 0}, d2 = {0, 0};
-    for (int l = 0; l < n_rep; ++l) {
-      cplx ph = phase(l);
+    rep_sum2(phl, fc2s + (size_t)a * n_rep * n + b, fc2s + (size_t)b * n_rep * n + a, n, n_cached, d1, d2);
+    for (int l = n_cached; l < n_rep; ++l) {
+      cplx ph = phase_of(l);
       d1 = cadd(d1, cscale(ph, fc2s[((size_t)a * n_rep + l) * n + b]));
       d2 = cadd(d2, cscale(ph, fc2s[((size_t)b * n_rep + l) * n + a]));
     }
@@ -457,8 +511,9 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
     for (int k = lane; k < n * n; k += 64) {
       int a = k / n, b = k % n;
       cplx d = {0, 0};
-      for (int l = 0; l < n_rep; ++l) {
-        cplx ph = phase(l);
+      rep_dsum(phl, fc2s + (size_t)a * n_rep * n + b, repcart + c, n, n_cached, d);
+      for (int l = n_cached; l < n_rep; ++l) {
+        cplx ph = phase_of(l);
         double cr = repcart[3 * l + c];
         d = cadd(d, cscale(cplx{ph.y * cr, -ph.x * cr}, fc2s[((size_t)a * n_rep + l) * n + b]));
       }
