@@ -232,7 +232,6 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         q2 = (wrap_sub(prt.h[0].t, b0, N0) * N1 + wrap_sub(prt.h[1].t, b1, N1)) * N2 +
              wrap_sub(prt.h[2].t, b2, N2);
         const int m1 = q1 * NB3 + s1;
-        const unsigned dmask = dbl ? ~0u : 0u;
         const float4 f1 = modef[m1];
 #pragma unroll
         for (int s2 = 0; s2 < NB3; ++s2) {
@@ -245,31 +244,38 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           const float scl = wq_abs_max + fabsf(f1.w) + fabsf(f2.w);
           const Band bp = make_band_f(s2p, scl, e_sig), bm = make_band_f(s2m, scl, e_sig);
           const float cp = f1.w - f2.w, cm = -f1.w - f2.w;
-          // the upper band edge for all branches first (branch-free): a
-          // candidate is any process with |x| < hi; ar is the coalescence |x+|
-          // of the mirrored ordering, (w + w2) - w1, and the decay |x-| is the
-          // same number in FP32 for both orderings
-          unsigned amb_p = 0, amb_r = 0, amb_m = 0;
+          // The upper band edge for all branches first (branch-free): a
+          // candidate is any process with |x| < hi.  The coalescence |x+| =
+          // |w + cp| and that of the mirrored ordering, |w - cp| (= (w + w2) -
+          // w1), share the edge bp.hi, and for w >= 0 the smaller of the two
+          // is |w - |cp||, bitwise in FP32 (w + cp and w - cp round
+          // monotonically); so one test per branch covers both, with cpe =
+          // -|cp| on mirrored entries and cp otherwise.  The decay |x-| is the
+          // same FP32 number for both orderings.  Live branches of q have w
+          // >= 2 pi nu_min > 0; the others drop out through `live`.
+          const float cpe = dbl ? -fabsf(cp) : cp;
+          unsigned amb_pr = 0, amb_m = 0;
 #pragma unroll
           for (int s = 0; s < NB3; ++s) {
-            const float ap = fabsf(wqf[s] + cp), ar = fabsf(wqf[s] - cp), am = fabsf(wqf[s] + cm);
-            amb_p |= (ap < bp.hi) ? (1u << s) : 0u;
-            amb_r |= (ar < bp.hi) ? (1u << s) : 0u;
+            const float apr = fabsf(wqf[s] + cpe), am = fabsf(wqf[s] + cm);
+            amb_pr |= (apr < bp.hi) ? (1u << s) : 0u;
             amb_m |= (am < bm.hi) ? (1u << s) : 0u;
           }
-          amb_r &= dmask;
-          unsigned cand = (amb_p | amb_r | amb_m) & live;
+          unsigned cand = (amb_pr | amb_m) & live;
           unsigned b = 0;
           if (cand) {
-            // the rare candidates: certain passes in FP32, the band members
-            // take the exact FP64 test
-            unsigned amb = 0;
+            // the rare candidates: which process is near (as the tests above),
+            // certain passes in FP32, the band members take the exact FP64 test
+            unsigned amb = 0, amb_p = 0, amb_r = 0;
             for (unsigned c = cand; c; c &= c - 1) {
               const int s = __ffs(c) - 1;
               const float w = wqs[s];
-              const bool sure = ((amb_p >> s & 1u) && fabsf(w + cp) < bp.lo) ||
-                                ((amb_m >> s & 1u) && fabsf(w + cm) < bm.lo) ||
-                                ((amb_r >> s & 1u) && fabsf(w - cp) < bp.lo);
+              const float ap = fabsf(w + cp), ar = fabsf(w - cp), am = fabsf(w + cm);
+              const bool hp = ap < bp.hi, hr = dbl && ar < bp.hi;
+              amb_p |= hp ? (1u << s) : 0u;
+              amb_r |= hr ? (1u << s) : 0u;
+              const bool sure = (hp && ap < bp.lo) || ((amb_m >> s & 1u) && am < bm.lo) ||
+                                (hr && ar < bp.lo);
               b |= sure ? (1u << s) : 0u;
               amb |= sure ? 0u : (1u << s);
             }
