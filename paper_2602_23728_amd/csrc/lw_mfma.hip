@@ -241,7 +241,10 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
         const float d = 4e-7f * scl + 1e-9f;
         bhi_p[r] = 2.0f * band_sqrt((float)s2p) * (1.0f + 1e-6f) + d;
         bhi_m[r] = 2.0f * band_sqrt((float)s2m) * (1.0f + 1e-6f) + d;
-        cpv[r] = (float)(w1 - w2);
+        // with the mirrored ordering, |w + cp| and |w - cp| share the edge
+        // bhi_p, and for w >= 0 the smaller is |w - |cp|| (bitwise in FP32):
+        // one test covers both
+        cpv[r] = dbl ? -fabsf((float)(w1 - w2)) : (float)(w1 - w2);
         cmv[r] = (float)(-w1 - w2);
       }
     }
@@ -371,9 +374,8 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
       for (int r = 0; r < 4; ++r) {
         bool near = false;
         if (pr_ok >> r & 1u) {
-          const float ap = fabsf(wsf + cpv[r]), am = fabsf(wsf + cmv[r]);
-          const float ar = fabsf(wsf - cpv[r]);  // coalescence of the mirrored ordering
-          near = ap < bhi_p[r] || am < bhi_m[r] || (dbl && ar < bhi_p[r]);
+          // coalescence of either ordering, or decay (w > 0: s is live)
+          near = fabsf(wsf + cpv[r]) < bhi_p[r] || fabsf(wsf + cmv[r]) < bhi_m[r];
         }
         const unsigned long long mask = __ballot(near);
         if (near) {
