@@ -254,28 +254,27 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           // same FP32 number for both orderings.  Live branches of q have w
           // >= 2 pi nu_min > 0; the others drop out through `live`.
           const float cpe = dbl ? -fabsf(cp) : cp;
-          unsigned amb_pr = 0, amb_m = 0;
+          unsigned cand = 0;
 #pragma unroll
           for (int s = 0; s < NB3; ++s) {
             const float apr = fabsf(wqf[s] + cpe), am = fabsf(wqf[s] + cm);
-            amb_pr |= (apr < bp.hi) ? (1u << s) : 0u;
-            amb_m |= (am < bm.hi) ? (1u << s) : 0u;
+            cand |= (apr < bp.hi || am < bm.hi) ? (1u << s) : 0u;
           }
-          unsigned cand = (amb_pr | amb_m) & live;
+          cand &= live;
           unsigned b = 0;
           if (cand) {
             // the rare candidates: which process is near (as the tests above),
             // certain passes in FP32, the band members take the exact FP64 test
-            unsigned amb = 0, amb_p = 0, amb_r = 0;
+            unsigned amb = 0, amb_p = 0, amb_r = 0, amb_m = 0;
             for (unsigned c = cand; c; c &= c - 1) {
               const int s = __ffs(c) - 1;
               const float w = wqs[s];
               const float ap = fabsf(w + cp), ar = fabsf(w - cp), am = fabsf(w + cm);
-              const bool hp = ap < bp.hi, hr = dbl && ar < bp.hi;
+              const bool hp = ap < bp.hi, hr = dbl && ar < bp.hi, hm = am < bm.hi;
               amb_p |= hp ? (1u << s) : 0u;
               amb_r |= hr ? (1u << s) : 0u;
-              const bool sure = (hp && ap < bp.lo) || ((amb_m >> s & 1u) && am < bm.lo) ||
-                                (hr && ar < bp.lo);
+              amb_m |= hm ? (1u << s) : 0u;
+              const bool sure = (hp && ap < bp.lo) || (hm && am < bm.lo) || (hr && ar < bp.lo);
               b |= sure ? (1u << s) : 0u;
               amb |= sure ? 0u : (1u << s);
             }
