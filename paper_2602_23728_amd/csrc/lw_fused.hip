@@ -233,12 +233,17 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
              wrap_sub(prt.h[2].t, b2, N2);
         const int m1 = q1 * NB3 + s1;
         const float4 f1 = modef[m1];
+        // the partner's mode copies one branch ahead, so that each load is
+        // in flight while the previous branch is classified
+        const float4* f2p = modef + (size_t)q2 * NB3;
+        float4 f2n = f2p[0];
 #pragma unroll
         for (int s2 = 0; s2 < NB3; ++s2) {
           const int m2 = q2 * NB3 + s2;
           // FP32 classification from the mode copies (a mode below the floor
           // carries a NaN frequency and fails every comparison)
-          const float4 f2 = modef[m2];
+          const float4 f2 = f2n;
+          if (s2 + 1 < NB3) f2n = f2p[s2 + 1];
           float s2p, s2m, e_sig;
           widths2_f(p, f1, f2, s2p, s2m, e_sig);
           const float scl = wq_abs_max + fabsf(f1.w) + fabsf(f2.w);
