@@ -135,15 +135,25 @@ __global__ __launch_bounds__(kJdosThreads) void jdos_kernel(
       int b0, b1, b2;
       dbl = prt.get(qi, N1, N2, b0, b1, b2);
       q1 = (b0 * N1 + b1) * N2 + b2;
-      const int c0 = ((-a0 - b0) % N0 + N0) % N0, c1 = ((-a1 - b1) % N1 + N1) % N1,
-                c2 = ((-a2 - b2) % N2 + N2) % N2;
-      const int q2 = (c0 * N1 + c1) * N2 + c2;
+      const int q2 = (wrap_sub(prt.h[0].t, b0, N0) * N1 + wrap_sub(prt.h[1].t, b1, N1)) * N2 +
+                     wrap_sub(prt.h[2].t, b2, N2);
       const float4 f1 = modef[q1 * NB3 + s1];
       const unsigned dmask = dbl ? ~0u : 0u;
+      // the partner's mode copies (NaN frequency below the floor); up to 8
+      // branches one branch ahead, each load in flight while the previous
+      // branch is classified (with 16 the extra registers halve occupancy)
+      const float4* f2p = modef + (size_t)q2 * NB3;
+      float4 f2n = f2p[0];
 #pragma unroll
       for (int s2 = 0; s2 < NBM; ++s2) {
         if (s2 >= NB3) break;
-        const float4 f2 = modef[q2 * NB3 + s2];  // NaN frequency below the floor
+        float4 f2;
+        if constexpr (NBM <= 8) {
+          f2 = f2n;
+          if (s2 + 1 < NB3) f2n = f2p[s2 + 1];
+        } else {
+          f2 = f2p[s2];
+        }
         float s2p, s2m, e_sig;
         widths2_f(p, f1, f2, s2p, s2m, e_sig);
         const float scl = wq_abs_max + fabsf(f1.w) + fabsf(f2.w);
