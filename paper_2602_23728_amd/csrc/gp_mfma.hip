@@ -409,18 +409,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
       cur ^= 1;
     }
   } else {
+    // one LDS buffer, the next slice prefetched into registers while the
+    // current one is multiplied: each thread moves two 16-byte pieces (8 bf16)
+    // of each of the four arrays per slice, as named scalars
+    static_assert(kMT * (KT / 8) == 2 * 256, "two pieces per array and thread");
+    const int r0 = tid / (KT / 8), r1 = (tid + 256) / (KT / 8), cc = (tid % (KT / 8)) * 8;
+    const __bf16* pah0 = eth + (size_t)(i0 + r0) * np + cc;
+    const __bf16* pah1 = eth + (size_t)(i0 + r1) * np + cc;
+    const __bf16* pal0 = etl + (size_t)(i0 + r0) * np + cc;
+    const __bf16* pal1 = etl + (size_t)(i0 + r1) * np + cc;
+    const __bf16* pbh0 = wth + wbase + (size_t)(j0 + r0) * np + cc;
+    const __bf16* pbh1 = wth + wbase + (size_t)(j0 + r1) * np + cc;
+    const __bf16* pbl0 = wtl + wbase + (size_t)(j0 + r0) * np + cc;
+    const __bf16* pbl1 = wtl + wbase + (size_t)(j0 + r1) * np + cc;
+    const int l0 = r0 * LDA16 + cc, l1 = r1 * LDA16 + cc;
+    uint4 xah0 = *reinterpret_cast<const uint4*>(pah0), xah1 = *reinterpret_cast<const uint4*>(pah1);
+    uint4 xal0 = *reinterpret_cast<const uint4*>(pal0), xal1 = *reinterpret_cast<const uint4*>(pal1);
+    uint4 xbh0 = *reinterpret_cast<const uint4*>(pbh0), xbh1 = *reinterpret_cast<const uint4*>(pbh1);
+    uint4 xbl0 = *reinterpret_cast<const uint4*>(pbl0), xbl1 = *reinterpret_cast<const uint4*>(pbl1);
+    *reinterpret_cast<uint4*>(&sAh[l0]) = xah0;
+    *reinterpret_cast<uint4*>(&sAh[l1]) = xah1;
+    *reinterpret_cast<uint4*>(&sAl[l0]) = xal0;
+    *reinterpret_cast<uint4*>(&sAl[l1]) = xal1;
+    *reinterpret_cast<uint4*>(&sBh[l0]) = xbh0;
+    *reinterpret_cast<uint4*>(&sBh[l1]) = xbh1;
+    *reinterpret_cast<uint4*>(&sBl[l0]) = xbl0;
+    *reinterpret_cast<uint4*>(&sBl[l1]) = xbl1;
+    __syncthreads();
     for (int k0 = 0; k0 < np; k0 += KT) {
-      // 8 bf16 (16 bytes) per copy
-      for (int idx = tid; idx < kMT * (KT / 8); idx += 256) {
-        const int r = idx / (KT / 8), c = (idx % (KT / 8)) * 8;
-        const size_t ga = (size_t)(i0 + r) * np + k0 + c;
-        const size_t gb = wbase + (size_t)(j0 + r) * np + k0 + c;
-        *reinterpret_cast<uint4*>(&sAh[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&eth[ga]);
-        *reinterpret_cast<uint4*>(&sAl[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&etl[ga]);
-        *reinterpret_cast<uint4*>(&sBh[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&wth[gb]);
-        *reinterpret_cast<uint4*>(&sBl[r * LDA16 + c]) = *reinterpret_cast<const uint4*>(&wtl[gb]);
+      const bool more = k0 + KT < np;
+      if (more) {
+        const int kn = k0 + KT;
+        xah0 = *reinterpret_cast<const uint4*>(pah0 + kn);
+        xah1 = *reinterpret_cast<const uint4*>(pah1 + kn);
+        xal0 = *reinterpret_cast<const uint4*>(pal0 + kn);
+        xal1 = *reinterpret_cast<const uint4*>(pal1 + kn);
+        xbh0 = *reinterpret_cast<const uint4*>(pbh0 + kn);
+        xbh1 = *reinterpret_cast<const uint4*>(pbh1 + kn);
+        xbl0 = *reinterpret_cast<const uint4*>(pbl0 + kn);
+        xbl1 = *reinterpret_cast<const uint4*>(pbl1 + kn);
       }
-      __syncthreads();
       bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -439,7 +467,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
           acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ta], bl[tb], acc[ta][tb], 0, 0, 0);
           acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ta], bh[tb], acc[ta][tb], 0, 0, 0);
         }
-      __syncthreads();
+      __syncthreads();  // every wave has read slice k0
+      if (more) {
+        *reinterpret_cast<uint4*>(&sAh[l0]) = xah0;
+        *reinterpret_cast<uint4*>(&sAh[l1]) = xah1;
+        *reinterpret_cast<uint4*>(&sAl[l0]) = xal0;
+        *reinterpret_cast<uint4*>(&sAl[l1]) = xal1;
+        *reinterpret_cast<uint4*>(&sBh[l0]) = xbh0;
+        *reinterpret_cast<uint4*>(&sBh[l1]) = xbh1;
+        *reinterpret_cast<uint4*>(&sBl[l0]) = xbl0;
+        *reinterpret_cast<uint4*>(&sBl[l1]) = xbl1;
+      }
+      __syncthreads();  // slice k0 + KT visible
     }
   }
 
