@@ -260,6 +260,55 @@ def test_bitwise_deterministic(diamond):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "mfma_fp32", "mfma_bf16x3"])
+def test_workspace_contents_do_not_matter(diamond, prec, monkeypatch):
+    """Every byte the kernels read from the workspace is written first within
+    the call: Gamma is bitwise the same for a workspace filled with 0x00, 0xff
+    or 0x7f and for a second call on the same workspace (full mesh and a
+    subset)."""
+    m, c = diamond
+    mesh = (5, 5, 5)
+    if prec.startswith("mfma"):
+        monkeypatch.setenv("KALDO_CRYSTAL_PATH", "mfma")
+    P = {"fp32": K.FP32, "fp64": K.FP64, "mfma_fp32": K.FP32, "mfma_bf16x3": K.BF16X3}[prec]
+    om, ev, ve = _oracle_inputs(m, mesh)
+    sub = np.arange(0, om.size, 7, dtype=np.int32)
+    nb = K.linewidths_workspace(c, mesh, P)
+    ref = None
+    for fill in (0x00, 0xFF, 0x7F):
+        ws = torch.full((max(nb, 1),), fill, dtype=torch.uint8, device="cuda")
+        for subset in (None, dev(sub)):
+            for _ in range(2):
+                g = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, P,
+                                      subset=subset, workspace=ws)).reshape(-1)
+                key = "full" if subset is None else "sub"
+                if ref is None:
+                    ref = {}
+                if key not in ref:
+                    ref[key] = g
+                assert np.array_equal(g, ref[key]), (fill, key)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_gamma_workspace_contents_do_not_matter(diamond, prec):
+    """The Gamma-point projection (MFMA forms) on workspaces filled with 0x00,
+    0xff and 0x7f, twice each: bitwise the same Gamma."""
+    m, _ = diamond
+    sc = models.supercell_gamma(m, (3, 3, 3))
+    c = K.Crystal.from_model(sc)
+    om, E = oph.phonons_gamma_real(sc)
+    P = K.FP32 if prec == "fp32" else K.BF16X3
+    nb = int(K.lib().kaldo_linewidths_gamma_workspace(c.handle, P))
+    ref = None
+    for fill in (0x00, 0xFF, 0x7F):
+        ws = torch.full((max(nb, 1),), fill, dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            g = host(K.linewidths_gamma(c, dev(om), dev(E), 300.0, B_FIXED, P, workspace=ws))
+            if ref is None:
+                ref = g
+            assert np.array_equal(g, ref), fill
+
+
 # ------------------------------------------------------------------ Gamma point
 
 def test_gamma_point_supercell_and_zone_folding(diamond):
