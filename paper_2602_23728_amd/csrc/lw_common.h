@@ -164,15 +164,11 @@ struct Band {
 // expansion the compiler emits for sqrtf.  The bands carry a 1e-6 relative
 // margin (about 17 ulp), so the pre-classification stays conservative.
 __device__ __forceinline__ float band_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ Band make_band(double sig2, float scale_sum) {
-  const float t = 2.0f * band_sqrt((float)sig2);
-  const float d = 4e-7f * scale_sum + 1e-9f;
-  return {t * (1.0f - 1e-6f) - d, t * (1.0f + 1e-6f) + d};
-}
 
-// FP32 twin of make_band for widths computed from the FP32 mode copy (see
-// widths2_f): the interval is widened by e_sig, the bound on how far 2 sigma
-// computed that way can lie from 2 sigma computed in FP64.
+// The band [lo, hi] around T = 2 sigma for widths computed from the FP32
+// mode copy (see widths2_f): d covers the FP32 error of |x| (scale_sum =
+// |w| + |w1| + |w2|), e_sig how far 2 sigma computed that way can lie from
+// 2 sigma computed in FP64, and the 1e-6 relative margin the rounding of T.
 __device__ __forceinline__ Band make_band_f(float sig2, float scale_sum, float e_sig) {
   const float t = 2.0f * band_sqrt(sig2);
   const float d = 4e-7f * scale_sum + 1e-9f + e_sig;
