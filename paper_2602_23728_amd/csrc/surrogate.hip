@@ -549,7 +549,7 @@ struct TrainArgs {
   const float* X;       // [n][n_in]
   const float* y;       // [n]
   const float* counts;  // [M][n]
-  float* params;        // [M][P] caller's parameters, read at start, written every step
+  float* params;        // [M][P] caller's parameters, read at start, written after the last step
   int Pp;               // padded parameter stride of the workspace arrays
   float* wp;            // [M][Pp] padded working copy of the parameters
   float* m1;            // [M][Pp]
@@ -787,6 +787,7 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
     b1t *= b1;
     b2t *= b2;
     const float c1 = 1.f / (1.f - b1t), c2 = 1.f / (1.f - b2t);
+    const bool last = step == a.steps - 1;
     for (int q = q_lo + tid; q < q_hi; q += kTrainThreads) {
       const float4 mo = reinterpret_cast<const float4*>(m1)[q];
       const float4 vo = reinterpret_cast<const float4*>(m2)[q];
@@ -817,7 +818,9 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(TrainArgs a) {
         mn[e] = b1 * mov[e] + (1.f - b1) * sv;
         vn[e] = b2 * vov[e] + (1.f - b2) * sv * sv;
         pn[e] = pov[e] - a.lr * (mn[e] * c1) / (sqrtf(vn[e] * c2) + eps);
-        if (p < P) {
+        // the caller's copy only after the last step (the working copy wp
+        // carries the parameters between steps)
+        if (last && p < P) {
           a.params[(size_t)mem * P + p] = pn[e];
           if (a.grad_out) a.grad_out[(size_t)mem * P + p] = sv;
         }
