@@ -167,6 +167,29 @@ def test_linewidths_ragged_mesh_random_cell():
             assert gamma_close(G, Go) <= tol
 
 
+@pytest.mark.parametrize("mesh", [(1, 1, 1), (1, 4, 3), (4, 1, 2)])
+@pytest.mark.parametrize("path", ["fused", "mfma"])
+def test_linewidths_meshes_with_unit_extent(diamond, mesh, path, monkeypatch):
+    """Degenerate meshes: the Gamma point alone (every partner is q itself,
+    the acoustic branches below the floor) and meshes with one point along
+    some axes (a single, self-mirrored coordinate there)."""
+    m, c = diamond
+    if path == "mfma":
+        monkeypatch.setenv("KALDO_CRYSTAL_PATH", "mfma")
+    om, ev, ve = _oracle_inputs(m, mesh)
+    Go = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_ADAPT)
+    precs = ((K.FP64, 1e-10), (K.FP32, 1e-5)) if path == "fused" else ((K.FP32, 1e-5),)
+    for prec, tol in precs:
+        G = host(K.linewidths(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT, prec))
+        assert np.all(np.isfinite(G))
+        if Go.max() == 0.0:
+            assert np.all(G == 0.0)
+        elif prec == K.FP64:
+            assert np.max(np.abs(G - Go)) <= tol * Go.max()
+        else:
+            assert gamma_close(G, Go) <= tol
+
+
 def test_c2_full_size_golden(diamond):
     path = os.path.join(GOLDEN, "c2_oracle.npz")
     if not os.path.exists(path):
