@@ -413,6 +413,27 @@ def test_gamma_point_mfma_forms(diamond, prec, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-4), ("bf16x3", 1e-3)])
+def test_gamma_point_mfma_single_ragged_tile(prec, tol):
+    """The Gamma-point projection on a 20-atom random glass: 60 modes, a single
+    tile of the 128-wide tiling, mostly zero padding.  The per-mode error of
+    the precision forms is their product rounding (FP32: 6e-8 relative;
+    BF16x3, with lo*lo dropped: about 1.5e-5) times the cancellation in V,
+    which this random cluster amplifies about 500-fold (measured: FP32 3e-5,
+    BF16x3 2e-4; the FP64 form agrees to 1e-13); the bounds leave a 3-5x
+    margin."""
+    g = models.random_cluster_glass(seed=9, n_atoms=20, box=8.0)
+    c = K.Crystal.from_model(g)
+    om, E = oph.phonons_gamma_real(g)
+    Go = olw.gamma_point_linewidths(g, om, E, 300.0, B_FIXED)
+    P = {"fp64": K.FP64, "fp32": K.FP32, "bf16x3": K.BF16X3}[prec]
+    G = host(K.linewidths_gamma(c, dev(om), dev(E), 300.0, B_FIXED, P))
+    assert np.all(np.isfinite(G))
+    err = gamma_close(G, Go)
+    print(f"{prec}: max rel err {err:.3e}")
+    assert err <= tol
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-4)])
 def test_glass_c4_mfma_sampled(prec, tol):
     cfg = configs.CONFIGS["C4"]
