@@ -9,10 +9,11 @@
 //     the phase e^{+i q.R''} folded in) built in FP64 and stored in LDS in an
 //     atom-block layout [block (jb, kb, d)][beta gamma][s].
 //  2. The (q1, s') candidates are swept in chunks, one per thread: for every
-//     s'' and s the FP64 energy cut |x+-| < 2 sigma+- of the oracle, with
-//     x+ = (w + w1) - w2, x- = (w - w1) - w2, decides; the passing
-//     (q1, s, s', s'') are compacted in a fixed order (block-wide exclusive
-//     scan) into an LDS queue.  When Phi3 is symmetric in its last two slots
+//     s'' and s the energy cut |x+-| < 2 sigma+- of the oracle, with
+//     x+ = (w + w1) - w2, x- = (w - w1) - w2, decides (pre-classified in FP32
+//     against a conservative band from the FP32 mode copies; band members
+//     take the FP64 test); the passing (q1, q2, s, s', s'') are compacted in
+//     a fixed order (block-wide exclusive scan) into an LDS queue.  When Phi3 is symmetric in its last two slots
 //     the ordered pair (q1 s', q2 s'') and its mirror (q2 s'', q1 s') have
 //     the same V, so only q1 <_lex q2 is swept (and q1 == q2 once) and an
 //     entry carries the terms of both orderings, each with its own cut.
