@@ -1,11 +1,13 @@
 // Gamma-point projection on the matrix cores.
 //
 // For each mode mu the vertex matrix is V_mu = E^T W_mu with W_mu = A_mu E
-// (paper: Eq. phi3_proj with real eigenvectors).  V_mu is symmetric, so only
-// tiles (I, J) with I <= J of the 128 x 128 tiling are computed; an
-// off-diagonal tile stands for both orders of the partner pair, and its
-// epilogue adds w(mu', mu'') + w(mu'', mu').  Tiles whose partner
-// frequencies cannot meet the 2-sigma cut in either order exit before any
+// (paper: Eq. phi3_proj with real eigenvectors).  When Phi3 is symmetric in
+// its last two slots V_mu is symmetric, so only tiles (I, J) with I <= J of
+// the 128 x 128 tiling are computed; an off-diagonal tile then stands for
+// both orders of the partner pair, and its epilogue adds w(mu', mu'') +
+// w(mu'', mu').  Without that symmetry every tile (I, J) is computed with the
+// weight of its own order.  Tiles whose partner frequencies cannot meet the
+// 2-sigma cut (in either order, for the symmetric form) exit before any
 // load (exact interval test).
 //
 // Operands live in HBM transposed, k-contiguous: ET[m][k] = E[k][m] and
@@ -36,13 +38,17 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-// ET (FP32 or bf16 hi/lo) from E (FP64, [k][m]); zero padding beyond n.
+// ET (FP32 or bf16 hi/lo) from E (FP64, [k][m]); zero padding beyond n.  A
+// non-finite entry of E raises kFlagNonFinite.
 __global__ void gm_prep_et(int n, int np, const double* __restrict__ E, float* __restrict__ et32,
-                           __bf16* __restrict__ eth, __bf16* __restrict__ etl) {
+                           __bf16* __restrict__ eth, __bf16* __restrict__ etl,
+                           int32_t* __restrict__ flags) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)np * np) return;
   const int m = idx / np, k = idx % np;
-  const float v = (m < n && k < n) ? (float)E[(size_t)k * n + m] : 0.0f;
+  const double x = (m < n && k < n) ? E[(size_t)k * n + m] : 0.0;
+  if (!(x - x == 0.0)) raise_flag(flags, kFlagNonFinite);
+  const float v = (float)x;
   if (et32) et32[idx] = v;
   if (eth) {
     __bf16 h, l;
@@ -89,10 +95,11 @@ __global__ void gm_block_ranges(int n, int nt, const double* __restrict__ omega,
   brange[2 * I + 1] = hi;
 }
 
-// Whether tile (I, J), I <= J, of mode frequency w can hold a pair that meets
-// the 2-sigma cut in either order (exact interval test on the block ranges).
+// Whether tile (I, J) of mode frequency w can hold a pair that meets the
+// 2-sigma cut (exact interval test on the block ranges); for the symmetric
+// form (I <= J) in either order of the pair.
 __device__ __forceinline__ bool gm_tile_live(const LwParams& p, double w, const double* brange,
-                                             int I, int J) {
+                                             int I, int J, bool sym) {
   const double lo1 = brange[2 * I], hi1 = brange[2 * I + 1];
   const double lo2 = brange[2 * J], hi2 = brange[2 * J + 1];
   if (!(lo1 <= hi1 && lo2 <= hi2)) return false;
@@ -102,11 +109,11 @@ __device__ __forceinline__ bool gm_tile_live(const LwParams& p, double w, const 
     const bool cm = (w - h1 - h2) < reach && (w - l1 - l2) > -reach;
     return cp || cm;
   };
-  return can(lo1, hi1, lo2, hi2) || (I != J && can(lo2, hi2, lo1, hi1));
+  return can(lo1, hi1, lo2, hi2) || (sym && I != J && can(lo2, hi2, lo1, hi1));
 }
 
-// need[jb][J] = 1 when some live tile (I <= J) of mode m0 + jb reads the W
-// columns of block J.
+// need[jb][J] = 1 when some live tile (I, J) of mode m0 + jb reads the W
+// columns of block J (I <= J for the symmetric form, every I otherwise).
 __global__ void gm_need(LwParams p, int nt, int m0, int nb, const double* __restrict__ omega,
                         const uint8_t* __restrict__ phys, const uint8_t* __restrict__ sel,
                         const double* __restrict__ brange, uint8_t* __restrict__ need) {
@@ -115,8 +122,9 @@ __global__ void gm_need(LwParams p, int nt, int m0, int nb, const double* __rest
   const int jb = k / nt, J = k % nt;
   const int mu = m0 + jb;
   bool any = false;
+  const bool sym = p.half != 0;
   if (sel[mu] && phys[mu])
-    for (int I = 0; I <= J; ++I) any = any || gm_tile_live(p, omega[mu], brange, I, J);
+    for (int I = 0; I < (sym ? J + 1 : nt); ++I) any = any || gm_tile_live(p, omega[mu], brange, I, J, sym);
   need[k] = any ? 1 : 0;
 }
 
@@ -124,8 +132,11 @@ struct GmTileInfo {
   int ti, tj;
 };
 
-__device__ __forceinline__ GmTileInfo tri_tile(int t, int nt) {
-  // t-th tile of the upper triangle (ti <= tj), row-major
+// t-th tile: of the upper triangle (ti <= tj) for the symmetric form, of the
+// full nt x nt tiling otherwise; row-major.
+__host__ __device__ inline int gm_tile_count(int nt, bool sym) { return sym ? nt * (nt + 1) / 2 : nt * nt; }
+__device__ __forceinline__ GmTileInfo gm_tile(int t, int nt, bool sym) {
+  if (!sym) return {t / nt, t % nt};
   int ti = 0, rem = t;
   while (rem >= nt - ti) {
     rem -= nt - ti;
@@ -156,8 +167,8 @@ __global__ __launch_bounds__(1024) void gm_live_list(LwParams p, int nt, int n_t
       const int jb = k / n_tri, t = k % n_tri;
       const int mu = m0 + jb;
       if (sel[mu] && phys[mu]) {
-        const GmTileInfo tt = tri_tile(t, nt);
-        f = gm_tile_live(p, omega[mu], brange, tt.ti, tt.tj) ? 1 : 0;
+        const GmTileInfo tt = gm_tile(t, nt, p.half != 0);
+        f = gm_tile_live(p, omega[mu], brange, tt.ti, tt.tj, p.half != 0) ? 1 : 0;
       }
     }
     int incl = f;
@@ -318,7 +329,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
   if ((int)blockIdx.x >= *live_count) return;
   const int pair = live_list[blockIdx.x];
   const int jb = pair / n_tri, t = pair % n_tri;
-  const GmTileInfo tt = tri_tile(t, nt);
+  const GmTileInfo tt = gm_tile(t, nt, p.half != 0);
   const int mu = m0 + jb;
   const int i0 = tt.ti * kMT, j0 = tt.tj * kMT;
   const double w = omega[mu];
@@ -483,7 +494,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gemm_waves_
   }
 
   // Epilogue: lane holds V[m = row0 + 4*lg + r][n = col0 + lr] of each 16 x 16 tile.
-  const bool offdiag = tt.ti != tt.tj;
+  // An off-diagonal tile of the symmetric form also stands for its mirror.
+  const bool offdiag = p.half != 0 && tt.ti != tt.tj;
   const double s2 = 2.0 * p.sig_fixed;
   double sum = 0.0;
 #pragma unroll
@@ -544,7 +556,7 @@ bool gm_supported(const kaldo_crystal* c) {
 size_t gm_workspace_bytes(const kaldo_crystal* c, int prec) {
   const size_t n = c->nb3;
   const size_t np = (n + kMT - 1) / kMT * kMT;
-  const size_t nt = np / kMT, n_tri = nt * (nt + 1) / 2;
+  const size_t nt = np / kMT, n_tri = gm_tile_count((int)nt, c->bloch.sym_jk != 0);
   const bool split = prec == KALDO_BF16X3;
   size_t o = 0;
   auto take = [&](size_t bytes) { o += (bytes + 255) / 256 * 256; };
@@ -562,9 +574,10 @@ size_t gm_workspace_bytes(const kaldo_crystal* c, int prec) {
 int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* evec,
            const double* occ, const uint8_t* phys, const uint8_t* sel, unsigned char* ws,
            int prec, double* gamma, hipStream_t st) {
+  int32_t* flags = c->d_flags;
   const int n = c->nb3;
   const int np = (n + kMT - 1) / kMT * kMT;
-  const int nt = np / kMT, n_tri = nt * (nt + 1) / 2;
+  const int nt = np / kMT, n_tri = gm_tile_count(nt, p.half != 0);
   const bool split = prec == KALDO_BF16X3;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -600,7 +613,7 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
   KALDO_LAUNCH("gm_block_ranges", gm_block_ranges, dim3((nt + 63) / 64), dim3(64), 0, st, n, nt, omega,
                phys, brange);
   KALDO_LAUNCH("gm_prep_et", gm_prep_et, dim3((nn + 255) / 256), dim3(256), 0, st, n, np, evec,
-               et32, eth, etl);
+               et32, eth, etl, flags);
   for (int m0 = 0; m0 < n; m0 += kMBatch) {
     const int nb = std::min(kMBatch, n - m0);
     const long na = (long)c->gamma.n_bc * kMBatch;

@@ -484,3 +484,29 @@ def test_c2_golden_bf16x3(diamond):
     kerr = kappa_close(kg, g["kappa"])
     print(f"C2 bf16x3: Gamma max rel err {err:.3e}, kappa rel err {kerr:.3e}")
     assert kerr <= 1e-4
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 1e-4)])
+def test_gamma_point_fc3_not_mirror_symmetric(diamond, prec, tol):
+    """Gamma-point projection with a Phi3 that is not symmetric in its last
+    two slots (entries with j < k scaled by 1.3): V_mu is then not a
+    symmetric matrix, the triangle-only tiling would be wrong, and every
+    (I, J) tile must be computed with the weight of its own order."""
+    import dataclasses
+    m, _ = diamond
+    sc = models.supercell_gamma(m, (3, 3, 3))
+    val = np.where(sc.fc3_j < sc.fc3_k, 1.3, 1.0) * sc.fc3_val
+    sa = dataclasses.replace(sc, fc3_val=val)
+    c = K.Crystal.from_model(sa)
+    om, E = oph.phonons_gamma_real(sc)
+    Go = olw.gamma_point_linewidths(sa, om, E, 300.0, B_FIXED)
+    Gs = olw.gamma_point_linewidths(sc, om, E, 300.0, B_FIXED)
+    assert np.max(np.abs(Go - Gs)) > 1e-2 * Gs.max()  # the perturbation matters
+    P = {"fp64": K.FP64, "fp32": K.FP32, "bf16x3": K.BF16X3}[prec]
+    G = host(K.linewidths_gamma(c, dev(om), dev(E), 300.0, B_FIXED, P))
+    if prec == "fp64":
+        assert np.max(np.abs(G - Go)) <= tol * Go.max()
+    else:
+        err = gamma_close(G, Go)
+        print(f"{prec}: max rel err {err:.3e}")
+        assert err <= tol
