@@ -35,8 +35,15 @@
  * valid after the stream is synchronised.
  *
  * Errors: every call returns a kaldo_status; no exception crosses the ABI.
- * Arguments are validated before anything is enqueued (KALDO_EINVAL);
- * device-runtime failures return KALDO_EDEVICE.  kaldo_last_error() returns
+ * Host arguments (sizes, structs, host arrays) are validated before anything
+ * is enqueued (KALDO_EINVAL); device-runtime failures return KALDO_EDEVICE.
+ * Device-resident inputs cannot be read before the call returns without a
+ * synchronisation, so the kernels validate them as they read them and record
+ * what they find in a sticky status word of the crystal handle:
+ * kaldo_device_status() synchronises the stream, returns that status
+ * (KALDO_EINVAL for a non-finite omega/eta/v/Gamma or a subset index out of
+ * range, KALDO_ENUMERIC for an imaginary mode above nu_min or an eigen-solver
+ * that stopped at its sweep cap) and clears it.  kaldo_last_error() returns
  * a thread-local description of the last failure in the calling thread.
  *
  * Determinism: all reductions run in a fixed order; identical inputs give
@@ -119,8 +126,25 @@ int kaldo_crystal_create(int32_t n_basis, const double* lattice, const double* m
                          const int32_t* fc3_k, const double* fc3_val,
                          kaldo_crystal** out);
 
-/* Frees the handle and its device memory.  NULL is a no-op. */
+/* Frees the handle and its device memory.  NULL is a no-op.  Synchronous
+ * (hipFree); call it before the process starts tearing down the HIP runtime,
+ * not from a static destructor or an interpreter finaliser. */
 int kaldo_crystal_destroy(kaldo_crystal* c);
+
+/* kaldo_device_status -- outcome of the device-side input checks of every
+ * call made on this handle since the last query (paper: the selective
+ * calculation of "Computational Implementation", whose min_frequency makes a
+ * mode below it unphysical; a mode with omega^2 < 0 above it is an error).
+ * Synchronises `stream` (the stream the calls were enqueued on), reads the
+ * handle's status word and clears it.  Returns KALDO_OK if nothing was found;
+ * KALDO_EINVAL if a kernel read a non-finite omega, eigenvector component,
+ * velocity or linewidth, or a modes_subset index outside [0, n_modes) (such
+ * entries are ignored); KALDO_ENUMERIC if a mode had omega < 0 with
+ * |nu| >= nu_min_thz (the linewidth and conductivity kernels treat it as
+ * unphysical), or if kaldo_phonons' Jacobi solver reached its sweep cap on
+ * some q.  kaldo_last_error() then lists every condition found.  Calls on
+ * other streams that are still running may set the word after it is read. */
+int kaldo_device_status(kaldo_crystal* c, void* stream);
 
 /* kaldo_phonons -- harmonic phonons on a Gamma-centred mesh, FP64 on the GPU.
  * (paper: Eq. dynmat_reciprocal with phase e^{-i q.R_l}, Eq. eigenvalue_crystal,
@@ -137,7 +161,10 @@ int kaldo_crystal_destroy(kaldo_crystal* c);
  *           elements; 0 where |nu| < 1e-3 THz
  * Requires nb3 <= 32 (one workgroup per q, matrices held in LDS); larger
  * cells at the Gamma point use kaldo_phonons_gamma.  Cyclic Jacobi, at most
- * 60 sweeps (converged to off-diagonal norm <= 1e-16 of the total). */
+ * 60 sweeps (converged to off-diagonal norm <= 1e-16 of the total); a q whose
+ * solver stops at the cap sets the handle's non-convergence status
+ * (kaldo_device_status -> KALDO_ENUMERIC).  The environment variable
+ * KALDO_JACOBI_SWEEPS (1..60) lowers the cap, for tests of that status. */
 int kaldo_phonons(const kaldo_crystal* c, const int32_t* mesh, double* omega,
                   double* evec, double* vel, void* stream);
 
@@ -361,13 +388,17 @@ int kaldo_gate_calibrate(int64_t n, const int32_t* modes, const double* gamma, c
 /* kaldo_gate_select -- rows k with score[k] >= *tau whose mode is not yet
  * computed (computed[modes[k]] == 0) are appended in row order to fallback
  * (device int32[n]) and marked computed; *n_fallback (device int32) = their
- * count.  The listed modes must be distinct. */
-int kaldo_gate_select(int64_t n, const int32_t* modes, const float* score, const float* tau,
-                      uint8_t* computed, int32_t* fallback, int32_t* n_fallback, void* stream);
+ * count.  The listed modes must be distinct; computed is device
+ * uint8[n_modes] and rows whose mode lies outside [0, n_modes) are skipped. */
+int kaldo_gate_select(int64_t n, int64_t n_modes, const int32_t* modes, const float* score,
+                      const float* tau, uint8_t* computed, int32_t* fallback, int32_t* n_fallback,
+                      void* stream);
 
 /* kaldo_surrogate_fill -- gamma[modes[k]] = exp(mean[k] sd + mu) for rows whose
- * mode is not computed; other entries untouched. */
-int kaldo_surrogate_fill(int64_t n, const int32_t* modes, const float* mean,
+ * mode is not computed; other entries untouched.  computed is device
+ * uint8[n_modes], gamma device double[n_modes]; rows whose mode lies outside
+ * [0, n_modes) are skipped. */
+int kaldo_surrogate_fill(int64_t n, int64_t n_modes, const int32_t* modes, const float* mean,
                          const float* y_mu_sd, const uint8_t* computed, double* gamma,
                          void* stream);
 

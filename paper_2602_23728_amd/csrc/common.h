@@ -34,6 +34,15 @@ constexpr double kGammaFloorRel = 1e-8;
 constexpr int kMaxNb3Phonons = 32;
 constexpr int kMaxNb3Linewidths = 16;
 
+// Sticky device status of a handle (read and cleared by kaldo_device_status):
+// bits the kernels set when they find a problem in device-resident inputs,
+// with an atomic OR on the handle's status word (only on the error path).
+constexpr int32_t kFlagNonFinite = 1;    // non-finite omega, eta, v or Gamma input
+constexpr int32_t kFlagImaginary = 2;    // omega < 0 with |nu| >= nu_min
+constexpr int32_t kFlagNoConverge = 4;   // an eigen-solver stopped at its sweep cap
+constexpr int32_t kFlagSubset = 8;       // a modes_subset index outside [0, n_modes)
+__device__ __forceinline__ void raise_flag(int32_t* flags, int32_t bit) { atomicOr(flags, bit); }
+
 // ----------------------------------------------------------------- errors
 void set_error(const std::string& msg);
 
@@ -116,6 +125,7 @@ struct kaldo_crystal_s {
   double* d_fc2 = nullptr;  // [nb3][n_rep][nb3] divided by sqrt(m m)
   int32_t* d_rep = nullptr; // [n_rep][3]
   double* d_repcart = nullptr;  // [n_rep][3] Cartesian replica vectors
+  int32_t* d_flags = nullptr;   // sticky device status word (kFlag* bits)
   kaldo::Fc3Bloch bloch;
   kaldo::Fc3Gamma gamma;
   std::vector<void*> allocations;

@@ -299,6 +299,7 @@ extern "C" int kaldo_crystal_create(int32_t n_basis, const double* lattice, cons
   int rc = upload(c, &c->d_fc2, scaled);
   if (!rc) rc = upload(c, &c->d_rep, c->rep);
   if (!rc) rc = upload(c, &c->d_repcart, repcart);
+  if (!rc) rc = upload(c, &c->d_flags, std::vector<int32_t>(1, 0));
   if (!rc) rc = build_bloch(c, nnz, fc3_i, fc3_j, fc3_k, fc3_val);
   if (!rc && n_rep == 1) rc = build_gamma(c, nnz, fc3_i, fc3_j, fc3_k, fc3_val);
   if (rc) {
@@ -308,6 +309,23 @@ extern "C" int kaldo_crystal_create(int32_t n_basis, const double* lattice, cons
   }
   *out = c;
   return KALDO_OK;
+}
+
+extern "C" int kaldo_device_status(kaldo_crystal* c, void* stream) {
+  KALDO_REQUIRE(c != nullptr, "kaldo_device_status: NULL handle");
+  KALDO_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  int32_t flags = 0;
+  KALDO_HIP(hipMemcpy(&flags, c->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+  if (flags == 0) return KALDO_OK;
+  const int32_t zero = 0;
+  KALDO_HIP(hipMemcpy(c->d_flags, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  std::string msg = "kaldo_device_status:";
+  if (flags & kFlagNonFinite) msg += " non-finite value in a device input (omega, eta, v or Gamma);";
+  if (flags & kFlagSubset) msg += " modes_subset index out of range;";
+  if (flags & kFlagImaginary) msg += " imaginary mode (omega^2 < 0) above nu_min;";
+  if (flags & kFlagNoConverge) msg += " eigen-solver did not converge within its sweep cap;";
+  set_error(msg);
+  return (flags & (kFlagNonFinite | kFlagSubset)) ? KALDO_EINVAL : KALDO_ENUMERIC;
 }
 
 extern "C" int kaldo_crystal_destroy(kaldo_crystal* c) {

@@ -27,15 +27,24 @@ constexpr int kGpTile = 64;
 constexpr int kGpK = 16;
 constexpr int kGpBatch = 64;
 
+// E rounded to T; a non-finite entry raises kFlagNonFinite.
 template <typename T>
-__global__ void gp_round(long n, const double* __restrict__ src, T* __restrict__ dst) {
+__global__ void gp_round(long n, const double* __restrict__ src, T* __restrict__ dst,
+                         int32_t* __restrict__ flags) {
   long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) dst[k] = (T)src[k];
+  if (k >= n) return;
+  const double x = src[k];
+  dst[k] = (T)x;
+  if (!(x - x == 0.0)) raise_flag(flags, kFlagNonFinite);
 }
 
-__global__ void gp_prepare(int n, const double* __restrict__ omega, double inv_kt_hbar,
-                           double nu_min, double* __restrict__ occ, uint8_t* __restrict__ phys,
-                           uint8_t* __restrict__ sel, int sel_all) {
+// Per mode: population and masks, and validation of omega (non-finite:
+// kFlagNonFinite; imaginary with |nu| >= nu_min: kFlagImaginary).  The
+// eigenvectors are checked where they are rounded to the contraction type.
+__global__ void gp_prepare(int n, const double* __restrict__ omega,
+                           double inv_kt_hbar, double nu_min, double* __restrict__ occ,
+                           uint8_t* __restrict__ phys, uint8_t* __restrict__ sel, int sel_all,
+                           int32_t* __restrict__ flags) {
   int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   double w = omega[m];
@@ -43,14 +52,19 @@ __global__ void gp_prepare(int n, const double* __restrict__ omega, double inv_k
   phys[m] = p;
   occ[m] = p ? 1.0 / expm1(w * inv_kt_hbar) : 0.0;
   sel[m] = sel_all ? 1 : 0;
+  if (!(w - w == 0.0)) raise_flag(flags, kFlagNonFinite);
+  if (w < 0.0 && (-w / kTwoPi) >= nu_min) raise_flag(flags, kFlagImaginary);
 }
 
 __global__ void gp_select(const int32_t* __restrict__ subset, long n_subset, int n,
-                          uint8_t* __restrict__ sel) {
+                          uint8_t* __restrict__ sel, int32_t* __restrict__ flags) {
   long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_subset) return;
   int m = subset[k];
-  if (m >= 0 && m < n) sel[m] = 1;
+  if (m >= 0 && m < n)
+    sel[m] = 1;
+  else
+    raise_flag(flags, kFlagSubset);
 }
 
 // avals[j][k] = sum_{t in pattern k} coef_t E[a_t][mode m0 + j]  (FP64 sum)
@@ -245,16 +259,17 @@ static int run_gamma(const kaldo_crystal* c, const double* omega, const double* 
   T* W = reinterpret_cast<T*>(ws + g.off_w);
   double* partial = reinterpret_cast<double*>(ws + g.off_partial);
   KALDO_LAUNCH("gp_prepare", gp_prepare, dim3((n + 255) / 256), dim3(256), 0, st, n, omega,
-                     kHbar / (kKb * Tk), b->nu_min_thz, occ, phys, sel, subset ? 0 : 1);
+               kHbar / (kKb * Tk), b->nu_min_thz, occ, phys, sel, subset ? 0 : 1, c->d_flags);
   if (subset && n_subset > 0)
     KALDO_LAUNCH("gp_select", gp_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
-                       (long)n_subset, n, sel);
+                 (long)n_subset, n, sel, c->d_flags);
   int32_t mesh1[3] = {1, 1, 1};
   LwParams p = make_params(c, mesh1, Tk, b);
   if (use_mfma(c, prec))
     return run_gm(c, p, omega, evec, occ, phys, sel, ws + g.off_rest, prec, gamma, st);
   long nn = (long)n * n;
-  KALDO_LAUNCH("gp_round", gp_round<T>, dim3((nn + 255) / 256), dim3(256), 0, st, nn, evec, Et);
+  KALDO_LAUNCH("gp_round", gp_round<T>, dim3((nn + 255) / 256), dim3(256), 0, st, nn, evec, Et,
+               c->d_flags);
   for (int m0 = 0; m0 < n; m0 += kGpBatch) {
     int nb = std::min(kGpBatch, n - m0);
     long na = (long)c->gamma.n_bc * nb;

@@ -13,12 +13,23 @@ __global__ __launch_bounds__(kKappaThreads) void kappa_kernel(long n_modes, cons
                                                     const double* __restrict__ vel,
                                                     const double* __restrict__ gamma,
                                                     double inv_kt_hbar, double nu_min,
-                                                    double scale, double* __restrict__ kappa) {
+                                                    double scale, double* __restrict__ kappa,
+                                                    int32_t* __restrict__ flags) {
   __shared__ double red[kKappaThreads][6];
   const int t = threadIdx.x;
   // max Gamma (order-independent)
   double gmax = 0.0;
-  for (long m = t; m < n_modes; m += kKappaThreads) gmax = fmax(gmax, gamma[m]);
+  double chk = 0.0;  // x - x: 0 for finite inputs, NaN otherwise
+  bool imag = false;
+  for (long m = t; m < n_modes; m += kKappaThreads) {
+    const double g = gamma[m], w = omega[m];
+    gmax = fmax(gmax, g);
+    chk += (g - g) + (w - w) + (vel[3 * m] - vel[3 * m]) + (vel[3 * m + 1] - vel[3 * m + 1]) +
+           (vel[3 * m + 2] - vel[3 * m + 2]);
+    imag = imag || (w < 0.0 && (-w / kTwoPi) >= nu_min);
+  }
+  if (!(chk == 0.0)) raise_flag(flags, kFlagNonFinite);
+  if (imag) raise_flag(flags, kFlagImaginary);
   red[t][0] = gmax;
   __syncthreads();
   for (int w = kKappaThreads / 2; w > 0; w >>= 1) {
@@ -71,7 +82,7 @@ extern "C" int kaldo_kappa_rta(const kaldo_crystal* c, const int32_t* mesh, cons
   const long n_modes = nq * c->nb3;
   const double scale = kKappaUnit / ((double)nq * c->volume);
   KALDO_LAUNCH("kappa_kernel", kappa_kernel, dim3(1), dim3(kKappaThreads), 0, static_cast<hipStream_t>(stream), n_modes,
-                     omega, vel, gamma, kHbar / (kKb * temperature), nu_min_thz, scale, kappa);
+                     omega, vel, gamma, kHbar / (kKb * temperature), nu_min_thz, scale, kappa, c->d_flags);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
 }

@@ -31,11 +31,14 @@ namespace kaldo {
 
 // modef[m] = (v, omega) in FP32 for the sweep's pre-classification, omega
 // NaN below the frequency floor so that every comparison against the mode
-// fails, as the physical mask demands.
-__global__ void lw_prepare(int n_modes, const double* __restrict__ omega,
-                           const double* __restrict__ vel, double inv_kt_hbar,
-                           double nu_min, double* __restrict__ occ, uint8_t* __restrict__ phys,
-                           uint8_t* __restrict__ sel, float4* __restrict__ modef, int sel_all) {
+// fails, as the physical mask demands.  Also validates the mode's inputs:
+// a non-finite omega, v or eigenvector column raises kFlagNonFinite, an
+// imaginary mode (omega < 0) with |nu| >= nu_min raises kFlagImaginary.
+__global__ void lw_prepare(int n_modes, int nb3, const double* __restrict__ omega,
+                           const double* __restrict__ vel, const double* __restrict__ evec,
+                           double inv_kt_hbar, double nu_min, double* __restrict__ occ,
+                           uint8_t* __restrict__ phys, uint8_t* __restrict__ sel,
+                           float4* __restrict__ modef, int sel_all, int32_t* __restrict__ flags) {
   int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_modes) return;
   double w = omega[m];
@@ -43,16 +46,26 @@ __global__ void lw_prepare(int n_modes, const double* __restrict__ omega,
   phys[m] = p;
   occ[m] = p ? 1.0 / expm1(w * inv_kt_hbar) : 0.0;
   sel[m] = sel_all ? 1 : 0;
-  modef[m] = make_float4((float)vel[3 * (size_t)m], (float)vel[3 * (size_t)m + 1],
-                         (float)vel[3 * (size_t)m + 2], p ? (float)w : __builtin_nanf(""));
+  const double v0 = vel[3 * (size_t)m], v1 = vel[3 * (size_t)m + 1], v2 = vel[3 * (size_t)m + 2];
+  modef[m] = make_float4((float)v0, (float)v1, (float)v2, p ? (float)w : __builtin_nanf(""));
+  // x - x is 0 for every finite x and NaN otherwise
+  double chk = (w - w) + (v0 - v0) + (v1 - v1) + (v2 - v2);
+  const int q = m / nb3, s = m - q * nb3;
+  const double* col = evec + ((size_t)q * nb3 * nb3 + s) * 2;
+  for (int j = 0; j < nb3; ++j) chk += (col[2 * j * nb3] - col[2 * j * nb3]) + (col[2 * j * nb3 + 1] - col[2 * j * nb3 + 1]);
+  if (!(chk == 0.0)) raise_flag(flags, kFlagNonFinite);
+  if (w < 0.0 && (-w / kTwoPi) >= nu_min) raise_flag(flags, kFlagImaginary);
 }
 
 __global__ void lw_select(const int32_t* __restrict__ subset, long n_subset, int n_modes,
-                          uint8_t* __restrict__ sel) {
+                          uint8_t* __restrict__ sel, int32_t* __restrict__ flags) {
   long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_subset) return;
   int m = subset[k];
-  if (m >= 0 && m < n_modes) sel[m] = 1;
+  if (m >= 0 && m < n_modes)
+    sel[m] = 1;
+  else
+    raise_flag(flags, kFlagSubset);
 }
 
 template <typename T>
@@ -195,35 +208,6 @@ __global__ void lw_finish(int nq, int nb3, int nblk, double scale, const double*
   gamma[m] = phys[m] ? scale * acc : 0.0;
 }
 
-struct CrystalWs {
-  size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, off_phase, off_modef, off_qlist, off_fpart, total;
-};
-
-static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
-  const int nb3 = c->nb3;
-  const size_t cs = prec == KALDO_FP64 ? 16 : 8;
-  const long nblk = (nq + 63) / 64;
-  CrystalWs w;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    size_t r = o;
-    o += (bytes + 255) / 256 * 256;
-    return r;
-  };
-  w.off_occ = take(sizeof(double) * nq * nb3);
-  w.off_phys = take(nq * nb3);
-  w.off_sel = take(nq * nb3);
-  w.off_eta = take(cs * nq * nb3 * nb3);
-  w.off_at = take(cs * nq * (size_t)c->bloch.n_e * nb3);
-  w.off_partial = take(sizeof(double) * nq * nblk * nb3);
-  w.off_phase = take(cs * nq * (size_t)std::max(1, c->bloch.n_d));
-  w.off_modef = take(sizeof(float4) * nq * nb3);
-  w.off_qlist = take(sizeof(int32_t) * (2 * nq + 1));
-  w.off_fpart = take(sizeof(double) * nq * kFusedMaxChunks * nb3);
-  w.total = o;
-  return w;
-}
-
 // Which crystal kernel serves a request: the dense MFMA kernel for the split
 // form (and, in FP32, for cells of 9 or more branches, where dense 16-wide
 // tiles beat the pruned VALU path), otherwise the fused pruned kernel, and the
@@ -242,6 +226,45 @@ static CrystalPath choose_path(const kaldo_crystal* c, int prec) {
     return CrystalPath::Mfma;
   if (fused_supported(c, prec)) return CrystalPath::Fused;
   return CrystalPath::Generic;
+}
+
+// Workspace layout of the path that serves the request (offsets of buffers
+// another path needs are left at 0 and never used).
+struct CrystalWs {
+  CrystalPath path;
+  size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, off_phase, off_modef, off_qlist, off_fpart, total;
+};
+
+static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
+  const int nb3 = c->nb3;
+  const size_t cs = prec == KALDO_FP64 ? 16 : 8;
+  const long nblk = (nq + 63) / 64;
+  CrystalWs w{};
+  w.path = choose_path(c, prec);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  w.off_occ = take(sizeof(double) * nq * nb3);
+  w.off_phys = take(nq * nb3);
+  w.off_sel = take(nq * nb3);
+  w.off_modef = take(sizeof(float4) * nq * nb3);
+  if (w.path == CrystalPath::Generic) {
+    w.off_eta = take(cs * nq * nb3 * nb3);
+    w.off_at = take(cs * nq * (size_t)c->bloch.n_e * nb3);
+    w.off_partial = take(sizeof(double) * nq * nblk * nb3);
+  } else if (w.path == CrystalPath::Fused) {
+    w.off_eta = take(cs * nq * nb3 * nb3);
+    w.off_phase = take(cs * nq * (size_t)std::max(1, c->bloch.n_d));
+    w.off_qlist = take(sizeof(int32_t) * (2 * nq + 1));
+    w.off_fpart = take(sizeof(double) * nq * kFusedMaxChunks * nb3);
+  } else {
+    w.off_phase = take(sizeof(float2) * nq * (size_t)std::max(1, c->bloch.n_d));
+  }
+  w.total = o;
+  return w;
 }
 
 template <typename T>
@@ -263,12 +286,13 @@ static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double
   float4* modef = reinterpret_cast<float4*>(ws + w.off_modef);
   const double inv_kt_hbar = kHbar / (kKb * T_k);
   KALDO_LAUNCH("lw_prepare", lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes,
-                     omega, vel, inv_kt_hbar, b->nu_min_thz, occ, phys, sel, modef, subset ? 0 : 1);
+               nb3, omega, vel, evec, inv_kt_hbar, b->nu_min_thz, occ, phys, sel, modef,
+               subset ? 0 : 1, c->d_flags);
   if (subset && n_subset > 0)
     KALDO_LAUNCH("lw_select", lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
-                       (long)n_subset, n_modes, sel);
+                 (long)n_subset, n_modes, sel, c->d_flags);
   LwParams p = make_params(c, mesh, T_k, b);
-  const CrystalPath path = choose_path(c, prec);
+  const CrystalPath path = w.path;
   if (path == CrystalPath::Mfma) {
     float2* phase_tab = reinterpret_cast<float2*>(ws + w.off_phase);
     return launch_mfma(c, p, prec == KALDO_BF16X3, omega, vel, occ, phys, sel, evec, phase_tab,
@@ -308,11 +332,15 @@ extern "C" size_t kaldo_linewidths_workspace(const kaldo_crystal* c, const int32
   return crystal_ws(c, (long)mesh[0] * mesh[1] * mesh[2], precision).total;
 }
 
-extern "C" int kaldo_linewidths(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
-                                const double* evec, const double* vel, double temperature,
-                                const kaldo_broadening* b, int32_t precision,
-                                const int32_t* modes_subset, int64_t n_subset, void* workspace,
-                                size_t workspace_bytes, double* gamma, void* stream) {
+namespace kaldo {
+
+// Validation and enqueue of kaldo_linewidths on a given workspace (shared by
+// the entry points that differ only in where the workspace comes from).
+int linewidths_enqueue(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                       const double* evec, const double* vel, double temperature,
+                       const kaldo_broadening* b, int32_t precision,
+                       const int32_t* modes_subset, int64_t n_subset, void* workspace,
+                       size_t workspace_bytes, double* gamma, hipStream_t st) {
   KALDO_REQUIRE(c && mesh && omega && evec && vel && b && gamma, "kaldo_linewidths: NULL argument");
   KALDO_REQUIRE(mesh[0] >= 1 && mesh[1] >= 1 && mesh[2] >= 1, "kaldo_linewidths: mesh must be >= 1");
   KALDO_REQUIRE(c->nb3 <= kMaxNb3Linewidths, "kaldo_linewidths: nb3 > 16 (use kaldo_linewidths_gamma)");
@@ -331,11 +359,22 @@ extern "C" int kaldo_linewidths(const kaldo_crystal* c, const int32_t* mesh, con
   CrystalWs w = crystal_ws(c, nq, precision);
   KALDO_REQUIRE(workspace && workspace_bytes >= w.total, "kaldo_linewidths: workspace too small");
   if (modes_subset && n_subset == 0) return KALDO_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
   auto* ws = static_cast<unsigned char*>(workspace);
   if (precision == KALDO_FP64)
     return run_crystal<double>(c, mesh, omega, evec, vel, temperature, b, modes_subset, n_subset,
                                ws, w, precision, gamma, st);
   return run_crystal<float>(c, mesh, omega, evec, vel, temperature, b, modes_subset, n_subset, ws,
                             w, precision, gamma, st);
+}
+
+}  // namespace kaldo
+
+extern "C" int kaldo_linewidths(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                                const double* evec, const double* vel, double temperature,
+                                const kaldo_broadening* b, int32_t precision,
+                                const int32_t* modes_subset, int64_t n_subset, void* workspace,
+                                size_t workspace_bytes, double* gamma, void* stream) {
+  return linewidths_enqueue(c, mesh, omega, evec, vel, temperature, b, precision, modes_subset,
+                            n_subset, workspace, workspace_bytes, gamma,
+                            static_cast<hipStream_t>(stream));
 }

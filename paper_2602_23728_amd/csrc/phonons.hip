@@ -5,7 +5,9 @@
 //
 // Paper: Eq. dynmat (mass scaling), Eq. dynmat_reciprocal (phase e^{-i q.R_l}),
 // Eq. eigenvalue_crystal, Eq. groupvel (analytic dD/dq).
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -26,13 +28,14 @@ __device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.x * s, a.y 
 // [-s e^{-i phi}, c]] with t = tan(theta) the smaller root of
 // t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp)/(2|a|), annihilates a_pq.
 // All 64 lanes of the workgroup call it; control flow is uniform.
-__device__ void jacobi_hermitian_seq(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
+__device__ bool jacobi_hermitian_seq(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
   for (int k = lane; k < n * n; k += 64) {
     int r = k / n, c = k % n;
     V[r * ld + c] = {r == c ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
   __shared__ double red[64];
+  bool converged = false;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // off-diagonal and total Frobenius norms
     double off = 0.0, tot = 0.0;
@@ -59,7 +62,10 @@ __device__ void jacobi_hermitian_seq(cplx* A, cplx* V, int n, int ld, int lane, 
     }
     tot = red[0];
     __syncthreads();
-    if (off <= 1e-32 * tot || off == 0.0) break;
+    if (off <= 1e-32 * tot || off == 0.0) {
+      converged = true;
+      break;
+    }
     for (int p = 0; p < n - 1; ++p) {
       for (int q = p + 1; q < n; ++q) {
         double app = A[p * ld + p].x, aqq = A[q * ld + q].x;
@@ -102,6 +108,7 @@ __device__ void jacobi_hermitian_seq(cplx* A, cplx* V, int n, int ld, int lane, 
     }
   }
   __syncthreads();
+  return converged;
 }
 
 // The same rotations, a round at a time: on the Hermitian n x n matrix A
@@ -119,7 +126,7 @@ __device__ void jacobi_hermitian_seq(cplx* A, cplx* V, int n, int ld, int lane, 
 // triangles are computed in different orders and are re-paired each sweep.
 // All 64 lanes of the workgroup call it; control flow is uniform.
 template <int NMAX>
-__device__ void jacobi_hermitian_par(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
+__device__ bool jacobi_hermitian_par(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
   constexpr int HP = (NMAX + 1) / 2;  // pairs per round at most
   __shared__ int rp[HP], rq[HP];
   __shared__ double rc[HP], rapp[HP], raqq[HP];
@@ -146,6 +153,7 @@ __device__ void jacobi_hermitian_par(cplx* A, cplx* V, int n, int ld, int lane, 
     const int task = lane + 64 * i;
     t3[i] = task < n * half ? (task % half) | (task / half) << 8 : -1;
   }
+  bool converged = false;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // The two triangles are updated by different rotation orders within a
     // round, so they drift apart by rounding; the lower one is reset to the
@@ -183,7 +191,10 @@ __device__ void jacobi_hermitian_par(cplx* A, cplx* V, int n, int ld, int lane, 
     }
     tot = red[0];
     __syncthreads();
-    if (off <= 1e-32 * tot || off == 0.0) break;
+    if (off <= 1e-32 * tot || off == 0.0) {
+      converged = true;
+      break;
+    }
     for (int round = 0; round < np2 - 1; ++round) {
       // 1. rotation of pair k (-1 for the dummy index or a zero pivot)
       if (lane < half) {
@@ -259,17 +270,20 @@ __device__ void jacobi_hermitian_par(cplx* A, cplx* V, int n, int ld, int lane, 
     }
   }
   __syncthreads();
+  return converged;
 }
 
 // The round-parallel form for small matrices (measured: 1.5-2x faster for
 // 3N_b = 6), the pivot-by-pivot form for larger ones (2x faster at 3N_b = 15,
 // where the round's update passes cost more than they save).
+// Returns whether the off-diagonal norm fell below the stopping threshold
+// before the sweep cap (the same value in every lane).
 template <int NMAX>
-__device__ void jacobi_hermitian(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
+__device__ bool jacobi_hermitian(cplx* A, cplx* V, int n, int ld, int lane, int max_sweeps) {
   if constexpr (NMAX <= 8)
-    jacobi_hermitian_par<NMAX>(A, V, n, ld, lane, max_sweeps);
+    return jacobi_hermitian_par<NMAX>(A, V, n, ld, lane, max_sweeps);
   else
-    jacobi_hermitian_seq(A, V, n, ld, lane, max_sweeps);
+    return jacobi_hermitian_seq(A, V, n, ld, lane, max_sweeps);
 }
 
 // Sort eigenpairs ascending: lam[k] with columns V[:,k] -> sorted into
@@ -355,7 +369,8 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
                                                      const double* __restrict__ repcart, int N0,
                                                      int N1, int N2, double* __restrict__ omega,
                                                      double* __restrict__ evec,
-                                                     double* __restrict__ vel) {
+                                                     double* __restrict__ vel,
+                                                     int32_t* __restrict__ flags, int max_sweeps) {
   constexpr int LD = NMAX;
   __shared__ cplx A[NMAX * LD];
   __shared__ cplx V[NMAX * LD];
@@ -401,7 +416,7 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
     A[a * LD + b] = {0.5 * (d1.x + d2.x), 0.5 * (d1.y - d2.y)};
   }
   __syncthreads();
-  jacobi_hermitian<NMAX>(A, V, n, LD, lane, 60);
+  if (!jacobi_hermitian<NMAX>(A, V, n, LD, lane, max_sweeps) && lane == 0) raise_flag(flags, kFlagNoConverge);
   if (lane < n) lam[lane] = A[lane * LD + lane].x;
   sort_eigen(lam, lsort, V, W, n, LD, lane);
 
@@ -458,7 +473,7 @@ __global__ __launch_bounds__(64) void phonons_kernel(int nb3, int n_rep, const d
       }
       __syncthreads();
       // eigenvectors of the m x m block into W (as V), Z diagonalised in place
-      jacobi_hermitian<NMAX>(Z, W, m, LD, lane, 60);
+      if (!jacobi_hermitian<NMAX>(Z, W, m, LD, lane, max_sweeps) && lane == 0) raise_flag(flags, kFlagNoConverge);
       if (lane < m) zl[lane] = Z[lane * LD + lane].x;
       sort_eigen(zl, zs, W, Z, m, LD, lane);
       // P <- P W: rows a of V's cluster columns
@@ -547,15 +562,19 @@ extern "C" int kaldo_phonons(const kaldo_crystal* c, const int32_t* mesh, double
   const long nq = (long)mesh[0] * mesh[1] * mesh[2];
   KALDO_REQUIRE(nq <= (1L << 24), "kaldo_phonons: mesh too large");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // Sweep cap of the Jacobi solver: 60, or fewer through KALDO_JACOBI_SWEEPS
+  // (a test hook that forces the non-convergence status on the host side).
+  int sweeps = 60;
+  if (const char* e = std::getenv("KALDO_JACOBI_SWEEPS")) sweeps = std::max(1, std::min(60, std::atoi(e)));
   if (c->nb3 <= 8) {
     KALDO_LAUNCH("phonons_kernel", phonons_kernel<8>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
-                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
+                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel, c->d_flags, sweeps);
   } else if (c->nb3 <= 16) {
     KALDO_LAUNCH("phonons_kernel", phonons_kernel<16>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
-                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
+                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel, c->d_flags, sweeps);
   } else {
     KALDO_LAUNCH("phonons_kernel", phonons_kernel<32>, dim3(nq), dim3(64), 0, st, c->nb3, c->n_rep, c->d_fc2,
-                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel);
+                       c->d_rep, c->d_repcart, mesh[0], mesh[1], mesh[2], omega, evec, vel, c->d_flags, sweeps);
   }
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;

@@ -270,22 +270,28 @@ __global__ void jdos_finish(int n_modes, int nb3, int nq, const uint8_t* __restr
 __global__ void jdos_prepare(int n_modes, const double* __restrict__ omega,
                              const double* __restrict__ vel, double nu_min,
                              uint8_t* __restrict__ phys, uint8_t* __restrict__ sel,
-                             float4* __restrict__ modef, int sel_all) {
+                             float4* __restrict__ modef, int sel_all, int32_t* __restrict__ flags) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_modes) return;
-  const bool ph = (omega[m] / kTwoPi) >= nu_min;
+  const double w = omega[m];
+  const bool ph = (w / kTwoPi) >= nu_min;
   phys[m] = ph;
   sel[m] = sel_all ? 1 : 0;
-  modef[m] = make_float4((float)vel[3 * (size_t)m], (float)vel[3 * (size_t)m + 1],
-                         (float)vel[3 * (size_t)m + 2], ph ? (float)omega[m] : __builtin_nanf(""));
+  const double v0 = vel[3 * (size_t)m], v1 = vel[3 * (size_t)m + 1], v2 = vel[3 * (size_t)m + 2];
+  modef[m] = make_float4((float)v0, (float)v1, (float)v2, ph ? (float)w : __builtin_nanf(""));
+  if (!((w - w) + (v0 - v0) + (v1 - v1) + (v2 - v2) == 0.0)) raise_flag(flags, kFlagNonFinite);
+  if (w < 0.0 && (-w / kTwoPi) >= nu_min) raise_flag(flags, kFlagImaginary);
 }
 
 __global__ void jdos_select(const int32_t* __restrict__ subset, long n, int n_modes,
-                            uint8_t* __restrict__ sel) {
+                            uint8_t* __restrict__ sel, int32_t* __restrict__ flags) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int m = subset[k];
-  if (m >= 0 && m < n_modes) sel[m] = 1;
+  if (m >= 0 && m < n_modes)
+    sel[m] = 1;
+  else
+    raise_flag(flags, kFlagSubset);
 }
 
 // ----------------------------------------------------------------- features
@@ -1040,7 +1046,7 @@ __global__ void gate_score_kernel(int n, const int32_t* __restrict__ modes, cons
 
 // Rows k with score >= tau whose mode is not yet computed are appended, in
 // row order, to `fallback` and marked computed.
-__global__ __launch_bounds__(1024) void gate_select_kernel(int n, const int32_t* __restrict__ modes,
+__global__ __launch_bounds__(1024) void gate_select_kernel(int n, int n_modes, const int32_t* __restrict__ modes,
                                                            const float* __restrict__ score,
                                                            const float* __restrict__ tau_p,
                                                            uint8_t* __restrict__ computed,
@@ -1055,7 +1061,8 @@ __global__ __launch_bounds__(1024) void gate_select_kernel(int n, const int32_t*
   for (int base = 0; base < n; base += 1024) {
     const int k = base + tid;
     const int m = k < n ? modes[k] : 0;
-    const int f = (k < n && !(score[k] < tau) && !computed[m]) ? 1 : 0;
+    const bool in_range = m >= 0 && m < n_modes;  // rows of other indices are skipped
+    const int f = (k < n && in_range && !(score[k] < tau) && !computed[m]) ? 1 : 0;
     int incl = f;
     for (int off = 1; off < 64; off <<= 1) {
       const int v = __shfl_up(incl, off, 64);
@@ -1080,12 +1087,13 @@ __global__ __launch_bounds__(1024) void gate_select_kernel(int n, const int32_t*
 }
 
 // Gamma of rows whose mode is not computed: exp(mean sd + mu).
-__global__ void fill_kernel(int n, const int32_t* __restrict__ modes, const float* __restrict__ mean,
+__global__ void fill_kernel(int n, int n_modes, const int32_t* __restrict__ modes, const float* __restrict__ mean,
                             const float* __restrict__ y_mu_sd, const uint8_t* __restrict__ computed,
                             double* __restrict__ gamma) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int m = modes[k];
+  if (m < 0 || m >= n_modes) return;  // rows of other indices are skipped
   if (!computed[m]) gamma[m] = exp((double)mean[k] * (double)y_mu_sd[1] + (double)y_mu_sd[0]);
 }
 
@@ -1205,10 +1213,10 @@ extern "C" int kaldo_jdos(const kaldo_crystal* c, const int32_t* mesh, const dou
   int32_t* n_live = qlist + 2 * nq;
   hipStream_t st = static_cast<hipStream_t>(stream);
   KALDO_LAUNCH("jdos_prepare", jdos_prepare, dim3((nm + 255) / 256), dim3(256), 0, st, nm, omega, vel,
-               b->nu_min_thz, phys, sel, modef, modes_subset ? 0 : 1);
+               b->nu_min_thz, phys, sel, modef, modes_subset ? 0 : 1, c->d_flags);
   if (modes_subset)
     KALDO_LAUNCH("jdos_select", jdos_select, dim3((unsigned)((n_subset + 255) / 256)), dim3(256), 0,
-                 st, modes_subset, (long)n_subset, nm, sel);
+                 st, modes_subset, (long)n_subset, nm, sel, c->d_flags);
   if (modes_subset)
     KALDO_LAUNCH("lw_live_q", lw_live_q<>, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel,
                  live_list, idx_of_q, n_live);
@@ -1430,26 +1438,29 @@ extern "C" int kaldo_gate_score(int64_t n, const int32_t* modes, const float* me
   return KALDO_OK;
 }
 
-extern "C" int kaldo_gate_select(int64_t n, const int32_t* modes, const float* score, const float* tau,
-                                 uint8_t* computed, int32_t* fallback, int32_t* n_fallback,
-                                 void* stream) {
+extern "C" int kaldo_gate_select(int64_t n, int64_t n_modes, const int32_t* modes, const float* score,
+                                 const float* tau, uint8_t* computed, int32_t* fallback,
+                                 int32_t* n_fallback, void* stream) {
   KALDO_REQUIRE(n >= 0 && n < (1l << 31) && modes && score && tau && computed && fallback && n_fallback,
                 "kaldo_gate_select: bad arguments");
+  KALDO_REQUIRE(n_modes >= 1 && n_modes < (1l << 31), "kaldo_gate_select: n_modes out of range");
   KALDO_LAUNCH("gate_select", gate_select_kernel, dim3(1), dim3(1024), 0,
-               static_cast<hipStream_t>(stream), (int)n, modes, score, tau, computed, fallback,
-               n_fallback);
+               static_cast<hipStream_t>(stream), (int)n, (int)n_modes, modes, score, tau, computed,
+               fallback, n_fallback);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
 }
 
-extern "C" int kaldo_surrogate_fill(int64_t n, const int32_t* modes, const float* mean,
-                                    const float* y_mu_sd, const uint8_t* computed, double* gamma,
-                                    void* stream) {
+extern "C" int kaldo_surrogate_fill(int64_t n, int64_t n_modes, const int32_t* modes,
+                                    const float* mean, const float* y_mu_sd,
+                                    const uint8_t* computed, double* gamma, void* stream) {
   KALDO_REQUIRE(n >= 0 && n < (1l << 31) && (n == 0 || (modes && mean && y_mu_sd && computed && gamma)),
                 "kaldo_surrogate_fill: bad arguments");
+  KALDO_REQUIRE(n_modes >= 1 && n_modes < (1l << 31), "kaldo_surrogate_fill: n_modes out of range");
   if (n == 0) return KALDO_OK;
   KALDO_LAUNCH("surrogate_fill", fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-               static_cast<hipStream_t>(stream), (int)n, modes, mean, y_mu_sd, computed, gamma);
+               static_cast<hipStream_t>(stream), (int)n, (int)n_modes, modes, mean, y_mu_sd,
+               computed, gamma);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
 }

@@ -7,8 +7,11 @@ stream as the HIP stream.  It fails loudly if the library is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 import torch
@@ -96,11 +99,12 @@ def lib():
         L.kaldo_mlp_predict.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P, P, P, P, P]
         L.kaldo_gate_calibrate.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, P, ctypes.c_int32,
                                            ctypes.c_double, ctypes.c_double, P, P]
-        L.kaldo_gate_select.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P]
+        L.kaldo_gate_select.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P, P, P, P]
         L.kaldo_surrogate_domain.argtypes = [ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int64, P, P]
         L.kaldo_gate_score.argtypes = [ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int32,
                                        ctypes.c_double, P, P, P]
-        L.kaldo_surrogate_fill.argtypes = [ctypes.c_int64, P, P, P, P, P, P]
+        L.kaldo_surrogate_fill.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P, P, P]
+        L.kaldo_device_status.argtypes = [P, P]
         L.kaldo_star_map.argtypes = [I32P, ctypes.c_int32, P, P, P, P, P]
         L.kaldo_profile_begin.argtypes = []
         L.kaldo_profile_end.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -117,7 +121,7 @@ EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
             "kaldo_surrogate_features", "kaldo_standardize", "kaldo_surrogate_targets",
             "kaldo_mlp_param_count", "kaldo_mlp_workspace", "kaldo_mlp_train", "kaldo_mlp_predict",
             "kaldo_gate_calibrate", "kaldo_gate_select", "kaldo_surrogate_fill", "kaldo_star_map",
-            "kaldo_surrogate_domain", "kaldo_gate_score"]
+            "kaldo_surrogate_domain", "kaldo_gate_score", "kaldo_device_status"]
 
 
 def _check(rc):
@@ -154,8 +158,22 @@ def _mesh(mesh):
     return m
 
 
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Frees every open handle while the HIP runtime is still up: atexit
+    handlers run before the interpreter's finalisers and before the C
+    runtime's static destructors (which tear the HIP runtime down)."""
+    for c in list(_LIVE):
+        c.close()
+
+
 class Crystal:
-    """A cell with FC2 / FC3 uploaded to the current device."""
+    """A cell with FC2 / FC3 uploaded to the current device.  close() frees
+    the device tables; handles still open at exit are closed by an atexit
+    hook, never from a finaliser during interpreter shutdown."""
 
     def __init__(self, n_basis, lattice, mass, rep, fc2, fc3_i, fc3_j, fc3_k, fc3_val):
         self._keep = [_f64(lattice).reshape(9), _f64(mass), _i32(rep).reshape(-1), _f64(fc2).reshape(-1),
@@ -170,6 +188,7 @@ class Crystal:
                                           int(len(fv)), _ptr(fi, I32P), _ptr(fj, I32P),
                                           _ptr(fk, I32P), _ptr(fv, F64P), ctypes.byref(h)))
         self.handle = h
+        _LIVE.add(self)
 
     @classmethod
     def from_model(cls, m):
@@ -180,7 +199,14 @@ class Crystal:
             lib().kaldo_crystal_destroy(self.handle)
             self.handle = None
 
+    def device_status(self):
+        """Synchronises the current stream and raises KaldoError if a kernel
+        found invalid device inputs since the last query (kaldo_device_status)."""
+        _check(lib().kaldo_device_status(self.handle, _stream()))
+
     def __del__(self):
+        if sys.is_finalizing():
+            return  # the atexit hook has closed it, or the runtime is going away
         try:
             self.close()
         except Exception:
@@ -421,15 +447,17 @@ def gate_select(modes, score, tau, computed, out=None):
     if out is None:
         out = (torch.empty(max(n, 1), dtype=torch.int32, device="cuda"),
                torch.empty(1, dtype=torch.int32, device="cuda"))
-    _check(lib().kaldo_gate_select(n, _dev(modes), _dev(score), _dev(tau), _dev(computed),
-                                   _dev(out[0]), _dev(out[1]), _stream()))
+    _check(lib().kaldo_gate_select(n, int(computed.numel()), _dev(modes), _dev(score), _dev(tau),
+                                   _dev(computed), _dev(out[0]), _dev(out[1]), _stream()))
     return out
 
 
 def surrogate_fill(modes, mean, y_mu_sd, computed, gamma):
     modes = modes.to(torch.int32).contiguous()
-    _check(lib().kaldo_surrogate_fill(int(modes.numel()), _dev(modes), _dev(mean), _dev(y_mu_sd),
-                                      _dev(computed), _dev(gamma), _stream()))
+    assert gamma.numel() == computed.numel(), "gamma and computed cover the same modes"
+    _check(lib().kaldo_surrogate_fill(int(modes.numel()), int(computed.numel()), _dev(modes),
+                                      _dev(mean), _dev(y_mu_sd), _dev(computed), _dev(gamma),
+                                      _stream()))
     return gamma
 
 
