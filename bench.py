@@ -1,13 +1,24 @@
 """Benchmark of the three-phonon linewidth hot path on one MI355X.
 
 A step is one pass of the whole path over the diamond 2-atom cell on a
-15x15x15 Gamma-centred mesh (20,250 modes, T = 300 K, adaptive Gaussian
-smearing): GPU phonons (FP64) -> linewidths (FP32 projection, FP64 cut and
-sums) -> RTA conductivity.  Inputs (force constants, buffers) are resident in
-HBM before the timed region.  Prints one JSON line.
+24x24x24 Gamma-centred mesh (82,944 modes, the largest configuration; T =
+300 K, adaptive Gaussian smearing): GPU phonons (FP64) -> linewidths (FP64
+projection, FP64 cut, weights and sums: the paper's arithmetic) -> RTA
+conductivity.  Inputs (force constants, buffers) are resident in HBM before
+the timed region.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp64]
-                    [--no-cpu-baseline]
+Beside the headline the line carries, each timed on the GPU the same way:
+  fp32        the same step with the FP32 projection, and its speedup;
+  c3_split    the perovskite 12^3 mesh in FP32 and in BF16x3 (split
+              precision on the matrix cores): step times, speedup, and the
+              conductivity difference between the two forms;
+  c4          the 512-atom Gamma-point glass: FP32 and BF16x3 projection
+              times and their fraction of the FP32 / BF16 matrix-core peak,
+              for the vertex GEMM alone and for the whole projection.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C5]
+                    [--precision fp64|fp32|bf16x3] [--no-cpu-baseline]
+                    [--no-extras] [--form plain|learned] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -15,6 +26,7 @@ import argparse
 import ctypes
 import json
 import os
+import platform
 import sys
 import time
 
@@ -23,16 +35,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_VECTOR_PEAK = 157.3  # TFLOP/s, MI355X vector FP32 and FP32 MFMA (datasheet)
+# MI355X datasheet peaks, TFLOP/s (dense).
+FP32_PEAK = 157.3   # FP32 vector = FP32 matrix core
+FP64_PEAK = 78.6    # FP64 vector = FP64 matrix core
+BF16_PEAK = 2500.0  # BF16 matrix core
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch) scaled by the copy-kernel calibration
-# (fetch x 1.99995, write x 1.0); valid only for the kernel sources hashed
-# here, reported as null once they change.
+# WRITE_SIZE (KiB per dispatch) scaled by the copy-kernel calibration; valid
+# only for the kernel sources hashed here, reported as null once they change.
 MEASURED_TRAFFIC = {
-    "lw_fused": {"sources": ["lw_fused.hip", "lw_common.h", "common.h"],
-                 "sha256": "255bd3fdb705aa75efcc7d9c549a4092699d1f8245ea98c12f883dfa4b121677",
-                 "bytes": 58784804, "config": "C2"},
+    ("lw_fused", "C2", "fp32"): {"sources": ["lw_fused.hip", "lw_common.h", "common.h"],
+                                 "sha256": "255bd3fdb705aa75efcc7d9c549a4092699d1f8245ea98c12f883dfa4b121677",
+                                 "bytes": 58784804},
 }
 
 
@@ -46,34 +60,44 @@ def fc3_mirror_symmetric(model, rel=1e-12):
     return all(abs(v - acc.get((i, k, j), 0.0)) <= tol for (i, j, k), v in acc.items())
 
 
-def measured_traffic(kernel, config):
+def measured_traffic(kernel, config, precision="fp32"):
     import hashlib
-    rec = MEASURED_TRAFFIC.get(kernel)
-    if rec is None or rec["config"] != config:
+    rec = MEASURED_TRAFFIC.get((kernel, config, precision))
+    if rec is None:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
         with open(os.path.join(ROOT, "paper_2602_23728_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return rec["bytes"] if h.hexdigest() == rec["sha256"] else None
+
+
 METRIC = "3-phonon linewidths: modes/s and MFMA util; speedup of split/surrogate at κ tol"
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--config", default="C5")
+    ap.add_argument("--precision", default="fp64", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-q", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="CPU time the oracle sample may take (the sample grows in q-point "
+                         "batches until it does)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline step (no FP32, C3 split or C4 legs)")
     ap.add_argument("--form", default="plain", choices=["plain", "learned"],
                     help="learned: the learned form against plain FP32 (full mesh and wedge)")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def profile_read(K):
@@ -84,8 +108,25 @@ def profile_read(K):
             for i in range(min(n.value, 64))}
 
 
-def cpu_baseline(cfg, model, nq_sample, seed=0):
-    """The oracle as it stands, on a bounded sample of the same workload."""
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(cfg, model, seconds, seed=0):
+    """The oracle as it stands, on a bounded sample of the same workload: its
+    phonons on every q-point, then its linewidths on seeded q-points taken in
+    batches of 8 until `seconds` have passed, extrapolated linearly to the
+    mesh.  Also returns the oracle's pass counts on that sample (the pruned
+    work model)."""
     from oracle import linewidths as olw
     from oracle import phonons as oph
     try:
@@ -97,57 +138,99 @@ def cpu_baseline(cfg, model, nq_sample, seed=0):
     om, ev, ve = oph.phonons(model, cfg.mesh)
     t_ph = time.perf_counter() - t0
     nq = om.shape[0]
-    qs = sorted(np.random.default_rng(seed).choice(nq, nq_sample, replace=False).tolist())
-    stats = {}
+    order = np.random.default_rng(seed).permutation(nq).tolist()
+    stats_all = {}
+    done = 0
     t0 = time.perf_counter()
-    olw.crystal_linewidths(model, cfg.mesh, om, ev, ve, cfg.temperature, cfg.broadening,
-                           q_list=qs, stats=stats)
+    while done < nq and (done < 8 or time.perf_counter() - t0 < seconds):
+        qs = sorted(order[done:done + 8])
+        st = {}
+        olw.crystal_linewidths(model, cfg.mesh, om, ev, ve, cfg.temperature, cfg.broadening,
+                               q_list=qs, stats=st)
+        for k, v in st.items():
+            stats_all[k] = stats_all.get(k, 0) + v
+        done += len(qs)
     t_lw = time.perf_counter() - t0
-    est = t_ph + t_lw * nq / nq_sample
+    est = t_ph + t_lw * nq / done
     n_modes = nq * 3 * model.n_basis
+    cpu_model, nproc = host_info()
     return dict(value=n_modes / est, unit="modes/s", cores=int(threads), kind="oracle",
+                nproc=nproc, cpu_model=cpu_model,
                 sample=(f"oracle phonons on all {nq} q-points ({t_ph:.1f} s) + linewidths on "
-                        f"{nq_sample} seeded q-points ({nq_sample * 3 * model.n_basis} modes, "
+                        f"{done} seeded q-points ({done * 3 * model.n_basis} modes, "
                         f"{t_lw:.1f} s), extrapolated linearly to {nq} q-points"),
-                est_total_s=est), stats
+                est_total_s=est), stats_all, om
 
 
-def bench_gamma_point(a, cfg, model, c, prec, K, torch):
-    """Gamma-point solid: host FP64 eigenproblem once (setup), then the GPU
-    linewidth pass timed."""
-    t0 = time.perf_counter()
-    om_h, E_h = K.phonons_gamma(model.n_basis, model.mass, model.fc2)
-    t_eig = time.perf_counter() - t0
-    om = torch.as_tensor(om_h).cuda()
-    E = torch.as_tensor(E_h).cuda()
-    n = len(om_h)
-    ws = torch.empty(int(K.lib().kaldo_linewidths_gamma_workspace(c.handle, prec)),
-                     dtype=torch.uint8, device="cuda")
-    gam = torch.empty(n, dtype=torch.float64, device="cuda")
+def pruned_work(model, nq, stats, om_oracle, nu_min):
+    """Pruned work model of the crystal projection (method's own minimum under
+    the 2-sigma cut), from the oracle's pass counts on its sample: per
+    physical mode F_pr = 8 N_q (f_blk n_p + f_pass (3N_b)^4) FLOP, f_blk the
+    share of (mode, q1) blocks with a pair passing in either process and
+    f_pass the share of (mode, q1, s', s'') candidates passing in either
+    process, both over physical modes.  Total = F_pr x physical modes."""
+    from collections import Counter
+    nb3 = 3 * model.n_basis
+    n_p = len(Counter(zip(model.fc3_j.tolist(), model.fc3_k.tolist())))
+    f_blk = stats["mode_blocks_pass"] / (stats["mode_phys"] * nq)
+    f_pass = stats["mode_pass"] / (stats["mode_phys"] * nq * nb3 * nb3)
+    F_pr = 8.0 * nq * (f_blk * n_p + f_pass * nb3 ** 4)
+    n_phys = int(np.sum(om_oracle / (2 * np.pi) >= nu_min))
+    F_blk = 8.0 * nq * (n_p + 2 * nb3 ** 3)
+    return dict(f_blk=f_blk, f_pass=f_pass, flop_per_mode=F_pr, n_p=n_p,
+                physical_modes=n_phys, total_flop=F_pr * n_phys, dense_flop_per_mode=F_blk)
+
+
+def crystal_step(K, torch, c, cfg, prec):
+    """Buffers and the step closure for one crystal config and precision."""
+    mesh = cfg.mesh
+    nq = int(np.prod(mesh))
+    nb3 = c.nb3
+    dev = torch.device("cuda")
+    om = torch.empty(nq, nb3, dtype=torch.float64, device=dev)
+    ev = torch.empty(nq, nb3, nb3, 2, dtype=torch.float64, device=dev)
+    ve = torch.empty(nq, nb3, 3, dtype=torch.float64, device=dev)
+    gam = torch.empty(nq, nb3, dtype=torch.float64, device=dev)
+    kap = torch.empty(3, 3, dtype=torch.float64, device=dev)
+    ws = torch.empty(max(1, K.linewidths_workspace(c, mesh, prec)), dtype=torch.uint8, device=dev)
 
     def step():
-        K.linewidths_gamma(c, om, E, cfg.temperature, cfg.broadening, prec, workspace=ws, out=gam)
+        K.phonons(c, mesh, out=(om, ev, ve))
+        K.linewidths(c, mesh, om, ev, ve, cfg.temperature, cfg.broadening, prec,
+                     workspace=ws, out=gam)
+        K.kappa_rta(c, mesh, om, ve, gam, cfg.temperature, cfg.broadening.nu_min_thz, out=kap)
 
-    for _ in range(a.warmup):
+    return step, dict(om=om, ev=ev, ve=ve, gam=gam, kap=kap)
+
+
+def timed(K, torch, step, steps, warmup, name):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    log(f"{name}: warmup done ({warmup} steps), timing {steps} steps")
     K.lib().kaldo_profile_begin()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = profile_read(K)
-    ms = 1e3 * elapsed / a.steps
-    print(f"bench: {ms:.3f} ms/step; kernels: " +
-          ", ".join(f"{k} {v[1] / v[0]:.3f} ms x{v[0] // a.steps}" for k, v in prof.items()),
-          file=sys.stderr, flush=True)
-    # Executed work of the vertex GEMM: 2 * 128^2 * n_pad FLOP per live tile,
-    # a tile (I <= J) of mode mu being live when the physical frequency ranges
-    # of blocks I and J can meet the 2-sigma cut in either order.
+    ms = 1e3 * elapsed / steps
+    log(f"{name}: {ms:.3f} ms/step; kernels: " +
+        ", ".join(f"{k} {v[1] / v[0]:.3f} ms" for k, v in prof.items()))
+    return ms, prof
+
+
+def gamma_point_live_flop(om_h, broadening, sym=True):
+    """Executed work of the vertex GEMM: 2 * 128^2 * n_pad FLOP per live tile,
+    a tile (I <= J for a symmetric Phi3) of mode mu being live when the
+    physical frequency ranges of blocks I and J can meet the 2-sigma cut (in
+    either order of the pair)."""
+    n = len(om_h)
     npad = (n + 127) // 128 * 128
     nt = npad // 128
-    phys = om_h / (2 * np.pi) >= cfg.broadening.nu_min_thz
+    phys = om_h / (2 * np.pi) >= broadening.nu_min_thz
     lo = np.full(nt, np.inf)
     hi = np.full(nt, -np.inf)
     for I in range(nt):
@@ -155,40 +238,84 @@ def bench_gamma_point(a, cfg, model, c, prec, K, torch):
         sel = sel[phys[sel]]
         if len(sel):
             lo[I], hi[I] = om_h[sel].min(), om_h[sel].max()
-    reach = 2 * (2 * np.pi * cfg.broadening.sigma_thz) * (1 + 1e-12) + 1e-9
+    reach = 2 * (2 * np.pi * broadening.sigma_thz) * (1 + 1e-12) + 1e-9
     w = om_h[phys][:, None, None]
     l1, h1, l2, h2 = lo[None, :, None], hi[None, :, None], lo[None, None, :], hi[None, None, :]
+
     def can(l1, h1, l2, h2):
         return (((w + l1 - h2) < reach) & ((w + h1 - l2) > -reach)) | \
                (((w - h1 - h2) < reach) & ((w - l1 - l2) > -reach))
     I, J = np.meshgrid(np.arange(nt), np.arange(nt), indexing="ij")
-    valid = (I <= J)[None] & (lo[:, None] <= hi[:, None])[None] & (lo[None, :] <= hi[None, :])[None]
-    live = valid & (can(l1, h1, l2, h2) | ((I != J)[None] & can(l2, h2, l1, h1)))
-    flop = float(live.sum()) * 2.0 * 128 * 128 * npad
-    gemm_ms = sum(v[1] for k, v in prof.items() if k.startswith("gm_gemm")) / a.steps
+    ok = (lo[:, None] <= hi[:, None])[None] & (lo[None, :] <= hi[None, :])[None]
+    if sym:
+        live = (I <= J)[None] & ok & (can(l1, h1, l2, h2) | ((I != J)[None] & can(l2, h2, l1, h1)))
+    else:
+        live = ok & can(l1, h1, l2, h2)
+    return float(live.sum()) * 2.0 * 128 * 128 * npad, int(live.sum()), int(phys.sum())
+
+
+def gamma_point_leg(a, K, torch, cfg, model, steps, warmup):
+    """Gamma-point glass: host FP64 eigenproblem once (set-up), then FP32 and
+    BF16x3 projections timed; fractions of the matrix-core peak for the
+    vertex GEMM alone and for the whole projection (A values + SpMM + GEMM)."""
+    c = K.Crystal.from_model(model)
+    t0 = time.perf_counter()
+    om_h, E_h = K.phonons_gamma(model.n_basis, model.mass, model.fc2)
+    t_eig = time.perf_counter() - t0
+    om = torch.as_tensor(om_h).cuda()
+    E = torch.as_tensor(E_h).cuda()
+    n = len(om_h)
+    flop, live, n_phys = gamma_point_live_flop(om_h, cfg.broadening, fc3_mirror_symmetric(model))
+    out = dict(modes=n, host_eigensolver_s=t_eig, live_tiles=live)
+    for name, prec in (("fp32", K.FP32), ("bf16x3", K.BF16X3)):
+        ws = torch.empty(int(K.lib().kaldo_linewidths_gamma_workspace(c.handle, prec)),
+                         dtype=torch.uint8, device="cuda")
+        gam = torch.empty(n, dtype=torch.float64, device="cuda")
+
+        def step():
+            K.linewidths_gamma(c, om, E, cfg.temperature, cfg.broadening, prec, workspace=ws,
+                               out=gam)
+        ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} {name}")
+        per = {k: v[1] / steps for k, v in prof.items()}
+        gemm = sum(v for k, v in per.items() if k.startswith("gm_gemm"))
+        proj = gemm + sum(v for k, v in per.items() if k in ("gm_avals", "gm_spmm", "gm_fused"))
+        split = prec == K.BF16X3
+        f = (3.0 if split else 1.0) * flop
+        peak = BF16_PEAK if split else FP32_PEAK
+        out[name] = dict(ms_per_step=ms, modes_per_s=n / (ms * 1e-3), gemm_ms=gemm,
+                         projection_ms=proj,
+                         gemm_tflops=f / (gemm * 1e-3) / 1e12,
+                         gemm_frac=f / (gemm * 1e-3) / 1e12 / peak,
+                         projection_frac=f / (proj * 1e-3) / 1e12 / peak, peak=peak,
+                         kernels_ms_per_step=per)
+        del ws
+    out["split_speedup"] = out["fp32"]["ms_per_step"] / out["bf16x3"]["ms_per_step"]
+    c.close()
+    return out
+
+
+def bench_gamma_point(a, cfg, model, K, torch):
+    """--config C4 alone: the Gamma-point leg as the JSON line."""
+    leg = gamma_point_leg(a, K, torch, cfg, model, a.steps, a.warmup)
+    r = leg["bf16x3" if a.precision == "bf16x3" else "fp32"]
     split = a.precision == "bf16x3"
-    achieved = (3.0 if split else 1.0) * flop / (gemm_ms * 1e-3) / 1e12
-    peak = 2500.0 if split else FP32_VECTOR_PEAK
-    roof = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
-                traffic=None, kernel="gm_gemm", kernel_ms_per_step=gemm_ms,
+    roof = dict(bound="mfma", achieved=r["gemm_tflops"], peak=r["peak"], unit="TFLOP/s",
+                frac=r["gemm_frac"], traffic=None, kernel="gm_gemm",
                 work_model="live tiles" + (" (three bf16 products counted)" if split else ""),
-                live_tiles=int(live.sum()), dense_tiles=int(phys.sum()) * nt * (nt + 1) // 2)
-    print(json.dumps({"metric": METRIC, "value": n / (ms * 1e-3), "unit": "modes/s",
-                      "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
-                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                projection_frac=r["projection_frac"])
+    print(json.dumps({"metric": METRIC, "value": r["modes_per_s"], "unit": "modes/s",
+                      "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+                      "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None,
                       "dtype": "bf16x3" if split else "f32", "data": "synthetic",
-                      "config": {"workload": f"{cfg.name}: {cfg.description}", "modes": n,
-                                 "precision": a.precision},
-                      "roofline": roof,
-                      "host_eigensolver_s": t_eig,
-                      "kernels_ms_per_step": {k: v[1] / a.steps for k, v in prof.items()}}))
+                      "config": {"workload": f"{cfg.name}: {cfg.description}",
+                                 "modes": leg["modes"], "precision": a.precision},
+                      "roofline": roof, "gamma_point": leg}))
 
 
 def bench_learned(a, cfg, model, c, K, torch):
     """The learned form on a crystal mesh, against the plain FP32 path on every
-    mode (the conductivity reference) and on the irreducible wedge.  Each of
-    the three chains (phonons -> linewidths -> conductivity) is timed over
-    `steps` repetitions; the wedge itself is host set-up."""
+    mode (the conductivity reference) and on the irreducible wedge."""
     from paper_2602_23728_amd import learned as L
     from synthetic import draws as D
     mesh, T, b = cfg.mesh, cfg.temperature, cfg.broadening
@@ -202,13 +329,13 @@ def bench_learned(a, cfg, model, c, K, torch):
         om, ev, ve = K.phonons(c, mesh)
         g = K.linewidths(c, mesh, om, ev, ve, T, b, K.FP32)
         K.kappa_rta(c, mesh, om, ve, g, T, b.nu_min_thz, out=kap)
-        return kap.clone()
+        state["k"] = kap.clone()
 
     def ibz():
         om, ev, ve = K.phonons(c, mesh)
         g = L.plain_ibz_linewidths(c, wedge, om, ev, ve, T, b, K.FP32)
         K.kappa_rta(c, mesh, om, ve, g, T, b.nu_min_thz, out=kap)
-        return kap.clone()
+        state["k"] = kap.clone()
 
     def learned():
         om, ev, ve = K.phonons(c, mesh)
@@ -221,27 +348,14 @@ def bench_learned(a, cfg, model, c, K, torch):
                                    steps=a.train_steps, lr=2e-2, tol=0.01)
         K.kappa_rta(c, mesh, om, ve, res.gamma, T, b.nu_min_thz, out=kap)
         state["res"] = res
-        return kap.clone()
+        state["k"] = kap.clone()
 
-    def timed(fn, name):
-        for _ in range(a.warmup):
-            fn()
-        torch.cuda.synchronize()
-        K.lib().kaldo_profile_begin()
-        t0 = time.perf_counter()
-        for _ in range(a.steps):
-            k = fn()
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / a.steps
-        prof = profile_read(K)
-        print(f"bench[{name}]: {ms:.3f} ms/step; kernels: " +
-              ", ".join(f"{kk} {v[1] / a.steps:.3f} ms" for kk, v in prof.items()),
-              file=sys.stderr, flush=True)
-        return ms, k.cpu().numpy(), {kk: v[1] / a.steps for kk, v in prof.items()}
-
-    ms_full, k_full, p_full = timed(full, "plain-full")
-    ms_ibz, k_ibz, p_ibz = timed(ibz, "plain-wedge")
-    ms_lrn, k_lrn, p_lrn = timed(learned, "learned")
+    ms_full, p_full = timed(K, torch, full, a.steps, a.warmup, "plain-full")
+    k_full = state["k"].cpu().numpy()
+    ms_ibz, p_ibz = timed(K, torch, ibz, a.steps, a.warmup, "plain-wedge")
+    k_ibz = state["k"].cpu().numpy()
+    ms_lrn, p_lrn = timed(K, torch, learned, a.steps, a.warmup, "learned")
+    k_lrn = state["k"].cpu().numpy()
     res = state["res"]
 
     def rel(k):
@@ -250,6 +364,7 @@ def bench_learned(a, cfg, model, c, K, torch):
 
     n_modes = nq * nb3
     n_rest = len(state["cand"]) - res.n_train - res.n_held
+    per = lambda p: {kk: v[1] / a.steps for kk, v in p.items()}  # noqa: E731
     print(json.dumps({
         "metric": METRIC, "value": n_modes / (ms_lrn * 1e-3), "unit": "modes/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_lrn, "higher_is_better": True,
@@ -264,8 +379,14 @@ def bench_learned(a, cfg, model, c, K, torch):
         "train": res.n_train, "held_out": res.n_held, "fallback": res.n_fallback,
         "fallback_frac_of_rest": res.n_fallback / max(1, n_rest), "tau": res.tau,
         "train_steps": a.train_steps,
-        "kernels_ms_per_step": {"plain_full": p_full, "plain_wedge": p_ibz, "learned": p_lrn},
+        "kernels_ms_per_step": {"plain_full": per(p_full), "plain_wedge": per(p_ibz),
+                                "learned": per(p_lrn)},
     }))
+
+
+def kappa_rel(k, ref):
+    kbar = np.trace(ref) / 3
+    return float(max(abs(np.trace(k) / 3 - kbar) / kbar, np.max(np.abs(k - ref)) / kbar))
 
 
 def main():
@@ -295,92 +416,96 @@ def main():
     model = configs.model_for(cfg)
     prec = {"fp32": K.FP32, "fp64": K.FP64, "bf16x3": K.BF16X3}[a.precision]
     torch.cuda.set_device(0)
-    c = K.Crystal.from_model(model)
     if cfg.mesh == (1, 1, 1):
-        return bench_gamma_point(a, cfg, model, c, prec, K, torch)
+        return bench_gamma_point(a, cfg, model, K, torch)
+    c = K.Crystal.from_model(model)
     if a.form == "learned":
-        return bench_learned(a, cfg, model, c, K, torch)
+        bench_learned(a, cfg, model, c, K, torch)
+        c.close()
+        return
     mesh = cfg.mesh
     nq = int(np.prod(mesh))
     nb3 = c.nb3
     n_modes = nq * nb3
-    dev = torch.device("cuda")
-    om = torch.empty(nq, nb3, dtype=torch.float64, device=dev)
-    ev = torch.empty(nq, nb3, nb3, 2, dtype=torch.float64, device=dev)
-    ve = torch.empty(nq, nb3, 3, dtype=torch.float64, device=dev)
-    gam = torch.empty(nq, nb3, dtype=torch.float64, device=dev)
-    kap = torch.empty(3, 3, dtype=torch.float64, device=dev)
-    ws = torch.empty(K.linewidths_workspace(c, mesh, prec), dtype=torch.uint8, device=dev)
 
-    def step():
-        K.phonons(c, mesh, out=(om, ev, ve))
-        K.linewidths(c, mesh, om, ev, ve, cfg.temperature, cfg.broadening, prec,
-                     workspace=ws, out=gam)
-        K.kappa_rta(c, mesh, om, ve, gam, cfg.temperature, cfg.broadening.nu_min_thz, out=kap)
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"bench: warmup done ({a.warmup} steps), timing {a.steps} steps", file=sys.stderr,
-          flush=True)
-    K.lib().kaldo_profile_begin()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = profile_read(K)
-    ms_per_step = 1e3 * elapsed / a.steps
-    kappa = kap.cpu().numpy()
-    print(f"bench: {ms_per_step:.3f} ms/step; kernels: " +
-          ", ".join(f"{k} {v[1] / v[0]:.3f} ms" for k, v in prof.items()), file=sys.stderr,
-          flush=True)
-
+    step, bufs = crystal_step(K, torch, c, cfg, prec)
+    ms_per_step, prof = timed(K, torch, step, a.steps, a.warmup, f"{cfg.name} {a.precision}")
+    c.device_status()  # raises if a kernel found invalid inputs
+    kappa = bufs["kap"].cpu().numpy()
     dom, (launches, total) = max(prof.items(), key=lambda kv: kv[1][1])
     avg_ms = total / launches
 
-    base, stats = (None, {})
+    extras = {}
+    if not a.no_extras:
+        if prec != K.FP32:
+            step32, b32 = crystal_step(K, torch, c, cfg, K.FP32)
+            ms32, prof32 = timed(K, torch, step32, a.steps, a.warmup, f"{cfg.name} fp32")
+            k32 = b32["kap"].cpu().numpy()
+            extras["fp32"] = dict(ms_per_step=ms32, modes_per_s=n_modes / (ms32 * 1e-3),
+                                  speedup_vs_headline=ms_per_step / ms32,
+                                  kappa_rel_diff_vs_headline=kappa_rel(k32, kappa),
+                                  kernels_ms={k: v[1] / v[0] for k, v in prof32.items()})
+            del b32
+        # split precision against plain FP32 on the perovskite 12^3 mesh
+        c3 = configs.CONFIGS["C3"]
+        m3 = configs.model_for(c3)
+        cc3 = K.Crystal.from_model(m3)
+        n3 = int(np.prod(c3.mesh)) * cc3.nb3
+        leg = {}
+        ks = {}
+        for name, p in (("fp32", K.FP32), ("bf16x3", K.BF16X3)):
+            s3, b3 = crystal_step(K, torch, cc3, c3, p)
+            ms3, pr3 = timed(K, torch, s3, max(3, a.steps // 4), 2, f"C3 {name}")
+            ks[name] = b3["kap"].cpu().numpy()
+            leg[name] = dict(ms_per_step=ms3, modes_per_s=n3 / (ms3 * 1e-3),
+                             kernels_ms={k: v[1] / v[0] for k, v in pr3.items()})
+            del b3
+        cc3.device_status()
+        leg["split_speedup"] = leg["fp32"]["ms_per_step"] / leg["bf16x3"]["ms_per_step"]
+        leg["kappa_rel_diff_split_vs_fp32"] = kappa_rel(ks["bf16x3"], ks["fp32"])
+        cc3.close()
+        extras["c3_split"] = leg
+        c4 = configs.CONFIGS["C4"]
+        extras["c4"] = gamma_point_leg(a, K, torch, c4, configs.model_for(c4),
+                                       max(3, a.steps // 4), 2)
+
+    base, stats, om_o = (None, {}, None)
     if not a.no_cpu_baseline:
-        base, stats = cpu_baseline(cfg, model, a.cpu_sample_q)
-        print(f"bench: cpu baseline {base['value']:.1f} modes/s", file=sys.stderr, flush=True)
-    # Work model per mode: dense-block F_blk = 8 N_q (n_p + 2 nb3^3) and the
-    # pruned F_pr = 8 N_q (f_blk n_p + f_pass nb3^4) with the oracle-measured
-    # fractions of partner blocks / candidates that pass the 2-sigma cut.
-    from collections import Counter
-    n_p = len(Counter(zip(model.fc3_j.tolist(), model.fc3_k.tolist())))
-    F_blk = 8.0 * nq * (n_p + 2 * nb3 ** 3)
+        base, stats, om_o = cpu_baseline(cfg, model, a.cpu_seconds)
+        log(f"cpu baseline {base['value']:.1f} modes/s ({base['sample']})")
     roof = None
     if dom in ("lw_crystal", "lw_fused") and stats:
-        f_blk = stats["blocks_pass"] / max(1, stats["blocks"])
-        f_pass = stats["passed"] / max(1, stats["cand"])
-        F_pr = 8.0 * nq * (f_blk * n_p + f_pass * nb3 ** 4)
-        achieved = F_pr * n_modes / (avg_ms * 1e-3) / 1e12
+        w = pruned_work(model, nq, stats, om_o, cfg.broadening.nu_min_thz)
+        fp64 = prec == K.FP64
+        peak = FP64_PEAK if fp64 else FP32_PEAK
+        achieved = w["total_flop"] / (avg_ms * 1e-3) / 1e12
         # With Phi3 symmetric in its last two slots the fused kernel visits each
         # mirrored partner pair (q1, q2) once: on average (N_q + 1) / 2 partner
-        # points per q (one q1 == q2 point per q on average), so it executes
-        # about half of the ordered-pair work F_pr counts.
+        # points per q, about half of the ordered-pair work counted above.
         f_exec = (nq + 1) / (2.0 * nq) if (dom == "lw_fused" and fc3_mirror_symmetric(model)) else 1.0
-        roof = dict(bound="alu", achieved=achieved, peak=FP32_VECTOR_PEAK, unit="TFLOP/s",
-                    frac=achieved / FP32_VECTOR_PEAK, traffic=measured_traffic(dom, cfg.name),
-                    kernel=dom, kernel_ms=avg_ms, work_model="pruned, ordered partner pairs",
-                    flop_per_mode=F_pr, f_blk=f_blk, f_pass=f_pass,
-                    executed_fraction=f_exec, executed_tflops=achieved * f_exec,
-                    executed_frac=achieved * f_exec / FP32_VECTOR_PEAK,
-                    dense_equiv_tflops=F_blk * n_modes / (avg_ms * 1e-3) / 1e12)
+        roof = dict(bound="alu", achieved=achieved, peak=peak, unit="TFLOP/s",
+                    frac=achieved / peak, traffic=measured_traffic(dom, cfg.name, a.precision),
+                    kernel=dom, kernel_ms=avg_ms,
+                    work_model="pruned, ordered partner pairs, physical modes "
+                               "(8 N_q (f_blk n_p + f_pass nb3^4) FLOP each)",
+                    flop_per_mode=w["flop_per_mode"], physical_modes=w["physical_modes"],
+                    f_blk=w["f_blk"], f_pass=w["f_pass"], executed_fraction=f_exec,
+                    executed_tflops=achieved * f_exec, executed_frac=achieved * f_exec / peak,
+                    dense_equiv_tflops=w["dense_flop_per_mode"] * w["physical_modes"]
+                    / (avg_ms * 1e-3) / 1e12)
     if dom.startswith("lw_mfma"):
         # Dense MFMA kernel: per (q, swept partner q1, live branch s) two complex
         # 16x16x16 products (T = B_s eta2, V = eta1^T T), each two real 16x16x32
         # products, i.e. 65,536 FLOP; the BF16x3 form issues three BF16 products
         # per real product.  Partners: (N_q + 1) / 2 per q on average when the
         # mirrored pair is visited once, else N_q.
-        om_h = om.cpu().numpy()
+        om_h = bufs["om"].cpu().numpy()
         n_live = int(np.sum(om_h / (2 * np.pi) >= cfg.broadening.nu_min_thz))
         partners = (nq + 1) / 2.0 if fc3_mirror_symmetric(model) else float(nq)
         split = prec == K.BF16X3
         flop = n_live * partners * 65536.0 * (3 if split else 1)
         achieved = flop / (avg_ms * 1e-3) / 1e12
-        peak = 2500.0 if split else FP32_VECTOR_PEAK
+        peak = BF16_PEAK if split else FP32_PEAK
         roof = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
                     traffic=None, kernel=dom, kernel_ms=avg_ms,
                     work_model="dense 16x16 tiles per (q, partner, live branch)"
@@ -406,6 +531,8 @@ def main():
         "kernels_ms": {k: v[1] / v[0] for k, v in prof.items()},
         "kappa_trace_over_3": float(np.trace(kappa) / 3),
     }
+    out.update(extras)
+    c.close()
     print(json.dumps(out))
 
 

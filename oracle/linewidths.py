@@ -161,7 +161,15 @@ def crystal_linewidths(model, mesh, omega, evec, vel, T, broadening, q_list=None
     out = np.full((nq, nb3), np.nan)
     qs = range(nq) if q_list is None else q_list
     if stats is not None:
-        stats.update(cand=0, passed=0, blocks=0, blocks_pass=0)
+        # cand/passed: ordered (q1, s', s'') candidates and passes counted per
+        # process over physical modes; blocks/blocks_pass: q1 blocks of a q with
+        # any passing pair of any branch.  Per mode (all modes of the listed q,
+        # masked ones included): mode_blocks/mode_blocks_pass count (mu, q1)
+        # blocks and those with a pair passing in either process,
+        # mode_cand/mode_pass the (mu, q1, s', s'') candidates and those
+        # passing in either process; mode_phys the physical modes among them.
+        stats.update(cand=0, passed=0, blocks=0, blocks_pass=0, mode_blocks=0,
+                     mode_blocks_pass=0, mode_cand=0, mode_pass=0, mode_phys=0, n_q=0)
     for q in qs:
         V, q2 = vertex_crystal(model, mesh, evec, q, pat)
         w = omega[q][None, :, None, None]
@@ -197,6 +205,12 @@ def crystal_linewidths(model, mesh, omega, evec, vel, T, broadening, q_list=None
                                    + (passm & phys[q][None, :, None, None]).sum())
             stats["blocks"] += nq
             stats["blocks_pass"] += int(anyp.reshape(nq, -1).any(axis=1).sum())
+            stats["mode_blocks"] += nq * nb3
+            stats["mode_blocks_pass"] += int(anyp.any(axis=(2, 3)).sum())
+            stats["mode_cand"] += nq * nb3 ** 3
+            stats["mode_pass"] += int(anyp.sum())
+            stats["mode_phys"] += int(phys[q].sum())
+            stats["n_q"] += 1
     return out
 
 

@@ -54,6 +54,7 @@ def test_argument_validation_without_device():
         K.Crystal(m.n_basis, m.lattice, m.mass, m.rep, m.fc2, m.fc3_i, bad, m.fc3_k, m.fc3_val)
     with pytest.raises(K.KaldoError):
         K.phonons_gamma(2, np.array([1.0, -1.0]), np.zeros((6, 1, 6)))
+    assert lib.kaldo_device_status(None, None) == -1 and b"NULL" in lib.kaldo_last_error()
 
 
 def test_learned_form_host_checks_without_device():
