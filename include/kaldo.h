@@ -210,6 +210,26 @@ int kaldo_linewidths(const kaldo_crystal* c, const int32_t* mesh, const double* 
                      const int32_t* modes_subset, int64_t n_subset, void* workspace,
                      size_t workspace_bytes, double* gamma, void* stream);
 
+/* kaldo_linewidths_noalloc -- kaldo_linewidths without a workspace argument
+ * and without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and kernels as kaldo_linewidths; the
+ * workspace is a device array inside the library, one per GPU, of
+ * kaldo_linewidths_noalloc_max_bytes() bytes (32 MiB), held until the process
+ * ends.  A request whose kaldo_linewidths_workspace() exceeds that size
+ * returns KALDO_EINVAL before anything is enqueued.  Every call on one GPU
+ * uses that GPU's array: calls that overlap in time on one GPU (other streams,
+ * other threads) race and must be serialised by the caller; nothing needs
+ * clearing between calls (every byte read is written first within a call). */
+int kaldo_linewidths_noalloc(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                             const double* evec, const double* vel, double temperature,
+                             const kaldo_broadening* broadening, int32_t precision,
+                             const int32_t* modes_subset, int64_t n_subset, double* gamma,
+                             void* stream);
+
+/* Size in bytes of kaldo_linewidths_noalloc's device scratch array. */
+size_t kaldo_linewidths_noalloc_max_bytes(void);
+
 /* Device workspace bytes kaldo_linewidths_gamma needs. */
 size_t kaldo_linewidths_gamma_workspace(const kaldo_crystal* c, int32_t precision);
 

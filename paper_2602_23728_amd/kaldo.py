@@ -105,6 +105,11 @@ def lib():
                                        ctypes.c_double, P, P, P]
         L.kaldo_surrogate_fill.argtypes = [ctypes.c_int64, ctypes.c_int64, P, P, P, P, P, P]
         L.kaldo_device_status.argtypes = [P, P]
+        L.kaldo_linewidths_noalloc.argtypes = [P, I32P, P, P, P, ctypes.c_double,
+                                               ctypes.POINTER(Broadening), ctypes.c_int32, P,
+                                               ctypes.c_int64, P, P]
+        L.kaldo_linewidths_noalloc_max_bytes.argtypes = []
+        L.kaldo_linewidths_noalloc_max_bytes.restype = ctypes.c_size_t
         L.kaldo_star_map.argtypes = [I32P, ctypes.c_int32, P, P, P, P, P]
         L.kaldo_profile_begin.argtypes = []
         L.kaldo_profile_end.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -121,7 +126,8 @@ EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
             "kaldo_surrogate_features", "kaldo_standardize", "kaldo_surrogate_targets",
             "kaldo_mlp_param_count", "kaldo_mlp_workspace", "kaldo_mlp_train", "kaldo_mlp_predict",
             "kaldo_gate_calibrate", "kaldo_gate_select", "kaldo_surrogate_fill", "kaldo_star_map",
-            "kaldo_surrogate_domain", "kaldo_gate_score", "kaldo_device_status"]
+            "kaldo_surrogate_domain", "kaldo_gate_score", "kaldo_device_status",
+            "kaldo_linewidths_noalloc", "kaldo_linewidths_noalloc_max_bytes"]
 
 
 def _check(rc):
@@ -268,6 +274,28 @@ def linewidths(c: Crystal, mesh, omega, evec, vel, temperature, broadening, prec
                                   float(temperature), ctypes.byref(b), int(precision), _dev(sub),
                                   0 if sub is None else int(sub.numel()), _dev(workspace),
                                   int(workspace.numel()), _dev(out), _stream()))
+    return out
+
+
+def linewidths_noalloc(c: Crystal, mesh, omega, evec, vel, temperature, broadening,
+                       precision=FP32, subset=None, out=None):
+    """Gamma [N_q, nb3] (rad/ps) on cuda, computed on the library's device
+    scratch array (kaldo_linewidths_noalloc); `out` must be given to avoid
+    any allocation on this side too."""
+    m = _mesh(mesh)
+    nq = int(np.prod(m))
+    if out is None:
+        out = torch.zeros(nq, c.nb3, dtype=torch.float64, device="cuda")
+    ev = _as_real(evec)
+    assert ev.is_contiguous(), "evec must be contiguous"
+    b = Broadening.of(broadening)
+    sub = None if subset is None else subset
+    if sub is not None:
+        assert sub.dtype == torch.int32 and sub.is_contiguous()
+    _check(lib().kaldo_linewidths_noalloc(c.handle, _ptr(m, I32P), _dev(omega), _dev(ev), _dev(vel),
+                                          float(temperature), ctypes.byref(b), int(precision),
+                                          _dev(sub), 0 if sub is None else int(sub.numel()),
+                                          _dev(out), _stream()))
     return out
 
 
