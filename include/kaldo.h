@@ -141,8 +141,8 @@ int kaldo_crystal_destroy(kaldo_crystal* c);
  * velocity or linewidth, or a modes_subset index outside [0, n_modes) (such
  * entries are ignored); KALDO_ENUMERIC if a mode had omega < 0 with
  * |nu| >= nu_min_thz (the linewidth and conductivity kernels treat it as
- * unphysical), or if kaldo_phonons' Jacobi solver reached its sweep cap on
- * some q.  kaldo_last_error() then lists every condition found.  Calls on
+ * unphysical), if kaldo_phonons' Jacobi solver reached its sweep cap on
+ * some q, or if kaldo_bte_solve met a zero pivot.  kaldo_last_error() then lists every condition found.  Calls on
  * other streams that are still running may set the word after it is read. */
 int kaldo_device_status(kaldo_crystal* c, void* stream);
 
@@ -259,6 +259,64 @@ int kaldo_linewidths_gamma(const kaldo_crystal* c, const double* omega, const do
 int kaldo_kappa_rta(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
                     const double* vel, const double* gamma, double temperature,
                     double nu_min_thz, double* kappa, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Full linearised BTE (paper, "Boltzmann Transport Equation": Eq. BTE,
+ * Eq. gamma1, Eq. invBTE, Eq. kappa_general, Eq. sc_iter, Eq. inverse).
+ * The scattering matrix Gamma~ = diag(Gamma0) + Gamma1 over all
+ * n = N_q nb3 modes (rad/ps, dense FP64, row-major, caller-owned device
+ * buffer of n*n doubles), built from the same vertex, cut, widths and
+ * populations as kaldo_linewidths (Gamma0 = 2 Gamma).  Per ordered candidate
+ * (q s; q1 s'; q2 s'') with coalescence and decay rates
+ *   d+ = 2 P |V|^2 (n1 - n2) g(x+)/(w w1 w2), d- = P |V|^2 (n1 + n2 + 1) g(x-)/(w w1 w2)
+ * (P = pi hbar U^3/(8 N_q)), row (q, s) receives Gamma0 += d+ + d-,
+ * column (q1, s') += d+ w1/w, column tr(q1, s') -= d- w1/w and column
+ * tr(q2, s'') -= (d+ + d-) w2/w, where tr() is the time-reversal partner (the
+ * mode at -q' whose eigenvector overlaps eta(q', s')* most).  These rows make
+ * Eq. sc_iter the iterative scheme of the adaptive-smearing reference the
+ * paper cites (the printed Eq. gamma1 is read this way).  Modes with
+ * nu < nu_min or Gamma0 <= 1e-8 max Gamma0 are decoupled (zero row and
+ * column, unit diagonal, lambda = 0).  Cells of 1 or 2 atoms
+ * (KALDO_EUNSUPPORTED otherwise); N_q <= 65535.
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes of kaldo_scattering_matrix, kaldo_bte_solve and
+ * kaldo_bte_iterate (one workspace serves all three). */
+size_t kaldo_bte_workspace(const kaldo_crystal* c, const int32_t* mesh);
+
+/* kaldo_scattering_matrix -- builds Gamma~ into `matrix` (device double[n][n])
+ * and the diagonal rates Gamma0 into `gamma0` (device double[n]); FP64
+ * projection, fixed-order sums (bitwise reproducible).
+ *   omega, evec, vel, temperature, broadening: as kaldo_linewidths */
+int kaldo_scattering_matrix(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                            const double* evec, const double* vel, double temperature,
+                            const kaldo_broadening* broadening, void* workspace,
+                            size_t workspace_bytes, double* matrix, double* gamma0, void* stream);
+
+/* kaldo_bte_solve -- Eq. inverse: lambda = Gamma~^-1 v (device double[n][3],
+ * Angstrom) by a blocked LU factorisation without pivoting (64 x 64 blocks,
+ * trailing updates on the FP64 matrix cores), then
+ * kappa_ab = 1/(N_q V) sum c v_a lambda_b (device double[9], W/(m K)).
+ * `matrix` is overwritten by its LU factors.  A zero pivot sets the handle's
+ * status (kaldo_device_status -> KALDO_ENUMERIC).  Enqueued; returns at once. */
+int kaldo_bte_solve(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                    const double* vel, const double* gamma0, double temperature,
+                    double nu_min_thz, double* matrix, void* workspace, size_t workspace_bytes,
+                    double* lambda, double* kappa, void* stream);
+
+/* kaldo_bte_iterate -- Eq. sc_iter from the RTA start lambda0 = v/Gamma0:
+ * lambda <- (v - Gamma1 lambda)/Gamma0 until |k_new - k_old| <= tolerance
+ * |k_old| for k = Tr(kappa)/3, or n_iterations updates.  `matrix` is read
+ * only.  Synchronises `stream` once per iteration (the stopping test is on
+ * the host); *iterations (host, may be NULL) = updates done.  Returns
+ * KALDO_ENUMERIC if it did not stop within n_iterations (the iteration
+ * contracts only when the off-diagonal part is small against the diagonal);
+ * lambda and kappa then hold the last iterate. */
+int kaldo_bte_iterate(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                      const double* vel, const double* gamma0, double temperature,
+                      double nu_min_thz, const double* matrix, int32_t n_iterations,
+                      double tolerance, void* workspace, size_t workspace_bytes, double* lambda,
+                      double* kappa, int32_t* iterations, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned form.  The paper restricts the scattering calculation to the

@@ -72,65 +72,81 @@ def time_reversal_partner(mesh, evec):
     return tr
 
 
+class _Setup:
+    """Per-call tables shared by the rows of one scattering matrix."""
+
+    def __init__(self, model, mesh, omega, evec, T, broadening):
+        self.pat = Patterns(model)
+        self.nq, self.nb3 = omega.shape
+        self.h2 = mesh_step2(model.lattice, mesh)
+        nu = omega / TWO_PI
+        self.phys = nu >= broadening.nu_min_thz
+        self.occ = np.where(self.phys, bose(np.where(self.phys, omega, 1.0), T), 0.0)
+        self.tr = time_reversal_partner(mesh, evec).reshape(self.nq, self.nb3)
+
+
+def scattering_rows(model, mesh, omega, evec, vel, T, broadening, q, setup=None):
+    """Rows (q, s) of the scattering matrix: (Gamma0 [3N_b], Gamma1 [3N_b, n])."""
+    st = setup or _Setup(model, mesh, omega, evec, T, broadening)
+    nq, nb3, phys, occ, tr = st.nq, st.nb3, st.phys, st.occ, st.tr
+    n = nq * nb3
+    g0 = np.zeros(nb3)
+    g1 = np.zeros((nb3, n))
+    if not phys[q].any():
+        return g0, g1
+    sig_fixed = TWO_PI * broadening.sigma_thz
+    sig_floor = TWO_PI * broadening.sigma_floor_thz
+    pref = 2.0 * PREFACTOR / nq
+    b = np.arange(nb3)
+    V, q2 = vertex_crystal(model, mesh, evec, q, st.pat)
+    w = omega[q][None, :, None, None]
+    w1 = omega[:, None, :, None]
+    w2 = omega[q2][:, None, None, :]
+    m12 = phys[:, None, :, None] & phys[q2][:, None, None, :] & phys[q][None, :, None, None]
+    n1 = occ[:, None, :, None]
+    n2 = occ[q2][:, None, None, :]
+    if broadening.adaptive:
+        v1 = vel[:, :, None, :]
+        v2 = vel[q2][:, None, :, :]
+        sp = adaptive_sigma(v1 + v2, st.h2, sig_floor)[:, None, :, :]
+        sm = adaptive_sigma(-v1 + v2, st.h2, sig_floor)[:, None, :, :]
+    else:
+        sp = sm = np.full((1, 1, 1, 1), sig_fixed)
+    gp = smearing((w + w1) - w2, np.broadcast_to(sp, V.shape), broadening.shape)
+    gm = smearing((w - w1) - w2, np.broadcast_to(sm, V.shape), broadening.shape)
+    safe_w = np.where(m12, w, 1.0)
+    safe = np.where(m12, safe_w * (w1 * w2), 1.0)
+    a2 = np.where(m12, np.abs(V) ** 2 / safe, 0.0)
+    dp = pref * a2 * (n1 - n2) * gp                  # (q1, s, s', s'')
+    dm = pref * a2 * 0.5 * (n1 + n2 + 1.0) * gm
+    g0[:] = (dp + dm).sum(axis=(0, 2, 3))
+    r1 = w1 / safe_w                                 # w1 / w
+    r2 = w2 / safe_w                                 # w2 / w
+    # columns: (q1, s'), tr(q1, s'), tr(q2, s'')
+    col1 = (np.arange(nq)[:, None] * nb3 + b[None, :])            # (q1, s')
+    colm1 = tr                                                    # tr(q1, s')
+    colm2 = tr[q2]                                                # tr(q2, s'')
+    absorbed = (dp * r1).sum(axis=3)                              # (q1, s, s')
+    emitted1 = (dm * r1).sum(axis=3)                              # (q1, s, s')
+    emitted2 = ((dp + dm) * r2).sum(axis=2)                       # (q1, s, s'')
+    for s in range(nb3):
+        np.add.at(g1[s], col1.reshape(-1), absorbed[:, s, :].reshape(-1))
+        np.add.at(g1[s], colm1.reshape(-1), -emitted1[:, s, :].reshape(-1))
+        np.add.at(g1[s], colm2.reshape(-1), -emitted2[:, s, :].reshape(-1))
+    return g0, g1
+
+
 def scattering_matrix(model, mesh, omega, evec, vel, T, broadening, q_list=None):
     """(Gamma0 [n], Gamma1 [n, n]) over all n = N_q 3N_b modes (rad/ps); with
     q_list only the rows of those q-points are filled."""
-    pat = Patterns(model)
-    pts = mesh_points(mesh)
-    N = np.asarray(mesh)
-    nq, nb3 = omega.shape
-    n = nq * nb3
-    h2 = mesh_step2(model.lattice, mesh)
-    nu = omega / TWO_PI
-    phys = nu >= broadening.nu_min_thz
-    occ = np.where(phys, bose(np.where(phys, omega, 1.0), T), 0.0)
-    sig_fixed = TWO_PI * broadening.sigma_thz
-    sig_floor = TWO_PI * broadening.sigma_floor_thz
-    tr = time_reversal_partner(mesh, evec).reshape(nq, nb3)
-    g0 = np.zeros(n)
-    g1 = np.zeros((n, n))
-    pref = 2.0 * PREFACTOR / nq
-    b = np.arange(nb3)
+    st = _Setup(model, mesh, omega, evec, T, broadening)
+    nq, nb3 = st.nq, st.nb3
+    g0 = np.zeros(nq * nb3)
+    g1 = np.zeros((nq * nb3, nq * nb3))
     for q in (range(nq) if q_list is None else q_list):
-        if not phys[q].any():
-            continue
-        V, q2 = vertex_crystal(model, mesh, evec, q, pat)
-        w = omega[q][None, :, None, None]
-        w1 = omega[:, None, :, None]
-        w2 = omega[q2][:, None, None, :]
-        m12 = phys[:, None, :, None] & phys[q2][:, None, None, :] & phys[q][None, :, None, None]
-        n1 = occ[:, None, :, None]
-        n2 = occ[q2][:, None, None, :]
-        if broadening.adaptive:
-            v1 = vel[:, :, None, :]
-            v2 = vel[q2][:, None, :, :]
-            sp = adaptive_sigma(v1 + v2, h2, sig_floor)[:, None, :, :]
-            sm = adaptive_sigma(-v1 + v2, h2, sig_floor)[:, None, :, :]
-        else:
-            sp = sm = np.full((1, 1, 1, 1), sig_fixed)
-        gp = smearing((w + w1) - w2, np.broadcast_to(sp, V.shape), broadening.shape)
-        gm = smearing((w - w1) - w2, np.broadcast_to(sm, V.shape), broadening.shape)
-        safe_w = np.where(m12, w, 1.0)
-        safe = np.where(m12, safe_w * (w1 * w2), 1.0)
-        a2 = np.where(m12, np.abs(V) ** 2 / safe, 0.0)
-        dp = pref * a2 * (n1 - n2) * gp                  # (q1, s, s', s'')
-        dm = pref * a2 * 0.5 * (n1 + n2 + 1.0) * gm
-        rows = q * nb3 + b
-        g0[rows] = (dp + dm).sum(axis=(0, 2, 3))
-        r1 = w1 / safe_w                                 # w1 / w
-        r2 = w2 / safe_w                                 # w2 / w
-        # columns: (q1, s'), tr(q1, s'), tr(q2, s'')
-        col1 = (np.arange(nq)[:, None] * nb3 + b[None, :])            # (q1, s')
-        colm1 = tr                                                    # tr(q1, s')
-        colm2 = tr[q2]                                                # tr(q2, s'')
-        absorbed = (dp * r1).sum(axis=3)                              # (q1, s, s')
-        emitted1 = (dm * r1).sum(axis=3)                              # (q1, s, s')
-        emitted2 = ((dp + dm) * r2).sum(axis=2)                       # (q1, s, s'')
-        for s in range(nb3):
-            r = rows[s]
-            np.add.at(g1[r], col1.reshape(-1), absorbed[:, s, :].reshape(-1))
-            np.add.at(g1[r], colm1.reshape(-1), -emitted1[:, s, :].reshape(-1))
-            np.add.at(g1[r], colm2.reshape(-1), -emitted2[:, s, :].reshape(-1))
+        r0, r1 = scattering_rows(model, mesh, omega, evec, vel, T, broadening, q, st)
+        g0[q * nb3:(q + 1) * nb3] = r0
+        g1[q * nb3:(q + 1) * nb3] = r1
     return g0, g1
 
 

@@ -1,0 +1,824 @@
+// Full scattering matrix of the linearised BTE and its two solutions
+// (paper: "Boltzmann Transport Equation": Eq. BTE, Eq. gamma1, Eq. invBTE,
+// Eq. kappa_general, Eq. sc_iter, Eq. inverse).
+//
+// Rows of Gamma~ = diag(Gamma0) + Gamma1, one per mode mu = (q, s).  For each
+// ordered candidate (q s; q1 s'; q2 s''), q + q1 + q2 = G, passing the 2-sigma
+// cut of the linewidths, with the coalescence and decay rates
+//   d+ = 2 P |V|^2 (n1 - n2) g(x+) / (w w1 w2),
+//   d- = 2 P |V|^2 1/2 (n1 + n2 + 1) g(x-) / (w w1 w2),   P = pi hbar U^3/(8 N_q),
+// row mu receives Gamma0 += d+ + d- (= 2 Gamma of Eq. gamma), and
+//   column (q1, s')       +d+ w1/w          (absorbed partner)
+//   column tr(q1, s')     -d- w1/w          (emitted partner of the decay)
+//   column tr(q2, s'')    -(d+ + d-) w2/w   (emitted partner of both)
+// tr(q', s') is the time-reversal partner of a mode: the mode at -q' whose
+// eigenvector overlaps eta(q', s')* most (the vertex holds eta(q2); the
+// emitted phonon is the mode at -q2 with the conjugate eigenvector).  These
+// rows make Eq. sc_iter the iterative scheme of the adaptive-smearing
+// reference the paper cites.  Modes without RTA conductivity (nu < nu_min,
+// Gamma0 <= 1e-8 max Gamma0) are decoupled: zero row and column, unit
+// diagonal, zero right-hand side.
+//
+// Kernels:
+//   bte_tr_map     time-reversal partner of every mode (largest overlap)
+//   bte_zero       clears the n x n matrix
+//   bte_rows<NB3>  one workgroup (one wave) per q: A~_q (FP64, LDS), then the
+//                  partners q1 in rounds of 64 (one per lane): exact FP64 cut,
+//                  vertex of the passing candidates, per-lane sums per column
+//                  kind in LDS, written in three passes whose columns are a
+//                  bijection of q1 (no two lanes of a pass touch one element),
+//                  Gamma0 reduced in a fixed order and added to the diagonal
+//   bte_gmax, bte_decouple   the RTA selection
+//   lu_diag, lu_panels, lu_update   blocked LU without pivoting (64 x 64
+//                  blocks; the trailing update on FP64 matrix cores)
+//   lu_forward, lu_backward   the two triangular sweeps for the 3 RHS
+//   bte_gemv, bte_sc_init, bte_sc_update   the iteration of Eq. sc_iter
+//   bte_kappa      Eq. kappa_general, fixed-order reduction
+// Every reduction and every sequence of additions into one matrix element
+// runs in a fixed order: results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+#include "lw_common.h"
+
+namespace kaldo {
+
+constexpr int kLuB = 64;  // LU block edge
+
+typedef __attribute__((__vector_size__(4 * sizeof(double)))) double d4;
+
+// ------------------------------------------------------------------ tables
+
+__global__ void bte_tr_map(int nq, int nb3, int N0, int N1, int N2,
+                           const double* __restrict__ evec, int32_t* __restrict__ tr) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nq * nb3) return;
+  const int q = m / nb3, s = m - q * nb3;
+  const int a0 = q / (N1 * N2), a1 = (q / N2) % N1, a2 = q % N2;
+  const int mq = (((N0 - a0) % N0) * N1 + (N1 - a1) % N1) * N2 + (N2 - a2) % N2;
+  const double* x = evec + (size_t)q * nb3 * nb3 * 2;
+  const double* y = evec + (size_t)mq * nb3 * nb3 * 2;
+  int best = 0;
+  double bo = -1.0;
+  for (int t = 0; t < nb3; ++t) {
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < nb3; ++i) {
+      const double xr = x[(i * nb3 + s) * 2], xi = x[(i * nb3 + s) * 2 + 1];
+      const double yr = y[(i * nb3 + t) * 2], yi = y[(i * nb3 + t) * 2 + 1];
+      re += yr * xr - yi * xi;  // eta_i(-q, t) eta_i(q, s), no conjugate
+      im += yr * xi + yi * xr;
+    }
+    const double o = re * re + im * im;
+    if (o > bo) {
+      bo = o;
+      best = t;
+    }
+  }
+  tr[m] = mq * nb3 + best;
+}
+
+__global__ void bte_zero(size_t n, double* __restrict__ x) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * blockDim.x)
+    x[k] = 0.0;
+}
+
+// Per-process rates of one candidate without |V|^2 and the prefactor:
+// dp = (n1 - n2) g(x+) / (w w1 w2), dm = 1/2 (n1 + n2 + 1) g(x-) / (w w1 w2),
+// each 0 unless its own |x| < 2 sigma.
+__device__ __forceinline__ void process_rates(const LwParams& p, double w, double w1, double w2,
+                                              double n1, double n2, double sp, double sm,
+                                              double& dp, double& dm) {
+  const double xp = (w + w1) - w2, xm = (w - w1) - w2;
+  const double den = w * (w1 * w2);
+  dp = fabs(xp) < 2.0 * sp ? (n1 - n2) * smear(p.shape, xp, sp) / den : 0.0;
+  dm = fabs(xm) < 2.0 * sm ? 0.5 * (n1 + n2 + 1.0) * smear(p.shape, xm, sm) / den : 0.0;
+}
+
+// ------------------------------------------------------------------ rows
+
+template <int NB3>
+__global__ __launch_bounds__(64) void bte_rows(
+    LwParams p, int n_rep, const int32_t* __restrict__ rep, const double* __restrict__ omega,
+    const double* __restrict__ vel, const double* __restrict__ occ,
+    const uint8_t* __restrict__ phys, const double* __restrict__ evec,
+    const double2* __restrict__ phase_tab, const int32_t* __restrict__ d_ptr,
+    const int32_t* __restrict__ e_jc, const int32_t* __restrict__ e_kc,
+    const int32_t* __restrict__ t_ptr, const int32_t* __restrict__ t_i,
+    const int32_t* __restrict__ t_l2, const double* __restrict__ t_coef,
+    const int32_t* __restrict__ tr, double pref, double* __restrict__ mat,
+    double* __restrict__ gamma0) {
+  extern __shared__ double2 at[];  // [n_e][NB3]: A~_q, phases e^{+i q.R''} folded in
+  __shared__ double acc[3][NB3][NB3][64];  // [kind][s][s' or s''][lane]
+  __shared__ double2 phq[64];
+  __shared__ double red[NB3][64];
+  const int lane = threadIdx.x;
+  const int q = blockIdx.x;
+  const int nq = p.nq;
+  const size_t n = (size_t)nq * NB3;
+  const int N0 = p.N[0], N1 = p.N[1], N2 = p.N[2];
+  const int a0 = q / (N1 * N2), a1 = (q / N2) % N1, a2 = q % N2;
+  bool any = false;
+  for (int s = 0; s < NB3; ++s) any = any || phys[q * NB3 + s];
+  if (!any) {
+    if (lane < NB3) gamma0[q * NB3 + lane] = 0.0;
+    return;
+  }
+  for (int l = lane; l < n_rep; l += 64) {
+    const int32_t* r = rep + 3 * l;
+    const int m0 = ((a0 * r[0]) % N0 + N0) % N0, m1 = ((a1 * r[1]) % N1 + N1) % N1,
+              m2 = ((a2 * r[2]) % N2 + N2) % N2;
+    const double f = (double)m0 / N0 + (double)m1 / N1 + (double)m2 / N2;
+    double sn, cs;
+    sincospi(2.0 * f, &sn, &cs);
+    phq[l] = make_double2(cs, sn);
+  }
+  __syncthreads();
+  for (int k = lane; k < p.n_e * NB3; k += 64) {
+    const int e = k / NB3, s = k % NB3;
+    double re = 0.0, im = 0.0;
+    for (int t = t_ptr[e]; t < t_ptr[e + 1]; ++t) {
+      const size_t o = (((size_t)q * NB3 + t_i[t]) * NB3 + s) * 2;
+      const double ex = evec[o], ey = evec[o + 1];
+      const double2 f = phq[t_l2[t]];
+      const double c = t_coef[t];
+      re += c * (ex * f.x - ey * f.y);
+      im += c * (ex * f.y + ey * f.x);
+    }
+    at[k] = make_double2(re, im);
+  }
+  __syncthreads();
+  double g0[NB3];
+#pragma unroll
+  for (int s = 0; s < NB3; ++s) g0[s] = 0.0;
+  const int t0 = (N0 - a0) % N0, t1 = (N1 - a1) % N1, t2 = (N2 - a2) % N2;
+  for (int base = 0; base < nq; base += 64) {
+    const int q1 = base + lane;
+    const bool ok = q1 < nq;
+    for (int k = 0; k < 3; ++k)
+      for (int s = 0; s < NB3; ++s)
+        for (int u = 0; u < NB3; ++u) acc[k][s][u][lane] = 0.0;
+    int q2 = 0;
+    if (ok) {
+      const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
+      q2 = (wrap_sub(t0, b0, N0) * N1 + wrap_sub(t1, b1, N1)) * N2 + wrap_sub(t2, b2, N2);
+      const double2* ph = phase_tab + (size_t)q1 * p.n_d;
+      for (int s1 = 0; s1 < NB3; ++s1) {
+        const int m1 = q1 * NB3 + s1;
+        if (!phys[m1]) continue;
+        const double w1 = omega[m1], n1 = occ[m1];
+        for (int s2 = 0; s2 < NB3; ++s2) {
+          const int m2 = q2 * NB3 + s2;
+          if (!phys[m2]) continue;
+          const double w2 = omega[m2], n2 = occ[m2];
+          double sp, sm;
+          widths(p, vel, m1, m2, sp, sm);
+          for (int s = 0; s < NB3; ++s) {
+            const int mu = q * NB3 + s;
+            if (!phys[mu]) continue;
+            const double w = omega[mu];
+            double dp, dm;
+            process_rates(p, w, w1, w2, n1, n2, sp, sm, dp, dm);
+            if (dp == 0.0 && dm == 0.0) continue;
+            // V = sum_d e^{-i q1.R_d} sum_{e in d} A~[e][s] eta_jc(q1, s1) eta_kc(q2, s2)
+            double vr = 0.0, vi = 0.0;
+            for (int d = 0; d < p.n_d; ++d) {
+              double dr = 0.0, di = 0.0;
+              for (int e = d_ptr[d]; e < d_ptr[d + 1]; ++e) {
+                const double2 a = at[e * NB3 + s];
+                const size_t ox = (((size_t)q1 * NB3 + e_jc[e]) * NB3 + s1) * 2;
+                const size_t oy = (((size_t)q2 * NB3 + e_kc[e]) * NB3 + s2) * 2;
+                const double xr = evec[ox], xi = evec[ox + 1], yr = evec[oy], yi = evec[oy + 1];
+                const double zr = xr * yr - xi * yi, zi = xr * yi + xi * yr;
+                dr += a.x * zr - a.y * zi;
+                di += a.x * zi + a.y * zr;
+              }
+              const double2 f = ph[d];
+              vr += f.x * dr - f.y * di;
+              vi += f.x * di + f.y * dr;
+            }
+            const double v2 = pref * (vr * vr + vi * vi);
+            dp *= v2;
+            dm *= v2;
+            g0[s] += dp + dm;
+            acc[0][s][s1][lane] += dp * (w1 / w);
+            acc[1][s][s1][lane] += dm * (w1 / w);
+            acc[2][s][s2][lane] += (dp + dm) * (w2 / w);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // three passes; within each the columns of different lanes differ
+    if (ok) {
+      for (int s = 0; s < NB3; ++s) {
+        double* row = mat + (size_t)(q * NB3 + s) * n;
+        for (int u = 0; u < NB3; ++u) {
+          const double x = acc[0][s][u][lane];
+          if (x != 0.0) row[q1 * NB3 + u] += x;
+        }
+      }
+    }
+    __syncthreads();
+    if (ok) {
+      for (int s = 0; s < NB3; ++s) {
+        double* row = mat + (size_t)(q * NB3 + s) * n;
+        for (int u = 0; u < NB3; ++u) {
+          const double x = acc[1][s][u][lane];
+          if (x != 0.0) row[tr[q1 * NB3 + u]] -= x;
+        }
+      }
+    }
+    __syncthreads();
+    if (ok) {
+      for (int s = 0; s < NB3; ++s) {
+        double* row = mat + (size_t)(q * NB3 + s) * n;
+        for (int u = 0; u < NB3; ++u) {
+          const double x = acc[2][s][u][lane];
+          if (x != 0.0) row[tr[q2 * NB3 + u]] -= x;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // Gamma0: fixed-order tree over the lanes, then onto the diagonal
+  for (int s = 0; s < NB3; ++s) red[s][lane] = g0[s];
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (lane < w)
+      for (int s = 0; s < NB3; ++s) red[s][lane] += red[s][lane + w];
+    __syncthreads();
+  }
+  if (lane < NB3) {
+    const int mu = q * NB3 + lane;
+    const double g = phys[mu] ? red[lane][0] : 0.0;
+    gamma0[mu] = g;
+    mat[(size_t)mu * n + mu] += g;
+  }
+}
+
+// Largest Gamma0 (order-independent), one workgroup.
+__global__ __launch_bounds__(1024) void bte_gmax(long n, const double* __restrict__ g0,
+                                                 double* __restrict__ out) {
+  __shared__ double red[1024];
+  double m = 0.0;
+  for (long k = threadIdx.x; k < n; k += 1024) m = fmax(m, g0[k]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__device__ __forceinline__ bool bte_active(double w, double g, double gmax, double nu_min) {
+  return (w / kTwoPi >= nu_min) && (g > kGammaFloorRel * gmax) && (g > 0.0);
+}
+
+// Modes without RTA conductivity: zero row and column, unit diagonal.
+__global__ void bte_decouple(long n, const double* __restrict__ omega,
+                             const double* __restrict__ g0, const double* __restrict__ gmax,
+                             double nu_min, double* __restrict__ mat) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (bte_active(omega[i], g0[i], *gmax, nu_min)) return;
+  for (long j = 0; j < n; ++j) {
+    mat[i * n + j] = 0.0;
+    mat[j * n + i] = 0.0;
+  }
+  mat[i * n + i] = 1.0;
+}
+
+// Right-hand side: v on active modes, 0 elsewhere; rhs[i][3].
+__global__ void bte_rhs(long n, const double* __restrict__ omega, const double* __restrict__ vel,
+                        const double* __restrict__ g0, const double* __restrict__ gmax,
+                        double nu_min, double* __restrict__ rhs) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool a = bte_active(omega[i], g0[i], *gmax, nu_min);
+  for (int c = 0; c < 3; ++c) rhs[3 * i + c] = a ? vel[3 * i + c] : 0.0;
+}
+
+// kappa_ab = scale sum_i c_i v_ia lambda_ib over active modes; one workgroup.
+__global__ __launch_bounds__(1024) void bte_kappa(long n, const double* __restrict__ omega,
+                                                  const double* __restrict__ vel,
+                                                  const double* __restrict__ lam,
+                                                  const double* __restrict__ g0,
+                                                  const double* __restrict__ gmax,
+                                                  double inv_kt_hbar, double nu_min,
+                                                  double scale, double* __restrict__ kappa) {
+  __shared__ double red[1024][9];
+  const int t = threadIdx.x;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const double gm = *gmax;
+  for (long i = t; i < n; i += 1024) {
+    const double w = omega[i];
+    if (!bte_active(w, g0[i], gm, nu_min)) continue;
+    const double x = w * inv_kt_hbar;
+    const double em = expm1(x);
+    const double c = x * x * (em + 1.0) / (em * em);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) acc[3 * a + b] += c * vel[3 * i + a] * lam[3 * i + b];
+  }
+  for (int k = 0; k < 9; ++k) red[t][k] = acc[k];
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w)
+      for (int k = 0; k < 9; ++k) red[t][k] += red[t + w][k];
+    __syncthreads();
+  }
+  if (t < 9) kappa[t] = scale * red[0][t];
+}
+
+// ------------------------------------------------------------------ LU
+
+// Factor the diagonal block k (no pivoting) in LDS; write L\U back, and the
+// inverses of the unit lower L and of the upper U to linv/uinv [64][64].
+// Padding rows past n act as identity rows.
+__global__ __launch_bounds__(256) void lu_diag(long n, int k, double* __restrict__ mat,
+                                               double* __restrict__ linv,
+                                               double* __restrict__ uinv,
+                                               int32_t* __restrict__ flags) {
+  constexpr int B = kLuB;
+  __shared__ double D[B][B + 1];
+  __shared__ double X[B][B + 1];
+  const int tid = threadIdx.x;
+  const long r0 = (long)k * B;
+  for (int idx = tid; idx < B * B; idx += 256) {
+    const int i = idx / B, j = idx % B;
+    const long gi = r0 + i, gj = r0 + j;
+    D[i][j] = (gi < n && gj < n) ? mat[gi * n + gj] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < B; ++j) {
+    const double piv = D[j][j];
+    if (tid == 0 && !(fabs(piv) > 1e-300)) raise_flag(flags, kFlagSingular);
+    for (int i = j + 1 + tid; i < B; i += 256) D[i][j] /= piv;
+    __syncthreads();
+    for (int idx = tid; idx < (B - j - 1) * (B - j - 1); idx += 256) {
+      const int i = j + 1 + idx / (B - j - 1), c = j + 1 + idx % (B - j - 1);
+      D[i][c] -= D[i][j] * D[j][c];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < B * B; idx += 256) {
+    const int i = idx / B, j = idx % B;
+    const long gi = r0 + i, gj = r0 + j;
+    if (gi < n && gj < n) mat[gi * n + gj] = D[i][j];
+  }
+  // inverse of the unit lower triangle, column c by forward substitution
+  if (tid < B) {
+    const int c = tid;
+    for (int i = 0; i < B; ++i) {
+      double x = (i == c) ? 1.0 : 0.0;
+      for (int t = c; t < i; ++t) x -= D[i][t] * X[t][c];
+      X[i][c] = (i < c) ? 0.0 : x;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < B * B; idx += 256) linv[idx] = X[idx / B][idx % B];
+  __syncthreads();
+  // inverse of the upper triangle, column c by back substitution
+  if (tid < B) {
+    const int c = tid;
+    for (int i = B - 1; i >= 0; --i) {
+      double x = (i == c) ? 1.0 : 0.0;
+      for (int t = i + 1; t <= c; ++t) x -= D[i][t] * X[t][c];
+      X[i][c] = (i > c) ? 0.0 : x / D[i][i];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < B * B; idx += 256) uinv[idx] = X[idx / B][idx % B];
+}
+
+// Panels of step k: row blocks A_kj <- Linv A_kj (j > k, first nb - k - 1
+// workgroups), column blocks A_ik <- A_ik Uinv (i > k, the rest).
+__global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, double* __restrict__ mat,
+                                                 const double* __restrict__ linv,
+                                                 const double* __restrict__ uinv) {
+  constexpr int B = kLuB;
+  __shared__ double M[B][B + 1];
+  __shared__ double T[B][B + 1];
+  const int tid = threadIdx.x;
+  const int m = nb - k - 1;
+  const bool row = (int)blockIdx.x < m;
+  const int other = k + 1 + (row ? blockIdx.x : blockIdx.x - m);
+  const long bi = row ? k : other, bj = row ? other : k;
+  for (int idx = tid; idx < B * B; idx += 256) {
+    const int i = idx / B, j = idx % B;
+    const long gi = bi * B + i, gj = bj * B + j;
+    M[i][j] = (gi < n && gj < n) ? mat[gi * n + gj] : 0.0;
+    T[i][j] = row ? linv[idx] : uinv[idx];
+  }
+  __syncthreads();
+  double out[16];
+  for (int r = 0; r < 16; ++r) {
+    const int idx = tid + 256 * r, i = idx / B, j = idx % B;
+    double s = 0.0;
+    if (row)
+      for (int t = 0; t < B; ++t) s += T[i][t] * M[t][j];
+    else
+      for (int t = 0; t < B; ++t) s += M[i][t] * T[t][j];
+    out[r] = s;
+  }
+  for (int r = 0; r < 16; ++r) {
+    const int idx = tid + 256 * r, i = idx / B, j = idx % B;
+    const long gi = bi * B + i, gj = bj * B + j;
+    if (gi < n && gj < n) mat[gi * n + gj] = out[r];
+  }
+}
+
+// Trailing update of step k: A_ij -= A_ik A_kj for i, j > k, one 64 x 64
+// block per workgroup, four waves of 32 x 32 on v_mfma_f64_16x16x4f64.
+__global__ __launch_bounds__(256) void lu_update(long n, int nb, int k, double* __restrict__ mat) {
+  constexpr int B = kLuB;
+  __shared__ double L[B][B + 1];
+  __shared__ double U[B][B + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m = nb - k - 1;
+  const long bi = k + 1 + blockIdx.x / m, bj = k + 1 + blockIdx.x % m;
+  for (int idx = tid; idx < B * B; idx += 256) {
+    const int i = idx / B, j = idx % B;
+    const long li = bi * B + i, lj = (long)k * B + j;
+    L[i][j] = (li < n && lj < n) ? mat[li * n + lj] : 0.0;
+    const long ui = (long)k * B + i, uj = bj * B + j;
+    U[i][j] = (ui < n && uj < n) ? mat[ui * n + uj] : 0.0;
+  }
+  __syncthreads();
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  const int lr = lane & 15, lg = lane >> 4;
+  d4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < B; kk += 4) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double av = L[wm + 16 * a + lr][kk + lg];  // A[row = lane % 16][k = lane / 16]
+        const double bv = U[kk + lg][wn + 16 * b + lr];  // B[k = lane / 16][col = lane % 16]
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][b], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // FP64 16x16 accumulator: item r of lane l is row 4 r + l / 16, column l % 16
+        const long gi = bi * B + wm + 16 * a + 4 * r + lg, gj = bj * B + wn + 16 * b + lr;
+        if (gi < n && gj < n) mat[gi * n + gj] -= acc[a][b][r];
+      }
+}
+
+// Row block k of a triangular sweep with 3 right-hand sides: r = b_k -
+// sum over the already solved blocks of A[k rows][those columns] x, then
+// x_k = Tinv r.  Forward (lower, blocks j < k) or backward (upper, j > k).
+template <bool FORWARD>
+__global__ __launch_bounds__(256) void lu_sweep(long n, int nb, int k, const double* __restrict__ mat,
+                                                const double* __restrict__ tinv,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ x) {
+  constexpr int B = kLuB;
+  __shared__ double part[4][B][3];
+  __shared__ double r[B][3];
+  const int tid = threadIdx.x, row = tid >> 2, sub = tid & 3;
+  const long gi = (long)k * B + row;
+  const long c_lo = FORWARD ? 0 : (long)(k + 1) * B;
+  const long c_hi = FORWARD ? (long)k * B : n;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (gi < n)
+    for (long c = c_lo + sub; c < c_hi; c += 4) {
+      const double a = mat[gi * n + c];
+      s0 += a * x[3 * c];
+      s1 += a * x[3 * c + 1];
+      s2 += a * x[3 * c + 2];
+    }
+  part[sub][row][0] = s0;
+  part[sub][row][1] = s1;
+  part[sub][row][2] = s2;
+  __syncthreads();
+  if (tid < B * 3) {
+    const int i = tid / 3, c = tid % 3;
+    const long g = (long)k * B + i;
+    const double bb = g < n ? b[3 * g + c] : 0.0;
+    r[i][c] = bb - (((part[0][i][c] + part[1][i][c]) + part[2][i][c]) + part[3][i][c]);
+  }
+  __syncthreads();
+  if (tid < B * 3) {
+    const int i = tid / 3, c = tid % 3;
+    double s = 0.0;
+    for (int t = 0; t < B; ++t) s += tinv[i * B + t] * r[t][c];
+    const long g = (long)k * B + i;
+    if (g < n) x[3 * g + c] = s;
+  }
+}
+
+// ------------------------------------------------------------------ iteration
+
+// y = A x for 3 right-hand sides, one workgroup per row, fixed-order sums.
+__global__ __launch_bounds__(256) void bte_gemv(long n, const double* __restrict__ mat,
+                                                const double* __restrict__ x,
+                                                double* __restrict__ y) {
+  __shared__ double red[256][3];
+  const long i = blockIdx.x;
+  const int t = threadIdx.x;
+  const double* a = mat + i * n;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (long c = t; c < n; c += 256) {
+    const double v = a[c];
+    s0 += v * x[3 * c];
+    s1 += v * x[3 * c + 1];
+    s2 += v * x[3 * c + 2];
+  }
+  red[t][0] = s0;
+  red[t][1] = s1;
+  red[t][2] = s2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < 3; ++c) red[t][c] += red[t + w][c];
+    __syncthreads();
+  }
+  if (t < 3) y[3 * i + t] = red[0][t];
+}
+
+// lambda0 = v / Gamma0 on active modes (Eq. sc_iter's start, the RTA).
+__global__ void bte_sc_init(long n, const double* __restrict__ rhs, const double* __restrict__ g0,
+                            double* __restrict__ lam) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool a = rhs[3 * i] != 0.0 || rhs[3 * i + 1] != 0.0 || rhs[3 * i + 2] != 0.0;
+  for (int c = 0; c < 3; ++c) lam[3 * i + c] = a ? rhs[3 * i + c] / g0[i] : 0.0;
+}
+
+// lambda <- (v - Gamma1 lambda) / Gamma0 = lambda + (v - Gamma~ lambda) / Gamma0
+// (y = Gamma~ lambda); decoupled modes keep lambda = 0.
+__global__ void bte_sc_update(long n, const double* __restrict__ rhs,
+                              const double* __restrict__ g0, const double* __restrict__ omega,
+                              const double* __restrict__ gmax, double nu_min,
+                              const double* __restrict__ y, double* __restrict__ lam) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (!bte_active(omega[i], g0[i], *gmax, nu_min)) return;
+  for (int c = 0; c < 3; ++c) lam[3 * i + c] += (rhs[3 * i + c] - y[3 * i + c]) / g0[i];
+}
+
+// ------------------------------------------------------------------ host
+
+struct BteWs {
+  size_t off_occ, off_phys, off_tr, off_phase, off_gmax, off_rhs, off_lam, off_y, off_y2,
+      off_linv, off_uinv, off_kappa, total;
+};
+
+static BteWs bte_ws(const kaldo_crystal* c, long nq) {
+  const long n = nq * c->nb3;
+  const long nb = (n + kLuB - 1) / kLuB;
+  BteWs w;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  w.off_occ = take(8 * n);
+  w.off_phys = take(n);
+  w.off_tr = take(4 * n);
+  w.off_phase = take(16 * nq * (size_t)std::max(1, c->bloch.n_d));
+  w.off_gmax = take(8);
+  w.off_rhs = take(24 * n);
+  w.off_lam = take(24 * n);
+  w.off_y = take(24 * n);
+  w.off_y2 = take(24 * n);
+  w.off_linv = take(8 * kLuB * kLuB * nb);
+  w.off_uinv = take(8 * kLuB * kLuB * nb);
+  w.off_kappa = take(8 * 9);
+  w.total = o;
+  return w;
+}
+
+static bool bte_supported(const kaldo_crystal* c) {
+  if (c->nb3 != 3 && c->nb3 != 6) return false;
+  return (size_t)c->bloch.n_e * c->nb3 * 16 <= 64 * 1024 && c->n_rep <= 64;
+}
+
+__global__ void bte_prepare(int n_modes, const double* __restrict__ omega, double inv_kt_hbar,
+                            double nu_min, double* __restrict__ occ, uint8_t* __restrict__ phys,
+                            int32_t* __restrict__ flags) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_modes) return;
+  const double w = omega[m];
+  const bool p = (w / kTwoPi) >= nu_min;
+  phys[m] = p;
+  occ[m] = p ? 1.0 / expm1(w * inv_kt_hbar) : 0.0;
+  if (!(w - w == 0.0)) raise_flag(flags, kFlagNonFinite);
+  if (w < 0.0 && (-w / kTwoPi) >= nu_min) raise_flag(flags, kFlagImaginary);
+}
+
+static int check_common(const kaldo_crystal* c, const int32_t* mesh, double T, long* nq_out) {
+  KALDO_REQUIRE(c && mesh, "bte: NULL argument");
+  KALDO_REQUIRE(mesh[0] >= 1 && mesh[1] >= 1 && mesh[2] >= 1, "bte: mesh must be >= 1");
+  KALDO_REQUIRE(std::isfinite(T) && T > 0, "bte: temperature <= 0");
+  const long nq = (long)mesh[0] * mesh[1] * mesh[2];
+  KALDO_REQUIRE(nq <= 65535L, "bte: mesh too large (N_q > 65535)");
+  *nq_out = nq;
+  return KALDO_OK;
+}
+
+}  // namespace kaldo
+
+using namespace kaldo;
+
+extern "C" size_t kaldo_bte_workspace(const kaldo_crystal* c, const int32_t* mesh) {
+  if (!c || !mesh || mesh[0] < 1 || mesh[1] < 1 || mesh[2] < 1) return 0;
+  return bte_ws(c, (long)mesh[0] * mesh[1] * mesh[2]).total;
+}
+
+extern "C" int kaldo_scattering_matrix(const kaldo_crystal* c, const int32_t* mesh,
+                                       const double* omega, const double* evec, const double* vel,
+                                       double temperature, const kaldo_broadening* b,
+                                       void* workspace, size_t workspace_bytes, double* matrix,
+                                       double* gamma0, void* stream) {
+  long nq = 0;
+  int rc = check_common(c, mesh, temperature, &nq);
+  if (rc) return rc;
+  KALDO_REQUIRE(omega && evec && vel && b && matrix && gamma0, "kaldo_scattering_matrix: NULL argument");
+  rc = check_broadening(b, true);
+  if (rc) return rc;
+  if (!bte_supported(c)) {
+    set_error("kaldo_scattering_matrix: implemented for cells of 1 or 2 atoms whose folded FC3 fits 64 KB of LDS");
+    return KALDO_EUNSUPPORTED;
+  }
+  const BteWs w = bte_ws(c, nq);
+  KALDO_REQUIRE(workspace && workspace_bytes >= w.total, "kaldo_scattering_matrix: workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto* ws = static_cast<unsigned char*>(workspace);
+  const int nb3 = c->nb3;
+  const long n = nq * nb3;
+  double* occ = reinterpret_cast<double*>(ws + w.off_occ);
+  uint8_t* phys = ws + w.off_phys;
+  int32_t* tr = reinterpret_cast<int32_t*>(ws + w.off_tr);
+  double2* phase = reinterpret_cast<double2*>(ws + w.off_phase);
+  double* gmax = reinterpret_cast<double*>(ws + w.off_gmax);
+  LwParams p = make_params(c, mesh, temperature, b);
+  KALDO_LAUNCH("bte_prepare", bte_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+               (int)n, omega, kHbar / (kKb * temperature), b->nu_min_thz, occ, phys, c->d_flags);
+  KALDO_LAUNCH("bte_tr_map", bte_tr_map, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+               (int)nq, nb3, mesh[0], mesh[1], mesh[2], evec, tr);
+  const long nph = nq * std::max(1, p.n_d);
+  KALDO_LAUNCH("lw_phase_table", lw_phase_table<double>, dim3((unsigned)((nph + 255) / 256)),
+               dim3(256), 0, st, (int)nq, p.n_d, mesh[0], mesh[1], mesh[2], c->bloch.dvec, phase);
+  const size_t n2 = (size_t)n * n;
+  KALDO_LAUNCH("bte_zero", bte_zero, dim3((unsigned)std::min<size_t>((n2 + 255) / 256, 1u << 20)),
+               dim3(256), 0, st, n2, matrix);
+  const size_t lds = (size_t)c->bloch.n_e * nb3 * sizeof(double2);
+  const double pref = 2.0 * kPrefactor / (double)nq;
+  const Fc3Bloch& bl = c->bloch;
+  if (nb3 == 6)
+    KALDO_LAUNCH("bte_rows", bte_rows<6>, dim3((unsigned)nq), dim3(64), lds, st, p, c->n_rep,
+                 c->d_rep, omega, vel, occ, phys, evec, phase, bl.d_ptr, bl.e_jc, bl.e_kc,
+                 bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix, gamma0);
+  else
+    KALDO_LAUNCH("bte_rows", bte_rows<3>, dim3((unsigned)nq), dim3(64), lds, st, p, c->n_rep,
+                 c->d_rep, omega, vel, occ, phys, evec, phase, bl.d_ptr, bl.e_jc, bl.e_kc,
+                 bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix, gamma0);
+  KALDO_LAUNCH("bte_gmax", bte_gmax, dim3(1), dim3(1024), 0, st, n, gamma0, gmax);
+  KALDO_LAUNCH("bte_decouple", bte_decouple, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+               n, omega, gamma0, gmax, b->nu_min_thz, matrix);
+  KALDO_HIP(hipGetLastError());
+  return KALDO_OK;
+}
+
+static int bte_solve_common(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                            const double* vel, const double* gamma0, double T, double nu_min,
+                            void* workspace, size_t workspace_bytes, const BteWs& w, long nq,
+                            hipStream_t st) {
+  KALDO_REQUIRE(omega && vel && gamma0, "bte: NULL argument");
+  KALDO_REQUIRE(std::isfinite(nu_min) && nu_min >= 0, "bte: nu_min_thz < 0");
+  KALDO_REQUIRE(workspace && workspace_bytes >= w.total, "bte: workspace too small");
+  auto* ws = static_cast<unsigned char*>(workspace);
+  const long n = nq * c->nb3;
+  double* gmax = reinterpret_cast<double*>(ws + w.off_gmax);
+  double* rhs = reinterpret_cast<double*>(ws + w.off_rhs);
+  (void)mesh;
+  (void)T;
+  KALDO_LAUNCH("bte_gmax", bte_gmax, dim3(1), dim3(1024), 0, st, n, gamma0, gmax);
+  KALDO_LAUNCH("bte_rhs", bte_rhs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, omega,
+               vel, gamma0, gmax, nu_min, rhs);
+  KALDO_HIP(hipGetLastError());
+  return KALDO_OK;
+}
+
+extern "C" int kaldo_bte_solve(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                               const double* vel, const double* gamma0, double temperature,
+                               double nu_min_thz, double* matrix, void* workspace,
+                               size_t workspace_bytes, double* lambda, double* kappa,
+                               void* stream) {
+  long nq = 0;
+  int rc = check_common(c, mesh, temperature, &nq);
+  if (rc) return rc;
+  KALDO_REQUIRE(matrix && lambda && kappa, "kaldo_bte_solve: NULL argument");
+  const BteWs w = bte_ws(c, nq);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = bte_solve_common(c, mesh, omega, vel, gamma0, temperature, nu_min_thz, workspace,
+                        workspace_bytes, w, nq, st);
+  if (rc) return rc;
+  auto* ws = static_cast<unsigned char*>(workspace);
+  const long n = nq * c->nb3;
+  const int nb = (int)((n + kLuB - 1) / kLuB);
+  double* linv = reinterpret_cast<double*>(ws + w.off_linv);
+  double* uinv = reinterpret_cast<double*>(ws + w.off_uinv);
+  double* rhs = reinterpret_cast<double*>(ws + w.off_rhs);
+  double* y = reinterpret_cast<double*>(ws + w.off_y);
+  double* gmax = reinterpret_cast<double*>(ws + w.off_gmax);
+  const size_t blk = (size_t)kLuB * kLuB;
+  for (int k = 0; k < nb; ++k) {
+    KALDO_LAUNCH("lu_diag", lu_diag, dim3(1), dim3(256), 0, st, n, k, matrix, linv + k * blk,
+                 uinv + k * blk, c->d_flags);
+    const int m = nb - k - 1;
+    if (m > 0) {
+      KALDO_LAUNCH("lu_panels", lu_panels, dim3(2 * m), dim3(256), 0, st, n, nb, k, matrix,
+                   linv + k * blk, uinv + k * blk);
+      KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)m * m), dim3(256), 0, st, n, nb, k,
+                   matrix);
+    }
+  }
+  for (int k = 0; k < nb; ++k)
+    KALDO_LAUNCH("lu_forward", lu_sweep<true>, dim3(1), dim3(256), 0, st, n, nb, k, matrix,
+                 linv + k * blk, rhs, y);
+  for (int k = nb - 1; k >= 0; --k)
+    KALDO_LAUNCH("lu_backward", lu_sweep<false>, dim3(1), dim3(256), 0, st, n, nb, k, matrix,
+                 uinv + k * blk, y, lambda);
+  const double scale = kKappaUnit / ((double)nq * c->volume);
+  KALDO_LAUNCH("bte_kappa", bte_kappa, dim3(1), dim3(1024), 0, st, n, omega, vel, lambda, gamma0,
+               gmax, kHbar / (kKb * temperature), nu_min_thz, scale, kappa);
+  KALDO_HIP(hipGetLastError());
+  return KALDO_OK;
+}
+
+extern "C" int kaldo_bte_iterate(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                                 const double* vel, const double* gamma0, double temperature,
+                                 double nu_min_thz, const double* matrix, int32_t n_iterations,
+                                 double tolerance, void* workspace, size_t workspace_bytes,
+                                 double* lambda, double* kappa, int32_t* iterations,
+                                 void* stream) {
+  long nq = 0;
+  int rc = check_common(c, mesh, temperature, &nq);
+  if (rc) return rc;
+  KALDO_REQUIRE(matrix && lambda && kappa, "kaldo_bte_iterate: NULL argument");
+  KALDO_REQUIRE(n_iterations >= 0 && std::isfinite(tolerance) && tolerance >= 0,
+                "kaldo_bte_iterate: bad n_iterations or tolerance");
+  const BteWs w = bte_ws(c, nq);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = bte_solve_common(c, mesh, omega, vel, gamma0, temperature, nu_min_thz, workspace,
+                        workspace_bytes, w, nq, st);
+  if (rc) return rc;
+  auto* ws = static_cast<unsigned char*>(workspace);
+  const long n = nq * c->nb3;
+  double* rhs = reinterpret_cast<double*>(ws + w.off_rhs);
+  double* y = reinterpret_cast<double*>(ws + w.off_y);
+  double* gmax = reinterpret_cast<double*>(ws + w.off_gmax);
+  double* kap_ws = reinterpret_cast<double*>(ws + w.off_kappa);
+  const double scale = kKappaUnit / ((double)nq * c->volume);
+  const double ikt = kHbar / (kKb * temperature);
+  const dim3 g1((unsigned)((n + 255) / 256));
+  KALDO_LAUNCH("bte_sc_init", bte_sc_init, g1, dim3(256), 0, st, n, rhs, gamma0, lambda);
+  KALDO_LAUNCH("bte_kappa", bte_kappa, dim3(1), dim3(1024), 0, st, n, omega, vel, lambda, gamma0,
+               gmax, ikt, nu_min_thz, scale, kap_ws);
+  double kh[9];
+  KALDO_HIP(hipMemcpyAsync(kh, kap_ws, sizeof(kh), hipMemcpyDeviceToHost, st));
+  KALDO_HIP(hipStreamSynchronize(st));
+  double k_prev = (kh[0] + kh[4] + kh[8]) / 3.0;
+  int it = 0;
+  bool conv = false;
+  while (it < n_iterations) {
+    KALDO_LAUNCH("bte_gemv", bte_gemv, dim3((unsigned)n), dim3(256), 0, st, n, matrix, lambda, y);
+    KALDO_LAUNCH("bte_sc_update", bte_sc_update, g1, dim3(256), 0, st, n, rhs, gamma0, omega, gmax,
+                 nu_min_thz, y, lambda);
+    KALDO_LAUNCH("bte_kappa", bte_kappa, dim3(1), dim3(1024), 0, st, n, omega, vel, lambda, gamma0,
+                 gmax, ikt, nu_min_thz, scale, kap_ws);
+    KALDO_HIP(hipMemcpyAsync(kh, kap_ws, sizeof(kh), hipMemcpyDeviceToHost, st));
+    KALDO_HIP(hipStreamSynchronize(st));
+    ++it;
+    const double k_new = (kh[0] + kh[4] + kh[8]) / 3.0;
+    const bool stop = std::fabs(k_new - k_prev) <= tolerance * std::fabs(k_prev);
+    k_prev = k_new;
+    if (stop) {
+      conv = true;
+      break;
+    }
+  }
+  KALDO_HIP(hipMemcpyAsync(kappa, kap_ws, sizeof(kh), hipMemcpyDeviceToDevice, st));
+  KALDO_HIP(hipStreamSynchronize(st));
+  if (iterations) *iterations = it;
+  if (!conv || !std::isfinite(k_prev)) {
+    set_error("kaldo_bte_iterate: no convergence within n_iterations (the iteration contracts only "
+              "when the off-diagonal part is small against the diagonal); kappa is the last iterate's");
+    return KALDO_ENUMERIC;
+  }
+  return KALDO_OK;
+}

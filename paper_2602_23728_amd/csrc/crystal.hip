@@ -324,6 +324,7 @@ extern "C" int kaldo_device_status(kaldo_crystal* c, void* stream) {
   if (flags & kFlagSubset) msg += " modes_subset index out of range;";
   if (flags & kFlagImaginary) msg += " imaginary mode (omega^2 < 0) above nu_min;";
   if (flags & kFlagNoConverge) msg += " eigen-solver did not converge within its sweep cap;";
+  if (flags & kFlagSingular) msg += " zero pivot in the LU factorisation of the scattering matrix;";
   set_error(msg);
   return (flags & (kFlagNonFinite | kFlagSubset)) ? KALDO_EINVAL : KALDO_ENUMERIC;
 }

@@ -109,6 +109,16 @@ def lib():
                                                ctypes.POINTER(Broadening), ctypes.c_int32, P,
                                                ctypes.c_int64, P, P]
         L.kaldo_linewidths_noalloc_max_bytes.argtypes = []
+        L.kaldo_bte_workspace.argtypes = [P, I32P]
+        L.kaldo_bte_workspace.restype = ctypes.c_size_t
+        L.kaldo_scattering_matrix.argtypes = [P, I32P, P, P, P, ctypes.c_double,
+                                              ctypes.POINTER(Broadening), P, ctypes.c_size_t, P,
+                                              P, P]
+        L.kaldo_bte_solve.argtypes = [P, I32P, P, P, P, ctypes.c_double, ctypes.c_double, P, P,
+                                      ctypes.c_size_t, P, P, P]
+        L.kaldo_bte_iterate.argtypes = [P, I32P, P, P, P, ctypes.c_double, ctypes.c_double, P,
+                                        ctypes.c_int32, ctypes.c_double, P, ctypes.c_size_t, P, P,
+                                        ctypes.POINTER(ctypes.c_int32), P]
         L.kaldo_linewidths_noalloc_max_bytes.restype = ctypes.c_size_t
         L.kaldo_star_map.argtypes = [I32P, ctypes.c_int32, P, P, P, P, P]
         L.kaldo_profile_begin.argtypes = []
@@ -127,7 +137,9 @@ EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
             "kaldo_mlp_param_count", "kaldo_mlp_workspace", "kaldo_mlp_train", "kaldo_mlp_predict",
             "kaldo_gate_calibrate", "kaldo_gate_select", "kaldo_surrogate_fill", "kaldo_star_map",
             "kaldo_surrogate_domain", "kaldo_gate_score", "kaldo_device_status",
-            "kaldo_linewidths_noalloc", "kaldo_linewidths_noalloc_max_bytes"]
+            "kaldo_linewidths_noalloc", "kaldo_linewidths_noalloc_max_bytes",
+            "kaldo_bte_workspace", "kaldo_scattering_matrix", "kaldo_bte_solve",
+            "kaldo_bte_iterate"]
 
 
 def _check(rc):
@@ -325,6 +337,69 @@ def kappa_rta(c: Crystal, mesh, omega, vel, gamma, temperature, nu_min_thz, out=
     _check(lib().kaldo_kappa_rta(c.handle, _ptr(m, I32P), _dev(omega), _dev(vel), _dev(gamma),
                                  float(temperature), float(nu_min_thz), _dev(out), _stream()))
     return out
+
+
+# ------------------------------------------------------------------ full BTE
+
+def bte_workspace(c: Crystal, mesh):
+    return int(lib().kaldo_bte_workspace(c.handle, _ptr(_mesh(mesh), I32P)))
+
+
+def scattering_matrix(c: Crystal, mesh, omega, evec, vel, temperature, broadening, workspace=None,
+                      out=None):
+    """(matrix [n, n], gamma0 [n]) float64 on cuda, n = N_q nb3."""
+    m = _mesh(mesh)
+    n = int(np.prod(m)) * c.nb3
+    if workspace is None:
+        workspace = torch.empty(max(bte_workspace(c, m), 1), dtype=torch.uint8, device="cuda")
+    if out is None:
+        out = (torch.empty(n, n, dtype=torch.float64, device="cuda"),
+               torch.empty(n, dtype=torch.float64, device="cuda"))
+    ev = _as_real(evec).contiguous()
+    b = Broadening.of(broadening)
+    _check(lib().kaldo_scattering_matrix(c.handle, _ptr(m, I32P), _dev(omega), _dev(ev), _dev(vel),
+                                         float(temperature), ctypes.byref(b), _dev(workspace),
+                                         int(workspace.numel()), _dev(out[0]), _dev(out[1]),
+                                         _stream()))
+    return out
+
+
+def bte_solve(c: Crystal, mesh, omega, vel, gamma0, temperature, nu_min_thz, matrix,
+              workspace=None):
+    """Eq. inverse on the GPU (matrix overwritten by its LU factors):
+    (lambda [n, 3], kappa [3, 3]) float64 on cuda."""
+    m = _mesh(mesh)
+    n = int(np.prod(m)) * c.nb3
+    if workspace is None:
+        workspace = torch.empty(max(bte_workspace(c, m), 1), dtype=torch.uint8, device="cuda")
+    lam = torch.empty(n, 3, dtype=torch.float64, device="cuda")
+    kap = torch.empty(3, 3, dtype=torch.float64, device="cuda")
+    _check(lib().kaldo_bte_solve(c.handle, _ptr(m, I32P), _dev(omega), _dev(vel), _dev(gamma0),
+                                 float(temperature), float(nu_min_thz), _dev(matrix),
+                                 _dev(workspace), int(workspace.numel()), _dev(lam), _dev(kap),
+                                 _stream()))
+    return lam, kap
+
+
+def bte_iterate(c: Crystal, mesh, omega, vel, gamma0, temperature, nu_min_thz, matrix,
+                n_iterations=200, tolerance=1e-10, workspace=None, check=True):
+    """Eq. sc_iter on the GPU: (lambda [n, 3], kappa [3, 3], iterations, status).
+    Raises on non-convergence when check is True."""
+    m = _mesh(mesh)
+    n = int(np.prod(m)) * c.nb3
+    if workspace is None:
+        workspace = torch.empty(max(bte_workspace(c, m), 1), dtype=torch.uint8, device="cuda")
+    lam = torch.empty(n, 3, dtype=torch.float64, device="cuda")
+    kap = torch.empty(3, 3, dtype=torch.float64, device="cuda")
+    it = ctypes.c_int32()
+    rc = lib().kaldo_bte_iterate(c.handle, _ptr(m, I32P), _dev(omega), _dev(vel), _dev(gamma0),
+                                 float(temperature), float(nu_min_thz), _dev(matrix),
+                                 int(n_iterations), float(tolerance), _dev(workspace),
+                                 int(workspace.numel()), _dev(lam), _dev(kap), ctypes.byref(it),
+                                 _stream())
+    if check:
+        _check(rc)
+    return lam, kap, it.value, rc
 
 
 # ------------------------------------------------------------------ learned form
