@@ -294,6 +294,48 @@ def gamma_point_leg(a, K, torch, cfg, model, steps, warmup):
     return out
 
 
+def bte_leg(K, torch, steps, warmup):
+    """Full BTE on the diamond 15^3 mesh (20,250 modes): the dense FP64
+    scattering matrix (3.3 GB) and its direct inversion (Eq. inverse) by the
+    blocked LU, timed per step (the factorisation overwrites the matrix, so
+    every step rebuilds it); the LU's trailing updates run on the FP64 matrix
+    cores, (2/3) n^3 FLOP in all."""
+    from synthetic import configs
+    cfg = configs.CONFIGS["C2"]
+    model = configs.model_for(cfg)
+    c = K.Crystal.from_model(model)
+    mesh = cfg.mesh
+    nq = int(np.prod(mesh))
+    n = nq * c.nb3
+    om, ev, ve = K.phonons(c, mesh)
+    ws = torch.empty(K.bte_workspace(c, mesh), dtype=torch.uint8, device="cuda")
+    mat = torch.empty(n, n, dtype=torch.float64, device="cuda")
+    g0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    state = {}
+
+    def step():
+        K.scattering_matrix(c, mesh, om, ev, ve, cfg.temperature, cfg.broadening, workspace=ws,
+                            out=(mat, g0))
+        state["lk"] = K.bte_solve(c, mesh, om, ve, g0, cfg.temperature,
+                                  cfg.broadening.nu_min_thz, mat, workspace=ws)
+
+    ms, prof = timed(K, torch, step, steps, warmup, "C2 full BTE")
+    c.device_status()
+    per = {k: v[1] / steps for k, v in prof.items()}
+    build = sum(v for k, v in per.items() if k.startswith("bte_") and k != "bte_kappa")
+    lu = sum(v for k, v in per.items() if k.startswith("lu_"))
+    upd = per.get("lu_update", 0.0)
+    flop_lu = 2.0 / 3.0 * float(n) ** 3
+    kap = state["lk"][1].cpu().numpy()
+    out = dict(modes=n, matrix_bytes=n * n * 8, ms_per_step=ms, build_ms=build, lu_solve_ms=lu,
+               lu_update_ms=upd, lu_tflops=flop_lu / (lu * 1e-3) / 1e12,
+               lu_frac_fp64=flop_lu / (lu * 1e-3) / 1e12 / FP64_PEAK,
+               kappa_inv_trace_over_3=float(np.trace(kap) / 3), kernels_ms_per_step=per)
+    del mat, ws
+    c.close()
+    return out
+
+
 def bench_gamma_point(a, cfg, model, K, torch):
     """--config C4 alone: the Gamma-point leg as the JSON line."""
     leg = gamma_point_leg(a, K, torch, cfg, model, a.steps, a.warmup)
@@ -468,6 +510,7 @@ def main():
         c4 = configs.CONFIGS["C4"]
         extras["c4"] = gamma_point_leg(a, K, torch, c4, configs.model_for(c4),
                                        max(3, a.steps // 4), 2)
+        extras["bte_c2"] = bte_leg(K, torch, 3, 1)
 
     base, stats, om_o = (None, {}, None)
     if not a.no_cpu_baseline:

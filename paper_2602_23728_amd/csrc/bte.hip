@@ -31,7 +31,7 @@
 //   bte_gmax, bte_decouple   the RTA selection
 //   lu_diag, lu_panels, lu_update   blocked LU without pivoting (64 x 64
 //                  blocks; the trailing update on FP64 matrix cores)
-//   lu_forward, lu_backward   the two triangular sweeps for the 3 RHS
+//   lu_tri, lu_rupdate   the two triangular sweeps for the 3 RHS
 //   bte_gemv, bte_sc_init, bte_sc_update   the iteration of Eq. sc_iter
 //   bte_kappa      Eq. kappa_general, fixed-order reduction
 // Every reduction and every sequence of additions into one matrix element
@@ -475,28 +475,58 @@ __global__ __launch_bounds__(256) void lu_update(long n, int nb, int k, double* 
       }
 }
 
-// Row block k of a triangular sweep with 3 right-hand sides: r = b_k -
-// sum over the already solved blocks of A[k rows][those columns] x, then
-// x_k = Tinv r.  Forward (lower, blocks j < k) or backward (upper, j > k).
-template <bool FORWARD>
-__global__ __launch_bounds__(256) void lu_sweep(long n, int nb, int k, const double* __restrict__ mat,
-                                                const double* __restrict__ tinv,
-                                                const double* __restrict__ b,
-                                                double* __restrict__ x) {
+// Triangular sweeps with 3 right-hand sides, right-looking: the residual r
+// starts as the right-hand side; step k solves block k, x_k = Tinv_k r_k
+// (lu_tri, one workgroup), then removes its contribution from the blocks
+// still to solve, r_i -= A_ik x_k (lu_rupdate, one workgroup per block:
+// i > k forward with the L blocks, i < k backward with the U blocks).  Every
+// r_i is updated in the order of k: the sums are fixed-order.
+__global__ __launch_bounds__(256) void lu_tri(long n, int k, const double* __restrict__ tinv,
+                                              const double* __restrict__ r,
+                                              double* __restrict__ x) {
   constexpr int B = kLuB;
+  __shared__ double rk[B][3];
+  const int tid = threadIdx.x;
+  if (tid < B * 3) {
+    const int i = tid / 3, c = tid % 3;
+    const long g = (long)k * B + i;
+    rk[i][c] = g < n ? r[3 * g + c] : 0.0;
+  }
+  __syncthreads();
+  if (tid < B * 3) {
+    const int i = tid / 3, c = tid % 3;
+    double s = 0.0;
+    for (int t = 0; t < B; ++t) s += tinv[i * B + t] * rk[t][c];
+    const long g = (long)k * B + i;
+    if (g < n) x[3 * g + c] = s;
+  }
+}
+
+template <bool FORWARD>
+__global__ __launch_bounds__(256) void lu_rupdate(long n, int k, const double* __restrict__ mat,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ r) {
+  constexpr int B = kLuB;
+  __shared__ double xk[B][3];
   __shared__ double part[4][B][3];
-  __shared__ double r[B][3];
   const int tid = threadIdx.x, row = tid >> 2, sub = tid & 3;
-  const long gi = (long)k * B + row;
-  const long c_lo = FORWARD ? 0 : (long)(k + 1) * B;
-  const long c_hi = FORWARD ? (long)k * B : n;
+  const long bi = FORWARD ? k + 1 + (long)blockIdx.x : (long)blockIdx.x;
+  if (tid < B * 3) {
+    const int i = tid / 3, c = tid % 3;
+    const long g = (long)k * B + i;
+    xk[i][c] = g < n ? x[3 * g + c] : 0.0;
+  }
+  __syncthreads();
+  const long gi = bi * B + row;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (gi < n)
-    for (long c = c_lo + sub; c < c_hi; c += 4) {
-      const double a = mat[gi * n + c];
-      s0 += a * x[3 * c];
-      s1 += a * x[3 * c + 1];
-      s2 += a * x[3 * c + 2];
+    for (int t = sub; t < B; t += 4) {
+      const long gc = (long)k * B + t;
+      if (gc >= n) break;
+      const double a = mat[gi * n + gc];
+      s0 += a * xk[t][0];
+      s1 += a * xk[t][1];
+      s2 += a * xk[t][2];
     }
   part[sub][row][0] = s0;
   part[sub][row][1] = s1;
@@ -504,18 +534,14 @@ __global__ __launch_bounds__(256) void lu_sweep(long n, int nb, int k, const dou
   __syncthreads();
   if (tid < B * 3) {
     const int i = tid / 3, c = tid % 3;
-    const long g = (long)k * B + i;
-    const double bb = g < n ? b[3 * g + c] : 0.0;
-    r[i][c] = bb - (((part[0][i][c] + part[1][i][c]) + part[2][i][c]) + part[3][i][c]);
+    const long g = bi * B + i;
+    if (g < n) r[3 * g + c] -= ((part[0][i][c] + part[1][i][c]) + part[2][i][c]) + part[3][i][c];
   }
-  __syncthreads();
-  if (tid < B * 3) {
-    const int i = tid / 3, c = tid % 3;
-    double s = 0.0;
-    for (int t = 0; t < B; ++t) s += tinv[i * B + t] * r[t][c];
-    const long g = (long)k * B + i;
-    if (g < n) x[3 * g + c] = s;
-  }
+}
+
+__global__ void bte_copy3(long n, const double* __restrict__ src, double* __restrict__ dst) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * n) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------------ iteration
@@ -747,12 +773,24 @@ extern "C" int kaldo_bte_solve(const kaldo_crystal* c, const int32_t* mesh, cons
                    matrix);
     }
   }
-  for (int k = 0; k < nb; ++k)
-    KALDO_LAUNCH("lu_forward", lu_sweep<true>, dim3(1), dim3(256), 0, st, n, nb, k, matrix,
-                 linv + k * blk, rhs, y);
-  for (int k = nb - 1; k >= 0; --k)
-    KALDO_LAUNCH("lu_backward", lu_sweep<false>, dim3(1), dim3(256), 0, st, n, nb, k, matrix,
-                 uinv + k * blk, y, lambda);
+  // forward: y = L^-1 b, the residual in y2 (starting as b)
+  double* r = reinterpret_cast<double*>(ws + w.off_y2);
+  const dim3 g3((unsigned)((3 * n + 255) / 256));
+  KALDO_LAUNCH("bte_copy3", bte_copy3, g3, dim3(256), 0, st, n, rhs, r);
+  for (int k = 0; k < nb; ++k) {
+    KALDO_LAUNCH("lu_tri", lu_tri, dim3(1), dim3(256), 0, st, n, k, linv + k * blk, r, y);
+    if (nb - k - 1 > 0)
+      KALDO_LAUNCH("lu_rupdate", lu_rupdate<true>, dim3(nb - k - 1), dim3(256), 0, st, n, k,
+                   matrix, y, r);
+  }
+  // backward: lambda = U^-1 y, the residual in y2 (starting as y)
+  KALDO_LAUNCH("bte_copy3", bte_copy3, g3, dim3(256), 0, st, n, y, r);
+  for (int k = nb - 1; k >= 0; --k) {
+    KALDO_LAUNCH("lu_tri", lu_tri, dim3(1), dim3(256), 0, st, n, k, uinv + k * blk, r, lambda);
+    if (k > 0)
+      KALDO_LAUNCH("lu_rupdate", lu_rupdate<false>, dim3(k), dim3(256), 0, st, n, k, matrix,
+                   lambda, r);
+  }
   const double scale = kKappaUnit / ((double)nq * c->volume);
   KALDO_LAUNCH("bte_kappa", bte_kappa, dim3(1), dim3(1024), 0, st, n, omega, vel, lambda, gamma0,
                gmax, kHbar / (kKb * temperature), nu_min_thz, scale, kappa);
