@@ -47,6 +47,9 @@ MEASURED_TRAFFIC = {
     ("lw_fused", "C2", "fp32"): {"sources": ["lw_fused.hip", "lw_common.h", "common.h"],
                                  "sha256": "255bd3fdb705aa75efcc7d9c549a4092699d1f8245ea98c12f883dfa4b121677",
                                  "bytes": 58784804},
+    ("lw_fused", "C5", "fp64"): {"sources": ["lw_fused.hip", "lw_common.h", "common.h"],
+                                 "sha256": "768df0d7b0cfe874ee3fc5e5caabe2d55308a1f2dc3b1fc3bd986c8bc1d1d144",
+                                 "bytes": 24163433789},
 }
 
 
@@ -88,8 +91,9 @@ def parse(argv=None):
                          "batches until it does)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline step (no FP32, C3 split or C4 legs)")
-    ap.add_argument("--form", default="plain", choices=["plain", "learned"],
-                    help="learned: the learned form against plain FP32 (full mesh and wedge)")
+    ap.add_argument("--form", default="plain", choices=["plain", "learned", "bte"],
+                    help="learned: the learned form against plain FP32 (full mesh and wedge); "
+                         "bte: only the full-BTE leg (diamond 15^3)")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -464,6 +468,17 @@ def main():
     if a.form == "learned":
         bench_learned(a, cfg, model, c, K, torch)
         c.close()
+        return
+    if a.form == "bte":
+        c.close()
+        leg = bte_leg(K, torch, a.steps, a.warmup)
+        print(json.dumps({"metric": METRIC, "value": leg["modes"] / (leg["ms_per_step"] * 1e-3),
+                          "unit": "modes/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+                          "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic",
+                          "config": {"workload": "C2 full BTE: scattering matrix and inverse"},
+                          "bte_c2": leg}))
         return
     mesh = cfg.mesh
     nq = int(np.prod(mesh))
