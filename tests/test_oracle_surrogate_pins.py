@@ -175,10 +175,12 @@ def test_star_members_share_frequencies_and_jdos():
     np.testing.assert_allclose(dm, dm[ir], rtol=1e-8, atol=1e-12 * dm.max())
 
 
-def test_star_map_reproduces_full_mesh_linewidths():
+@pytest.mark.parametrize("which", ["diamond", "perovskite"])
+def test_star_map_reproduces_full_mesh_linewidths(which):
     """Gamma computed on every q equals, after averaging over degenerate
-    clusters, the star map of the representatives' values."""
-    m = models.diamond()
+    clusters, the star map of the representatives' values, and the
+    representatives alone (a q_list of the wedge) give the same map."""
+    m = models.diamond() if which == "diamond" else models.perovskite(0)
     mesh = (4, 4, 4)
     ir = osur.ibz_map(m, mesh)
     om, ev, ve = phonons.phonons(m, mesh)
@@ -187,6 +189,8 @@ def test_star_map_reproduces_full_mesh_linewidths():
     own = osur.star_map(np.arange(len(ir)), om, g)   # cluster averages at each q itself
     scale = g.max()
     np.testing.assert_allclose(mapped, own, rtol=1e-7, atol=1e-9 * scale)
+    g_ir = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, B_FIXED, q_list=np.unique(ir))
+    np.testing.assert_allclose(osur.star_map(ir, om, g_ir), own, rtol=1e-7, atol=1e-9 * scale)
 
 
 def test_features_are_star_invariant():
