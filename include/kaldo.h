@@ -41,8 +41,8 @@
  * synchronisation, so the kernels validate them as they read them and record
  * what they find in a sticky status word of the crystal handle:
  * kaldo_device_status() synchronises the stream, returns that status
- * (KALDO_EINVAL for a non-finite omega/eta/v/Gamma or a subset index out of
- * range, KALDO_ENUMERIC for an imaginary mode above nu_min or an eigen-solver
+ * (KALDO_EINVAL for a non-finite omega/eta/v/Gamma, a subset index or a
+ * temperature-cache index out of range, KALDO_ENUMERIC for an imaginary mode above nu_min or an eigen-solver
  * that stopped at its sweep cap) and clears it.  kaldo_last_error() returns
  * a thread-local description of the last failure in the calling thread.
  *
@@ -138,8 +138,9 @@ int kaldo_crystal_destroy(kaldo_crystal* c);
  * Synchronises `stream` (the stream the calls were enqueued on), reads the
  * handle's status word and clears it.  Returns KALDO_OK if nothing was found;
  * KALDO_EINVAL if a kernel read a non-finite omega, eigenvector component,
- * velocity or linewidth, or a modes_subset index outside [0, n_modes) (such
- * entries are ignored); KALDO_ENUMERIC if a mode had omega < 0 with
+ * velocity or linewidth, a modes_subset index outside [0, n_modes), or a
+ * temperature-cache row pointer or partner index out of range (such entries
+ * are ignored); KALDO_ENUMERIC if a mode had omega < 0 with
  * |nu| >= nu_min_thz (the linewidth and conductivity kernels treat it as
  * unphysical), if kaldo_phonons' Jacobi solver reached its sweep cap on
  * some q, or if kaldo_bte_solve met a zero pivot.  kaldo_last_error() then lists every condition found.  Calls on
@@ -317,6 +318,65 @@ int kaldo_bte_iterate(const kaldo_crystal* c, const int32_t* mesh, const double*
                       double nu_min_thz, const double* matrix, int32_t n_iterations,
                       double tolerance, void* workspace, size_t workspace_bytes, double* lambda,
                       double* kappa, int32_t* iterations, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Temperature sweeps.  The paper separates the temperature-invariant part of
+ * the calculation from the populations so that a sweep over temperatures
+ * reuses the projection of Eq. phi3_proj ("Performance and Scalability",
+ * multi-temperature optimisation).  In Eq. gamma only the Bose populations of
+ * the two partners (Eq. bose) depend on T, so the library stores, per mode
+ * and per partner entry that passes the 2-sigma cut, two factors c and d with
+ *   Gamma_mu(T) = pi hbar U^3/(8 N_q) sum_row c (n1 - n2) + d (n1 + n2 + 1),
+ *   c = |V|^2 g(x+)/(w w1 w2),  d = 1/2 |V|^2 g(x-)/(w w1 w2)
+ * (each g zero outside its cut).  When Phi3 is symmetric in its last two
+ * slots one entry stands for a pair and its mirror (q2 s'', q1 s'): then
+ * c = |V|^2 (g(x+) - g(x+')) / (w w1 w2) and d sums both decay terms, x+' =
+ * (w + w2) - w1.
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes of kaldo_tcache_build (0 on bad arguments). */
+size_t kaldo_tcache_workspace(const kaldo_crystal* c, const int32_t* mesh, int32_t precision);
+
+/* kaldo_tcache_build -- the temperature-independent factors of every mode in
+ * modes_subset (all modes when modes_subset is NULL), computed by the fused
+ * pruned kernel (cells of at most 5 basis atoms and 64 replicas whose A~
+ * tables fit in LDS; else KALDO_EUNSUPPORTED; precision FP64 or FP32 for the
+ * projection, factors always FP64).  Rows are CSR by mode:
+ *   row_ptr    device int64[n_modes + 1] out: entries of mode m are
+ *              [row_ptr[m], row_ptr[m+1]); rows of modes not selected or
+ *              below nu_min are empty
+ *   capacity   entries `pairs` and `factors` can hold
+ *   pairs      device uint32[capacity][2] out: flat partner modes (m1, m2)
+ *   factors    device double[capacity][2] out: (c, d) as above
+ *   n_entries  host out: entries needed
+ * Runs a count pass, writes row_ptr and synchronises `stream` once to read
+ * the total.  With pairs and factors NULL it stops there (a size query);
+ * with capacity < *n_entries it returns KALDO_EINVAL and writes no entry;
+ * otherwise a record pass fills the rows (enqueued; valid after a stream
+ * synchronisation).  The order of a row is fixed by the inputs, so the
+ * output is bitwise reproducible.  Other arguments as kaldo_linewidths. */
+int kaldo_tcache_build(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                       const double* evec, const double* vel, const kaldo_broadening* broadening,
+                       int32_t precision, const int32_t* modes_subset, int64_t n_subset,
+                       void* workspace, size_t workspace_bytes, int64_t* row_ptr, int64_t capacity,
+                       uint32_t* pairs, double* factors, int64_t* n_entries, void* stream);
+
+/* Device workspace bytes of kaldo_tcache_gamma (0 on bad arguments). */
+size_t kaldo_tcache_gamma_workspace(const kaldo_crystal* c, const int32_t* mesh);
+
+/* kaldo_tcache_gamma -- Gamma at each of n_temps temperatures (host
+ * double[n_temps], K, finite and > 0) from a cache of kaldo_tcache_build:
+ *   gamma   device double[n_temps][n_modes] out, rad/ps; 0 for modes below
+ *           nu_min_thz and for empty rows
+ * One pass over the entries per batch of up to 8 temperatures; FP64, fixed
+ * summation order (bitwise reproducible).  Row pointers outside
+ * [0, n_entries] or partner indices outside [0, n_modes) are skipped and set
+ * the handle's status (kaldo_device_status -> KALDO_EINVAL).  Enqueued. */
+int kaldo_tcache_gamma(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                       double nu_min_thz, const int64_t* row_ptr, int64_t n_entries,
+                       const uint32_t* pairs, const double* factors, int32_t n_temps,
+                       const double* temperatures, void* workspace, size_t workspace_bytes,
+                       double* gamma, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned form.  The paper restricts the scattering calculation to the

@@ -42,6 +42,7 @@ constexpr int32_t kFlagImaginary = 2;    // omega < 0 with |nu| >= nu_min
 constexpr int32_t kFlagNoConverge = 4;   // an eigen-solver stopped at its sweep cap
 constexpr int32_t kFlagSubset = 8;       // a modes_subset index outside [0, n_modes)
 constexpr int32_t kFlagSingular = 16;    // a zero pivot in an LU factorisation
+constexpr int32_t kFlagCache = 32;       // a temperature-cache row or pair index out of range
 __device__ __forceinline__ void raise_flag(int32_t* flags, int32_t bit) { atomicOr(flags, bit); }
 
 // ----------------------------------------------------------------- errors

@@ -322,11 +322,12 @@ extern "C" int kaldo_device_status(kaldo_crystal* c, void* stream) {
   std::string msg = "kaldo_device_status:";
   if (flags & kFlagNonFinite) msg += " non-finite value in a device input (omega, eta, v or Gamma);";
   if (flags & kFlagSubset) msg += " modes_subset index out of range;";
+  if (flags & kFlagCache) msg += " temperature-cache row or pair index out of range;";
   if (flags & kFlagImaginary) msg += " imaginary mode (omega^2 < 0) above nu_min;";
   if (flags & kFlagNoConverge) msg += " eigen-solver did not converge within its sweep cap;";
   if (flags & kFlagSingular) msg += " zero pivot in the LU factorisation of the scattering matrix;";
   set_error(msg);
-  return (flags & (kFlagNonFinite | kFlagSubset)) ? KALDO_EINVAL : KALDO_ENUMERIC;
+  return (flags & (kFlagNonFinite | kFlagSubset | kFlagCache)) ? KALDO_EINVAL : KALDO_ENUMERIC;
 }
 
 extern "C" int kaldo_crystal_destroy(kaldo_crystal* c) {

@@ -235,12 +235,12 @@ struct CrystalWs {
   size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, off_phase, off_modef, off_qlist, off_fpart, total;
 };
 
-static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
+static CrystalWs crystal_ws_for(const kaldo_crystal* c, long nq, int prec, CrystalPath path) {
   const int nb3 = c->nb3;
   const size_t cs = prec == KALDO_FP64 ? 16 : 8;
   const long nblk = (nq + 63) / 64;
   CrystalWs w{};
-  w.path = choose_path(c, prec);
+  w.path = path;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -265,6 +265,10 @@ static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
   }
   w.total = o;
   return w;
+}
+
+static CrystalWs crystal_ws(const kaldo_crystal* c, long nq, int prec) {
+  return crystal_ws_for(c, nq, prec, choose_path(c, prec));
 }
 
 template <typename T>
@@ -377,4 +381,95 @@ extern "C" int kaldo_linewidths(const kaldo_crystal* c, const int32_t* mesh, con
   return linewidths_enqueue(c, mesh, omega, evec, vel, temperature, b, precision, modes_subset,
                             n_subset, workspace, workspace_bytes, gamma,
                             static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Temperature cache: the temperature-independent factors of Eq. gamma for
+// every cut-passing partner entry, built by the fused kernel's count and
+// record passes (the sweeps over temperature are in tcache.hip).
+
+using namespace kaldo;
+
+extern "C" size_t kaldo_tcache_workspace(const kaldo_crystal* c, const int32_t* mesh,
+                                         int32_t precision) {
+  if (!c || !mesh || mesh[0] < 1 || mesh[1] < 1 || mesh[2] < 1) return 0;
+  return crystal_ws_for(c, (long)mesh[0] * mesh[1] * mesh[2], precision, CrystalPath::Fused).total;
+}
+
+extern "C" int kaldo_tcache_build(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                                  const double* evec, const double* vel,
+                                  const kaldo_broadening* b, int32_t precision,
+                                  const int32_t* modes_subset, int64_t n_subset, void* workspace,
+                                  size_t workspace_bytes, int64_t* row_ptr, int64_t capacity,
+                                  uint32_t* pairs, double* factors, int64_t* n_entries,
+                                  void* stream) {
+  KALDO_REQUIRE(c && mesh && omega && evec && vel && b && row_ptr && n_entries,
+                "kaldo_tcache_build: NULL argument");
+  KALDO_REQUIRE(mesh[0] >= 1 && mesh[1] >= 1 && mesh[2] >= 1, "kaldo_tcache_build: mesh must be >= 1");
+  KALDO_REQUIRE(c->nb3 <= kMaxNb3Linewidths, "kaldo_tcache_build: nb3 > 16");
+  int rc = check_broadening(b, true);
+  if (rc) return rc;
+  KALDO_REQUIRE(precision == KALDO_FP64 || precision == KALDO_FP32 || precision == KALDO_BF16X3,
+                "kaldo_tcache_build: unknown precision");
+  if (precision == KALDO_BF16X3 || !fused_record_supported(c, precision)) {
+    set_error("kaldo_tcache_build: needs the fused kernel (FP64 or FP32, at most 5 basis atoms, "
+              "64 replicas, A~ tables and record queue in LDS)");
+    return KALDO_EUNSUPPORTED;
+  }
+  KALDO_REQUIRE(n_subset >= 0 && (n_subset == 0 || modes_subset), "kaldo_tcache_build: bad subset");
+  KALDO_REQUIRE(capacity >= 0, "kaldo_tcache_build: capacity < 0");
+  KALDO_REQUIRE((pairs == nullptr) == (factors == nullptr),
+                "kaldo_tcache_build: pairs and factors must both be given or both be NULL");
+  const long nq = (long)mesh[0] * mesh[1] * mesh[2];
+  KALDO_REQUIRE(nq <= 65535L, "kaldo_tcache_build: mesh too large (N_q > 65535)");
+  const CrystalWs w = crystal_ws_for(c, nq, precision, CrystalPath::Fused);
+  KALDO_REQUIRE(workspace && workspace_bytes >= w.total, "kaldo_tcache_build: workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nb3 = c->nb3;
+  const int n_modes = (int)nq * nb3;
+  *n_entries = 0;
+  if (modes_subset && n_subset == 0) {
+    KALDO_HIP(hipMemsetAsync(row_ptr, 0, sizeof(int64_t) * (n_modes + 1), st));
+    KALDO_HIP(hipStreamSynchronize(st));
+    return KALDO_OK;
+  }
+  auto* ws = static_cast<unsigned char*>(workspace);
+  double* occ = reinterpret_cast<double*>(ws + w.off_occ);
+  uint8_t* phys = ws + w.off_phys;
+  uint8_t* sel = ws + w.off_sel;
+  float4* modef = reinterpret_cast<float4*>(ws + w.off_modef);
+  int32_t* qlist = reinterpret_cast<int32_t*>(ws + w.off_qlist);
+  // the populations lw_prepare writes are not used: any temperature will do
+  KALDO_LAUNCH("lw_prepare", lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes, nb3,
+               omega, vel, evec, kHbar / (kKb * 300.0), b->nu_min_thz, occ, phys, sel, modef,
+               modes_subset ? 0 : 1, c->d_flags);
+  if (modes_subset)
+    KALDO_LAUNCH("lw_select", lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st,
+                 modes_subset, (long)n_subset, n_modes, sel, c->d_flags);
+  const LwParams p = make_params(c, mesh, 300.0, b);
+  TcOut tc{reinterpret_cast<long long*>(ws + w.off_fpart), reinterpret_cast<long long*>(row_ptr),
+           reinterpret_cast<uint2*>(pairs), reinterpret_cast<double2*>(factors), c->d_flags};
+  const int64_t ns = modes_subset ? n_subset : 0;
+  auto pass = [&](int mode) {
+    if (precision == KALDO_FP64)
+      return launch_fused_cache<double>(c, p, mode, omega, vel, modef, phys, sel, evec,
+                                        reinterpret_cast<double2*>(ws + w.off_eta),
+                                        reinterpret_cast<double2*>(ws + w.off_phase), qlist, ns, tc, st);
+    return launch_fused_cache<float>(c, p, mode, omega, vel, modef, phys, sel, evec,
+                                     reinterpret_cast<float2*>(ws + w.off_eta),
+                                     reinterpret_cast<float2*>(ws + w.off_phase), qlist, ns, tc, st);
+  };
+  rc = pass(kModeCount);
+  if (rc) return rc;
+  int64_t total = 0;
+  KALDO_HIP(hipMemcpyAsync(&total, row_ptr + n_modes, sizeof(total), hipMemcpyDeviceToHost, st));
+  KALDO_HIP(hipStreamSynchronize(st));
+  *n_entries = total;
+  if (!pairs) return KALDO_OK;
+  if (capacity < total) {
+    set_error("kaldo_tcache_build: capacity " + std::to_string(capacity) + " below the " +
+              std::to_string(total) + " entries needed");
+    return KALDO_EINVAL;
+  }
+  return pass(kModeRecord);
 }

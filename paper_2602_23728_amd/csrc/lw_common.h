@@ -99,6 +99,10 @@ __device__ __forceinline__ void widths_v(const LwParams& p, const double* v1, co
 // the squared velocity sums S+- they come from (fixed width: S = 0).
 __device__ __forceinline__ void widths2(const LwParams& p, const double* v1, const double* v2,
                                         double& s2p, double& s2m, double& Sp, double& Sm) {
+  // no fused multiply-adds: the cut decisions made from S must come out the
+  // same in every kernel that takes them (the cache's count and record
+  // passes place entries by them), in the order the sums are written
+#pragma clang fp contract(off)
   if (!p.adaptive) {
     s2p = s2m = p.sig_fixed * p.sig_fixed;
     Sp = Sm = 0.0;
@@ -148,6 +152,18 @@ __device__ __forceinline__ double pair_weight(const LwParams& p, double w, doubl
   const double gm = pm ? smear(p.shape, xm, sm) : 0.0;
   const double pop = (n1 - n2) * gp + 0.5 * (n1 + n2 + 1.0) * gm;
   return pop / (w * (w1 * w2));
+}
+
+// The temperature-independent factors of one ordered partner pair:
+// ap = g(x+; sigma+)/(w w1 w2) and am = g(x-; sigma-)/(w w1 w2), each zero
+// unless its own process passes |x| < 2 sigma (the cut of pair_weight).
+__device__ __forceinline__ void pair_factors(const LwParams& p, double w, double w1, double w2,
+                                             double sp, double sm, double& ap, double& am) {
+  const double xp = (w + w1) - w2;
+  const double xm = (w - w1) - w2;
+  const double den = w * (w1 * w2);
+  ap = fabs(xp) < 2.0 * sp ? smear(p.shape, xp, sp) / den : 0.0;
+  am = fabs(xm) < 2.0 * sm ? smear(p.shape, xm, sm) / den : 0.0;
 }
 
 // FP32 pre-classification of |x| < T against an FP64 reference: a_f is |x|
@@ -413,6 +429,26 @@ __host__ __device__ inline int fused_chunks(int n_live, int target) {
   return c < 1 ? 1 : (c > kFusedMaxChunks ? kFusedMaxChunks : c);
 }
 bool fused_supported(const kaldo_crystal* c, int prec);
+bool fused_record_supported(const kaldo_crystal* c, int prec);  // the cache's record pass
+
+// What one launch of the fused kernel produces: Gamma (the linewidth sums),
+// or, for the temperature cache, the number of cut-passing partner entries
+// per (live q, chunk, branch) (count) and then the entries themselves
+// (record).
+enum FusedMode { kModeGamma = 0, kModeCount = 1, kModeRecord = 2 };
+struct TcOut {
+  long long* count;    // [n_live][kFusedMaxChunks][nb3], written by count, read by record
+  long long* row_ptr;  // [n_modes + 1] row offsets per mode, written by count
+  uint2* pairs;        // (m1, m2) of each entry, written by record
+  double2* factors;    // (c, d) of each entry, written by record
+  int32_t* flags;      // the handle's status word
+};
+template <typename T>
+int launch_fused_cache(const kaldo_crystal* c, const LwParams& p, int mode, const double* omega,
+                       const double* vel, const float4* modef, const uint8_t* phys,
+                       const uint8_t* sel, const double* evec, typename Cx<T>::type* eta,
+                       typename Cx<T>::type* phase_tab, int32_t* qlist, int64_t n_subset, TcOut tc,
+                       hipStream_t st);
 template <typename T>
 int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* vel,
                  const float4* modef, const double* occ, const uint8_t* phys, const uint8_t* sel,

@@ -65,7 +65,14 @@ __global__ void lw_fused_finish(int n_modes, int nb3, const uint8_t* __restrict_
   gamma[m] = scale * acc;
 }
 
-template <int NB, typename T>
+// MODE (FusedMode): kModeGamma sums the linewidth terms into `part`;
+// kModeCount runs only the sweep's cut decisions and writes the number of
+// passing entries per branch of this work item to tc.count; kModeRecord
+// re-runs the same decisions, projects the passing entries and stores each
+// one's temperature-independent factors at a fixed place of its mode's row:
+// the row start, plus the counts of the earlier chunks, plus its rank among
+// the chunk's entries of that branch in queue order.
+template <int NB, typename T, int MODE = kModeGamma>
 __global__ __launch_bounds__(kFusedThreads)
 __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     LwParams p, int n_rep, const int32_t* __restrict__ rep, const double* __restrict__ omega,
@@ -77,17 +84,23 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     const double* __restrict__ t_coef, const int32_t* __restrict__ e_blk,
     const int32_t* __restrict__ e_bg, const int32_t* __restrict__ blk_d,
     const int32_t* __restrict__ pair_ptr, const int32_t* __restrict__ live_list,
-    const int32_t* __restrict__ n_live_ptr, int n_chunk, double* __restrict__ part) {
+    const int32_t* __restrict__ n_live_ptr, int n_chunk, double* __restrict__ part, TcOut tc) {
   constexpr int NB3 = 3 * NB;
   constexpr int BS = kFusedThreads;
   constexpr int CAP = kFusedCap;
+  constexpr bool kRecord = MODE == kModeRecord;
+  constexpr int NPK = (NB3 + 1) / 2;  // branch counters packed two per int (16 bits each)
   using C = typename Cx<T>::type;
   extern __shared__ double2 smem[];
   C* at = reinterpret_cast<C*>(smem);  // [n_blk][9][NB3]
   __shared__ int rq_q1[CAP];
   __shared__ int rq_q2[CAP];
   __shared__ int rq_code[CAP];
+  __shared__ int rq_dst[kRecord ? CAP : 1];  // rank of the entry within its branch's share
+  __shared__ long long rbase[NB3];           // where this work item's entries of a branch start
+  __shared__ long long rlim[NB3];            // and how many the count pass found
   __shared__ int wave_tot[BS / 64];
+  __shared__ int wave_tot_s[BS / 64][NPK];
   __shared__ double2 phq[64];
   __shared__ double wq64[NB3];
   __shared__ float wqs[NB3];  // FP32 frequencies of q, indexed per candidate
@@ -118,8 +131,18 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     }
     if (tid < NB3) wq64[tid] = omega[q * NB3 + tid];
     if (tid < NB3) wqs[tid] = (float)omega[q * NB3 + tid];
+    if constexpr (kRecord) {
+      if (tid < NB3) {
+        long long b = tc.row_ptr[q * NB3 + tid];
+        for (int c = 0; c < chunk; ++c) b += tc.count[((size_t)kq * kFusedMaxChunks + c) * NB3 + tid];
+        rbase[tid] = b;
+        rlim[tid] = tc.count[((size_t)kq * kFusedMaxChunks + chunk) * NB3 + tid];
+      }
+    }
 
-    // 1. A~_q in LDS
+    // 1. A~_q in LDS (the count pass projects nothing)
+    if constexpr (MODE == kModeCount) __syncthreads();
+    if constexpr (MODE != kModeCount) {
     for (int l = tid; l < n_rep; l += BS) {
       const int32_t* r = rep + 3 * l;
       int m0 = ((a0 * r[0]) % N0 + N0) % N0, m1 = ((a1 * r[1]) % N1 + N1) % N1,
@@ -146,10 +169,17 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
       at[(e_blk[e] * 9 + e_bg[e]) * NB3 + s] = Cx<T>::make((T)re, (T)im);
     }
     __syncthreads();
+    }
 
     double acc[NB3];
+    int cnt[NB3];  // count pass: this thread's passing entries per branch
+    int run[NB3];  // record pass: entries of each branch in the rounds before
 #pragma unroll
-    for (int s = 0; s < NB3; ++s) acc[s] = 0.0;
+    for (int s = 0; s < NB3; ++s) {
+      acc[s] = 0.0;
+      cnt[s] = 0;
+      run[s] = 0;
+    }
 
     // 3. projection of queue entries [0, n)
     auto process = [&](int n) {
@@ -161,9 +191,12 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         const int m1 = q1 * NB3 + s1, m2 = q2 * NB3 + s2;
         double sp, sm;
         widths(p, vel, m1, m2, sp, sm);
-        double w = pair_weight(p, wq64[s], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
-        // the mirrored ordering: same widths (|v1 +- v2| are symmetric), its own cut
-        if (dbl) w += pair_weight(p, wq64[s], omega[m2], omega[m1], occ[m2], occ[m1], sp, sm);
+        double w = 0.0;
+        if constexpr (MODE == kModeGamma) {
+          w = pair_weight(p, wq64[s], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
+          // the mirrored ordering: same widths (|v1 +- v2| are symmetric), its own cut
+          if (dbl) w += pair_weight(p, wq64[s], omega[m2], omega[m1], occ[m2], occ[m1], sp, sm);
+        }
         C x[NB3], y[NB3];
         const C* xs = etaT + ((size_t)q1 * NB3 + s1) * NB3;
         const C* ys = etaT + ((size_t)q2 * NB3 + s2) * NB3;
@@ -203,9 +236,33 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
             }
           }
         }
-        const double c = w * ((double)vr * (double)vr + (double)vi * (double)vi);
+        const double v2 = (double)vr * (double)vr + (double)vi * (double)vi;
+        if constexpr (kRecord) {
+          // a+ (n1 - n2) + 1/2 a- (n1 + n2 + 1) of this ordering plus, when
+          // the entry stands for both, the mirrored one's a+r (n2 - n1) +
+          // 1/2 a-r (n1 + n2 + 1): stored as c (n1 - n2) + d (n1 + n2 + 1)
+          double ap, am;
+          pair_factors(p, wq64[s], omega[m1], omega[m2], sp, sm, ap, am);
+          if (dbl) {
+            double apr, amr;
+            pair_factors(p, wq64[s], omega[m2], omega[m1], sp, sm, apr, amr);
+            ap -= apr;
+            am += amr;
+          }
+          // both passes take the same decisions, so the rank is below the
+          // count; a write outside this work item's share is refused
+          if (rq_dst[r] < rlim[s]) {
+            const long long dst = rbase[s] + rq_dst[r];
+            tc.pairs[dst] = make_uint2((unsigned)m1, (unsigned)m2);
+            tc.factors[dst] = make_double2(v2 * ap, 0.5 * (v2 * am));
+          } else {
+            raise_flag(tc.flags, kFlagCache);
+          }
+        } else {
+          const double c = w * v2;
 #pragma unroll
-        for (int k = 0; k < NB3; ++k) acc[k] += (k == s) ? c : 0.0;
+          for (int k = 0; k < NB3; ++k) acc[k] += (k == s) ? c : 0.0;
+        }
       }
     };
 
@@ -306,6 +363,35 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           count += __popc(b);
         }
       }
+      if constexpr (MODE == kModeCount) {
+#pragma unroll
+        for (int s2 = 0; s2 < NB3; ++s2)
+#pragma unroll
+          for (int s = 0; s < NB3; ++s) cnt[s] += (int)((bits[s2] >> s) & 1u);
+        continue;  // no queue: the round ends here (no barrier was passed)
+      }
+      // record pass: per-branch counts of this thread, packed two per int
+      // (a round holds at most BS * NB3 < 2^16 entries of one branch)
+      int pk[NPK], pk_incl[NPK];
+      if constexpr (kRecord) {
+#pragma unroll
+        for (int k = 0; k < NPK; ++k) pk[k] = 0;
+#pragma unroll
+        for (int s2 = 0; s2 < NB3; ++s2)
+#pragma unroll
+          for (int s = 0; s < NB3; ++s) pk[s >> 1] += (int)((bits[s2] >> s) & 1u) << ((s & 1) * 16);
+#pragma unroll
+        for (int k = 0; k < NPK; ++k) {
+          int v = pk[k];
+#pragma unroll
+          for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(v, off, 64);
+            if (lane >= off) v += t;
+          }
+          pk_incl[k] = v;
+          if (lane == 63) wave_tot_s[wv][k] = v;
+        }
+      }
       // block-wide exclusive scan of count (fixed order)
       int incl = count;
 #pragma unroll
@@ -323,25 +409,72 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         total += t;
       }
       const int my_off = wave_off + incl - count;
+      // record pass: this thread's first rank per branch within the round and
+      // the round's total per branch
+      int s_off[NB3], s_tot[NB3];
+      if constexpr (kRecord) {
+#pragma unroll
+        for (int k = 0; k < NPK; ++k) {
+          int off = 0, tot = 0;
+#pragma unroll
+          for (int w = 0; w < BS / 64; ++w) {
+            const int t = wave_tot_s[w][k];
+            off += (w < wv) ? t : 0;
+            tot += t;
+          }
+          const int ex = off + pk_incl[k] - pk[k];
+          s_off[2 * k] = ex & 0xffff;
+          s_tot[2 * k] = tot & 0xffff;
+          if (2 * k + 1 < NB3) {
+            s_off[2 * k + 1] = (int)((unsigned)ex >> 16);
+            s_tot[2 * k + 1] = (int)((unsigned)tot >> 16);
+          }
+        }
+      }
       __syncthreads();
       int written = 0;
       while (written < total) {
         const int take = min(CAP - fill, total - written);
         if (count > 0 && my_off < written + take && my_off + count > written) {
           int rank = my_off;
+          if constexpr (kRecord) {
+            // the order of the loop below (s'' ascending, then s ascending),
+            // with static indices into the per-branch counters
+            int loc[NB3];
 #pragma unroll
-          for (int s2 = 0; s2 < NB3; ++s2) {
-            unsigned b = bits[s2];
-            while (b) {
-              const int s = __ffs(b) - 1;
-              b &= b - 1;
-              if (rank >= written && rank < written + take) {
-                const int slot = fill + rank - written;
-                rq_q1[slot] = q1;
-                rq_q2[slot] = q2;
-                rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (dbl << 24);
+            for (int s = 0; s < NB3; ++s) loc[s] = 0;
+#pragma unroll
+            for (int s2 = 0; s2 < NB3; ++s2) {
+#pragma unroll
+              for (int s = 0; s < NB3; ++s) {
+                if ((bits[s2] >> s) & 1u) {
+                  if (rank >= written && rank < written + take) {
+                    const int slot = fill + rank - written;
+                    rq_q1[slot] = q1;
+                    rq_q2[slot] = q2;
+                    rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (dbl << 24);
+                    rq_dst[slot] = run[s] + s_off[s] + loc[s];
+                  }
+                  ++loc[s];
+                  ++rank;
+                }
               }
-              ++rank;
+            }
+          } else {
+#pragma unroll
+            for (int s2 = 0; s2 < NB3; ++s2) {
+              unsigned b = bits[s2];
+              while (b) {
+                const int s = __ffs(b) - 1;
+                b &= b - 1;
+                if (rank >= written && rank < written + take) {
+                  const int slot = fill + rank - written;
+                  rq_q1[slot] = q1;
+                  rq_q2[slot] = q2;
+                  rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (dbl << 24);
+                }
+                ++rank;
+              }
             }
           }
         }
@@ -354,8 +487,33 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           __syncthreads();
         }
       }
+      if constexpr (kRecord) {
+#pragma unroll
+        for (int s = 0; s < NB3; ++s) run[s] += s_tot[s];
+      }
+    }
+
+    if constexpr (MODE == kModeCount) {
+      // 4c. entries per branch of this work item (integer sums: any order)
+      __shared__ int cnt_red[BS / 64][NB3];
+#pragma unroll
+      for (int s = 0; s < NB3; ++s) {
+        int v = cnt[s];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) cnt_red[wv][s] = v;
+      }
+      __syncthreads();
+      if (tid < NB3) {
+        long long t = 0;
+#pragma unroll
+        for (int w = 0; w < BS / 64; ++w) t += cnt_red[w][tid];
+        tc.count[((size_t)kq * kFusedMaxChunks + chunk) * NB3 + tid] = t;
+      }
+      return;
     }
     process(fill);
+    if constexpr (kRecord) return;
 
     // 4. fixed-order reduction per branch
 #pragma unroll
@@ -370,6 +528,43 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
       if (tid == 0) part[((size_t)kq * kFusedMaxChunks + chunk) * NB3 + s] = red[0];
     }
   }
+}
+
+// Row pointers of the temperature cache: the entry count of mode (q, s) is
+// the sum over its chunks (0 when q has no live mode), rows in mode order.
+// One workgroup; each thread scans a contiguous run of modes, then one
+// block-wide scan of the runs' sums places them.
+__global__ __launch_bounds__(1024) void tc_rows(int n_modes, int nb3,
+                                                const int32_t* __restrict__ idx_of_q, int n_chunk,
+                                                const long long* __restrict__ count,
+                                                long long* __restrict__ row_ptr) {
+  __shared__ long long sums[1024];
+  const int tid = threadIdx.x;
+  const int per = (n_modes + 1023) / 1024;
+  const int lo = min(n_modes, tid * per), hi = min(n_modes, lo + per);
+  auto mode_count = [&](int m) -> long long {
+    const int q = m / nb3, s = m - q * nb3, k = idx_of_q[q];
+    if (k < 0) return 0;
+    long long t = 0;
+    for (int c = 0; c < n_chunk; ++c) t += count[((size_t)k * kFusedMaxChunks + c) * nb3 + s];
+    return t;
+  };
+  long long own = 0;
+  for (int m = lo; m < hi; ++m) own += mode_count(m);
+  sums[tid] = own;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const long long v = tid >= off ? sums[tid - off] : 0;
+    __syncthreads();
+    sums[tid] += v;
+    __syncthreads();
+  }
+  long long r = sums[tid] - own;
+  for (int m = lo; m < hi; ++m) {
+    row_ptr[m] = r;
+    r += mode_count(m);
+  }
+  if (tid == 1023) row_ptr[n_modes] = sums[1023];
 }
 
 // eta rounded to T and transposed to [q][mode][component].
@@ -389,43 +584,62 @@ size_t fused_lds_bytes(const kaldo_crystal* c, int prec) {
   return (size_t)c->bloch.n_blk * 9 * c->nb3 * cs;
 }
 
-bool fused_supported(const kaldo_crystal* c, int prec) {
+// Static LDS of the kernel besides the A~ tables: the queue, scan and
+// reduction buffers, and for the cache's record pass the per-entry ranks.
+static size_t fused_static_lds(bool record) {
+  const size_t stat = kFusedCap * 12 + kFusedThreads * 8 + 64 * 16 + 64 + 4 * 8 * 4 + 16 * 8;
+  return stat + (record ? kFusedCap * 4 : 0);
+}
+
+static bool fused_fits(const kaldo_crystal* c, int prec, bool record) {
   if (c->nb < 1 || c->nb > 5 || c->n_rep > 64) return false;
-  if (const char* f = std::getenv("KALDO_FORCE_GENERIC"))
-    if (f[0] == '1') return false;
   int dev = 0, lds_max = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return false;
-  // dynamic LDS plus the static queue / scan / reduction buffers
-  const size_t stat = kFusedCap * 12 + kFusedThreads * 8 + 64 * 16 + 64;
-  return fused_lds_bytes(c, prec) + stat <= (size_t)lds_max;
+  return fused_lds_bytes(c, prec) + fused_static_lds(record) <= (size_t)lds_max;
 }
 
-template <typename T>
-int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* vel,
-                 const float4* modef, const double* occ, const uint8_t* phys, const uint8_t* sel,
-                 const double* evec, typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab,
-                 int32_t* qlist, double* part, int64_t n_subset, double scale, double* gamma,
-                 hipStream_t st) {
+bool fused_supported(const kaldo_crystal* c, int prec) {
+  if (const char* f = std::getenv("KALDO_FORCE_GENERIC"))
+    if (f[0] == '1') return false;
+  return fused_fits(c, prec, false);
+}
+bool fused_record_supported(const kaldo_crystal* c, int prec) { return fused_fits(c, prec, true); }
+
+// The fused launch of one mode: tables, live list, chunking and the kernel,
+// then what the mode needs after it (the Gamma finish, or the cache's row
+// pointers).  Count and record passes of one request see the same live list
+// and chunk count, so they make the same cut decisions in the same order.
+template <typename T, int MODE>
+static int launch_fused_impl(const kaldo_crystal* c, const LwParams& p, const double* omega,
+                             const double* vel, const float4* modef, const double* occ,
+                             const uint8_t* phys, const uint8_t* sel, const double* evec,
+                             typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab,
+                             int32_t* qlist, double* part, int64_t n_subset, double scale,
+                             double* gamma, TcOut tc, hipStream_t st) {
   const int nq = p.nq;
   const int n_modes = nq * c->nb3;
   const long ne = (long)n_modes * c->nb3;
-  KALDO_LAUNCH("lw_eta_transpose", lw_eta_transpose<T>, dim3((ne + 255) / 256), dim3(256), 0, st,
-               (long)nq, c->nb3, evec, eta);
-  const long nph = (long)nq * std::max(1, p.n_d);
-  KALDO_LAUNCH("lw_phase_table", lw_phase_table<T>, dim3((nph + 255) / 256), dim3(256), 0, st, nq,
-               p.n_d, p.N[0], p.N[1], p.N[2], c->bloch.dvec, phase_tab);
   int32_t* live_list = qlist;
   int32_t* idx_of_q = qlist + nq;
   int32_t* n_live = qlist + 2 * nq;
+  if (MODE != kModeCount) {
+    KALDO_LAUNCH("lw_eta_transpose", lw_eta_transpose<T>, dim3((ne + 255) / 256), dim3(256), 0, st,
+                 (long)nq, c->nb3, evec, eta);
+    const long nph = (long)nq * std::max(1, p.n_d);
+    KALDO_LAUNCH("lw_phase_table", lw_phase_table<T>, dim3((nph + 255) / 256), dim3(256), 0, st, nq,
+                 p.n_d, p.N[0], p.N[1], p.N[2], c->bloch.dvec, phase_tab);
+  }
   if (n_subset > 0)
     KALDO_LAUNCH("lw_live_q", lw_live_q<>, dim3(1), dim3(1024), 0, st, nq, c->nb3, phys, sel, live_list,
                  idx_of_q, n_live);
   else
     KALDO_LAUNCH("lw_all_q", lw_all_q<>, dim3((nq + 255) / 256), dim3(256), 0, st, nq, live_list,
                  idx_of_q, n_live);
-  const size_t lds = fused_lds_bytes(c, sizeof(T) == 8 ? KALDO_FP64 : KALDO_FP32);
+  // the count pass builds no A~ tables: no dynamic LDS
+  const size_t lds =
+      MODE == kModeCount ? 0 : fused_lds_bytes(c, sizeof(T) == 8 ? KALDO_FP64 : KALDO_FP32);
   const Fc3Bloch& b = c->bloch;
   // Chunks per q from the number of live q-points the host can know of: at
   // most min(N_q, n_subset) (the grid covers that many), estimated as
@@ -438,18 +652,15 @@ int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega,
   // and no chunk shorter than one sweep round (a q sweeps about N_q 3N_b / 2 items)
   const int max_chunks =
       (int)std::max<long>(1, std::min<long>(kFusedMaxChunks, (long)nq * c->nb3 / (2 * kFusedThreads)));
-#define KALDO_FUSED_CASE(NBV)                                                                  \
-  case NBV: {                                                                                  \
-    const int n_chunk =                                                                        \
-        std::min(fused_chunks((int)std::min<long>(guess, 1l << 30), kWorkItems), max_chunks);  \
-    KALDO_LAUNCH("lw_fused", (lw_fused<NBV, T>), dim3((unsigned)(upper * n_chunk)),            \
-                 dim3(kFusedThreads), lds, st, p, c->n_rep, c->d_rep, omega, vel, modef, occ,  \
-                 phys, sel, evec, eta, phase_tab, b.t_ptr, b.t_i, b.t_l2, b.t_coef, b.e_blk,   \
-                 b.e_bg, b.blk_d, b.pair_ptr, live_list, n_live, n_chunk, part);               \
-    KALDO_LAUNCH("lw_fused_finish", lw_fused_finish, dim3((n_modes + 255) / 256), dim3(256), 0, \
-                 st, n_modes, c->nb3, phys, sel, idx_of_q, n_chunk, part, scale, gamma);       \
-    break;                                                                                     \
-  }
+  const int n_chunk =
+      std::min(fused_chunks((int)std::min<long>(guess, 1l << 30), kWorkItems), max_chunks);
+#define KALDO_FUSED_CASE(NBV)                                                                    \
+  case NBV:                                                                                      \
+    KALDO_LAUNCH("lw_fused", (lw_fused<NBV, T, MODE>), dim3((unsigned)(upper * n_chunk)),        \
+                 dim3(kFusedThreads), lds, st, p, c->n_rep, c->d_rep, omega, vel, modef, occ,    \
+                 phys, sel, evec, eta, phase_tab, b.t_ptr, b.t_i, b.t_l2, b.t_coef, b.e_blk,     \
+                 b.e_bg, b.blk_d, b.pair_ptr, live_list, n_live, n_chunk, part, tc);             \
+    break;
   switch (c->nb) {
     KALDO_FUSED_CASE(1)
     KALDO_FUSED_CASE(2)
@@ -461,8 +672,40 @@ int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega,
       return KALDO_EUNSUPPORTED;
   }
 #undef KALDO_FUSED_CASE
+  if (MODE == kModeGamma)
+    KALDO_LAUNCH("lw_fused_finish", lw_fused_finish, dim3((n_modes + 255) / 256), dim3(256), 0, st,
+                 n_modes, c->nb3, phys, sel, idx_of_q, n_chunk, part, scale, gamma);
+  if (MODE == kModeCount)
+    KALDO_LAUNCH("tc_rows", tc_rows, dim3(1), dim3(1024), 0, st, n_modes, c->nb3, idx_of_q, n_chunk,
+                 tc.count, tc.row_ptr);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
+}
+
+template <typename T>
+int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* vel,
+                 const float4* modef, const double* occ, const uint8_t* phys, const uint8_t* sel,
+                 const double* evec, typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab,
+                 int32_t* qlist, double* part, int64_t n_subset, double scale, double* gamma,
+                 hipStream_t st) {
+  return launch_fused_impl<T, kModeGamma>(c, p, omega, vel, modef, occ, phys, sel, evec, eta,
+                                          phase_tab, qlist, part, n_subset, scale, gamma, TcOut{},
+                                          st);
+}
+
+template <typename T>
+int launch_fused_cache(const kaldo_crystal* c, const LwParams& p, int mode, const double* omega,
+                       const double* vel, const float4* modef, const uint8_t* phys,
+                       const uint8_t* sel, const double* evec, typename Cx<T>::type* eta,
+                       typename Cx<T>::type* phase_tab, int32_t* qlist, int64_t n_subset, TcOut tc,
+                       hipStream_t st) {
+  if (mode == kModeCount)
+    return launch_fused_impl<T, kModeCount>(c, p, omega, vel, modef, nullptr, phys, sel, evec, eta,
+                                            phase_tab, qlist, nullptr, n_subset, 0.0, nullptr, tc,
+                                            st);
+  return launch_fused_impl<T, kModeRecord>(c, p, omega, vel, modef, nullptr, phys, sel, evec, eta,
+                                           phase_tab, qlist, nullptr, n_subset, 0.0, nullptr, tc,
+                                           st);
 }
 
 template int launch_fused<float>(const kaldo_crystal*, const LwParams&, const double*,
@@ -473,5 +716,13 @@ template int launch_fused<double>(const kaldo_crystal*, const LwParams&, const d
                                   const double*, const float4*, const double*, const uint8_t*,
                                   const uint8_t*, const double*, double2*, double2*, int32_t*,
                                   double*, int64_t, double, double*, hipStream_t);
+template int launch_fused_cache<float>(const kaldo_crystal*, const LwParams&, int, const double*,
+                                       const double*, const float4*, const uint8_t*,
+                                       const uint8_t*, const double*, float2*, float2*, int32_t*,
+                                       int64_t, TcOut, hipStream_t);
+template int launch_fused_cache<double>(const kaldo_crystal*, const LwParams&, int, const double*,
+                                        const double*, const float4*, const uint8_t*,
+                                        const uint8_t*, const double*, double2*, double2*,
+                                        int32_t*, int64_t, TcOut, hipStream_t);
 
 }  // namespace kaldo

@@ -120,6 +120,15 @@ def lib():
                                         ctypes.c_int32, ctypes.c_double, P, ctypes.c_size_t, P, P,
                                         ctypes.POINTER(ctypes.c_int32), P]
         L.kaldo_linewidths_noalloc_max_bytes.restype = ctypes.c_size_t
+        L.kaldo_tcache_workspace.argtypes = [P, I32P, ctypes.c_int32]
+        L.kaldo_tcache_workspace.restype = ctypes.c_size_t
+        L.kaldo_tcache_build.argtypes = [P, I32P, P, P, P, ctypes.POINTER(Broadening),
+                                         ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_size_t, P,
+                                         ctypes.c_int64, P, P, ctypes.POINTER(ctypes.c_int64), P]
+        L.kaldo_tcache_gamma_workspace.argtypes = [P, I32P]
+        L.kaldo_tcache_gamma_workspace.restype = ctypes.c_size_t
+        L.kaldo_tcache_gamma.argtypes = [P, I32P, P, ctypes.c_double, P, ctypes.c_int64, P, P,
+                                         ctypes.c_int32, F64P, P, ctypes.c_size_t, P, P]
         L.kaldo_star_map.argtypes = [I32P, ctypes.c_int32, P, P, P, P, P]
         L.kaldo_profile_begin.argtypes = []
         L.kaldo_profile_end.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -139,7 +148,8 @@ EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
             "kaldo_surrogate_domain", "kaldo_gate_score", "kaldo_device_status",
             "kaldo_linewidths_noalloc", "kaldo_linewidths_noalloc_max_bytes",
             "kaldo_bte_workspace", "kaldo_scattering_matrix", "kaldo_bte_solve",
-            "kaldo_bte_iterate"]
+            "kaldo_bte_iterate", "kaldo_tcache_workspace", "kaldo_tcache_build",
+            "kaldo_tcache_gamma_workspace", "kaldo_tcache_gamma"]
 
 
 def _check(rc):
@@ -164,6 +174,23 @@ def _dev(t):
         return None
     assert t.is_cuda and t.is_contiguous(), "device tensor expected"
     return ctypes.c_void_p(t.data_ptr())
+
+
+_EMPTY = {}
+
+
+def _sub(t):
+    """Pointer of a modes_subset tensor: NULL only for "no subset" (None); an
+    empty subset gets a valid pointer with a count of 0 (an empty tensor's
+    data pointer is NULL, which the library reads as "all modes")."""
+    if t is None:
+        return None
+    if t.numel() == 0:
+        dev = t.device.index if t.device.index is not None else torch.cuda.current_device()
+        if dev not in _EMPTY:
+            _EMPTY[dev] = torch.zeros(1, dtype=torch.int32, device=t.device)
+        return ctypes.c_void_p(_EMPTY[dev].data_ptr())
+    return _dev(t)
 
 
 def _stream():
@@ -283,7 +310,7 @@ def linewidths(c: Crystal, mesh, omega, evec, vel, temperature, broadening, prec
     b = Broadening.of(broadening)
     sub = None if subset is None else subset.to(torch.int32).contiguous()
     _check(lib().kaldo_linewidths(c.handle, _ptr(m, I32P), _dev(omega), _dev(ev), _dev(vel),
-                                  float(temperature), ctypes.byref(b), int(precision), _dev(sub),
+                                  float(temperature), ctypes.byref(b), int(precision), _sub(sub),
                                   0 if sub is None else int(sub.numel()), _dev(workspace),
                                   int(workspace.numel()), _dev(out), _stream()))
     return out
@@ -306,7 +333,7 @@ def linewidths_noalloc(c: Crystal, mesh, omega, evec, vel, temperature, broadeni
         assert sub.dtype == torch.int32 and sub.is_contiguous()
     _check(lib().kaldo_linewidths_noalloc(c.handle, _ptr(m, I32P), _dev(omega), _dev(ev), _dev(vel),
                                           float(temperature), ctypes.byref(b), int(precision),
-                                          _dev(sub), 0 if sub is None else int(sub.numel()),
+                                          _sub(sub), 0 if sub is None else int(sub.numel()),
                                           _dev(out), _stream()))
     return out
 
@@ -323,7 +350,7 @@ def linewidths_gamma(c: Crystal, omega, evec, temperature, broadening, precision
     sub = None if subset is None else subset.to(torch.int32).contiguous()
     _check(lib().kaldo_linewidths_gamma(c.handle, _dev(omega), _dev(evec.contiguous()),
                                         float(temperature), ctypes.byref(b), int(precision),
-                                        _dev(sub), 0 if sub is None else int(sub.numel()),
+                                        _sub(sub), 0 if sub is None else int(sub.numel()),
                                         _dev(workspace), int(workspace.numel()), _dev(out),
                                         _stream()))
     return out
@@ -402,6 +429,101 @@ def bte_iterate(c: Crystal, mesh, omega, vel, gamma0, temperature, nu_min_thz, m
     return lam, kap, it.value, rc
 
 
+# ------------------------------------------------------------------ temperature sweeps
+
+class TempCache:
+    """Temperature-independent factors of Eq. gamma on cuda (see
+    kaldo_tcache_build): row_ptr int64 [n_modes + 1], pairs int32 [n, 2]
+    (partner modes, read as uint32), factors float64 [n, 2] (c, d)."""
+
+    def __init__(self, mesh, row_ptr, pairs, factors):
+        self.mesh = tuple(int(x) for x in mesh)
+        self.row_ptr = row_ptr
+        self.pairs = pairs
+        self.factors = factors
+
+    @property
+    def n_entries(self):
+        return int(self.pairs.shape[0])
+
+    @property
+    def nbytes(self):
+        return (self.row_ptr.numel() * 8 + self.pairs.numel() * 4 + self.factors.numel() * 8)
+
+
+def tcache_workspace(c: Crystal, mesh, precision=FP64):
+    return int(lib().kaldo_tcache_workspace(c.handle, _ptr(_mesh(mesh), I32P), int(precision)))
+
+
+def tcache_count(c: Crystal, mesh, omega, evec, vel, broadening, precision=FP64, subset=None,
+                 workspace=None, row_ptr=None):
+    """Count pass alone: (row_ptr int64 [n_modes + 1] on cuda, entries)."""
+    m = _mesh(mesh)
+    n_modes = int(np.prod(m)) * c.nb3
+    if workspace is None:
+        workspace = torch.empty(max(tcache_workspace(c, m, precision), 1), dtype=torch.uint8,
+                                device="cuda")
+    if row_ptr is None:
+        row_ptr = torch.empty(n_modes + 1, dtype=torch.int64, device="cuda")
+    ev = _as_real(evec).contiguous()
+    b = Broadening.of(broadening)
+    sub = None if subset is None else subset.to(torch.int32).contiguous()
+    n = ctypes.c_int64()
+    _check(lib().kaldo_tcache_build(c.handle, _ptr(m, I32P), _dev(omega), _dev(ev), _dev(vel),
+                                    ctypes.byref(b), int(precision), _sub(sub),
+                                    0 if sub is None else int(sub.numel()), _dev(workspace),
+                                    int(workspace.numel()), _dev(row_ptr), 0, None, None,
+                                    ctypes.byref(n), _stream()))
+    return row_ptr, n.value
+
+
+def tcache_build(c: Crystal, mesh, omega, evec, vel, broadening, precision=FP64, subset=None,
+                 workspace=None):
+    """TempCache of the modes in `subset` (all modes by default): a count
+    call for the size, then the filling call."""
+    m = _mesh(mesh)
+    if workspace is None:
+        workspace = torch.empty(max(tcache_workspace(c, m, precision), 1), dtype=torch.uint8,
+                                device="cuda")
+    row_ptr, n = tcache_count(c, m, omega, evec, vel, broadening, precision, subset, workspace)
+    pairs = torch.empty(max(n, 1), 2, dtype=torch.int32, device="cuda")
+    factors = torch.empty(max(n, 1), 2, dtype=torch.float64, device="cuda")
+    ev = _as_real(evec).contiguous()
+    b = Broadening.of(broadening)
+    sub = None if subset is None else subset.to(torch.int32).contiguous()
+    got = ctypes.c_int64()
+    _check(lib().kaldo_tcache_build(c.handle, _ptr(m, I32P), _dev(omega), _dev(ev), _dev(vel),
+                                    ctypes.byref(b), int(precision), _sub(sub),
+                                    0 if sub is None else int(sub.numel()), _dev(workspace),
+                                    int(workspace.numel()), _dev(row_ptr), int(pairs.shape[0]),
+                                    _dev(pairs), _dev(factors), ctypes.byref(got), _stream()))
+    assert got.value == n
+    return TempCache(m, row_ptr, pairs[:n], factors[:n])
+
+
+def tcache_gamma_workspace(c: Crystal, mesh):
+    return int(lib().kaldo_tcache_gamma_workspace(c.handle, _ptr(_mesh(mesh), I32P)))
+
+
+def tcache_gamma(c: Crystal, cache: TempCache, omega, nu_min_thz, temperatures, workspace=None,
+                 out=None):
+    """Gamma [n_T, N_q, nb3] (rad/ps) on cuda at each temperature."""
+    m = _mesh(cache.mesh)
+    nq = int(np.prod(m))
+    t = _f64(np.atleast_1d(temperatures))
+    if workspace is None:
+        workspace = torch.empty(max(tcache_gamma_workspace(c, m), 1), dtype=torch.uint8,
+                                device="cuda")
+    if out is None:
+        out = torch.empty(len(t), nq, c.nb3, dtype=torch.float64, device="cuda")
+    n = cache.n_entries
+    _check(lib().kaldo_tcache_gamma(c.handle, _ptr(m, I32P), _dev(omega), float(nu_min_thz),
+                                    _dev(cache.row_ptr), n, _dev(cache.pairs) if n else None,
+                                    _dev(cache.factors) if n else None, len(t), _ptr(t, F64P),
+                                    _dev(workspace), int(workspace.numel()), _dev(out), _stream()))
+    return out
+
+
 # ------------------------------------------------------------------ learned form
 
 def mesh_ibz(lattice, frac, mass, mesh):
@@ -434,7 +556,7 @@ def jdos(c: Crystal, mesh, omega, vel, broadening, subset=None, workspace=None, 
     b = Broadening.of(broadening)
     sub = None if subset is None else subset.to(torch.int32).contiguous()
     _check(lib().kaldo_jdos(c.handle, _ptr(m, I32P), _dev(omega), _dev(vel), ctypes.byref(b),
-                            _dev(sub), 0 if sub is None else int(sub.numel()), _dev(workspace),
+                            _sub(sub), 0 if sub is None else int(sub.numel()), _dev(workspace),
                             int(workspace.numel()), _dev(out[0]), _dev(out[1]), _stream()))
     return out
 

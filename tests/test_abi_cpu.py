@@ -55,6 +55,16 @@ def test_argument_validation_without_device():
     with pytest.raises(K.KaldoError):
         K.phonons_gamma(2, np.array([1.0, -1.0]), np.zeros((6, 1, 6)))
     assert lib.kaldo_device_status(None, None) == -1 and b"NULL" in lib.kaldo_last_error()
+    n = ctypes.c_int64(5)
+    rc = lib.kaldo_tcache_build(None, mesh, None, None, None, ctypes.byref(b), 0, None, 0, None, 0,
+                                None, 0, None, None, ctypes.byref(n), None)
+    assert rc == -1 and b"NULL" in lib.kaldo_last_error()
+    temps = np.array([300.0])
+    rc = lib.kaldo_tcache_gamma(None, mesh, None, 0.1, None, 0, None, None, 1,
+                                temps.ctypes.data_as(K.F64P), None, 0, None, None)
+    assert rc == -1 and b"NULL" in lib.kaldo_last_error()
+    assert lib.kaldo_tcache_workspace(None, mesh, 0) == 0
+    assert lib.kaldo_tcache_gamma_workspace(None, mesh) == 0
 
 
 def test_learned_form_host_checks_without_device():

@@ -1,0 +1,252 @@
+"""GPU temperature cache and sweeps (multi-temperature optimisation of
+"Performance and Scalability"; Eq. gamma, Eq. bose) against the FP64 oracle:
+
+* the cache rows element by element against the oracle's cache (each GPU
+  entry stands for an ordered pair and, for symmetric Phi3, its mirror: the
+  oracle's two ordered entries are merged the same way on the host), counts
+  bit-exact;
+* Gamma(T) from the cache against the oracle's direct Eq. gamma at several
+  temperatures, in one call with batches of 8, 4, 2 and 1;
+* the diamond 15^3 mesh against the stored oracle Gamma at 300 K, and
+  against the GPU's own direct Gamma at other temperatures;
+* the wedge: a cache of the representatives' modes, star-mapped, against
+  the full mesh; edge cases (empty subset, size query, short capacity, bad
+  rows, no temperatures).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import linewidths as olw
+from oracle import phonons as oph
+from oracle import tsweep as ots
+from synthetic import configs, models
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2602_23728_amd import kaldo as K  # noqa: E402
+from paper_2602_23728_amd import learned as L  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+B_ADAPT = configs.Broadening(adaptive=True)
+B_FIXED = configs.Broadening(adaptive=False)
+B_LORENTZ = configs.Broadening(shape=configs.LORENTZ, adaptive=False)
+TEMPS = [20.0, 77.0, 150.0, 300.0, 450.0, 600.0, 900.0, 1200.0, 1500.0, 2000.0, 2500.0, 3000.0,
+         5000.0, 7000.0, 10000.0]                               # 15 = 8 + 4 + 2 + 1
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "diamond-adaptive": (lambda: models.diamond(), (4, 4, 4), B_ADAPT),
+    "random-fixed": (lambda: models.random_cell(11, 2), (3, 4, 5), B_FIXED),
+    "random-lorentz": (lambda: models.random_cell(5, 2), (3, 3, 4), B_LORENTZ),
+    "random3-fixed": (lambda: models.random_cell(7, 3), (3, 3, 3), B_FIXED),
+}
+
+
+def merged_oracle_rows(cache, nb3, half):
+    """The oracle's ordered entries folded as the GPU stores them: with
+    symmetric Phi3 the pair with q1 <lex q2 carries its mirror's terms
+    (c = a+ - a+', d = 1/2 (a- + a-')); pairs with q1 == q2 stay ordered."""
+    rows = []
+    rp = cache["row_ptr"]
+    for mu in range(len(rp) - 1):
+        d = {}
+        for k in range(rp[mu], rp[mu + 1]):
+            m1, m2 = int(cache["m1"][k]), int(cache["m2"][k])
+            ap, am = cache["a_plus"][k], cache["a_minus"][k]
+            q1, q2 = m1 // nb3, m2 // nb3
+            if half and q1 > q2:
+                key, c, dd = (m2, m1), -ap, 0.5 * am
+            else:
+                key, c, dd = (m1, m2), ap, 0.5 * am
+            old = d.get(key, (0.0, 0.0))
+            d[key] = (old[0] + c, old[1] + dd)
+        rows.append(d)
+    return rows
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cache_rows_match_oracle(name):
+    mk, mesh, b = CASES[name]
+    m = mk()
+    c = K.Crystal.from_model(m)
+    om, ev, ve = oph.phonons(m, mesh)
+    tc = K.tcache_build(c, mesh, dev(om), dev(ev), dev(ve), b, K.FP64)
+    c.device_status()
+    rp, pairs, fac = host(tc.row_ptr), host(tc.pairs).astype(np.int64), host(tc.factors)
+    oc = ots.linewidth_cache(m, mesh, om, ev, ve, b)
+    nb3 = om.shape[1]
+    # is Phi3 symmetric in its last two slots (the GPU then merges mirrors)?
+    half = len(oc["m1"]) != rp[-1]
+    rows = merged_oracle_rows(oc, nb3, half)
+    scale = max(np.abs(oc["a_plus"]).max(), np.abs(oc["a_minus"]).max())
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0)
+    for mu, want in enumerate(rows):
+        lo, hi = rp[mu], rp[mu + 1]
+        got = {(int(a), int(bb)): (x, y) for (a, bb), (x, y) in zip(pairs[lo:hi], fac[lo:hi])}
+        assert len(got) == hi - lo, mu                      # no duplicate entry
+        assert set(got) == set(want), mu                    # the same pairs (bit-exact counts)
+        for k, (x, y) in want.items():
+            assert abs(got[k][0] - x) <= 1e-11 * scale and abs(got[k][1] - y) <= 1e-11 * scale
+    # bitwise reproducible
+    tc2 = K.tcache_build(c, mesh, dev(om), dev(ev), dev(ve), b, K.FP64)
+    assert np.array_equal(host(tc2.pairs), host(tc.pairs))
+    assert np.array_equal(host(tc2.factors), host(tc.factors))
+    c.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sweep_matches_oracle_direct_gamma(name):
+    mk, mesh, b = CASES[name]
+    m = mk()
+    c = K.Crystal.from_model(m)
+    om, ev, ve = oph.phonons(m, mesh)
+    tc = K.tcache_build(c, mesh, dev(om), dev(ev), dev(ve), b, K.FP64)
+    g = host(K.tcache_gamma(c, tc, dev(om), b.nu_min_thz, TEMPS))
+    c.device_status()
+    assert g.shape == (len(TEMPS),) + om.shape
+    for k, T in enumerate(TEMPS):
+        want = olw.crystal_linewidths(m, mesh, om, ev, ve, T, b)
+        np.testing.assert_allclose(g[k], want, rtol=1e-10, atol=1e-12 * np.abs(want).max(),
+                                   err_msg=f"T={T}")
+    # one temperature at a time gives the same bits as the batched call
+    for k in (0, 9, 14):
+        g1 = host(K.tcache_gamma(c, tc, dev(om), b.nu_min_thz, [TEMPS[k]]))[0]
+        np.testing.assert_allclose(g1, g[k], rtol=1e-15, atol=0)
+    c.close()
+
+
+def test_fp32_projection_cache():
+    mk, mesh, b = CASES["diamond-adaptive"]
+    m = mk()
+    c = K.Crystal.from_model(m)
+    om, ev, ve = oph.phonons(m, mesh)
+    tc = K.tcache_build(c, mesh, dev(om), dev(ev), dev(ve), b, K.FP32)
+    g = host(K.tcache_gamma(c, tc, dev(om), b.nu_min_thz, [300.0]))[0]
+    want = olw.crystal_linewidths(m, mesh, om, ev, ve, 300.0, b)
+    big = want > 1e-3 * want.max()
+    assert np.max(np.abs(g[big] - want[big]) / want[big]) < 1e-5
+    c.close()
+
+
+def test_c2_sweep_against_stored_oracle_and_direct_gpu():
+    g = np.load(os.path.join(GOLDEN, "c2_oracle.npz"))
+    cfg = configs.CONFIGS["C2"]
+    m = configs.model_for(cfg)
+    c = K.Crystal.from_model(m)
+    om, ev, ve = dev(g["omega"]), dev(g["evec"]), dev(g["vel"])
+    tc = K.tcache_build(c, cfg.mesh, om, ev, ve, cfg.broadening, K.FP64)
+    temps = [100.0, 300.0, 800.0]
+    gs = host(K.tcache_gamma(c, tc, om, cfg.broadening.nu_min_thz, temps))
+    c.device_status()
+    want = g["gamma"]
+    sel = want > 1e-3 * want.max()
+    err = np.max(np.abs(gs[1][sel] - want[sel]) / want[sel])
+    print(f"C2 cache: {tc.n_entries} entries ({tc.nbytes / 1e6:.1f} MB); max rel err at 300 K {err:.3g}")
+    assert err <= 1e-10
+    for k, T in enumerate(temps):
+        direct = host(K.linewidths(c, cfg.mesh, om, ev, ve, T, cfg.broadening, K.FP64))
+        np.testing.assert_allclose(gs[k], direct, rtol=1e-11, atol=1e-13 * direct.max())
+    c.close()
+
+
+def test_wedge_cache_star_maps_to_full_mesh():
+    """Fixed width (adaptive widths of degenerate partners follow a gauge that
+    is not point-symmetric): the representatives' cache, star-mapped, equals
+    the full-mesh sweep."""
+    m = models.diamond()
+    mesh = (8, 8, 8)
+    b = B_FIXED
+    c = K.Crystal.from_model(m)
+    om, ev, ve = (dev(x) for x in oph.phonons(m, mesh))
+    w = L.Wedge(m.lattice, m.frac, m.mass, mesh)
+    sub = dev(w.rep_modes(c.nb3))
+    full = K.tcache_build(c, mesh, om, ev, ve, b, K.FP64)
+    part = K.tcache_build(c, mesh, om, ev, ve, b, K.FP64, subset=sub)
+    assert part.n_entries < full.n_entries / 5
+    temps = [150.0, 300.0]
+    gf = K.tcache_gamma(c, full, om, b.nu_min_thz, temps)
+    gp = K.tcache_gamma(c, part, om, b.nu_min_thz, temps)
+    for k in range(len(temps)):
+        mapped = host(K.star_map(mesh, c.nb3, w.ir_dev, om, gp[k].contiguous()))
+        own = host(K.star_map(mesh, c.nb3, torch.arange(int(np.prod(mesh)), dtype=torch.int32,
+                                                        device="cuda"), om, gf[k].contiguous()))
+        np.testing.assert_allclose(mapped, own, rtol=1e-9, atol=1e-12 * own.max())
+    c.device_status()
+    c.close()
+
+
+def test_edge_cases():
+    m = models.diamond()
+    mesh = (3, 3, 3)
+    c = K.Crystal.from_model(m)
+    om, ev, ve = (dev(x) for x in oph.phonons(m, mesh))
+    n_modes = 27 * 6
+    # empty subset: empty rows
+    tc = K.tcache_build(c, mesh, om, ev, ve, B_FIXED, K.FP64,
+                        subset=torch.zeros(0, dtype=torch.int32, device="cuda"))
+    assert tc.n_entries == 0 and int(host(tc.row_ptr).max()) == 0
+    g = host(K.tcache_gamma(c, tc, om, 0.1, [300.0]))
+    assert np.all(g == 0)
+    # (an empty subset reaches the library as a valid pointer with count 0,
+    # not as NULL = all modes: kaldo_linewidths then writes nothing)
+    out = torch.full((27, 6), 5.0, dtype=torch.float64, device="cuda")
+    K.linewidths(c, mesh, om, ev, ve, 300.0, B_FIXED, K.FP64,
+                 subset=torch.zeros(0, dtype=torch.int32, device="cuda"), out=out)
+    assert float(out.min()) == 5.0 == float(out.max())
+    # size query, then a short capacity
+    rp, n = K.tcache_count(c, mesh, om, ev, ve, B_FIXED, K.FP64)
+    assert n > 0 and int(host(rp)[-1]) == n
+    ws = torch.empty(K.tcache_workspace(c, mesh, K.FP64), dtype=torch.uint8, device="cuda")
+    pairs = torch.empty(n - 1, 2, dtype=torch.int32, device="cuda")
+    fac = torch.empty(n - 1, 2, dtype=torch.float64, device="cuda")
+    import ctypes
+    got = ctypes.c_int64()
+    b = K.Broadening.of(B_FIXED)
+    mm = np.array(mesh, np.int32)
+    evr = torch.view_as_real(ev) if ev.is_complex() else ev
+    rc = K.lib().kaldo_tcache_build(c.handle, mm.ctypes.data_as(K.I32P), K._dev(om), K._dev(evr),
+                                    K._dev(ve), ctypes.byref(b), K.FP64, None, 0, K._dev(ws),
+                                    ws.numel(), K._dev(rp), n - 1, K._dev(pairs), K._dev(fac),
+                                    ctypes.byref(got), K._stream())
+    assert rc == -1 and got.value == n and b"capacity" in K.lib().kaldo_last_error()
+    # BF16X3 has no record pass
+    with pytest.raises(K.KaldoError) as e:
+        K.tcache_build(c, mesh, om, ev, ve, B_FIXED, K.BF16X3)
+    assert e.value.status == -5
+    # no temperatures: nothing to do; a non-positive temperature: EINVAL
+    full = K.tcache_build(c, mesh, om, ev, ve, B_FIXED, K.FP64)
+    out = torch.full((1, 27, 6), 7.0, dtype=torch.float64, device="cuda")
+    K.tcache_gamma(c, full, om, 0.1, np.zeros(0), out=out)
+    assert float(out.min()) == 7.0
+    with pytest.raises(K.KaldoError):
+        K.tcache_gamma(c, full, om, 0.1, [300.0, -1.0])
+    # row pointers beyond the entries: skipped and reported by the status word
+    bad_rp = full.row_ptr.clone()
+    bad_rp[5] = full.n_entries + 100
+    bad = K.TempCache(mesh, bad_rp, full.pairs, full.factors)
+    K.tcache_gamma(c, bad, om, 0.1, [300.0])
+    with pytest.raises(K.KaldoError) as e:
+        c.device_status()
+    assert e.value.status == -1 and "temperature-cache" in str(e.value)
+    # partner index out of range: skipped and reported
+    bad_pairs = full.pairs.clone()
+    bad_pairs[0, 1] = n_modes + 3
+    K.tcache_gamma(c, K.TempCache(mesh, full.row_ptr, bad_pairs, full.factors), om, 0.1, [300.0])
+    with pytest.raises(K.KaldoError):
+        c.device_status()
+    c.close()
