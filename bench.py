@@ -14,11 +14,16 @@ Beside the headline the line carries, each timed on the GPU the same way:
               conductivity difference between the two forms;
   c4          the 512-atom Gamma-point glass: FP32 and BF16x3 projection
               times and their fraction of the FP32 / BF16 matrix-core peak,
-              for the vertex GEMM alone and for the whole projection.
+              for the vertex GEMM alone and for the whole projection;
+  bte_c2      the full BTE on the diamond 15^3 mesh (scattering matrix and
+              its direct inversion);
+  tsweep      Gamma at 16 temperatures from the temperature cache of the
+              headline mesh (and of its irreducible wedge), against the
+              direct path per temperature.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C5]
                     [--precision fp64|fp32|bf16x3] [--no-cpu-baseline]
-                    [--no-extras] [--form plain|learned] [--copy-calibration]
+                    [--no-extras] [--form plain|learned|bte|tsweep] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -50,6 +55,9 @@ MEASURED_TRAFFIC = {
     ("lw_fused", "C5", "fp64"): {"sources": ["lw_fused.hip", "lw_common.h", "common.h"],
                                  "sha256": "768df0d7b0cfe874ee3fc5e5caabe2d55308a1f2dc3b1fc3bd986c8bc1d1d144",
                                  "bytes": 24163433789},
+    ("tc_gamma", "C5", "fp64"): {"sources": ["tcache.hip", "lw_common.h", "common.h"],
+                                 "sha256": "9d025a5f1699a29049b92eb6b685e1a765ed8cab38d285275e23d705edd734af",
+                                 "bytes": 3433888276},
 }
 
 
@@ -91,9 +99,10 @@ def parse(argv=None):
                          "batches until it does)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline step (no FP32, C3 split or C4 legs)")
-    ap.add_argument("--form", default="plain", choices=["plain", "learned", "bte"],
+    ap.add_argument("--form", default="plain", choices=["plain", "learned", "bte", "tsweep"],
                     help="learned: the learned form against plain FP32 (full mesh and wedge); "
-                         "bte: only the full-BTE leg (diamond 15^3)")
+                         "bte: only the full-BTE leg (diamond 15^3); tsweep: only the "
+                         "temperature-sweep leg on --config")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -340,6 +349,82 @@ def bte_leg(K, torch, steps, warmup):
     return out
 
 
+def tsweep_leg(K, torch, cfg, model, c, steps, warmup, n_temps=16, direct_gamma=None):
+    """Temperature sweep from the cache (multi-temperature optimisation):
+    the FP64 cache of the full mesh built once (count + record passes, timed
+    as set-up), then Gamma at n_temps temperatures per step (two batches of
+    8, one pass over the entries each), and the same for the irreducible
+    wedge (cache of the representatives' modes, star-mapped per T).
+    Roofline of tc_gamma: algorithmic HBM bytes per launch = 24 per entry
+    (8-byte partner pair + 16-byte factors) + 8 (N + 1) row pointers + 8 NT N
+    outputs + 8 NT N populations read once, N modes, NT = 8."""
+    from paper_2602_23728_amd import learned as L
+    mesh = cfg.mesh
+    nq = int(np.prod(mesh))
+    n_modes = nq * c.nb3
+    om, ev, ve = K.phonons(c, mesh)
+    b = cfg.broadening
+    temps = np.linspace(100.0, 1600.0, n_temps)
+    ws = torch.empty(K.tcache_workspace(c, mesh, K.FP64), dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    K.lib().kaldo_profile_begin()
+    cache = K.tcache_build(c, mesh, om, ev, ve, b, K.FP64, workspace=ws)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    bprof = profile_read(K)
+    c.device_status()
+    log(f"{cfg.name} tcache: {cache.n_entries} entries ({cache.nbytes / 1e9:.2f} GB), "
+        f"build {build_s * 1e3:.1f} ms")
+    gws = torch.empty(K.tcache_gamma_workspace(c, mesh), dtype=torch.uint8, device="cuda")
+    out = torch.empty(n_temps, nq, c.nb3, dtype=torch.float64, device="cuda")
+
+    def step():
+        K.tcache_gamma(c, cache, om, b.nu_min_thz, temps, workspace=gws, out=out)
+    ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} sweep of {n_temps} T")
+    c.device_status()
+    launches, total = prof["tc_gamma"]
+    avg = total / launches
+    nt = 8
+    alg = 24.0 * cache.n_entries + 8.0 * (n_modes + 1) + 2 * 8.0 * nt * n_modes
+    res = dict(temperatures=n_temps, entries=cache.n_entries, cache_bytes=cache.nbytes,
+               build_ms=build_s * 1e3,
+               build_kernels_ms={k: v[1] for k, v in bprof.items()},
+               ms_per_step=ms, ms_per_temperature=ms / n_temps,
+               modes_temperatures_per_s=n_modes * n_temps / (ms * 1e-3),
+               tc_gamma_ms=avg,
+               roofline=dict(bound="hbm", achieved=alg / (avg * 1e-3) / 1e9, peak=8000.0,
+                             unit="GB/s", frac=alg / (avg * 1e-3) / 1e9 / 8000.0,
+                             traffic=measured_traffic("tc_gamma", cfg.name, "fp64"),
+                             kernel="tc_gamma", algorithmic_bytes=alg),
+               kernels_ms_per_step={k: v[1] / steps for k, v in prof.items()})
+    if direct_gamma is not None:
+        # the sweep at 300 K against the direct FP64 linewidths of the headline
+        g300 = K.tcache_gamma(c, cache, om, b.nu_min_thz, [cfg.temperature])[0]
+        d = direct_gamma
+        sel = d > 1e-3 * d.max()
+        res["max_rel_diff_vs_direct_300K"] = float(((g300 - d).abs()[sel] / d[sel]).max())
+    del cache, out
+    # the wedge: representatives only, star-mapped at every temperature
+    w = L.Wedge(model.lattice, model.frac, model.mass, mesh)
+    sub = torch.from_numpy(w.rep_modes(c.nb3)).cuda()
+    t0 = time.perf_counter()
+    wc = K.tcache_build(c, mesh, om, ev, ve, b, K.FP64, subset=sub, workspace=ws)
+    torch.cuda.synchronize()
+    wbuild = time.perf_counter() - t0
+    g_ir = torch.empty(n_temps, nq, c.nb3, dtype=torch.float64, device="cuda")
+    g_full = torch.empty_like(g_ir)
+
+    def wstep():
+        K.tcache_gamma(c, wc, om, b.nu_min_thz, temps, workspace=gws, out=g_ir)
+        for k in range(n_temps):
+            K.star_map(mesh, c.nb3, w.ir_dev, om, g_ir[k], out=g_full[k])
+    wms, _ = timed(K, torch, wstep, steps, warmup, f"{cfg.name} wedge sweep of {n_temps} T")
+    c.device_status()
+    res["wedge"] = dict(irreducible_q=int(w.n_ir), entries=wc.n_entries, build_ms=wbuild * 1e3,
+                        ms_per_step=wms, ms_per_temperature=wms / n_temps)
+    return res
+
+
 def bench_gamma_point(a, cfg, model, K, torch):
     """--config C4 alone: the Gamma-point leg as the JSON line."""
     leg = gamma_point_leg(a, K, torch, cfg, model, a.steps, a.warmup)
@@ -469,6 +554,21 @@ def main():
         bench_learned(a, cfg, model, c, K, torch)
         c.close()
         return
+    if a.form == "tsweep":
+        step, bufs = crystal_step(K, torch, c, cfg, K.FP64)
+        step()
+        torch.cuda.synchronize()
+        leg = tsweep_leg(K, torch, cfg, model, c, a.steps, a.warmup, direct_gamma=bufs["gam"])
+        print(json.dumps({"metric": METRIC,
+                          "value": leg["modes_temperatures_per_s"], "unit": "mode-temperatures/s",
+                          "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+                          "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic",
+                          "config": {"workload": f"{cfg.name} temperature sweep from the cache"},
+                          "tsweep": leg}))
+        c.close()
+        return
     if a.form == "bte":
         c.close()
         leg = bte_leg(K, torch, a.steps, a.warmup)
@@ -526,6 +626,12 @@ def main():
         extras["c4"] = gamma_point_leg(a, K, torch, c4, configs.model_for(c4),
                                        max(3, a.steps // 4), 2)
         extras["bte_c2"] = bte_leg(K, torch, 3, 1)
+        if prec == K.FP64:
+            leg = tsweep_leg(K, torch, cfg, model, c, max(3, a.steps // 4), 1,
+                             direct_gamma=bufs["gam"])
+            # per temperature, against the direct path's projection kernel
+            leg["speedup_per_temperature_vs_direct"] = avg_ms / leg["ms_per_temperature"]
+            extras["tsweep"] = leg
 
     base, stats, om_o = (None, {}, None)
     if not a.no_cpu_baseline:

@@ -10,12 +10,13 @@
 //   tc_occ     per mode: n(w, T_t) for a batch of NT temperatures, laid out
 //              [mode][NT] so that one entry's populations at every T of the
 //              batch are one contiguous gather per partner
-//   tc_gamma   one wave per mode row: lanes stride over the row's entries
-//              (coalesced 8-byte pair and 16-byte factor loads), gather the
-//              two partners' populations, accumulate NT sums, and reduce
-//              them across the wave in a fixed order (bitwise reproducible)
+//   tc_gamma   one wave per mode row: entries loaded 64 per instruction,
+//              handed to groups of NT/2 lanes of which each gathers two
+//              temperatures of the two partners' populations, and a fixed
+//              butterfly reduces the groups (bitwise reproducible)
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "common.h"
 #include "lw_common.h"
@@ -39,6 +40,16 @@ __global__ void tc_occ(int n_modes, const double* __restrict__ omega, double nu_
   for (int k = 0; k < NT; ++k) occ[(size_t)m * NT + k] = phys ? 1.0 / expm1(w * t.inv_kt_hbar[k]) : 0.0;
 }
 
+// One wave per mode row.  The row's entries are loaded 64 at a time, one
+// per lane (contiguous 512-byte pair and 1 KiB factor reads), U such groups
+// in flight, the next U issued before the current ones are used.  A
+// partner's populations at the batch's NT temperatures are one 8 NT-byte row
+// of the table; a lane gathers 16 bytes of it (two temperatures), so NT/2
+// lanes work on one entry, taking its pair and factors from the lane that
+// loaded it (cross-lane shuffles), and one gather instruction covers 128/NT
+// entries.  Lanes holding the same temperatures are reduced by a fixed
+// butterfly (bitwise reproducible).  A group past the row's end loads zero
+// factors, which add exactly 0.
 template <int NT>
 __global__ __launch_bounds__(256) void tc_gamma(int n_modes, const double* __restrict__ omega,
                                                 double nu_min, const long long* __restrict__ row_ptr,
@@ -46,7 +57,12 @@ __global__ __launch_bounds__(256) void tc_gamma(int n_modes, const double* __res
                                                 const double2* __restrict__ factors,
                                                 const double* __restrict__ occ, double scale,
                                                 double* __restrict__ gamma, int32_t* flags) {
+  constexpr int TPL = NT >= 2 ? 2 : 1;  // temperatures per lane
+  constexpr int LPE = NT / TPL;         // lanes per entry
+  constexpr int EPW = 64 / LPE;         // entries per wave and gather
+  constexpr int U = 4;                  // groups of 64 entries in flight
   const int lane = threadIdx.x & 63;
+  const int sub = lane % LPE, grp = lane / LPE;
   const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (m >= n_modes) return;
   long long lo = row_ptr[m], hi = row_ptr[m + 1];
@@ -54,29 +70,82 @@ __global__ __launch_bounds__(256) void tc_gamma(int n_modes, const double* __res
     if (lane == 0) raise_flag(flags, kFlagCache);
     lo = hi = 0;
   }
-  double acc[NT];
+  double acc[TPL];
 #pragma unroll
-  for (int k = 0; k < NT; ++k) acc[k] = 0.0;
-  for (long long e = lo + lane; e < hi; e += 64) {
-    const uint2 ij = pairs[e];
-    const double2 f = factors[e];
+  for (int t = 0; t < TPL; ++t) acc[t] = 0.0;
+  // one entry: its two partners' populations at this lane's temperatures (a
+  // partner index out of range is skipped and reported)
+  auto add = [&](uint2 ij, double2 f) {
     if (ij.x >= (unsigned)n_modes || ij.y >= (unsigned)n_modes) {
       raise_flag(flags, kFlagCache);
-      continue;
+      return;
     }
-    const double* n1 = occ + (size_t)ij.x * NT;
-    const double* n2 = occ + (size_t)ij.y * NT;
+    if constexpr (TPL == 2) {
+      const double2 a = reinterpret_cast<const double2*>(occ + (size_t)ij.x * NT)[sub];
+      const double2 b = reinterpret_cast<const double2*>(occ + (size_t)ij.y * NT)[sub];
+      acc[0] += f.x * (a.x - b.x) + f.y * ((a.x + b.x) + 1.0);
+      acc[1] += f.x * (a.y - b.y) + f.y * ((a.y + b.y) + 1.0);
+    } else {
+      const double a = occ[ij.x], b = occ[ij.y];
+      acc[0] += f.x * (a - b) + f.y * ((a + b) + 1.0);
+    }
+  };
+  auto load = [&](long long base, uint2* ij, double2* f) {
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-      const double a = n1[k], b = n2[k];
-      acc[k] += f.x * (a - b) + f.y * ((a + b) + 1.0);
+    for (int u = 0; u < U; ++u) {
+      const long long k = base + 64 * u + lane;
+      if (k < hi) {
+        ij[u] = pairs[k];
+        f[u] = factors[k];
+      } else {
+        ij[u] = make_uint2(0u, 0u);
+        f[u] = make_double2(0.0, 0.0);
+      }
+    }
+  };
+  constexpr long long BLK = 64LL * U;
+  uint2 ij[U];
+  double2 f[U];
+  if (lo < hi) load(lo, ij, f);
+  for (long long base = lo; base < hi; base += BLK) {
+    uint2 cij[U];
+    double2 cf[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      cij[u] = ij[u];
+      cf[u] = f[u];
+    }
+    if (base + BLK < hi) load(base + BLK, ij, f);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if constexpr (LPE == 1) {
+        add(cij[u], cf[u]);
+      } else {
+        // group grp takes entry 64 u + EPW j + grp, loaded by lane EPW j + grp
+#pragma unroll
+        for (int j = 0; j < LPE; ++j) {
+          const int src = EPW * j + grp;
+          uint2 e;
+          e.x = (unsigned)__shfl((int)cij[u].x, src, 64);
+          e.y = (unsigned)__shfl((int)cij[u].y, src, 64);
+          double2 g;
+          g.x = __shfl(cf[u].x, src, 64);
+          g.y = __shfl(cf[u].y, src, 64);
+          add(e, g);
+        }
+      }
     }
   }
-  const bool phys = (omega[m] / kTwoPi) >= nu_min;
+  // lanes with the same `sub` hold the same temperatures
 #pragma unroll
-  for (int k = 0; k < NT; ++k) {
-    const double v = wave_sum_fixed(acc[k]);
-    if (lane == 0) gamma[(size_t)k * n_modes + m] = phys ? scale * v : 0.0;
+  for (int t = 0; t < TPL; ++t)
+#pragma unroll
+    for (int off = 32; off >= LPE; off >>= 1) acc[t] += __shfl_xor(acc[t], off, 64);
+  const bool phys = (omega[m] / kTwoPi) >= nu_min;
+  if (lane < LPE) {
+#pragma unroll
+    for (int t = 0; t < TPL; ++t)
+      gamma[(size_t)(TPL * lane + t) * n_modes + m] = phys ? scale * acc[t] : 0.0;
   }
 }
 
@@ -128,9 +197,15 @@ extern "C" int kaldo_tcache_gamma(const kaldo_crystal* c, const int32_t* mesh, c
   auto* rp = reinterpret_cast<const long long*>(row_ptr);
   auto* pr = reinterpret_cast<const uint2*>(pairs);
   auto* fa = reinterpret_cast<const double2*>(factors);
-  // batches of 8, 4, 2 and 1 temperatures (largest first)
+  // batches of 8, 4, 2 and 1 temperatures (largest first; KALDO_TC_BATCH =
+  // 1, 2, 4 or 8 caps the batch)
+  int cap = kTcMaxBatch;
+  if (const char* e = std::getenv("KALDO_TC_BATCH")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4 || v == 8) cap = v;
+  }
   for (int t0 = 0; t0 < n_temps;) {
-    const int left = n_temps - t0;
+    const int left = std::min(n_temps - t0, cap);
     const int nt = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
     TcTemps t{};
     for (int k = 0; k < nt; ++k) t.inv_kt_hbar[k] = kHbar / (kKb * temperatures[t0 + k]);
