@@ -17,6 +17,9 @@ Beside the headline the line carries, each timed on the GPU the same way:
               for the vertex GEMM alone and for the whole projection;
   bte_c2      the full BTE on the diamond 15^3 mesh (scattering matrix and
               its direct inversion);
+  wedge       the irreducible wedge (representatives' modes + star map)
+              against the full mesh on the diamond 15^3 (FP64) and perovskite
+              12^3 (FP32) meshes;
   tsweep      Gamma at 16 temperatures from the temperature cache of the
               headline mesh (and of its irreducible wedge), against the
               direct path per temperature.
@@ -425,6 +428,46 @@ def tsweep_leg(K, torch, cfg, model, c, steps, warmup, n_temps=16, direct_gamma=
     return res
 
 
+def wedge_leg(K, torch, name, prec, steps, warmup):
+    """The irreducible wedge against the full mesh on one configuration (its
+    own adaptive smearing): linewidths of the representatives' modes plus the
+    star map, against every mode; step times, speedup and the conductivity
+    difference (the adaptive widths of degenerate partners follow a gauge
+    that is not point-symmetric)."""
+    from paper_2602_23728_amd import learned as L
+    from synthetic import configs
+    cfg = configs.CONFIGS[name]
+    model = configs.model_for(cfg)
+    c = K.Crystal.from_model(model)
+    mesh = cfg.mesh
+    nq = int(np.prod(mesh))
+    om, ev, ve = K.phonons(c, mesh)
+    w = L.Wedge(model.lattice, model.frac, model.mass, mesh)
+    ws = torch.empty(max(1, K.linewidths_workspace(c, mesh, prec)), dtype=torch.uint8, device="cuda")
+    full = torch.empty(nq, c.nb3, dtype=torch.float64, device="cuda")
+    sub = torch.from_numpy(w.rep_modes(c.nb3)).cuda()
+    g_ir = torch.zeros(nq, c.nb3, dtype=torch.float64, device="cuda")
+    g_w = torch.empty_like(g_ir)
+
+    def s_full():
+        K.linewidths(c, mesh, om, ev, ve, cfg.temperature, cfg.broadening, prec, workspace=ws,
+                     out=full)
+
+    def s_wedge():
+        K.linewidths(c, mesh, om, ev, ve, cfg.temperature, cfg.broadening, prec, subset=sub,
+                     workspace=ws, out=g_ir)
+        K.star_map(mesh, c.nb3, w.ir_dev, om, g_ir, out=g_w)
+    ms_f, _ = timed(K, torch, s_full, steps, warmup, f"{name} full mesh")
+    ms_w, _ = timed(K, torch, s_wedge, steps, warmup, f"{name} wedge")
+    kf = K.kappa_rta(c, mesh, om, ve, full, cfg.temperature, cfg.broadening.nu_min_thz).cpu().numpy()
+    kw = K.kappa_rta(c, mesh, om, ve, g_w, cfg.temperature, cfg.broadening.nu_min_thz).cpu().numpy()
+    c.device_status()
+    c.close()
+    return dict(irreducible_q=int(w.n_ir), q_points=nq, full_ms=ms_f, wedge_ms=ms_w,
+                speedup=ms_f / ms_w, kappa_rel_diff=kappa_rel(kw, kf),
+                precision={K.FP64: "fp64", K.FP32: "fp32"}[prec])
+
+
 def bench_gamma_point(a, cfg, model, K, torch):
     """--config C4 alone: the Gamma-point leg as the JSON line."""
     leg = gamma_point_leg(a, K, torch, cfg, model, a.steps, a.warmup)
@@ -626,6 +669,8 @@ def main():
         extras["c4"] = gamma_point_leg(a, K, torch, c4, configs.model_for(c4),
                                        max(3, a.steps // 4), 2)
         extras["bte_c2"] = bte_leg(K, torch, 3, 1)
+        extras["wedge"] = {"C2": wedge_leg(K, torch, "C2", K.FP64, max(3, a.steps // 4), 1),
+                           "C3": wedge_leg(K, torch, "C3", K.FP32, max(3, a.steps // 4), 1)}
         if prec == K.FP64:
             leg = tsweep_leg(K, torch, cfg, model, c, max(3, a.steps // 4), 1,
                              direct_gamma=bufs["gam"])
