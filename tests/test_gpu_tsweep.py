@@ -164,6 +164,32 @@ def test_c2_sweep_against_stored_oracle_and_direct_gpu():
     c.close()
 
 
+def test_c3_fp32_cache_against_stored_oracle():
+    """The perovskite 12^3 mesh: the FP32 projection cache (its FP64 tables do
+    not fit in LDS: EUNSUPPORTED) against the oracle's FP64 Gamma at 300 K,
+    to the FP32 form's bar."""
+    path = os.path.join(GOLDEN, "c3_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py C3")
+    g = np.load(path)
+    cfg = configs.CONFIGS["C3"]
+    m = configs.model_for(cfg)
+    c = K.Crystal.from_model(m)
+    om, ev, ve = dev(g["omega"]), dev(g["evec"]), dev(g["vel"])
+    with pytest.raises(K.KaldoError) as e:
+        K.tcache_build(c, cfg.mesh, om, ev, ve, cfg.broadening, K.FP64)
+    assert e.value.status == -5
+    tc = K.tcache_build(c, cfg.mesh, om, ev, ve, cfg.broadening, K.FP32)
+    gs = host(K.tcache_gamma(c, tc, om, cfg.broadening.nu_min_thz, [300.0]))[0]
+    c.device_status()
+    want = g["gamma"]
+    sel = want > 1e-3 * want.max()
+    err = np.max(np.abs(gs[sel] - want[sel]) / want[sel])
+    print(f"C3 FP32 cache: {tc.n_entries} entries; max rel err at 300 K {err:.2e}")
+    assert err <= 1e-5
+    c.close()
+
+
 def test_wedge_cache_star_maps_to_full_mesh():
     """Fixed width (adaptive widths of degenerate partners follow a gauge that
     is not point-symmetric): the representatives' cache, star-mapped, equals
