@@ -320,6 +320,44 @@ int kaldo_bte_iterate(const kaldo_crystal* c, const int32_t* mesh, const double*
                       double* kappa, int32_t* iterations, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Isotope scattering, Eq. isotope (Tamura's perturbation theory, "Isotopic
+ * Scattering"):
+ *   gamma_iso(q,s) = pi/(2 N_q) w^2 sum_{q' s'} g(w - w'; sigma')
+ *                    sum_i g_i |sum_a eta*_{ia}(q,s) eta_{ia}(q',s')|^2
+ * The Cartesian sum sits inside the modulus (Tamura's form; it does not
+ * depend on the orientation of the axes, the printed placement outside the
+ * modulus would).  g(x; sigma) is the smearing of Eq. broadening with its
+ * 2 sigma cut; partners and modes below nu_min are excluded; the adaptive
+ * width of a partner is max(sigma_floor, |v(q',s')| h / sqrt(12)) (h^2 the
+ * mean-square mesh step, as for kaldo_linewidths), the rate at which w - w'
+ * varies with q'.  gamma_iso is a linewidth in the convention of Eq. gamma
+ * (the paper adds the two; tau = 1/(2 Gamma), Eq. lifetime).
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes of kaldo_isotope_linewidths (0 on bad arguments). */
+size_t kaldo_isotope_workspace(const kaldo_crystal* c, const int32_t* mesh);
+
+/* kaldo_isotope_linewidths -- gamma_iso of every mode (crystal cells of at
+ * most 5 basis atoms, else KALDO_EINVAL), FP64 throughout, fixed summation
+ * order (bitwise reproducible).
+ *   omega, evec, vel  device, layouts of kaldo_phonons
+ *   g_factor          host double[n_basis]: g_i = sum_iso f (dM/M_i)^2 of
+ *                     each basis atom, finite and >= 0 (the library knows
+ *                     no isotope tables: the caller supplies them)
+ *   broadening        shape, fixed or adaptive width, nu_min (as above)
+ *   accumulate        0: gamma = gamma_iso; 1: gamma += gamma_iso (e.g. onto
+ *                     the anharmonic Gamma of kaldo_linewidths)
+ *   gamma             device double[N_q][3 N_b], rad/ps; modes below nu_min
+ *                     get 0 (accumulate 0) or are left as they are
+ * Non-finite omega, eta or v and imaginary modes above nu_min set the
+ * handle's status word (kaldo_device_status).  Enqueued; returns at once. */
+int kaldo_isotope_linewidths(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
+                             const double* evec, const double* vel, const double* g_factor,
+                             const kaldo_broadening* broadening, int32_t accumulate,
+                             void* workspace, size_t workspace_bytes, double* gamma,
+                             void* stream);
+
+/* ------------------------------------------------------------------------
  * Temperature sweeps.  The paper separates the temperature-invariant part of
  * the calculation from the populations so that a sweep over temperatures
  * reuses the projection of Eq. phi3_proj ("Performance and Scalability",

@@ -1,0 +1,254 @@
+// Isotope (mass-disorder) scattering of a crystal on a Gamma-centred mesh.
+//
+// Paper: Eq. isotope (Tamura's perturbation theory):
+//   gamma_iso(q,s) = pi/(2 N_q) w^2 sum_{q' s'} delta(w - w')
+//                    sum_i g_i |sum_a eta*_{ia}(q,s) eta_{ia}(q',s')|^2
+// with the Cartesian sum inside the modulus (the form that does not depend on
+// the orientation of the Cartesian axes), delta the smearing of Eq.
+// broadening with its 2 sigma cut, partners and modes below nu_min excluded,
+// and for the adaptive width sigma = max(floor, |v(q',s')| h / sqrt(12)) (the
+// rate at which w - w' varies with the summed q').  gamma_iso is a linewidth
+// in the convention of Eq. gamma, to which it adds (Eq. lifetime).
+//
+//   iso_prep     per mode: (w, sigma) record (w NaN below nu_min), eta
+//                transposed to [q][mode][component], input checks
+//   iso_ranges   per (block of partner q-points, branch): the frequency range
+//                of its physical modes and their largest sigma
+//   iso_kernel   one wave per mode: the (block, branch) tiles whose range can
+//                meet the cut (range table in LDS), lanes over the block's
+//                q-points, exact FP64 cut per partner, overlap and smearing
+//                in FP64, per-lane sums in tile order, fixed wave reduction
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "lw_common.h"
+
+namespace kaldo {
+
+constexpr int kIsoMaxBasis = 5;          // 3 N_b <= 16
+constexpr size_t kIsoRangeLds = 48 << 10;  // bytes of range table kept in LDS
+
+struct IsoParams {
+  int nq, nb3, nb, blk, nblk;  // blk: partner q-points per tile (a multiple of 64)
+  int shape, adaptive;
+  double sig_fixed, sig_floor, h2, nu_min, scale;  // scale = pi / (2 N_q)
+  double g[kIsoMaxBasis];
+};
+
+__global__ void iso_prep(IsoParams p, const double* __restrict__ omega, const double* __restrict__ vel,
+                         const double* __restrict__ evec, double2* __restrict__ rec,
+                         double2* __restrict__ etaT, int32_t* flags) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= p.nq * p.nb3) return;
+  const int q = m / p.nb3, s = m - q * p.nb3;
+  const double w = omega[m];
+  const double v0 = vel[3 * (size_t)m], v1 = vel[3 * (size_t)m + 1], v2 = vel[3 * (size_t)m + 2];
+  const bool phys = (w / kTwoPi) >= p.nu_min;
+  double sig = p.sig_fixed;
+  if (p.adaptive) sig = fmax(sqrt((v0 * v0 + v1 * v1 + v2 * v2) * p.h2 / 12.0), p.sig_floor);
+  rec[m] = make_double2(phys ? w : __builtin_nan(""), sig);
+  double chk = (w - w) + (v0 - v0) + (v1 - v1) + (v2 - v2);
+  for (int j = 0; j < p.nb3; ++j) {
+    const size_t src = (((size_t)q * p.nb3 + j) * p.nb3 + s) * 2;
+    const double re = evec[src], im = evec[src + 1];
+    chk += (re - re) + (im - im);
+    etaT[(size_t)m * p.nb3 + j] = make_double2(re, im);
+  }
+  if (!(chk == 0.0)) raise_flag(flags, kFlagNonFinite);
+  if (w < 0.0 && (-w / kTwoPi) >= p.nu_min) raise_flag(flags, kFlagImaginary);
+}
+
+// range[(b * nb3 + s')] = (lowest w, highest w, largest sigma) of the physical
+// modes (q', s') with q' in tile b; an empty tile gets (+inf, -inf, 0).
+__global__ void iso_ranges(IsoParams p, const double2* __restrict__ rec, double* __restrict__ range) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= p.nblk * p.nb3) return;
+  const int b = k / p.nb3, s = k - b * p.nb3;
+  double lo = INFINITY, hi = -INFINITY, smax = 0.0;
+  const int q_end = min(p.nq, (b + 1) * p.blk);
+  for (int q = b * p.blk; q < q_end; ++q) {
+    const double2 r = rec[(size_t)q * p.nb3 + s];
+    if (r.x == r.x) {  // physical (not NaN)
+      lo = fmin(lo, r.x);
+      hi = fmax(hi, r.x);
+      smax = fmax(smax, r.y);
+    }
+  }
+  range[3 * (size_t)k] = lo;
+  range[3 * (size_t)k + 1] = hi;
+  range[3 * (size_t)k + 2] = smax;
+}
+
+template <int NB3>
+__global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __restrict__ rec,
+                                                  const double2* __restrict__ etaT,
+                                                  const double* __restrict__ range,
+                                                  int accumulate, double* __restrict__ gamma) {
+  constexpr int NB = NB3 / 3;
+  extern __shared__ double rng_lds[];  // the range table, [nblk][NB3][3]
+  const int n_modes = p.nq * NB3;
+  const int n_rng = p.nblk * NB3 * 3;
+  for (int k = threadIdx.x; k < n_rng; k += blockDim.x) rng_lds[k] = range[k];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= n_modes) return;
+  const double2 me = rec[m];
+  const double w = me.x;
+  if (!(w == w)) {  // below nu_min: no linewidth
+    if (lane == 0 && !accumulate) gamma[m] = 0.0;
+    return;
+  }
+  double2 e0[NB3];
+#pragma unroll
+  for (int j = 0; j < NB3; ++j) e0[j] = etaT[(size_t)m * NB3 + j];
+  double acc = 0.0;
+  for (int b = 0; b < p.nblk; ++b) {
+    for (int s1 = 0; s1 < NB3; ++s1) {
+      const double* r = rng_lds + 3 * (b * NB3 + s1);
+      const double reach = 2.0 * r[2] * (1.0 + 1e-12);
+      // the tile can hold a partner with |w - w'| < 2 sigma' only if w lies
+      // within reach of its range (an empty tile fails both tests)
+      if (!(w > r[0] - reach && w < r[1] + reach)) continue;
+      for (int q1 = b * p.blk + lane; q1 < min(p.nq, (b + 1) * p.blk); q1 += 64) {
+        const int m1 = q1 * NB3 + s1;
+        const double2 o = rec[m1];
+        const double x = w - o.x;
+        if (!(fabs(x) < 2.0 * o.y)) continue;  // also fails for partners below nu_min (NaN)
+        const double2* e1 = etaT + (size_t)m1 * NB3;
+        double ov = 0.0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          double dr = 0.0, di = 0.0;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const double2 u = e0[3 * i + a], v = e1[3 * i + a];
+            // conj(u) v
+            dr += u.x * v.x + u.y * v.y;
+            di += u.x * v.y - u.y * v.x;
+          }
+          ov += p.g[i] * (dr * dr + di * di);
+        }
+        acc += smear(p.shape, x, o.y) * ov;
+      }
+    }
+  }
+  acc = wave_sum_fixed(acc);
+  if (lane == 0) {
+    const double gi = p.scale * w * w * acc;
+    gamma[m] = accumulate ? gamma[m] + gi : gi;
+  }
+}
+
+struct IsoWs {
+  int blk, nblk;
+  size_t off_rec, off_eta, off_range, total;
+};
+
+static IsoWs iso_ws(long nq, int nb3) {
+  IsoWs w{};
+  // tiles of 64 q-points, widened until the range table fits the LDS budget
+  int blk = 64;
+  while (((nq + blk - 1) / blk) * (size_t)nb3 * 3 * sizeof(double) > kIsoRangeLds) blk += 64;
+  w.blk = blk;
+  w.nblk = (int)((nq + blk - 1) / blk);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += (bytes + 255) / 256 * 256;
+    return r;
+  };
+  w.off_rec = take(sizeof(double2) * nq * nb3);
+  w.off_eta = take(sizeof(double2) * nq * nb3 * nb3);
+  w.off_range = take(sizeof(double) * 3 * (size_t)w.nblk * nb3);
+  w.total = o;
+  return w;
+}
+
+}  // namespace kaldo
+
+using namespace kaldo;
+
+extern "C" size_t kaldo_isotope_workspace(const kaldo_crystal* c, const int32_t* mesh) {
+  if (!c || !mesh || mesh[0] < 1 || mesh[1] < 1 || mesh[2] < 1) return 0;
+  return iso_ws((long)mesh[0] * mesh[1] * mesh[2], c->nb3).total;
+}
+
+extern "C" int kaldo_isotope_linewidths(const kaldo_crystal* c, const int32_t* mesh,
+                                        const double* omega, const double* evec,
+                                        const double* vel, const double* g_factor,
+                                        const kaldo_broadening* b, int32_t accumulate,
+                                        void* workspace, size_t workspace_bytes, double* gamma,
+                                        void* stream) {
+  KALDO_REQUIRE(c && mesh && omega && evec && vel && g_factor && b && gamma,
+                "kaldo_isotope_linewidths: NULL argument");
+  KALDO_REQUIRE(mesh[0] >= 1 && mesh[1] >= 1 && mesh[2] >= 1,
+                "kaldo_isotope_linewidths: mesh must be >= 1");
+  KALDO_REQUIRE(c->nb <= kIsoMaxBasis, "kaldo_isotope_linewidths: more than 5 basis atoms");
+  KALDO_REQUIRE(accumulate == 0 || accumulate == 1, "kaldo_isotope_linewidths: accumulate must be 0 or 1");
+  int rc = check_broadening(b, true);
+  if (rc) return rc;
+  for (int i = 0; i < c->nb; ++i)
+    KALDO_REQUIRE(std::isfinite(g_factor[i]) && g_factor[i] >= 0,
+                  "kaldo_isotope_linewidths: g_factor must be finite and >= 0");
+  const long nq = (long)mesh[0] * mesh[1] * mesh[2];
+  KALDO_REQUIRE(nq <= 65535L, "kaldo_isotope_linewidths: mesh too large (N_q > 65535)");
+  const IsoWs w = iso_ws(nq, c->nb3);
+  KALDO_REQUIRE(workspace && workspace_bytes >= w.total,
+                "kaldo_isotope_linewidths: workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  IsoParams p{};
+  p.nq = (int)nq;
+  p.nb3 = c->nb3;
+  p.nb = c->nb;
+  p.blk = w.blk;
+  p.nblk = w.nblk;
+  p.shape = b->shape;
+  p.adaptive = b->adaptive;
+  p.sig_fixed = kTwoPi * b->sigma_thz;
+  p.sig_floor = kTwoPi * b->sigma_floor_thz;
+  p.nu_min = b->nu_min_thz;
+  p.scale = kPi / (2.0 * (double)nq);
+  {
+    double rc9[9];
+    reciprocal(c->lattice, rc9);
+    double h2 = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) {
+        const double x = rc9[3 * r + k] / mesh[r];
+        h2 += x * x;
+      }
+    p.h2 = h2 / 3.0;
+  }
+  for (int i = 0; i < c->nb; ++i) p.g[i] = g_factor[i];
+  auto* ws = static_cast<unsigned char*>(workspace);
+  auto* rec = reinterpret_cast<double2*>(ws + w.off_rec);
+  auto* eta = reinterpret_cast<double2*>(ws + w.off_eta);
+  auto* range = reinterpret_cast<double*>(ws + w.off_range);
+  const int n_modes = (int)nq * c->nb3;
+  KALDO_LAUNCH("iso_prep", iso_prep, dim3((n_modes + 255) / 256), dim3(256), 0, st, p, omega, vel,
+               evec, rec, eta, c->d_flags);
+  KALDO_LAUNCH("iso_ranges", iso_ranges, dim3((p.nblk * p.nb3 + 255) / 256), dim3(256), 0, st, p,
+               rec, range);
+  const size_t lds = sizeof(double) * 3 * (size_t)p.nblk * p.nb3;
+  const dim3 grid((n_modes + 3) / 4);
+#define KALDO_ISO_CASE(NB3V)                                                                   \
+  case NB3V:                                                                                   \
+    KALDO_LAUNCH("iso_kernel", iso_kernel<NB3V>, grid, dim3(256), lds, st, p, rec, eta, range, \
+                 accumulate, gamma);                                                           \
+    break;
+  switch (c->nb3) {
+    KALDO_ISO_CASE(3)
+    KALDO_ISO_CASE(6)
+    KALDO_ISO_CASE(9)
+    KALDO_ISO_CASE(12)
+    KALDO_ISO_CASE(15)
+    default:
+      set_error("kaldo_isotope_linewidths: unsupported branch count");
+      return KALDO_EUNSUPPORTED;
+  }
+#undef KALDO_ISO_CASE
+  KALDO_HIP(hipGetLastError());
+  return KALDO_OK;
+}

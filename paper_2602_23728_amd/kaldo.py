@@ -120,6 +120,10 @@ def lib():
                                         ctypes.c_int32, ctypes.c_double, P, ctypes.c_size_t, P, P,
                                         ctypes.POINTER(ctypes.c_int32), P]
         L.kaldo_linewidths_noalloc_max_bytes.restype = ctypes.c_size_t
+        L.kaldo_isotope_workspace.argtypes = [P, I32P]
+        L.kaldo_isotope_workspace.restype = ctypes.c_size_t
+        L.kaldo_isotope_linewidths.argtypes = [P, I32P, P, P, P, F64P, ctypes.POINTER(Broadening),
+                                               ctypes.c_int32, P, ctypes.c_size_t, P, P]
         L.kaldo_tcache_workspace.argtypes = [P, I32P, ctypes.c_int32]
         L.kaldo_tcache_workspace.restype = ctypes.c_size_t
         L.kaldo_tcache_build.argtypes = [P, I32P, P, P, P, ctypes.POINTER(Broadening),
@@ -149,7 +153,8 @@ EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
             "kaldo_linewidths_noalloc", "kaldo_linewidths_noalloc_max_bytes",
             "kaldo_bte_workspace", "kaldo_scattering_matrix", "kaldo_bte_solve",
             "kaldo_bte_iterate", "kaldo_tcache_workspace", "kaldo_tcache_build",
-            "kaldo_tcache_gamma_workspace", "kaldo_tcache_gamma"]
+            "kaldo_tcache_gamma_workspace", "kaldo_tcache_gamma", "kaldo_isotope_workspace",
+            "kaldo_isotope_linewidths"]
 
 
 def _check(rc):
@@ -427,6 +432,34 @@ def bte_iterate(c: Crystal, mesh, omega, vel, gamma0, temperature, nu_min_thz, m
     if check:
         _check(rc)
     return lam, kap, it.value, rc
+
+
+# ------------------------------------------------------------------ isotope scattering
+
+def isotope_workspace(c: Crystal, mesh):
+    return int(lib().kaldo_isotope_workspace(c.handle, _ptr(_mesh(mesh), I32P)))
+
+
+def isotope_linewidths(c: Crystal, mesh, omega, evec, vel, g_factor, broadening, out=None,
+                       accumulate=False, workspace=None):
+    """gamma_iso [N_q, nb3] (rad/ps) on cuda (Eq. isotope); with accumulate
+    it is added to `out` (e.g. the anharmonic Gamma) instead."""
+    m = _mesh(mesh)
+    nq = int(np.prod(m))
+    g = _f64(g_factor)
+    assert g.shape == (c.n_basis,), "one g factor per basis atom"
+    if workspace is None:
+        workspace = torch.empty(max(isotope_workspace(c, m), 1), dtype=torch.uint8, device="cuda")
+    if out is None:
+        assert not accumulate, "accumulate needs out"
+        out = torch.empty(nq, c.nb3, dtype=torch.float64, device="cuda")
+    ev = _as_real(evec).contiguous()
+    b = Broadening.of(broadening)
+    _check(lib().kaldo_isotope_linewidths(c.handle, _ptr(m, I32P), _dev(omega), _dev(ev), _dev(vel),
+                                          _ptr(g, F64P), ctypes.byref(b), int(bool(accumulate)),
+                                          _dev(workspace), int(workspace.numel()), _dev(out),
+                                          _stream()))
+    return out
 
 
 # ------------------------------------------------------------------ temperature sweeps

@@ -26,6 +26,35 @@ T_KELVIN = 300.0
 GAUSS = 0
 LORENTZ = 1
 
+# Natural isotope compositions (mass in u, abundance), for the isotope
+# scattering inputs: g = sum_iso f (1 - m_iso / m_avg)^2 of each element
+# (the mass-variance parameter of the paper's "Isotopic Scattering"; the
+# library takes g as an input).
+ISOTOPES = {
+    "Si": ((27.97692653465, 0.92223), (28.9764946649, 0.04685), (29.973770136, 0.03092)),
+    "Pb": ((203.9730440, 0.014), (205.9744657, 0.241), (206.9758973, 0.221),
+           (207.9766525, 0.524)),
+    "Cs": ((132.905451961, 1.0),),
+    "I": ((126.904472, 1.0),),
+}
+
+
+def mass_variance(element: str) -> float:
+    iso = ISOTOPES[element]
+    m_avg = sum(m * f for m, f in iso) / sum(f for _, f in iso)
+    return sum(f * (1.0 - m / m_avg) ** 2 for m, f in iso) / sum(f for _, f in iso)
+
+
+def natural_g(builder: str):
+    """g per basis atom of a model builder's cell with natural compositions:
+    the diamond cell is silicon; the perovskite sites A, B, X x 3 are taken as
+    Cs, Pb and I (masses 133, 207, 127)."""
+    if builder == "diamond":
+        return [mass_variance("Si")] * 2
+    if builder == "perovskite":
+        return [mass_variance("Cs"), mass_variance("Pb")] + [mass_variance("I")] * 3
+    raise ValueError(builder)
+
 
 @dataclasses.dataclass(frozen=True)
 class Broadening:

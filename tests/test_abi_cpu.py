@@ -63,6 +63,11 @@ def test_argument_validation_without_device():
     rc = lib.kaldo_tcache_gamma(None, mesh, None, 0.1, None, 0, None, None, 1,
                                 temps.ctypes.data_as(K.F64P), None, 0, None, None)
     assert rc == -1 and b"NULL" in lib.kaldo_last_error()
+    gf = np.array([2e-4, 2e-4])
+    rc = lib.kaldo_isotope_linewidths(None, mesh, None, None, None, gf.ctypes.data_as(K.F64P),
+                                      ctypes.byref(b), 0, None, 0, None, None)
+    assert rc == -1 and b"NULL" in lib.kaldo_last_error()
+    assert lib.kaldo_isotope_workspace(None, mesh) == 0
     assert lib.kaldo_tcache_workspace(None, mesh, 0) == 0
     assert lib.kaldo_tcache_gamma_workspace(None, mesh) == 0
 

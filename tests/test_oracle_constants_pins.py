@@ -17,7 +17,7 @@ import numpy as np
 
 from oracle import kappa, linewidths, surrogate
 from oracle.constants import HBAR, KAPPA_UNIT, KB, TWO_PI, U
-from synthetic import models
+from synthetic import configs, models
 
 # CODATA 2018: hbar/k_B in K s (exact, from the exact hbar and k_B), the
 # Faraday constant in C/mol and k_B in J/K.
@@ -127,3 +127,11 @@ def test_mode_weights_use_heat_capacity_and_star():
     w = surrogate.mode_weights(np.array([omega_at(1.0, T)]), np.array([[1.0, 2.0, 2.0]]), T,
                                np.array([6.0]))
     assert abs(w[0] - 6.0 * 0.9206735942077923 * 9.0) < 1e-7
+
+
+def test_natural_silicon_mass_variance():
+    """g of natural silicon from its isotope masses and abundances: the
+    literature value is 2.0e-4 (about 2.01e-4); a monoisotopic element gives 0."""
+    assert abs(configs.mass_variance("Si") - 2.007e-4) < 1e-6
+    assert configs.mass_variance("Cs") == 0.0
+    assert len(configs.natural_g("perovskite")) == 5
