@@ -17,6 +17,8 @@ Beside the headline the line carries, each timed on the GPU the same way:
               for the vertex GEMM alone and for the whole projection;
   bte_c2      the full BTE on the diamond 15^3 mesh (scattering matrix and
               its direct inversion);
+  isotope     isotope scattering of every mode of the headline mesh with
+              natural silicon, and the conductivity with it added;
   wedge       the irreducible wedge (representatives' modes + star map)
               against the full mesh on the diamond 15^3 (FP64) and perovskite
               12^3 (FP32) meshes;
@@ -26,7 +28,7 @@ Beside the headline the line carries, each timed on the GPU the same way:
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C5]
                     [--precision fp64|fp32|bf16x3] [--no-cpu-baseline]
-                    [--no-extras] [--form plain|learned|bte|tsweep] [--copy-calibration]
+                    [--no-extras] [--form plain|learned|bte|tsweep|isotope] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -102,10 +104,10 @@ def parse(argv=None):
                          "batches until it does)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline step (no FP32, C3 split or C4 legs)")
-    ap.add_argument("--form", default="plain", choices=["plain", "learned", "bte", "tsweep"],
+    ap.add_argument("--form", default="plain", choices=["plain", "learned", "bte", "tsweep", "isotope"],
                     help="learned: the learned form against plain FP32 (full mesh and wedge); "
                          "bte: only the full-BTE leg (diamond 15^3); tsweep: only the "
-                         "temperature-sweep leg on --config")
+                         "temperature-sweep leg on --config; isotope: only the isotope leg")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -428,6 +430,56 @@ def tsweep_leg(K, torch, cfg, model, c, steps, warmup, n_temps=16, direct_gamma=
     return res
 
 
+def isotope_leg(K, torch, cfg, model, c, steps, warmup, gamma_anh=None):
+    """Isotope scattering (Eq. isotope) of every mode of the configuration with
+    natural compositions: the kernel time, the work it must do (per mode, the
+    physical partners inside their cut, counted on the host by interval
+    stabbing; per partner 8 (3N_b) + 5 N_b + 10 FLOP: the complex overlaps
+    on each atom, their weighted squares and the smearing) against the FP64
+    peak, and the conductivity with gamma_iso added to the anharmonic Gamma."""
+    from synthetic import configs
+    mesh = cfg.mesh
+    om, ev, ve = K.phonons(c, mesh)
+    g = configs.natural_g(cfg.builder)
+    b = cfg.broadening
+    ws = torch.empty(K.isotope_workspace(c, mesh), dtype=torch.uint8, device="cuda")
+    out = torch.empty(om.shape, dtype=torch.float64, device="cuda")
+
+    def step():
+        K.isotope_linewidths(c, mesh, om, ev, ve, g, b, out=out, workspace=ws)
+    ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} isotope")
+    c.device_status()
+    w = om.cpu().numpy().reshape(-1)
+    v = ve.cpu().numpy().reshape(-1, 3)
+    phys = w / (2 * np.pi) >= b.nu_min_thz
+    if b.adaptive:
+        steps2 = np.linalg.inv(np.asarray(model.lattice, float)).T * 2 * np.pi / np.asarray(mesh)[:, None]
+        h2 = float(np.sum(steps2 * steps2) / 3.0)
+        sig = np.maximum(np.sqrt(np.sum(v * v, axis=1) * h2 / 12.0), 2 * np.pi * b.sigma_floor_thz)
+    else:
+        sig = np.full(w.shape, 2 * np.pi * b.sigma_thz)
+    lo = np.sort((w - 2 * sig)[phys])
+    hi = np.sort((w + 2 * sig)[phys])
+    wp = w[phys]
+    passing = float(np.sum(np.searchsorted(lo, wp, "left") - np.searchsorted(hi, wp, "right")))
+    nb = model.n_basis
+    flop = passing * (8 * 3 * nb + 5 * nb + 10)
+    k_ms = prof["iso_kernel"][1] / prof["iso_kernel"][0]
+    res = dict(ms_per_step=ms, iso_kernel_ms=k_ms, g_factor=g, passing_partners=passing,
+               roofline=dict(bound="alu", achieved=flop / (k_ms * 1e-3) / 1e12, peak=FP64_PEAK,
+                             unit="TFLOP/s", frac=flop / (k_ms * 1e-3) / 1e12 / FP64_PEAK,
+                             traffic=None, kernel="iso_kernel", flop_per_launch=flop),
+               gamma_iso_max=float(out.max()), kernels_ms={k: v[1] / v[0] for k, v in prof.items()})
+    if gamma_anh is not None:
+        tot = gamma_anh.clone()
+        K.isotope_linewidths(c, mesh, om, ev, ve, g, b, out=tot, accumulate=True, workspace=ws)
+        k0 = K.kappa_rta(c, mesh, om, ve, gamma_anh, cfg.temperature, b.nu_min_thz).cpu().numpy()
+        k1 = K.kappa_rta(c, mesh, om, ve, tot, cfg.temperature, b.nu_min_thz).cpu().numpy()
+        res["kappa_trace_over_3_anharmonic"] = float(np.trace(k0) / 3)
+        res["kappa_trace_over_3_with_isotopes"] = float(np.trace(k1) / 3)
+    return res
+
+
 def wedge_leg(K, torch, name, prec, steps, warmup):
     """The irreducible wedge against the full mesh on one configuration (its
     own adaptive smearing): linewidths of the representatives' modes plus the
@@ -597,6 +649,18 @@ def main():
         bench_learned(a, cfg, model, c, K, torch)
         c.close()
         return
+    if a.form == "isotope":
+        leg = isotope_leg(K, torch, cfg, model, c, a.steps, a.warmup)
+        n_m = int(np.prod(cfg.mesh)) * c.nb3
+        print(json.dumps({"metric": METRIC, "value": n_m / (leg["ms_per_step"] * 1e-3),
+                          "unit": "modes/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+                          "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic",
+                          "config": {"workload": f"{cfg.name} isotope scattering"},
+                          "isotope": leg}))
+        c.close()
+        return
     if a.form == "tsweep":
         step, bufs = crystal_step(K, torch, c, cfg, K.FP64)
         step()
@@ -669,6 +733,8 @@ def main():
         extras["c4"] = gamma_point_leg(a, K, torch, c4, configs.model_for(c4),
                                        max(3, a.steps // 4), 2)
         extras["bte_c2"] = bte_leg(K, torch, 3, 1)
+        extras["isotope"] = isotope_leg(K, torch, cfg, model, c, max(3, a.steps // 4), 1,
+                                        gamma_anh=bufs["gam"])
         extras["wedge"] = {"C2": wedge_leg(K, torch, "C2", K.FP64, max(3, a.steps // 4), 1),
                            "C3": wedge_leg(K, torch, "C3", K.FP32, max(3, a.steps // 4), 1)}
         if prec == K.FP64:

@@ -14,10 +14,12 @@
 //                transposed to [q][mode][component], input checks
 //   iso_ranges   per (block of partner q-points, branch): the frequency range
 //                of its physical modes and their largest sigma
-//   iso_kernel   one wave per mode: the (block, branch) tiles whose range can
-//                meet the cut (range table in LDS), lanes over the block's
-//                q-points, exact FP64 cut per partner, overlap and smearing
-//                in FP64, per-lane sums in tile order, fixed wave reduction
+//   iso_kernel   one wave per four modes of a branch at consecutive q-points
+//                (they share each partner's loads): the (block, branch) tiles
+//                whose range can meet the cut (range table in LDS), lanes
+//                over the block's q-points, exact FP64 cut per mode and
+//                partner, overlap and smearing in FP64, per-lane sums in tile
+//                order, fixed wave reduction per mode
 #include <algorithm>
 #include <cmath>
 
@@ -80,64 +82,111 @@ __global__ void iso_ranges(IsoParams p, const double2* __restrict__ rec, double*
   range[3 * (size_t)k + 2] = smax;
 }
 
+// Modes per wave: MPW modes of one branch at consecutive q-points (nearly the
+// same frequency, so nearly the same live tiles and passing partners) share
+// every partner's record and eigenvector load.
+constexpr int kIsoMpw = 4;
+
 template <int NB3>
 __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __restrict__ rec,
                                                   const double2* __restrict__ etaT,
                                                   const double* __restrict__ range,
                                                   int accumulate, double* __restrict__ gamma) {
   constexpr int NB = NB3 / 3;
+  constexpr int MPW = kIsoMpw;
   extern __shared__ double rng_lds[];  // the range table, [nblk][NB3][3]
-  const int n_modes = p.nq * NB3;
+  __shared__ double2 e0s[4][MPW][NB3];  // each wave's modes' eigenvectors
   const int n_rng = p.nblk * NB3 * 3;
   for (int k = threadIdx.x; k < n_rng; k += blockDim.x) rng_lds[k] = range[k];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (m >= n_modes) return;
-  const double2 me = rec[m];
-  const double w = me.x;
-  if (!(w == w)) {  // below nu_min: no linewidth
-    if (lane == 0 && !accumulate) gamma[m] = 0.0;
-    return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // wave -> (branch s, first q): waves of one branch are consecutive, so
+  // neighbouring workgroups also scan similar tiles
+  const int groups = (p.nq + MPW - 1) / MPW;
+  const int gid = blockIdx.x * 4 + wv;
+  const bool active = gid < NB3 * groups;
+  const int s = active ? gid / groups : 0;
+  const int q0 = active ? (gid - s * groups) * MPW : 0;
+  double w[MPW];
+  bool live_m[MPW];
+#pragma unroll
+  for (int k = 0; k < MPW; ++k) {
+    const int q = q0 + k;
+    const bool in = active && q < p.nq;
+    const double2 r = in ? rec[(size_t)q * NB3 + s] : make_double2(__builtin_nan(""), 0.0);
+    w[k] = r.x;
+    live_m[k] = in && (r.x == r.x);
+    if (in && lane < NB3) e0s[wv][k][lane] = etaT[((size_t)q * NB3 + s) * NB3 + lane];
   }
-  double2 e0[NB3];
+  __syncthreads();
+  if (!active) return;
+  double acc[MPW];
 #pragma unroll
-  for (int j = 0; j < NB3; ++j) e0[j] = etaT[(size_t)m * NB3 + j];
-  double acc = 0.0;
-  for (int b = 0; b < p.nblk; ++b) {
-    for (int s1 = 0; s1 < NB3; ++s1) {
-      const double* r = rng_lds + 3 * (b * NB3 + s1);
-      const double reach = 2.0 * r[2] * (1.0 + 1e-12);
-      // the tile can hold a partner with |w - w'| < 2 sigma' only if w lies
-      // within reach of its range (an empty tile fails both tests)
-      if (!(w > r[0] - reach && w < r[1] + reach)) continue;
-      for (int q1 = b * p.blk + lane; q1 < min(p.nq, (b + 1) * p.blk); q1 += 64) {
-        const int m1 = q1 * NB3 + s1;
-        const double2 o = rec[m1];
-        const double x = w - o.x;
-        if (!(fabs(x) < 2.0 * o.y)) continue;  // also fails for partners below nu_min (NaN)
-        const double2* e1 = etaT + (size_t)m1 * NB3;
-        double ov = 0.0;
+  for (int k = 0; k < MPW; ++k) acc[k] = 0.0;
+  bool any_live = false;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          double dr = 0.0, di = 0.0;
+  for (int k = 0; k < MPW; ++k) any_live |= live_m[k];
+  if (any_live) {
+    for (int b = 0; b < p.nblk; ++b) {
+      for (int s1 = 0; s1 < NB3; ++s1) {
+        const double* r = rng_lds + 3 * (b * NB3 + s1);
+        const double reach = 2.0 * r[2] * (1.0 + 1e-12);
+        // the tile can hold a partner with |w - w'| < 2 sigma' only if w lies
+        // within reach of its range (an empty tile fails every test)
+        bool tile = false;
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const double2 u = e0[3 * i + a], v = e1[3 * i + a];
-            // conj(u) v
-            dr += u.x * v.x + u.y * v.y;
-            di += u.x * v.y - u.y * v.x;
+        for (int k = 0; k < MPW; ++k) tile |= live_m[k] && w[k] > r[0] - reach && w[k] < r[1] + reach;
+        if (!tile) continue;
+        for (int q1 = b * p.blk + lane; q1 < min(p.nq, (b + 1) * p.blk); q1 += 64) {
+          const int m1 = q1 * NB3 + s1;
+          const double2 o = rec[m1];
+          bool pass[MPW];
+          bool any = false;
+#pragma unroll
+          for (int k = 0; k < MPW; ++k) {
+            pass[k] = live_m[k] && fabs(w[k] - o.x) < 2.0 * o.y;  // fails for partners below nu_min (NaN)
+            any |= pass[k];
           }
-          ov += p.g[i] * (dr * dr + di * di);
+          if (!any) continue;
+          double2 e1[NB3];
+          const double2* e1p = etaT + (size_t)m1 * NB3;
+#pragma unroll
+          for (int j = 0; j < NB3; ++j) e1[j] = e1p[j];
+#pragma unroll
+          for (int k = 0; k < MPW; ++k) {
+            if (!pass[k]) continue;
+            double ov = 0.0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+              double dr = 0.0, di = 0.0;
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                const double2 u = e0s[wv][k][3 * i + a], v = e1[3 * i + a];
+                // conj(u) v
+                dr += u.x * v.x + u.y * v.y;
+                di += u.x * v.y - u.y * v.x;
+              }
+              ov += p.g[i] * (dr * dr + di * di);
+            }
+            const double x = w[k] - o.x;
+            acc[k] += smear(p.shape, x, o.y) * ov;
+          }
         }
-        acc += smear(p.shape, x, o.y) * ov;
       }
     }
   }
-  acc = wave_sum_fixed(acc);
-  if (lane == 0) {
-    const double gi = p.scale * w * w * acc;
-    gamma[m] = accumulate ? gamma[m] + gi : gi;
+#pragma unroll
+  for (int k = 0; k < MPW; ++k) {
+    const double v = wave_sum_fixed(acc[k]);
+    const int q = q0 + k;
+    if (lane == 0 && q < p.nq) {
+      const size_t m = (size_t)q * NB3 + s;
+      if (live_m[k]) {
+        const double gi = p.scale * w[k] * w[k] * v;
+        gamma[m] = accumulate ? gamma[m] + gi : gi;
+      } else if (!accumulate) {
+        gamma[m] = 0.0;  // below nu_min: no linewidth
+      }
+    }
   }
 }
 
@@ -232,7 +281,8 @@ extern "C" int kaldo_isotope_linewidths(const kaldo_crystal* c, const int32_t* m
   KALDO_LAUNCH("iso_ranges", iso_ranges, dim3((p.nblk * p.nb3 + 255) / 256), dim3(256), 0, st, p,
                rec, range);
   const size_t lds = sizeof(double) * 3 * (size_t)p.nblk * p.nb3;
-  const dim3 grid((n_modes + 3) / 4);
+  const long n_waves = (long)c->nb3 * ((nq + kIsoMpw - 1) / kIsoMpw);
+  const dim3 grid((unsigned)((n_waves + 3) / 4));
 #define KALDO_ISO_CASE(NB3V)                                                                   \
   case NB3V:                                                                                   \
     KALDO_LAUNCH("iso_kernel", iso_kernel<NB3V>, grid, dim3(256), lds, st, p, rec, eta, range, \
