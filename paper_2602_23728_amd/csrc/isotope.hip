@@ -40,7 +40,7 @@ struct IsoParams {
 
 __global__ void iso_prep(IsoParams p, const double* __restrict__ omega, const double* __restrict__ vel,
                          const double* __restrict__ evec, double2* __restrict__ rec,
-                         double2* __restrict__ etaT, int32_t* flags) {
+                         double2* __restrict__ inv, double2* __restrict__ etaT, int32_t* flags) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= p.nq * p.nb3) return;
   const int q = m / p.nb3, s = m - q * p.nb3;
@@ -50,6 +50,8 @@ __global__ void iso_prep(IsoParams p, const double* __restrict__ omega, const do
   double sig = p.sig_fixed;
   if (p.adaptive) sig = fmax(sqrt((v0 * v0 + v1 * v1 + v2 * v2) * p.h2 / 12.0), p.sig_floor);
   rec[m] = make_double2(phys ? w : __builtin_nan(""), sig);
+  // 1/sigma and 1/(sqrt(pi) sigma) of the partner, once per mode
+  inv[m] = make_double2(1.0 / sig, 1.0 / (kSqrtPi * sig));
   double chk = (w - w) + (v0 - v0) + (v1 - v1) + (v2 - v2);
   for (int j = 0; j < p.nb3; ++j) {
     const size_t src = (((size_t)q * p.nb3 + j) * p.nb3 + s) * 2;
@@ -89,6 +91,7 @@ constexpr int kIsoMpw = 4;
 
 template <int NB3>
 __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __restrict__ rec,
+                                                  const double2* __restrict__ inv,
                                                   const double2* __restrict__ etaT,
                                                   const double* __restrict__ range,
                                                   int accumulate, double* __restrict__ gamma) {
@@ -147,6 +150,7 @@ __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __
             any |= pass[k];
           }
           if (!any) continue;
+          const double2 iv = inv[m1];
           double2 e1[NB3];
           const double2* e1p = etaT + (size_t)m1 * NB3;
 #pragma unroll
@@ -168,7 +172,14 @@ __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __
               ov += p.g[i] * (dr * dr + di * di);
             }
             const double x = w[k] - o.x;
-            acc[k] += smear(p.shape, x, o.y) * ov;
+            double d;
+            if (p.shape == KALDO_GAUSS) {
+              const double u = x * iv.x;
+              d = exp(-(u * u)) * iv.y;
+            } else {
+              d = smear(p.shape, x, o.y);
+            }
+            acc[k] += d * ov;
           }
         }
       }
@@ -192,7 +203,7 @@ __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __
 
 struct IsoWs {
   int blk, nblk;
-  size_t off_rec, off_eta, off_range, total;
+  size_t off_rec, off_inv, off_eta, off_range, total;
 };
 
 static IsoWs iso_ws(long nq, int nb3) {
@@ -209,6 +220,7 @@ static IsoWs iso_ws(long nq, int nb3) {
     return r;
   };
   w.off_rec = take(sizeof(double2) * nq * nb3);
+  w.off_inv = take(sizeof(double2) * nq * nb3);
   w.off_eta = take(sizeof(double2) * nq * nb3 * nb3);
   w.off_range = take(sizeof(double) * 3 * (size_t)w.nblk * nb3);
   w.total = o;
@@ -273,11 +285,12 @@ extern "C" int kaldo_isotope_linewidths(const kaldo_crystal* c, const int32_t* m
   for (int i = 0; i < c->nb; ++i) p.g[i] = g_factor[i];
   auto* ws = static_cast<unsigned char*>(workspace);
   auto* rec = reinterpret_cast<double2*>(ws + w.off_rec);
+  auto* inv = reinterpret_cast<double2*>(ws + w.off_inv);
   auto* eta = reinterpret_cast<double2*>(ws + w.off_eta);
   auto* range = reinterpret_cast<double*>(ws + w.off_range);
   const int n_modes = (int)nq * c->nb3;
   KALDO_LAUNCH("iso_prep", iso_prep, dim3((n_modes + 255) / 256), dim3(256), 0, st, p, omega, vel,
-               evec, rec, eta, c->d_flags);
+               evec, rec, inv, eta, c->d_flags);
   KALDO_LAUNCH("iso_ranges", iso_ranges, dim3((p.nblk * p.nb3 + 255) / 256), dim3(256), 0, st, p,
                rec, range);
   const size_t lds = sizeof(double) * 3 * (size_t)p.nblk * p.nb3;
@@ -285,7 +298,7 @@ extern "C" int kaldo_isotope_linewidths(const kaldo_crystal* c, const int32_t* m
   const dim3 grid((unsigned)((n_waves + 3) / 4));
 #define KALDO_ISO_CASE(NB3V)                                                                   \
   case NB3V:                                                                                   \
-    KALDO_LAUNCH("iso_kernel", iso_kernel<NB3V>, grid, dim3(256), lds, st, p, rec, eta, range, \
+    KALDO_LAUNCH("iso_kernel", iso_kernel<NB3V>, grid, dim3(256), lds, st, p, rec, inv, eta, range, \
                  accumulate, gamma);                                                           \
     break;
   switch (c->nb3) {
