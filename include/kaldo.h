@@ -358,6 +358,57 @@ int kaldo_isotope_linewidths(const kaldo_crystal* c, const int32_t* mesh, const 
                              void* stream);
 
 /* ------------------------------------------------------------------------
+ * Quasi-harmonic Green-Kubo conductivity ("Quasi-Harmonic Green-Kubo"):
+ *   kappa_ab = 1/V sum_{mu nu} c_{mu nu} v^a_{mu nu} tau_{mu nu} v^b_{nu mu}
+ * (Eq. qhgk for a Gamma-point solid; for a crystal the s != s' pairs of each
+ * q, the interband term of Eq. qhgk_crystal, which adds to kaldo_kappa_rta's
+ * result).  Readings: c_{mu nu} = (hbar/T) w_mu w_nu (n_mu - n_nu)/(w_nu -
+ * w_mu) (the printed prefactor k_B/T would not reduce to Eq. heatcap's c_mu
+ * for w_nu -> w_mu; pairs closer than 1e-4 THz take the mean c); v^a_{mu nu}
+ * = eta_mu^H (dD/dq_a) eta_nu / (2 sqrt(w_mu w_nu)) with dD/dq_a built from
+ * the full separation of the two atoms (lattice vector plus basis offset, the
+ * minimum image within one cell), whose diagonal is the group velocity;
+ * tau_{mu nu} = g/(2((w_mu - w_nu)^2 + g^2)) with g = (Gamma_mu +
+ * Gamma_nu)/2 (Lorentzian, as printed), so tau_{mu mu} = 1/(2 Gamma_mu).
+ * Modes taken: nu >= nu_min and Gamma > 1e-8 max Gamma (as kaldo_kappa_rta).
+ * V: N_q times the cell volume.  FP64, fixed summation order.
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes of kaldo_qhgk_crystal / kaldo_qhgk_gamma. */
+size_t kaldo_qhgk_crystal_workspace(const kaldo_crystal* c, const int32_t* mesh);
+size_t kaldo_qhgk_gamma_workspace(const kaldo_crystal* c);
+
+/* kaldo_qhgk_crystal -- the interband term of Eq. qhgk_crystal (cells of at
+ * most 5 basis atoms).
+ *   frac              host double[n_basis][3] fractional basis positions
+ *                     (the handle keeps none; needed for the separations)
+ *   omega, evec       device, layouts of kaldo_phonons
+ *   gamma             device double[N_q][nb3] linewidths (rad/ps)
+ *   kappa             device double[9] out, W/(m K)
+ * Non-finite omega or Gamma and imaginary modes above nu_min set the handle's
+ * status word.  Enqueued; returns at once. */
+int kaldo_qhgk_crystal(const kaldo_crystal* c, const int32_t* mesh, const double* frac,
+                       const double* omega, const double* evec, const double* gamma,
+                       double temperature, double nu_min_thz, void* workspace,
+                       size_t workspace_bytes, double* kappa, void* stream);
+
+/* kaldo_qhgk_gamma -- Eq. qhgk for a Gamma-point solid (a handle with one
+ * replica), on the FP64 matrix cores.
+ *   frac              host double[n_basis][3] fractional positions, copied to
+ *                     the workspace on `stream`
+ *   omega, evec       device, layouts of kaldo_linewidths_gamma (real E)
+ *   gamma             device double[nb3] linewidths (rad/ps)
+ *   kappa             device double[9] out, W/(m K)
+ *   diffusivity       device double[nb3] out or NULL: D_mu = 1/3 sum_a sum_nu
+ *                     |v^a_{mu nu}|^2 tau_{mu nu} (A^2/ps), 0 for modes not taken
+ * Each bonded pair must have a single image within the force-constant range
+ * (minimum-image separations).  Enqueued; returns at once. */
+int kaldo_qhgk_gamma(const kaldo_crystal* c, const double* frac, const double* omega,
+                     const double* evec, const double* gamma, double temperature,
+                     double nu_min_thz, void* workspace, size_t workspace_bytes, double* kappa,
+                     double* diffusivity, void* stream);
+
+/* ------------------------------------------------------------------------
  * Temperature sweeps.  The paper separates the temperature-invariant part of
  * the calculation from the populations so that a sweep over temperatures
  * reuses the projection of Eq. phi3_proj ("Performance and Scalability",

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkaldo.so")
-SOURCES = ["crystal.hip", "profile.hip", "phonons.hip", "linewidths.hip", "lw_fused.hip", "lw_mfma.hip", "gamma_point.hip", "gp_mfma.hip", "kappa.hip", "surrogate.hip", "noalloc.hip", "bte.hip", "tcache.hip", "isotope.hip",
+SOURCES = ["crystal.hip", "profile.hip", "phonons.hip", "linewidths.hip", "lw_fused.hip", "lw_mfma.hip", "gamma_point.hip", "gp_mfma.hip", "kappa.hip", "surrogate.hip", "noalloc.hip", "bte.hip", "tcache.hip", "isotope.hip", "qhgk.hip",
            "eigen_host.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -124,6 +124,14 @@ def lib():
         L.kaldo_isotope_workspace.restype = ctypes.c_size_t
         L.kaldo_isotope_linewidths.argtypes = [P, I32P, P, P, P, F64P, ctypes.POINTER(Broadening),
                                                ctypes.c_int32, P, ctypes.c_size_t, P, P]
+        L.kaldo_qhgk_crystal_workspace.argtypes = [P, I32P]
+        L.kaldo_qhgk_crystal_workspace.restype = ctypes.c_size_t
+        L.kaldo_qhgk_gamma_workspace.argtypes = [P]
+        L.kaldo_qhgk_gamma_workspace.restype = ctypes.c_size_t
+        L.kaldo_qhgk_crystal.argtypes = [P, I32P, F64P, P, P, P, ctypes.c_double, ctypes.c_double, P,
+                                         ctypes.c_size_t, P, P]
+        L.kaldo_qhgk_gamma.argtypes = [P, F64P, P, P, P, ctypes.c_double, ctypes.c_double, P,
+                                       ctypes.c_size_t, P, P, P]
         L.kaldo_tcache_workspace.argtypes = [P, I32P, ctypes.c_int32]
         L.kaldo_tcache_workspace.restype = ctypes.c_size_t
         L.kaldo_tcache_build.argtypes = [P, I32P, P, P, P, ctypes.POINTER(Broadening),
@@ -154,7 +162,8 @@ EXPORTED = ["kaldo_crystal_create", "kaldo_crystal_destroy", "kaldo_phonons",
             "kaldo_bte_workspace", "kaldo_scattering_matrix", "kaldo_bte_solve",
             "kaldo_bte_iterate", "kaldo_tcache_workspace", "kaldo_tcache_build",
             "kaldo_tcache_gamma_workspace", "kaldo_tcache_gamma", "kaldo_isotope_workspace",
-            "kaldo_isotope_linewidths"]
+            "kaldo_isotope_linewidths", "kaldo_qhgk_crystal_workspace", "kaldo_qhgk_gamma_workspace",
+            "kaldo_qhgk_crystal", "kaldo_qhgk_gamma"]
 
 
 def _check(rc):
@@ -460,6 +469,43 @@ def isotope_linewidths(c: Crystal, mesh, omega, evec, vel, g_factor, broadening,
                                           _dev(workspace), int(workspace.numel()), _dev(out),
                                           _stream()))
     return out
+
+
+# ------------------------------------------------------------------ QHGK conductivity
+
+def qhgk_crystal(c: Crystal, mesh, frac, omega, evec, gamma, temperature, nu_min_thz,
+                 workspace=None, out=None):
+    """Interband term of Eq. qhgk_crystal: kappa [3, 3] float64 on cuda, W/(m K)."""
+    m = _mesh(mesh)
+    fr = _f64(frac).reshape(-1)
+    assert fr.shape == (3 * c.n_basis,)
+    if workspace is None:
+        workspace = torch.empty(max(int(lib().kaldo_qhgk_crystal_workspace(c.handle, _ptr(m, I32P))),
+                                    1), dtype=torch.uint8, device="cuda")
+    if out is None:
+        out = torch.empty(3, 3, dtype=torch.float64, device="cuda")
+    ev = _as_real(evec).contiguous()
+    _check(lib().kaldo_qhgk_crystal(c.handle, _ptr(m, I32P), _ptr(fr, F64P), _dev(omega), _dev(ev),
+                                    _dev(gamma), float(temperature), float(nu_min_thz),
+                                    _dev(workspace), int(workspace.numel()), _dev(out), _stream()))
+    return out
+
+
+def qhgk_gamma(c: Crystal, frac, omega, evec, gamma, temperature, nu_min_thz, diffusivity=True,
+               workspace=None):
+    """Eq. qhgk for a Gamma-point solid: (kappa [3, 3] W/(m K), mode diffusivity
+    [3N] A^2/ps or None) on cuda."""
+    fr = _f64(frac).reshape(-1)
+    assert fr.shape == (3 * c.n_basis,)
+    if workspace is None:
+        workspace = torch.empty(max(int(lib().kaldo_qhgk_gamma_workspace(c.handle)), 1),
+                                dtype=torch.uint8, device="cuda")
+    kap = torch.empty(3, 3, dtype=torch.float64, device="cuda")
+    diff = torch.empty(c.nb3, dtype=torch.float64, device="cuda") if diffusivity else None
+    _check(lib().kaldo_qhgk_gamma(c.handle, _ptr(fr, F64P), _dev(omega), _dev(evec), _dev(gamma),
+                                  float(temperature), float(nu_min_thz), _dev(workspace),
+                                  int(workspace.numel()), _dev(kap), _dev(diff), _stream()))
+    return kap, diff
 
 
 # ------------------------------------------------------------------ temperature sweeps

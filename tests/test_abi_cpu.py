@@ -68,6 +68,14 @@ def test_argument_validation_without_device():
                                       ctypes.byref(b), 0, None, 0, None, None)
     assert rc == -1 and b"NULL" in lib.kaldo_last_error()
     assert lib.kaldo_isotope_workspace(None, mesh) == 0
+    fr = np.zeros(6)
+    rc = lib.kaldo_qhgk_crystal(None, mesh, fr.ctypes.data_as(K.F64P), None, None, None, 300.0, 0.1,
+                                None, 0, None, None)
+    assert rc == -1 and b"NULL" in lib.kaldo_last_error()
+    rc = lib.kaldo_qhgk_gamma(None, fr.ctypes.data_as(K.F64P), None, None, None, 300.0, 0.1, None, 0,
+                              None, None, None)
+    assert rc == -1 and b"NULL" in lib.kaldo_last_error()
+    assert lib.kaldo_qhgk_crystal_workspace(None, mesh) == 0 and lib.kaldo_qhgk_gamma_workspace(None) == 0
     assert lib.kaldo_tcache_workspace(None, mesh, 0) == 0
     assert lib.kaldo_tcache_gamma_workspace(None, mesh) == 0
 
