@@ -17,6 +17,8 @@ Beside the headline the line carries, each timed on the GPU the same way:
               for the vertex GEMM alone and for the whole projection;
   bte_c2      the full BTE on the diamond 15^3 mesh (scattering matrix and
               its direct inversion);
+  qhgk        QHGK conductivity of the 512-atom glass (FP64 matrix cores) and
+              the interband term of the perovskite 12^3 mesh;
   isotope     isotope scattering of every mode of the headline mesh with
               natural silicon, and the conductivity with it added;
   wedge       the irreducible wedge (representatives' modes + star map)
@@ -28,7 +30,7 @@ Beside the headline the line carries, each timed on the GPU the same way:
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C5]
                     [--precision fp64|fp32|bf16x3] [--no-cpu-baseline]
-                    [--no-extras] [--form plain|learned|bte|tsweep|isotope] [--copy-calibration]
+                    [--no-extras] [--form plain|learned|bte|tsweep|isotope|qhgk] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -104,10 +106,11 @@ def parse(argv=None):
                          "batches until it does)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline step (no FP32, C3 split or C4 legs)")
-    ap.add_argument("--form", default="plain", choices=["plain", "learned", "bte", "tsweep", "isotope"],
+    ap.add_argument("--form", default="plain", choices=["plain", "learned", "bte", "tsweep", "isotope", "qhgk"],
                     help="learned: the learned form against plain FP32 (full mesh and wedge); "
                          "bte: only the full-BTE leg (diamond 15^3); tsweep: only the "
-                         "temperature-sweep leg on --config; isotope: only the isotope leg")
+                         "temperature-sweep leg on --config; isotope: only the isotope leg; qhgk: only "
+                         "the QHGK leg")
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -430,6 +433,65 @@ def tsweep_leg(K, torch, cfg, model, c, steps, warmup, n_temps=16, direct_gamma=
     return res
 
 
+def qhgk_leg(K, torch, steps, warmup):
+    """QHGK conductivity: the 512-atom glass (Eq. qhgk: host FP64
+    eigensolver once as set-up, Gamma from the FP32 projection, then the QHGK
+    kernels timed; the dense part is 3 (3N)^3 multiply-adds on
+    the FP64 matrix cores, of which the tiles on and above the diagonal are
+    computed) and the interband term of the perovskite 12^3 mesh
+    (Eq. qhgk_crystal) with its RTA conductivity."""
+    from synthetic import configs
+    out = {}
+    c4 = configs.CONFIGS["C4"]
+    m4 = configs.model_for(c4)
+    cg = K.Crystal.from_model(m4)
+    om_h, E_h = K.phonons_gamma(m4.n_basis, m4.mass, m4.fc2)
+    om, E = torch.as_tensor(om_h).cuda(), torch.as_tensor(E_h).cuda()
+    G = K.linewidths_gamma(cg, om, E, c4.temperature, c4.broadening, K.FP32)
+    ws = torch.empty(int(K.lib().kaldo_qhgk_gamma_workspace(cg.handle)), dtype=torch.uint8,
+                     device="cuda")
+    res = {}
+
+    def step():
+        res["k"] = K.qhgk_gamma(cg, m4.frac, om, E, G, c4.temperature, c4.broadening.nu_min_thz,
+                                workspace=ws)
+    ms, prof = timed(K, torch, step, steps, warmup, "C4 QHGK")
+    cg.device_status()
+    n3 = len(om_h)
+    # executed matrix-core work: the tiles on and above the diagonal (the
+    # products are symmetric in the mode pair), three components, 2 K FLOP
+    # per output element, K = 3N
+    nt = (n3 + 63) // 64
+    flop = nt * (nt + 1) / 2 * 64 * 64 * 3 * 2.0 * n3
+    gemm_ms = prof["qh_gemm"][1] / prof["qh_gemm"][0]
+    out["glass"] = dict(modes=n3, ms_per_step=ms, qh_gemm_ms=gemm_ms,
+                        kappa_trace_over_3=float(torch.trace(res["k"][0]).item() / 3),
+                        roofline=dict(bound="mfma", achieved=flop / (gemm_ms * 1e-3) / 1e12,
+                                      peak=FP64_PEAK, unit="TFLOP/s",
+                                      frac=flop / (gemm_ms * 1e-3) / 1e12 / FP64_PEAK,
+                                      traffic=None, kernel="qh_gemm", flop_per_launch=flop),
+                        kernels_ms={k: v[1] / v[0] for k, v in prof.items()})
+    cg.close()
+    c3 = configs.CONFIGS["C3"]
+    m3 = configs.model_for(c3)
+    cc = K.Crystal.from_model(m3)
+    om3, ev3, ve3 = K.phonons(cc, c3.mesh)
+    G3 = K.linewidths(cc, c3.mesh, om3, ev3, ve3, c3.temperature, c3.broadening, K.FP32)
+    kr = K.kappa_rta(cc, c3.mesh, om3, ve3, G3, c3.temperature, c3.broadening.nu_min_thz)
+
+    def step3():
+        res["ki"] = K.qhgk_crystal(cc, c3.mesh, m3.frac, om3, ev3, G3, c3.temperature,
+                                   c3.broadening.nu_min_thz)
+    ms3, prof3 = timed(K, torch, step3, steps, warmup, "C3 interband")
+    cc.device_status()
+    out["perovskite_interband"] = dict(
+        ms_per_step=ms3, kappa_rta_trace_over_3=float(torch.trace(kr).item() / 3),
+        kappa_interband_trace_over_3=float(torch.trace(res["ki"]).item() / 3),
+        kernels_ms={k: v[1] / v[0] for k, v in prof3.items()})
+    cc.close()
+    return out
+
+
 def isotope_leg(K, torch, cfg, model, c, steps, warmup, gamma_anh=None):
     """Isotope scattering (Eq. isotope) of every mode of the configuration with
     natural compositions: the kernel time, the work it must do (per mode, the
@@ -649,6 +711,18 @@ def main():
         bench_learned(a, cfg, model, c, K, torch)
         c.close()
         return
+    if a.form == "qhgk":
+        c.close()
+        leg = qhgk_leg(K, torch, a.steps, a.warmup)
+        g = leg["glass"]
+        print(json.dumps({"metric": METRIC, "value": g["modes"] / (g["ms_per_step"] * 1e-3),
+                          "unit": "modes/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+                          "ms_per_step": g["ms_per_step"], "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic",
+                          "config": {"workload": "C4 glass QHGK and C3 interband term"},
+                          "qhgk": leg}))
+        return
     if a.form == "isotope":
         leg = isotope_leg(K, torch, cfg, model, c, a.steps, a.warmup)
         n_m = int(np.prod(cfg.mesh)) * c.nb3
@@ -733,6 +807,7 @@ def main():
         extras["c4"] = gamma_point_leg(a, K, torch, c4, configs.model_for(c4),
                                        max(3, a.steps // 4), 2)
         extras["bte_c2"] = bte_leg(K, torch, 3, 1)
+        extras["qhgk"] = qhgk_leg(K, torch, max(3, a.steps // 4), 1)
         extras["isotope"] = isotope_leg(K, torch, cfg, model, c, max(3, a.steps // 4), 1,
                                         gamma_anh=bufs["gam"])
         extras["wedge"] = {"C2": wedge_leg(K, torch, "C2", K.FP64, max(3, a.steps // 4), 1),

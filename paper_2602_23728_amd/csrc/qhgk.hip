@@ -204,18 +204,29 @@ __global__ __launch_bounds__(256) void qh_crystal(QhCrystal p, const double* __r
   if (tid < 6) part[(size_t)q * 6 + tid] = red[0][tid];
 }
 
-// kappa[9] = scale * sum of the n_part partial 6-vectors, in order.
-__global__ void qh_finish(long n_part, const double* __restrict__ part, double scale,
-                          double* __restrict__ kappa) {
-  const int k = threadIdx.x;
+// kappa[9] = scale * sum of the n_part partial 6-vectors: thread t sums the
+// partials t, t + 256, ... in order, then a fixed tree over the threads.
+__global__ __launch_bounds__(256) void qh_finish(long n_part, const double* __restrict__ part,
+                                                 double scale, double* __restrict__ kappa) {
+  __shared__ double red[256][6];
   __shared__ double out[6];
-  if (k < 6) {
-    double s = 0.0;
-    for (long i = 0; i < n_part; ++i) s += part[i * 6 + k];
-    out[k] = scale * s;
-  }
+  const int t = threadIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long i = t; i < n_part; i += 256)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] += part[i * 6 + k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) red[t][k] = acc[k];
   __syncthreads();
-  if (k == 0) {
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) red[t][k] += red[t + w][k];
+    __syncthreads();
+  }
+  if (t < 6) out[t] = scale * red[0][t];
+  __syncthreads();
+  if (t == 0) {
     const int map[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
     for (int i = 0; i < 9; ++i) kappa[i] = out[map[i]];
   }
@@ -316,14 +327,16 @@ __global__ __launch_bounds__(256) void qh_spmm(int n3, const int32_t* __restrict
 constexpr int kQhTile = 64;
 constexpr int kQhK = 16;
 
-// One 64 x 64 tile of mode pairs (mu rows, nu columns) per workgroup, four
+// One 64 x 64 tile of mode pairs (mu rows, nu columns, tile row <= tile
+// column) per workgroup, four
 // waves of 32 x 32: G_a = E^T W_a for a = x, y, z on v_mfma_f64_16x16x4f64
 // (A[row = lane % 16][k = lane / 16], B[k = lane / 16][col = lane % 16];
 // accumulator item r of lane l is row 4 r + l / 16, column l % 16), then per
 // pair v_a = G_a/(2 sqrt(w_mu w_nu)) (the velocity matrix is -i G, and only
 // the products G_a G_b enter), weight c tau, the six products, and
 // tau |v|^2 per pair for the diffusivity, summed along each row in order.
-__global__ __launch_bounds__(256) void qh_gemm(int n3, int n_tiles, const double* __restrict__ E,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void qh_gemm(
+    int n3, int n_tiles, const double* __restrict__ E,
                                                const double* __restrict__ W,
                                                const double* __restrict__ omega,
                                                const double* __restrict__ gamma,
@@ -331,12 +344,25 @@ __global__ __launch_bounds__(256) void qh_gemm(int n3, int n_tiles, const double
                                                double* __restrict__ part,
                                                double* __restrict__ dpart) {
   constexpr int B = kQhTile, K = kQhK;
-  __shared__ double As[K][B];
-  __shared__ double Bs[3][K][B];
-  __shared__ double Dp[B][B + 1];
+  constexpr int PER = K * B / 256;  // staged elements per thread and operand
+  // the operand tiles during the K loop, the epilogue's row buffer after it
+  __shared__ union {
+    struct {
+      double As[K][B];
+      double Bs[3][K][B];
+    } op;
+    double Dp[B][B + 1];
+  } sm;
   __shared__ double red[256][6];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int ti = blockIdx.x / n_tiles, tj = blockIdx.x % n_tiles;
+  // tiles ti <= tj only: G_a is antisymmetric, so every product G_a G_b and
+  // the weights are symmetric in (mu, nu); an off-diagonal tile counts twice
+  int ti = 0, k_rest = blockIdx.x;
+  while (k_rest >= n_tiles - ti) {
+    k_rest -= n_tiles - ti;
+    ++ti;
+  }
+  const int tj = ti + k_rest;
   const int mu0 = ti * B, nu0 = tj * B;
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
   const int lr = lane & 15, lg = lane >> 4;
@@ -347,34 +373,50 @@ __global__ __launch_bounds__(256) void qh_gemm(int n3, int n_tiles, const double
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) acc[a][x][y] = qd4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < n3; k0 += K) {
-    __syncthreads();
-    for (int idx = tid; idx < K * B; idx += 256) {
-      const int kk = idx / B, cc = idx % B;
+  // register staging of one K chunk: element e = tid + 256 u of the K x B
+  // tile is (kk, cc) = (e / B, e % B)
+  double ra[PER], rb[3][PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, kk = e / B, cc = e % B;
       const int c = k0 + kk;
       const bool in_k = c < n3;
-      As[kk][cc] = (in_k && mu0 + cc < n3) ? E[(size_t)c * n3 + mu0 + cc] : 0.0;
+      ra[u] = (in_k && mu0 + cc < n3) ? E[(size_t)c * n3 + mu0 + cc] : 0.0;
 #pragma unroll
       for (int a = 0; a < 3; ++a)
-        Bs[a][kk][cc] = (in_k && nu0 + cc < n3) ? W[((size_t)a * n3 + c) * n3 + nu0 + cc] : 0.0;
+        rb[a][u] = (in_k && nu0 + cc < n3) ? W[((size_t)a * n3 + c) * n3 + nu0 + cc] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < n3; k0 += K) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, kk = e / B, cc = e % B;
+      sm.op.As[kk][cc] = ra[u];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sm.op.Bs[a][kk][cc] = rb[a][u];
     }
     __syncthreads();
+    if (k0 + K < n3) fetch(k0 + K);  // in flight during this chunk's products
 #pragma unroll
     for (int kk = 0; kk < K; kk += 4) {
       double av[2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = As[kk + lg][wm + 16 * x + lr];
+      for (int x = 0; x < 2; ++x) av[x] = sm.op.As[kk + lg][wm + 16 * x + lr];
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
-          const double bv = Bs[a][kk + lg][wn + 16 * y + lr];
+          const double bv = sm.op.Bs[a][kk + lg][wn + 16 * y + lr];
 #pragma unroll
           for (int x = 0; x < 2; ++x)
             acc[a][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv, acc[a][x][y], 0, 0, 0);
         }
     }
   }
+  __syncthreads();  // the operand tiles are dead: Dp reuses their LDS
   // epilogue
   double kap[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -404,7 +446,7 @@ __global__ __launch_bounds__(256) void qh_gemm(int n3, int n_tiles, const double
             dcontrib = tau * (v0 * v0 + v1 * v1 + v2 * v2) * (1.0 / 3.0);
           }
         }
-        Dp[il][jl] = dcontrib;
+        sm.Dp[il][jl] = dcontrib;
       }
 #pragma unroll
   for (int k = 0; k < 6; ++k) red[tid][k] = kap[k];
@@ -415,11 +457,20 @@ __global__ __launch_bounds__(256) void qh_gemm(int n3, int n_tiles, const double
       for (int k = 0; k < 6; ++k) red[tid][k] += red[tid + w][k];
     __syncthreads();
   }
-  if (tid < 6) part[(size_t)blockIdx.x * 6 + tid] = red[0][tid];
+  const double twice = ti == tj ? 1.0 : 2.0;
+  if (tid < 6) part[(size_t)blockIdx.x * 6 + tid] = twice * red[0][tid];
+  // diffusivity shares: row sums for the tile's mu (slot tj), and for an
+  // off-diagonal tile the column sums for its nu (slot ti); every (slot,
+  // mode) is written by exactly one tile
   if (dpart && tid < B) {
     double s = 0.0;
-    for (int j = 0; j < B; ++j) s += Dp[tid][j];
+    for (int j = 0; j < B; ++j) s += sm.Dp[tid][j];
     if (mu0 + tid < n3) dpart[(size_t)tj * n3 + mu0 + tid] = s;
+  } else if (dpart && ti != tj && tid < 2 * B) {
+    const int jl = tid - B;
+    double s = 0.0;
+    for (int i = 0; i < B; ++i) s += sm.Dp[i][jl];
+    if (nu0 + jl < n3) dpart[(size_t)ti * n3 + nu0 + jl] = s;
   }
 }
 
@@ -531,7 +582,7 @@ extern "C" int kaldo_qhgk_crystal(const kaldo_crystal* c, const int32_t* mesh, c
       return KALDO_EUNSUPPORTED;
   }
 #undef KALDO_QH_CASE
-  KALDO_LAUNCH("qh_finish", qh_finish, dim3(1), dim3(64), 0, st, nq, part,
+  KALDO_LAUNCH("qh_finish", qh_finish, dim3(1), dim3(256), 0, st, nq, part,
                kKappaUnit / ((double)nq * c->volume), kappa);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
@@ -574,9 +625,10 @@ extern "C" int kaldo_qhgk_gamma(const kaldo_crystal* c, const double* frac, cons
   KALDO_LAUNCH("qh_csr_fill", qh_csr_fill, dim3(n3), dim3(64), 0, st, n3, c->d_fc2, dfrac, dlat, ptr,
                col, val);
   KALDO_LAUNCH("qh_spmm", qh_spmm, dim3(n3), dim3(256), 0, st, n3, ptr, col, val, evec, Wm);
-  KALDO_LAUNCH("qh_gemm", qh_gemm, dim3(n_tiles * n_tiles), dim3(256), 0, st, n3, n_tiles, evec, Wm,
-               omega, gamma, mode, hk, part, diffusivity ? dpart : nullptr);
-  KALDO_LAUNCH("qh_finish", qh_finish, dim3(1), dim3(64), 0, st, (long)n_tiles * n_tiles, part,
+  const int n_pairs = n_tiles * (n_tiles + 1) / 2;
+  KALDO_LAUNCH("qh_gemm", qh_gemm, dim3(n_pairs), dim3(256), 0, st, n3, n_tiles, evec, Wm, omega,
+               gamma, mode, hk, part, diffusivity ? dpart : nullptr);
+  KALDO_LAUNCH("qh_finish", qh_finish, dim3(1), dim3(256), 0, st, (long)n_pairs, part,
                kKappaUnit / c->volume, kappa);
   if (diffusivity)
     KALDO_LAUNCH("qh_diff_finish", qh_diff_finish, dim3((n3 + 255) / 256), dim3(256), 0, st, n3,
