@@ -41,11 +41,13 @@ constexpr int kFusedThreads = 256;
 constexpr int kFusedCap = 2048;
 
 // Waves per SIMD the register allocation targets: four for the small FP32
-// cells (measured: the latency of the gathers needs the extra wave), the
-// compiler's choice otherwise.
+// cells, three for the small FP64 cells (measured: the latency of the gathers
+// needs the extra waves; 20.8 -> 18.5 ms on the diamond 24^3 mesh in FP64
+// with 14 spilled registers, while four waves spill 53), the compiler's
+// choice otherwise.
 template <int NB, typename T>
 constexpr int fused_waves_per_eu() {
-  return (NB <= 2 && sizeof(T) == 4) ? 4 : 1;
+  return (NB <= 2 && sizeof(T) == 4) ? 4 : (NB <= 2 ? 3 : 1);
 }
 
 // Gamma of the selected modes: the chunk sums of their q in chunk order.
