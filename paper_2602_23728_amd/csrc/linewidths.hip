@@ -34,11 +34,14 @@ namespace kaldo {
 // fails, as the physical mask demands.  Also validates the mode's inputs:
 // a non-finite omega, v or eigenvector column raises kFlagNonFinite, an
 // imaginary mode (omega < 0) with |nu| >= nu_min raises kFlagImaginary.
+// mrec (when given): the FP64 record (w, n), (vx, vy), (vz, 0) the fused
+// kernel reads per partner, three 16-byte loads instead of six scattered ones.
 __global__ void lw_prepare(int n_modes, int nb3, const double* __restrict__ omega,
                            const double* __restrict__ vel, const double* __restrict__ evec,
                            double inv_kt_hbar, double nu_min, double* __restrict__ occ,
                            uint8_t* __restrict__ phys, uint8_t* __restrict__ sel,
-                           float4* __restrict__ modef, int sel_all, int32_t* __restrict__ flags) {
+                           float4* __restrict__ modef, double2* __restrict__ mrec, int sel_all,
+                           int32_t* __restrict__ flags) {
   int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_modes) return;
   double w = omega[m];
@@ -48,6 +51,11 @@ __global__ void lw_prepare(int n_modes, int nb3, const double* __restrict__ omeg
   sel[m] = sel_all ? 1 : 0;
   const double v0 = vel[3 * (size_t)m], v1 = vel[3 * (size_t)m + 1], v2 = vel[3 * (size_t)m + 2];
   modef[m] = make_float4((float)v0, (float)v1, (float)v2, p ? (float)w : __builtin_nanf(""));
+  if (mrec) {
+    mrec[3 * (size_t)m] = make_double2(w, occ[m]);
+    mrec[3 * (size_t)m + 1] = make_double2(v0, v1);
+    mrec[3 * (size_t)m + 2] = make_double2(v2, 0.0);
+  }
   // x - x is 0 for every finite x and NaN otherwise
   double chk = (w - w) + (v0 - v0) + (v1 - v1) + (v2 - v2);
   const int q = m / nb3, s = m - q * nb3;
@@ -232,7 +240,8 @@ static CrystalPath choose_path(const kaldo_crystal* c, int prec) {
 // another path needs are left at 0 and never used).
 struct CrystalWs {
   CrystalPath path;
-  size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, off_phase, off_modef, off_qlist, off_fpart, total;
+  size_t off_occ, off_phys, off_sel, off_eta, off_at, off_partial, off_phase, off_modef, off_qlist,
+      off_fpart, off_mrec, total;
 };
 
 static CrystalWs crystal_ws_for(const kaldo_crystal* c, long nq, int prec, CrystalPath path) {
@@ -260,6 +269,7 @@ static CrystalWs crystal_ws_for(const kaldo_crystal* c, long nq, int prec, Cryst
     w.off_phase = take(cs * nq * (size_t)std::max(1, c->bloch.n_d));
     w.off_qlist = take(sizeof(int32_t) * (2 * nq + 1));
     w.off_fpart = take(sizeof(double) * nq * kFusedMaxChunks * nb3);
+    w.off_mrec = take(sizeof(double2) * 3 * nq * nb3);
   } else {
     w.off_phase = take(sizeof(float2) * nq * (size_t)std::max(1, c->bloch.n_d));
   }
@@ -288,9 +298,10 @@ static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double
   C* at = reinterpret_cast<C*>(ws + w.off_at);
   double* partial = reinterpret_cast<double*>(ws + w.off_partial);
   float4* modef = reinterpret_cast<float4*>(ws + w.off_modef);
+  double2* mrec = w.path == CrystalPath::Fused ? reinterpret_cast<double2*>(ws + w.off_mrec) : nullptr;
   const double inv_kt_hbar = kHbar / (kKb * T_k);
   KALDO_LAUNCH("lw_prepare", lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes,
-               nb3, omega, vel, evec, inv_kt_hbar, b->nu_min_thz, occ, phys, sel, modef,
+               nb3, omega, vel, evec, inv_kt_hbar, b->nu_min_thz, occ, phys, sel, modef, mrec,
                subset ? 0 : 1, c->d_flags);
   if (subset && n_subset > 0)
     KALDO_LAUNCH("lw_select", lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st, subset,
@@ -306,7 +317,7 @@ static int run_crystal(const kaldo_crystal* c, const int32_t* mesh, const double
     C* phase_tab = reinterpret_cast<C*>(ws + w.off_phase);
     int32_t* qlist = reinterpret_cast<int32_t*>(ws + w.off_qlist);
     double* fpart = reinterpret_cast<double*>(ws + w.off_fpart);
-    return launch_fused<T>(c, p, omega, vel, modef, occ, phys, sel, evec, eta, phase_tab, qlist,
+    return launch_fused<T>(c, p, omega, vel, modef, occ, mrec, phys, sel, evec, eta, phase_tab, qlist,
                            fpart, subset ? n_subset : 0, kPrefactor / (double)nq, gamma, st);
   }
   long ne = nq * nb3 * nb3;
@@ -438,10 +449,11 @@ extern "C" int kaldo_tcache_build(const kaldo_crystal* c, const int32_t* mesh, c
   uint8_t* phys = ws + w.off_phys;
   uint8_t* sel = ws + w.off_sel;
   float4* modef = reinterpret_cast<float4*>(ws + w.off_modef);
+  double2* mrec = reinterpret_cast<double2*>(ws + w.off_mrec);
   int32_t* qlist = reinterpret_cast<int32_t*>(ws + w.off_qlist);
   // the populations lw_prepare writes are not used: any temperature will do
   KALDO_LAUNCH("lw_prepare", lw_prepare, dim3((n_modes + 255) / 256), dim3(256), 0, st, n_modes, nb3,
-               omega, vel, evec, kHbar / (kKb * 300.0), b->nu_min_thz, occ, phys, sel, modef,
+               omega, vel, evec, kHbar / (kKb * 300.0), b->nu_min_thz, occ, phys, sel, modef, mrec,
                modes_subset ? 0 : 1, c->d_flags);
   if (modes_subset)
     KALDO_LAUNCH("lw_select", lw_select, dim3((n_subset + 255) / 256), dim3(256), 0, st,
@@ -452,10 +464,10 @@ extern "C" int kaldo_tcache_build(const kaldo_crystal* c, const int32_t* mesh, c
   const int64_t ns = modes_subset ? n_subset : 0;
   auto pass = [&](int mode) {
     if (precision == KALDO_FP64)
-      return launch_fused_cache<double>(c, p, mode, omega, vel, modef, phys, sel, evec,
+      return launch_fused_cache<double>(c, p, mode, omega, vel, modef, mrec, phys, sel, evec,
                                         reinterpret_cast<double2*>(ws + w.off_eta),
                                         reinterpret_cast<double2*>(ws + w.off_phase), qlist, ns, tc, st);
-    return launch_fused_cache<float>(c, p, mode, omega, vel, modef, phys, sel, evec,
+    return launch_fused_cache<float>(c, p, mode, omega, vel, modef, mrec, phys, sel, evec,
                                      reinterpret_cast<float2*>(ws + w.off_eta),
                                      reinterpret_cast<float2*>(ws + w.off_phase), qlist, ns, tc, st);
   };

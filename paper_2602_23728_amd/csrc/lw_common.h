@@ -445,16 +445,16 @@ struct TcOut {
 };
 template <typename T>
 int launch_fused_cache(const kaldo_crystal* c, const LwParams& p, int mode, const double* omega,
-                       const double* vel, const float4* modef, const uint8_t* phys,
-                       const uint8_t* sel, const double* evec, typename Cx<T>::type* eta,
-                       typename Cx<T>::type* phase_tab, int32_t* qlist, int64_t n_subset, TcOut tc,
-                       hipStream_t st);
+                       const double* vel, const float4* modef, const double2* mrec,
+                       const uint8_t* phys, const uint8_t* sel, const double* evec,
+                       typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab, int32_t* qlist,
+                       int64_t n_subset, TcOut tc, hipStream_t st);
 template <typename T>
 int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* vel,
-                 const float4* modef, const double* occ, const uint8_t* phys, const uint8_t* sel,
-                 const double* evec,
-                 typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab, int32_t* qlist,
-                 double* part, int64_t n_subset, double scale, double* gamma, hipStream_t st);
+                 const float4* modef, const double* occ, const double2* mrec, const uint8_t* phys,
+                 const uint8_t* sel, const double* evec, typename Cx<T>::type* eta,
+                 typename Cx<T>::type* phase_tab, int32_t* qlist, double* part, int64_t n_subset,
+                 double scale, double* gamma, hipStream_t st);
 
 // Dense MFMA crystal kernel (lw_mfma.hip).
 bool mfma_supported(const kaldo_crystal* c);

@@ -79,8 +79,9 @@ __global__ __launch_bounds__(kFusedThreads)
 __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     LwParams p, int n_rep, const int32_t* __restrict__ rep, const double* __restrict__ omega,
     const double* __restrict__ vel, const float4* __restrict__ modef, const double* __restrict__ occ,
-    const uint8_t* __restrict__ phys, const uint8_t* __restrict__ sel,
-    const double* __restrict__ evec, const typename Cx<T>::type* __restrict__ etaT,
+    const double2* __restrict__ mrec, const uint8_t* __restrict__ phys,
+    const uint8_t* __restrict__ sel, const double* __restrict__ evec,
+    const typename Cx<T>::type* __restrict__ etaT,
     const typename Cx<T>::type* __restrict__ phase_tab, const int32_t* __restrict__ t_ptr,
     const int32_t* __restrict__ t_i, const int32_t* __restrict__ t_l2,
     const double* __restrict__ t_coef, const int32_t* __restrict__ e_blk,
@@ -189,15 +190,24 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         const int q1 = rq_q1[r], q2 = rq_q2[r];
         const int code = rq_code[r];
         const int s = code & 255, s1 = (code >> 8) & 255, s2 = (code >> 16) & 255, dbl = code >> 24;
-        // FP64 weight of the entry (here, where every lane has an entry)
+        // FP64 weight of the entry (here, where every lane has an entry),
+        // from the partners' packed (w, n, v) records
         const int m1 = q1 * NB3 + s1, m2 = q2 * NB3 + s2;
+        const double2 a1 = mrec[3 * (size_t)m1], b1 = mrec[3 * (size_t)m1 + 1],
+                      c1 = mrec[3 * (size_t)m1 + 2];
+        const double2 a2 = mrec[3 * (size_t)m2], b2 = mrec[3 * (size_t)m2 + 1],
+                      c2 = mrec[3 * (size_t)m2 + 2];
+        const double w1 = a1.x, n1 = a1.y, w2 = a2.x, n2 = a2.y;
         double sp, sm;
-        widths(p, vel, m1, m2, sp, sm);
+        {
+          const double v1[3] = {b1.x, b1.y, c1.x}, v2[3] = {b2.x, b2.y, c2.x};
+          widths_v(p, v1, v2, sp, sm);
+        }
         double w = 0.0;
         if constexpr (MODE == kModeGamma) {
-          w = pair_weight(p, wq64[s], omega[m1], omega[m2], occ[m1], occ[m2], sp, sm);
+          w = pair_weight(p, wq64[s], w1, w2, n1, n2, sp, sm);
           // the mirrored ordering: same widths (|v1 +- v2| are symmetric), its own cut
-          if (dbl) w += pair_weight(p, wq64[s], omega[m2], omega[m1], occ[m2], occ[m1], sp, sm);
+          if (dbl) w += pair_weight(p, wq64[s], w2, w1, n2, n1, sp, sm);
         }
         C x[NB3], y[NB3];
         const C* xs = etaT + ((size_t)q1 * NB3 + s1) * NB3;
@@ -244,10 +254,10 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           // the entry stands for both, the mirrored one's a+r (n2 - n1) +
           // 1/2 a-r (n1 + n2 + 1): stored as c (n1 - n2) + d (n1 + n2 + 1)
           double ap, am;
-          pair_factors(p, wq64[s], omega[m1], omega[m2], sp, sm, ap, am);
+          pair_factors(p, wq64[s], w1, w2, sp, sm, ap, am);
           if (dbl) {
             double apr, amr;
-            pair_factors(p, wq64[s], omega[m2], omega[m1], sp, sm, apr, amr);
+            pair_factors(p, wq64[s], w2, w1, sp, sm, apr, amr);
             ap -= apr;
             am += amr;
           }
@@ -616,7 +626,8 @@ bool fused_record_supported(const kaldo_crystal* c, int prec) { return fused_fit
 template <typename T, int MODE>
 static int launch_fused_impl(const kaldo_crystal* c, const LwParams& p, const double* omega,
                              const double* vel, const float4* modef, const double* occ,
-                             const uint8_t* phys, const uint8_t* sel, const double* evec,
+                             const double2* mrec, const uint8_t* phys, const uint8_t* sel,
+                             const double* evec,
                              typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab,
                              int32_t* qlist, double* part, int64_t n_subset, double scale,
                              double* gamma, TcOut tc, hipStream_t st) {
@@ -660,7 +671,7 @@ static int launch_fused_impl(const kaldo_crystal* c, const LwParams& p, const do
   case NBV:                                                                                      \
     KALDO_LAUNCH("lw_fused", (lw_fused<NBV, T, MODE>), dim3((unsigned)(upper * n_chunk)),        \
                  dim3(kFusedThreads), lds, st, p, c->n_rep, c->d_rep, omega, vel, modef, occ,    \
-                 phys, sel, evec, eta, phase_tab, b.t_ptr, b.t_i, b.t_l2, b.t_coef, b.e_blk,     \
+                 mrec, phys, sel, evec, eta, phase_tab, b.t_ptr, b.t_i, b.t_l2, b.t_coef, b.e_blk, \
                  b.e_bg, b.blk_d, b.pair_ptr, live_list, n_live, n_chunk, part, tc);             \
     break;
   switch (c->nb) {
@@ -686,45 +697,45 @@ static int launch_fused_impl(const kaldo_crystal* c, const LwParams& p, const do
 
 template <typename T>
 int launch_fused(const kaldo_crystal* c, const LwParams& p, const double* omega, const double* vel,
-                 const float4* modef, const double* occ, const uint8_t* phys, const uint8_t* sel,
-                 const double* evec, typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab,
-                 int32_t* qlist, double* part, int64_t n_subset, double scale, double* gamma,
-                 hipStream_t st) {
-  return launch_fused_impl<T, kModeGamma>(c, p, omega, vel, modef, occ, phys, sel, evec, eta,
+                 const float4* modef, const double* occ, const double2* mrec, const uint8_t* phys,
+                 const uint8_t* sel, const double* evec, typename Cx<T>::type* eta,
+                 typename Cx<T>::type* phase_tab, int32_t* qlist, double* part, int64_t n_subset,
+                 double scale, double* gamma, hipStream_t st) {
+  return launch_fused_impl<T, kModeGamma>(c, p, omega, vel, modef, occ, mrec, phys, sel, evec, eta,
                                           phase_tab, qlist, part, n_subset, scale, gamma, TcOut{},
                                           st);
 }
 
 template <typename T>
 int launch_fused_cache(const kaldo_crystal* c, const LwParams& p, int mode, const double* omega,
-                       const double* vel, const float4* modef, const uint8_t* phys,
-                       const uint8_t* sel, const double* evec, typename Cx<T>::type* eta,
-                       typename Cx<T>::type* phase_tab, int32_t* qlist, int64_t n_subset, TcOut tc,
-                       hipStream_t st) {
+                       const double* vel, const float4* modef, const double2* mrec,
+                       const uint8_t* phys, const uint8_t* sel, const double* evec,
+                       typename Cx<T>::type* eta, typename Cx<T>::type* phase_tab, int32_t* qlist,
+                       int64_t n_subset, TcOut tc, hipStream_t st) {
   if (mode == kModeCount)
-    return launch_fused_impl<T, kModeCount>(c, p, omega, vel, modef, nullptr, phys, sel, evec, eta,
-                                            phase_tab, qlist, nullptr, n_subset, 0.0, nullptr, tc,
-                                            st);
-  return launch_fused_impl<T, kModeRecord>(c, p, omega, vel, modef, nullptr, phys, sel, evec, eta,
-                                           phase_tab, qlist, nullptr, n_subset, 0.0, nullptr, tc,
-                                           st);
+    return launch_fused_impl<T, kModeCount>(c, p, omega, vel, modef, nullptr, mrec, phys, sel, evec,
+                                            eta, phase_tab, qlist, nullptr, n_subset, 0.0, nullptr,
+                                            tc, st);
+  return launch_fused_impl<T, kModeRecord>(c, p, omega, vel, modef, nullptr, mrec, phys, sel, evec,
+                                           eta, phase_tab, qlist, nullptr, n_subset, 0.0, nullptr,
+                                           tc, st);
 }
 
 template int launch_fused<float>(const kaldo_crystal*, const LwParams&, const double*,
-                                 const double*, const float4*, const double*, const uint8_t*,
-                                 const uint8_t*, const double*, float2*, float2*, int32_t*,
-                                 double*, int64_t, double, double*, hipStream_t);
+                                 const double*, const float4*, const double*, const double2*,
+                                 const uint8_t*, const uint8_t*, const double*, float2*, float2*,
+                                 int32_t*, double*, int64_t, double, double*, hipStream_t);
 template int launch_fused<double>(const kaldo_crystal*, const LwParams&, const double*,
-                                  const double*, const float4*, const double*, const uint8_t*,
-                                  const uint8_t*, const double*, double2*, double2*, int32_t*,
-                                  double*, int64_t, double, double*, hipStream_t);
+                                  const double*, const float4*, const double*, const double2*,
+                                  const uint8_t*, const uint8_t*, const double*, double2*, double2*,
+                                  int32_t*, double*, int64_t, double, double*, hipStream_t);
 template int launch_fused_cache<float>(const kaldo_crystal*, const LwParams&, int, const double*,
-                                       const double*, const float4*, const uint8_t*,
-                                       const uint8_t*, const double*, float2*, float2*, int32_t*,
-                                       int64_t, TcOut, hipStream_t);
+                                       const double*, const float4*, const double2*,
+                                       const uint8_t*, const uint8_t*, const double*, float2*,
+                                       float2*, int32_t*, int64_t, TcOut, hipStream_t);
 template int launch_fused_cache<double>(const kaldo_crystal*, const LwParams&, int, const double*,
-                                        const double*, const float4*, const uint8_t*,
-                                        const uint8_t*, const double*, double2*, double2*,
-                                        int32_t*, int64_t, TcOut, hipStream_t);
+                                        const double*, const float4*, const double2*,
+                                        const uint8_t*, const uint8_t*, const double*, double2*,
+                                        double2*, int32_t*, int64_t, TcOut, hipStream_t);
 
 }  // namespace kaldo
