@@ -60,8 +60,8 @@ MEASURED_TRAFFIC = {
                                  "sha256": "255bd3fdb705aa75efcc7d9c549a4092699d1f8245ea98c12f883dfa4b121677",
                                  "bytes": 58784804},
     ("lw_fused", "C5", "fp64"): {"sources": ["lw_fused.hip", "lw_common.h", "common.h"],
-                                 "sha256": "a6a4c38df92e37b29cae4193f36ef93a2083acb9fca2cb21961357c491109dd1",
-                                 "bytes": 24125337053},
+                                 "sha256": "4fb3588685b7fc07d23e5d43c01da3873ce86a4b0d5e34c33c2143e6aa33206f",
+                                 "bytes": 25382366348},
     ("tc_gamma", "C5", "fp64"): {"sources": ["tcache.hip", "lw_common.h", "common.h"],
                                  "sha256": "9d025a5f1699a29049b92eb6b685e1a765ed8cab38d285275e23d705edd734af",
                                  "bytes": 3433888276},
