@@ -75,7 +75,11 @@ typedef enum {
   KALDO_FP64 = 0,   /* contraction in FP64                                  */
   KALDO_FP32 = 1,   /* operands rounded to FP32, FP32 products and sums     */
   KALDO_BF16X3 = 2  /* operands split x = hi + lo (bf16 each); products
-                       hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation */
+                       hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 accumulation;
+                       cells of fewer than 9 branches run the FP32 form
+                       instead (the 16-wide matrix-core tiles would be mostly
+                       padding: the pruned FP32 kernel is faster there and at
+                       least as accurate) */
 } kaldo_precision;
 
 typedef enum { KALDO_GAUSS = 0, KALDO_LORENTZ = 1 } kaldo_shape;

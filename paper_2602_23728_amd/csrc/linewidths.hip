@@ -226,7 +226,14 @@ enum class CrystalPath { Generic, Fused, Mfma };
 static CrystalPath choose_path(const kaldo_crystal* c, int prec) {
   const char* env = std::getenv("KALDO_CRYSTAL_PATH");
   const std::string want = env ? env : "";
-  if (prec == KALDO_BF16X3) return CrystalPath::Mfma;
+  if (prec == KALDO_BF16X3) {
+    // The split form pays only on 16-wide matrix-core tiles; with fewer than
+    // 9 branches they are mostly padding and the pruned FP32 kernel is much
+    // faster (28x on the diamond 15^3 mesh) and at least as accurate, so
+    // such requests run it (KALDO_CRYSTAL_PATH=mfma keeps the split form).
+    if (want != "mfma" && c->nb3 < 9 && fused_supported(c, KALDO_FP32)) return CrystalPath::Fused;
+    return CrystalPath::Mfma;
+  }
   if (const char* f = std::getenv("KALDO_FORCE_GENERIC"))
     if (f[0] == '1') return CrystalPath::Generic;
   if (want == "generic") return CrystalPath::Generic;
@@ -364,7 +371,8 @@ int linewidths_enqueue(const kaldo_crystal* c, const int32_t* mesh, const double
   if (rc) return rc;
   KALDO_REQUIRE(precision == KALDO_FP64 || precision == KALDO_FP32 || precision == KALDO_BF16X3,
                 "kaldo_linewidths: unknown precision");
-  if (precision == KALDO_BF16X3 && !mfma_supported(c)) {
+  if (precision == KALDO_BF16X3 && choose_path(c, precision) == CrystalPath::Mfma &&
+      !mfma_supported(c)) {
     set_error("kaldo_linewidths: BF16X3 needs the MFMA kernel (nb3 <= 16, tables in LDS)");
     return KALDO_EUNSUPPORTED;
   }

@@ -470,20 +470,32 @@ def test_crystal_mfma_forms(name, mesh, prec, monkeypatch):
     assert kerr <= 1e-4
 
 
-def test_c2_golden_bf16x3(diamond):
+@pytest.mark.parametrize("route", ["default", "mfma"])
+def test_c2_golden_bf16x3(diamond, monkeypatch, route):
+    """BF16x3 on the diamond 15^3 mesh: by default (fewer than 9 branches) the
+    request runs the pruned FP32 kernel, bitwise the FP32 result; with the
+    matrix-core kernel forced, the split form meets its own bound."""
     path = os.path.join(GOLDEN, "c2_oracle.npz")
     if not os.path.exists(path):
         pytest.skip("golden file missing")
     g = np.load(path)
     m, c = diamond
     cfg = configs.CONFIGS["C2"]
+    if route == "mfma":
+        monkeypatch.setenv("KALDO_CRYSTAL_PATH", "mfma")
     G = host(K.linewidths(c, cfg.mesh, dev(g["omega"]), dev(g["evec"]), dev(g["vel"]), 300.0,
                           cfg.broadening, K.BF16X3))
     err = gamma_close(G, g["gamma"])
     kg = host(K.kappa_rta(c, cfg.mesh, dev(g["omega"]), dev(g["vel"]), dev(G), 300.0, 0.1))
     kerr = kappa_close(kg, g["kappa"])
-    print(f"C2 bf16x3: Gamma max rel err {err:.3e}, kappa rel err {kerr:.3e}")
-    assert err <= 1e-3
+    print(f"C2 bf16x3 ({route}): Gamma max rel err {err:.3e}, kappa rel err {kerr:.3e}")
+    if route == "default":
+        G32 = host(K.linewidths(c, cfg.mesh, dev(g["omega"]), dev(g["evec"]), dev(g["vel"]), 300.0,
+                                cfg.broadening, K.FP32))
+        assert np.array_equal(G, G32)
+        assert err <= 1e-5
+    else:
+        assert err <= 1e-3
     assert kerr <= 1e-4
 
 
