@@ -106,12 +106,14 @@ struct Fc3Gamma {
   int32_t* t_a = nullptr;      // [n_t]
   double* t_coef = nullptr;    // [n_t]
   // Row tiles of kSpmmRows rows of A_mu: the sorted unique columns each tile
-  // touches, and for every pattern entry the position of its column in its
-  // tile's list (so a tile's E rows can be staged once in LDS).
-  int n_rtiles = 0, max_u = 0, max_tile_entries = 0;
+  // touches (so a tile's E rows can be staged once in LDS), and the entries
+  // in ELL form: slot t of row b (t < max_row) holds the row's t-th entry,
+  // the position of its column in its tile's list at col_ell[t * nb3 + b]
+  // (0 for the zero padding of shorter rows).
+  int n_rtiles = 0, max_u = 0, max_tile_entries = 0, max_row = 0;
   int32_t* tile_u_ptr = nullptr;  // [n_rtiles + 1]
   int32_t* tile_u = nullptr;      // unique columns, concatenated
-  int32_t* col_local = nullptr;   // [n_bc]
+  int32_t* col_ell = nullptr;     // [max_row][nb3]
 };
 constexpr int kSpmmRows = 64;
 

@@ -215,7 +215,13 @@ static int build_gamma(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
     max_u = std::max<int>(max_u, static_cast<int>(u.size()));
     g_max_entries = std::max(g_max_entries, row_ptr[r1] - row_ptr[r0]);
   }
+  int max_row = 0;
+  for (int r = 0; r < nb3; ++r) max_row = std::max(max_row, row_ptr[r + 1] - row_ptr[r]);
+  std::vector<int32_t> col_ell((size_t)max_row * nb3, 0);
+  for (int r = 0; r < nb3; ++r)
+    for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k) col_ell[(size_t)(k - row_ptr[r]) * nb3 + r] = col_local[k];
   Fc3Gamma& g = c->gamma;
+  g.max_row = max_row;
   g.n_rtiles = n_rt;
   g.max_u = max_u;
   g.max_tile_entries = g_max_entries;
@@ -229,7 +235,7 @@ static int build_gamma(kaldo_crystal* c, int64_t nnz, const int32_t* fi, const i
   if ((rc = upload(c, &g.t_coef, t_coef))) return rc;
   if ((rc = upload(c, &g.tile_u_ptr, tile_u_ptr))) return rc;
   if ((rc = upload(c, &g.tile_u, tile_u))) return rc;
-  if ((rc = upload(c, &g.col_local, col_local))) return rc;
+  if ((rc = upload(c, &g.col_ell, col_ell))) return rc;
   return KALDO_OK;
 }
 

@@ -58,18 +58,33 @@ __global__ void gm_prep_et(int n, int np, const double* __restrict__ E, float* _
   }
 }
 
-// A_mu values on the fixed (b, c) pattern, FP32, for modes m0 .. m0 + nb - 1,
-// stored mode-contiguous: avT[e][j] (kMBatch columns).
-__global__ void gm_avals(int n, int n_bc, int m0, int nb, const int32_t* __restrict__ t_ptr,
-                         const int32_t* __restrict__ t_a, const double* __restrict__ t_coef,
-                         const double* __restrict__ E, float* __restrict__ avT) {
+// E in FP32 with rows k-major (e32[k][m] = E[k][m], n x n): the SpMM stages
+// its rows from this copy.
+__global__ void gm_prep_e(int n, const double* __restrict__ E, float* __restrict__ e32) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (long)n * n) e32[idx] = (float)E[idx];
+}
+
+// A_mu values in FP32 for modes m0 .. m0 + nb - 1, in the ELL layout the
+// SpMM reads with coalesced loads: the value of slot t of row b for mode j
+// is avE[((t * kMBatch / 4 + j / 4) * np + b) * 4 + j % 4] (zero for the
+// padding slots and for rows b >= n).
+__global__ void gm_avals(int n, int np, int max_row, int m0, int nb, const int32_t* __restrict__ row_ptr,
+                         const int32_t* __restrict__ t_ptr, const int32_t* __restrict__ t_a,
+                         const double* __restrict__ t_coef, const double* __restrict__ E,
+                         float* __restrict__ avE) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (long)n_bc * kMBatch) return;
-  const int e = k / kMBatch, j = k % kMBatch;
+  if (k >= (long)max_row * np * kMBatch) return;
+  const int j = k % kMBatch;
+  const long tb = k / kMBatch;
+  const int b = tb % np, t = tb / np;
   double s = 0.0;
-  if (j < nb)
-    for (int t = t_ptr[e]; t < t_ptr[e + 1]; ++t) s += t_coef[t] * E[(size_t)t_a[t] * n + m0 + j];
-  avT[k] = (float)s;
+  if (j < nb && b < n) {
+    const int e = row_ptr[b] + t;
+    if (e < row_ptr[b + 1])
+      for (int u = t_ptr[e]; u < t_ptr[e + 1]; ++u) s += t_coef[u] * E[(size_t)t_a[u] * n + m0 + j];
+  }
+  avE[(((size_t)t * (kMBatch / 4) + j / 4) * np + b) * 4 + j % 4] = (float)s;
 }
 
 // WT[j][c'][b] = sum_{k in row b} av[j][k] E[col_k][c'] for a tile of
@@ -197,24 +212,26 @@ __global__ void gm_zero(long n, double* __restrict__ x) {
 }
 
 constexpr int kSpmmCols = 64;            // columns c' per workgroup
+constexpr int kSpmmLds = kSpmmCols + 4;  // LDS row stride of the staged E rows (floats)
 constexpr int kSpmmModes = 16;           // modes per workgroup
 // WT[j][c'][b] = sum_{k in row b} A_mu_j[b][col_k] E[col_k][c'], for a tile of
 // kSpmmRows rows (one per lane), kSpmmCols columns (16 per wave) and
 // kSpmmModes modes.  The tile's E rows are staged in LDS (FP32); each lane
 // walks its row's entries once per group of 4 columns and updates 4 x 16
 // accumulators per entry.  Writes are contiguous along b.
-__global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtiles,
-                                               const int32_t* __restrict__ row_ptr,
-                                               const int32_t* __restrict__ col_local,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void gm_spmm(int n, int np, int nb, int n_rtiles, int max_row,
+                                               const int32_t* __restrict__ col_ell,
                                                const int32_t* __restrict__ tile_u_ptr,
                                                const int32_t* __restrict__ tile_u,
-                                               const float* __restrict__ avT,
-                                               const double* __restrict__ E,
+                                               const float* __restrict__ avE,
+                                               const float* __restrict__ e32,
                                                float* __restrict__ wt32, __bf16* __restrict__ wth,
                                                __bf16* __restrict__ wtl, int nt,
                                                const uint8_t* __restrict__ need) {
   extern __shared__ float4 es4[];
-  float* es = reinterpret_cast<float*>(es4);  // [n_u][kSpmmCols]
+  // [n_u][kSpmmLds]: rows padded by 16 bytes, so lanes reading the same
+  // columns of different rows fall in different banks
+  float* es = reinterpret_cast<float*>(es4);
   const int rt = blockIdx.x, c0 = blockIdx.y * kSpmmCols, j0 = blockIdx.z * kSpmmModes;
   {
     // columns no live GEMM tile of these modes reads are not computed
@@ -229,12 +246,28 @@ __global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtil
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int idx = tid; idx < n_u * kSpmmCols; idx += 256) {
     const int u = idx / kSpmmCols, x = idx % kSpmmCols;
-    es[idx] = (c0 + x < n) ? (float)E[(size_t)tile_u[u0 + u] * n + c0 + x] : 0.0f;
+    es[u * kSpmmLds + x] = (c0 + x < n) ? e32[(size_t)tile_u[u0 + u] * n + c0 + x] : 0.0f;
   }
   __syncthreads();
+  if (n_u == 0) {
+    // no entries in these rows: W is zero there
+    for (int idx = tid; idx < kSpmmModes * kSpmmCols * kSpmmRows; idx += 256) {
+      const int j = idx / (kSpmmCols * kSpmmRows), x = (idx / kSpmmRows) % kSpmmCols, bb = idx % kSpmmRows;
+      if (j0 + j >= nb) continue;
+      const size_t g = ((size_t)(j0 + j) * np + c0 + x) * np + b0 + bb;
+      if (wt32) wt32[g] = 0.0f;
+      if (wth) {
+        wth[g] = (__bf16)0.0f;
+        wtl[g] = (__bf16)0.0f;
+      }
+    }
+    return;
+  }
   const int b = b0 + lane;
-  const int k_lo = (has_rows && b < n) ? row_ptr[b] : 0;
-  const int k_hi = (has_rows && b < n) ? row_ptr[b + 1] : 0;
+  // every row takes max_row slots (padding slots hold zero values and read
+  // staged row 0); the A values of slot t for the workgroup's 16 modes are
+  // four 16-byte loads that are contiguous across the wave's lanes
+  const float4* av4 = reinterpret_cast<const float4*>(avE) + (size_t)(j0 / 4) * np + b;
   // each wave: 16 columns in two passes of 8 (8 x 16 accumulators), so every
   // nonzero's 16 mode values are loaded twice per column tile
   constexpr int XW = 8;
@@ -245,14 +278,14 @@ __global__ __launch_bounds__(256) void gm_spmm(int n, int np, int nb, int n_rtil
     for (int x = 0; x < XW; ++x)
 #pragma unroll
       for (int j = 0; j < kSpmmModes; ++j) acc[x][j] = 0.0f;
-    for (int k = k_lo; k < k_hi; ++k) {
-      const float4* ep = reinterpret_cast<const float4*>(&es[col_local[k] * kSpmmCols + x0]);
+    for (int t = 0; t < max_row; ++t) {
+      const float4* ep = reinterpret_cast<const float4*>(&es[col_ell[(size_t)t * n + min(b, n - 1)] * kSpmmLds + x0]);
       const float4 e0 = ep[0], e1 = ep[1];
-      const float4* ap = reinterpret_cast<const float4*>(avT + (size_t)k * kMBatch + j0);
+      const float4* ap = av4 + (size_t)t * (kMBatch / 4) * np;
       float a[kSpmmModes];
 #pragma unroll
       for (int q = 0; q < kSpmmModes / 4; ++q) {
-        const float4 v = ap[q];
+        const float4 v = ap[(size_t)q * np];
         a[4 * q] = v.x;
         a[4 * q + 1] = v.y;
         a[4 * q + 2] = v.z;
@@ -550,7 +583,7 @@ __global__ void gm_finish(int n, int n_tri, const double* __restrict__ partial,
 
 // The SpMM stages max_u rows of 64 floats in LDS.
 bool gm_supported(const kaldo_crystal* c) {
-  return (size_t)c->gamma.max_u * kSpmmCols * sizeof(float) <= 96 * 1024;
+  return (size_t)c->gamma.max_u * kSpmmLds * sizeof(float) <= 96 * 1024;
 }
 
 size_t gm_workspace_bytes(const kaldo_crystal* c, int prec) {
@@ -560,9 +593,10 @@ size_t gm_workspace_bytes(const kaldo_crystal* c, int prec) {
   const bool split = prec == KALDO_BF16X3;
   size_t o = 0;
   auto take = [&](size_t bytes) { o += (bytes + 255) / 256 * 256; };
-  take(np * np * 4);                       // et32 (needed by the SpMM in both forms)
+  take(np * np * 4);                       // et32
+  take(n * n * 4);                         // e32 (the SpMM's rows, both forms)
   if (split) take(np * np * 2 * 2);         // eth, etl
-  take((size_t)c->gamma.n_bc * kMBatch * 4);  // avals
+  take((size_t)std::max(1, c->gamma.max_row) * np * kMBatch * 4);  // avals (ELL)
   take(split ? np * np * kMBatch * 2 * 2 : np * np * kMBatch * 4);  // W
   take(n * n_tri * 8);                     // partials
   take(nt * 2 * 8);                        // block frequency ranges
@@ -586,13 +620,14 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
     return r;
   };
   float* et32 = reinterpret_cast<float*>(take((size_t)np * np * 4));
+  float* e32 = reinterpret_cast<float*>(take((size_t)n * n * 4));
   __bf16* eth = nullptr;
   __bf16* etl = nullptr;
   if (split) {
     eth = reinterpret_cast<__bf16*>(take((size_t)np * np * 2 * 2));  // hi and lo
     etl = eth + (size_t)np * np;
   }
-  float* av = reinterpret_cast<float*>(take((size_t)c->gamma.n_bc * kMBatch * 4));
+  float* av = reinterpret_cast<float*>(take((size_t)std::max(1, c->gamma.max_row) * np * kMBatch * 4));
   float* wt32 = nullptr;
   __bf16* wth = nullptr;
   __bf16* wtl = nullptr;
@@ -614,17 +649,21 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
                phys, brange);
   KALDO_LAUNCH("gm_prep_et", gm_prep_et, dim3((nn + 255) / 256), dim3(256), 0, st, n, np, evec,
                et32, eth, etl, flags);
+  KALDO_LAUNCH("gm_prep_e", gm_prep_e, dim3((unsigned)(((long)n * n + 255) / 256)), dim3(256), 0, st, n,
+               evec, e32);
   for (int m0 = 0; m0 < n; m0 += kMBatch) {
     const int nb = std::min(kMBatch, n - m0);
-    const long na = (long)c->gamma.n_bc * kMBatch;
-    KALDO_LAUNCH("gm_avals", gm_avals, dim3((na + 255) / 256), dim3(256), 0, st, n, c->gamma.n_bc,
-                 m0, nb, c->gamma.t_ptr, c->gamma.t_a, c->gamma.t_coef, evec, av);
+    const long na = (long)c->gamma.max_row * np * kMBatch;
+    if (na > 0)
+      KALDO_LAUNCH("gm_avals", gm_avals, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, n, np,
+                   c->gamma.max_row, m0, nb, c->gamma.row_ptr, c->gamma.t_ptr, c->gamma.t_a,
+                   c->gamma.t_coef, evec, av);
     KALDO_LAUNCH("gm_need", gm_need, dim3((nb * nt + 255) / 256), dim3(256), 0, st, p, nt, m0, nb, omega,
                  phys, sel, brange, need);
-    const size_t spmm_lds = (size_t)c->gamma.max_u * kSpmmCols * sizeof(float);
+    const size_t spmm_lds = (size_t)c->gamma.max_u * kSpmmLds * sizeof(float);
     KALDO_LAUNCH("gm_spmm", gm_spmm, dim3(np / kSpmmRows, np / kSpmmCols, (nb + kSpmmModes - 1) / kSpmmModes),
-                 dim3(256), spmm_lds, st, n, np, nb, c->gamma.n_rtiles, c->gamma.row_ptr,
-                 c->gamma.col_local, c->gamma.tile_u_ptr, c->gamma.tile_u, av, evec, wt32, wth, wtl, nt, need);
+                 dim3(256), spmm_lds, st, n, np, nb, c->gamma.n_rtiles, c->gamma.max_row,
+                 c->gamma.col_ell, c->gamma.tile_u_ptr, c->gamma.tile_u, av, e32, wt32, wth, wtl, nt, need);
     KALDO_LAUNCH("gm_live_list", gm_live_list, dim3(1), dim3(1024), 0, st, p, nt, n_tri, m0, nb, omega,
                  phys, sel, brange, live_list, live_count);
     if (split)
