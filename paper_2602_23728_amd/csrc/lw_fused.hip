@@ -219,32 +219,42 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         }
         const C* ph = phase_tab + (size_t)q1 * p.n_d;
         T vr = 0, vi = 0;
+        // V = sum_blk f_blk sum_beta x_beta (sum_gamma A~[blk][beta gamma] y_gamma):
+        // complex multiply-adds as chains of fused multiply-adds into the
+        // accumulators (four per product; the written form a.x b.x - a.y b.y
+        // costs a multiply, a fused one and an add per component), and no
+        // x (x) y table (nine complex values a block would have to keep or
+        // recompute)
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
 #pragma unroll
           for (int kb = 0; kb < NB; ++kb) {
             const int b_lo = pair_ptr[jb * NB + kb], b_hi = pair_ptr[jb * NB + kb + 1];
-            if (b_lo == b_hi) continue;
-            C z[9];
-#pragma unroll
-            for (int be = 0; be < 3; ++be)
-#pragma unroll
-              for (int ga = 0; ga < 3; ++ga) {
-                const C u = x[3 * jb + be], v = y[3 * kb + ga];
-                z[be * 3 + ga] = Cx<T>::make(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
-              }
             for (int blk = b_lo; blk < b_hi; ++blk) {
               const C* ab = at + (size_t)blk * 9 * NB3 + s;
               T ur = 0, ui = 0;
 #pragma unroll
-              for (int k = 0; k < 9; ++k) {
-                const C a = ab[k * NB3];
-                ur += a.x * z[k].x - a.y * z[k].y;
-                ui += a.x * z[k].y + a.y * z[k].x;
+              for (int be = 0; be < 3; ++be) {
+                T tr = 0, ti = 0;
+#pragma unroll
+                for (int ga = 0; ga < 3; ++ga) {
+                  const C a = ab[(be * 3 + ga) * NB3], v = y[3 * kb + ga];
+                  tr = fma(a.x, v.x, tr);
+                  tr = fma(-a.y, v.y, tr);
+                  ti = fma(a.x, v.y, ti);
+                  ti = fma(a.y, v.x, ti);
+                }
+                const C u = x[3 * jb + be];
+                ur = fma(u.x, tr, ur);
+                ur = fma(-u.y, ti, ur);
+                ui = fma(u.x, ti, ui);
+                ui = fma(u.y, tr, ui);
               }
               const C f = ph[blk_d[blk]];
-              vr += f.x * ur - f.y * ui;
-              vi += f.x * ui + f.y * ur;
+              vr = fma(f.x, ur, vr);
+              vr = fma(-f.y, ui, vr);
+              vi = fma(f.x, ui, vi);
+              vi = fma(f.y, ur, vi);
             }
           }
         }
