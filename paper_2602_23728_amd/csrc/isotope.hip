@@ -165,9 +165,11 @@ __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __
 #pragma unroll
               for (int a = 0; a < 3; ++a) {
                 const double2 u = e0s[wv][k][3 * i + a], v = e1[3 * i + a];
-                // conj(u) v
-                dr += u.x * v.x + u.y * v.y;
-                di += u.x * v.y - u.y * v.x;
+                // conj(u) v, as fused multiply-adds into the sums
+                dr = fma(u.x, v.x, dr);
+                dr = fma(u.y, v.y, dr);
+                di = fma(u.x, v.y, di);
+                di = fma(-u.y, v.x, di);
               }
               ov += p.g[i] * (dr * dr + di * di);
             }

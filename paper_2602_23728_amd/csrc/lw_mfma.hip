@@ -296,17 +296,23 @@ __global__ __launch_bounds__(kMfmaThreads) void lw_mfma(
             a[j] = ap[j * stride];
             f[j] = phb[wv][blk + j];
           }
+          // complex multiply-adds as fused multiply-adds into v (four per
+          // product instead of two multiplies, two fused and two adds)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            v.x += f[j].x * a[j].x - f[j].y * a[j].y;
-            v.y += f[j].x * a[j].y + f[j].y * a[j].x;
+            v.x = fmaf(f[j].x, a[j].x, v.x);
+            v.x = fmaf(-f[j].y, a[j].y, v.x);
+            v.y = fmaf(f[j].x, a[j].y, v.y);
+            v.y = fmaf(f[j].y, a[j].x, v.y);
           }
         }
         for (; blk < end; ++blk, ap += stride) {
           const float2 a = *ap;
           const float2 f = phb[wv][blk];
-          v.x += f.x * a.x - f.y * a.y;
-          v.y += f.x * a.y + f.y * a.x;
+          v.x = fmaf(f.x, a.x, v.x);
+          v.x = fmaf(-f.y, a.y, v.x);
+          v.y = fmaf(f.x, a.y, v.y);
+          v.y = fmaf(f.y, a.x, v.y);
         }
         Bt[pos] = v;
       }
