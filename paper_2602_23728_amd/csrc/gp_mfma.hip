@@ -310,12 +310,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
       for (int x = 0; x < XW; ++x) {
         const size_t g = ((size_t)(j0 + j) * np + c0 + x0 + x) * np + b;
         const float v = acc[x][j];
-        if (wt32) wt32[g] = v;
+        // W is read back only by the GEMM of this batch, long after it has
+        // left the caches: streaming (non-temporal) stores
+        if (wt32) __builtin_nontemporal_store(v, &wt32[g]);
         if (wth) {
           __bf16 h, l;
           split_bf16(v, h, l);
-          wth[g] = h;
-          wtl[g] = l;
+          __builtin_nontemporal_store(h, &wth[g]);
+          __builtin_nontemporal_store(l, &wtl[g]);
         }
       }
     }
