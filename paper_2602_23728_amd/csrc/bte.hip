@@ -29,8 +29,9 @@
 //                  bijection of q1 (no two lanes of a pass touch one element),
 //                  Gamma0 reduced in a fixed order and added to the diagonal
 //   bte_gmax, bte_decouple   the RTA selection
-//   lu_diag, lu_panels, lu_update   blocked LU without pivoting (64 x 64
-//                  blocks; the trailing update on FP64 matrix cores)
+//   lu_diag, lu_panels, lu_update, lu_gemm   blocked LU without pivoting
+//                  (64 x 64 blocks, panels of four; the updates on the FP64
+//                  matrix cores)
 //   lu_tri, lu_rupdate   the two triangular sweeps for the 3 RHS
 //   bte_gemv, bte_sc_init, bte_sc_update   the iteration of Eq. sc_iter
 //   bte_kappa      Eq. kappa_general, fixed-order reduction
@@ -45,7 +46,8 @@
 
 namespace kaldo {
 
-constexpr int kLuB = 64;  // LU block edge
+constexpr int kLuB = 64;     // LU block edge
+constexpr int kLuPanel = 4;  // blocks per panel of the blocked LU
 
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double d4;
 
@@ -431,15 +433,16 @@ __global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, double* 
   }
 }
 
-// Trailing update of step k: A_ij -= A_ik A_kj for i, j > k, one 64 x 64
-// block per workgroup, four waves of 32 x 32 on v_mfma_f64_16x16x4f64.
-__global__ __launch_bounds__(256) void lu_update(long n, int nb, int k, double* __restrict__ mat) {
+// Update of step k on a rectangle of blocks: A_ij -= A_ik A_kj for i in [i0,
+// i0 + ni), j in [j0, j0 + nj), one 64 x 64 block per workgroup, four waves
+// of 32 x 32 on v_mfma_f64_16x16x4f64.
+__global__ __launch_bounds__(256) void lu_update(long n, int k, int i0, int j0, int nj,
+                                                 double* __restrict__ mat) {
   constexpr int B = kLuB;
   __shared__ double L[B][B + 1];
   __shared__ double U[B][B + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m = nb - k - 1;
-  const long bi = k + 1 + blockIdx.x / m, bj = k + 1 + blockIdx.x % m;
+  const long bi = i0 + blockIdx.x / nj, bj = j0 + blockIdx.x % nj;
   for (int idx = tid; idx < B * B; idx += 256) {
     const int i = idx / B, j = idx % B;
     const long li = bi * B + i, lj = (long)k * B + j;
@@ -471,6 +474,94 @@ __global__ __launch_bounds__(256) void lu_update(long n, int nb, int k, double* 
       for (int r = 0; r < 4; ++r) {
         // FP64 16x16 accumulator: item r of lane l is row 4 r + l / 16, column l % 16
         const long gi = bi * B + wm + 16 * a + 4 * r + lg, gj = bj * B + wn + 16 * b + lr;
+        if (gi < n && gj < n) mat[gi * n + gj] -= acc[a][b][r];
+      }
+}
+
+// Deferred update of a panel: A_ij -= sum_k A_ik A_kj over the panel's
+// columns k in [kc, kc + kw) for the trailing elements i, j >= r0 (blocked
+// right-looking LU: the panel's own steps update only the panel's columns
+// and rows, this one product the rest).  128 x 128 tile per workgroup, four
+// waves of 64 x 64 as 4 x 4 v_mfma_f64_16x16x4f64 accumulators; K in slices
+// of 16 staged k-major in LDS (two buffers, the next slice fetched into
+// registers while the current one is multiplied).  Elements past n read as
+// zero and are not written.
+constexpr int kLgT = 128;  // tile edge
+constexpr int kLgK = 16;   // K slice
+constexpr int kLgLd = kLgT + 2;  // LDS row stride (doubles)
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void lu_gemm(long n, long r0, long kc, int kw, int ntl,
+                                               double* __restrict__ mat) {
+  __shared__ double As[2][kLgK][kLgLd];  // [k][row]
+  __shared__ double Bs[2][kLgK][kLgLd];  // [k][col]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const long row0 = r0 + (long)(blockIdx.x / ntl) * kLgT, col0 = r0 + (long)(blockIdx.x % ntl) * kLgT;
+  if (row0 >= n || col0 >= n) return;
+  // staging: A rows row0 + (tid >> 1), k = 8 (tid & 1) .. + 8; B row k =
+  // tid >> 4, columns col0 + 8 (tid & 15) .. + 8
+  const int ar = tid >> 1, ak = 8 * (tid & 1);
+  const int bk = tid >> 4, bc = 8 * (tid & 15);
+  const long ga = row0 + ar, gbc = col0 + bc;
+  const double* arow = mat + (ga < n ? ga : 0) * n;  // row ga (a valid row when ga >= n)
+  double pa[8], pb[8];
+  // slice k0: eight consecutive elements per operand and thread, from one
+  // base address (constant offsets)
+  auto fetch = [&](long k0) {
+    const long ka = k0 + ak;
+    const double* a = arow + ka;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) pa[t] = (ga < n && ka + t < n) ? a[t] : 0.0;
+    const long kb = k0 + bk;
+    const double* b = mat + (kb < n ? kb : 0) * n + gbc;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) pb[t] = (kb < n && gbc + t < n) ? b[t] : 0.0;
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) As[buf][ak + t][ar] = pa[t];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) Bs[buf][bk][bc + t] = pb[t];
+  };
+  const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
+  const int lr = lane & 15, lg = lane >> 4;
+  d4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  fetch(kc);
+  stage(0);
+  __syncthreads();
+  int cur = 0;
+  for (long k0 = kc; k0 < kc + kw; k0 += kLgK) {
+    const bool more = k0 + kLgK < kc + kw;
+    if (more) fetch(k0 + kLgK);
+#pragma unroll
+    for (int kk = 0; kk < kLgK; kk += 4) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        av[t] = As[cur][kk + lg][wm + 16 * t + lr];  // A[row = lane % 16][k = lane / 16]
+        bv[t] = Bs[cur][kk + lg][wn + 16 * t + lr];  // B[k = lane / 16][col = lane % 16]
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) stage(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // item r of lane l is row 4 r + l / 16, column l % 16
+        const long gi = row0 + wm + 16 * a + 4 * r + lg, gj = col0 + wn + 16 * b + lr;
         if (gi < n && gj < n) mat[gi * n + gj] -= acc[a][b][r];
       }
 }
@@ -762,15 +853,35 @@ extern "C" int kaldo_bte_solve(const kaldo_crystal* c, const int32_t* mesh, cons
   double* y = reinterpret_cast<double*>(ws + w.off_y);
   double* gmax = reinterpret_cast<double*>(ws + w.off_gmax);
   const size_t blk = (size_t)kLuB * kLuB;
-  for (int k = 0; k < nb; ++k) {
-    KALDO_LAUNCH("lu_diag", lu_diag, dim3(1), dim3(256), 0, st, n, k, matrix, linv + k * blk,
-                 uinv + k * blk, c->d_flags);
-    const int m = nb - k - 1;
-    if (m > 0) {
+  // Blocked right-looking LU in panels of kLuPanel blocks: the steps inside
+  // a panel update only the panel's columns (every row below) and the
+  // panel's rows (every column to the right); the rest of the trailing
+  // matrix takes one rank-(64 kLuPanel) product per panel (lu_gemm).
+  for (int k0 = 0; k0 < nb; k0 += kLuPanel) {
+    const int k1 = std::min(nb, k0 + kLuPanel);
+    for (int k = k0; k < k1; ++k) {
+      KALDO_LAUNCH("lu_diag", lu_diag, dim3(1), dim3(256), 0, st, n, k, matrix, linv + k * blk,
+                   uinv + k * blk, c->d_flags);
+      const int m = nb - k - 1;
+      if (m == 0) continue;
       KALDO_LAUNCH("lu_panels", lu_panels, dim3(2 * m), dim3(256), 0, st, n, nb, k, matrix,
                    linv + k * blk, uinv + k * blk);
-      KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)m * m), dim3(256), 0, st, n, nb, k,
-                   matrix);
+      const int pw = k1 - k - 1;  // panel columns (and rows) still to factor
+      if (pw > 0) {
+        // the panel's columns, every row below k
+        KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(m * pw)), dim3(256), 0, st, n, k, k + 1,
+                     k + 1, pw, matrix);
+        // the panel's rows, the columns past the panel
+        if (nb - k1 > 0)
+          KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(pw * (nb - k1))), dim3(256), 0, st, n,
+                       k, k + 1, k1, nb - k1, matrix);
+      }
+    }
+    if (k1 < nb) {
+      const long r0 = (long)k1 * kLuB;
+      const int ntl = (int)((n - r0 + kLgT - 1) / kLgT);
+      KALDO_LAUNCH("lu_gemm", lu_gemm, dim3((unsigned)(ntl * ntl)), dim3(256), 0, st, n, r0,
+                   (long)k0 * kLuB, (k1 - k0) * kLuB, ntl, matrix);
     }
   }
   // forward: y = L^-1 b, the residual in y2 (starting as b)
