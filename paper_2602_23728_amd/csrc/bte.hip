@@ -47,7 +47,7 @@
 namespace kaldo {
 
 constexpr int kLuB = 64;     // LU block edge
-constexpr int kLuPanel = 4;  // blocks per panel of the blocked LU
+constexpr int kLuPanel = 8;  // blocks per panel of the blocked LU
 
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double d4;
 
@@ -371,26 +371,45 @@ __global__ __launch_bounds__(256) void lu_diag(long n, int k, double* __restrict
     const long gi = r0 + i, gj = r0 + j;
     if (gi < n && gj < n) mat[gi * n + gj] = D[i][j];
   }
-  // inverse of the unit lower triangle, column c by forward substitution
-  if (tid < B) {
-    const int c = tid;
-    for (int i = 0; i < B; ++i) {
-      double x = (i == c) ? 1.0 : 0.0;
-      for (int t = c; t < i; ++t) x -= D[i][t] * X[t][c];
-      X[i][c] = (i < c) ? 0.0 : x;
+  // The two triangular inverses, column c by substitution, four threads per
+  // column (one wave holds a column's four: its stores are seen by its own
+  // later loads in order, so the steps need no barrier).  Each thread sums
+  // every fourth term of a step's dot product, its loads all issued before
+  // the products; the partial sums are added in a fixed order (the lane
+  // exchanges pair the same lanes every time).
+  static_assert(B * 4 == 256, "four threads per column");
+  const int col = tid >> 2, sub = tid & 3;
+  auto quad_sum = [&](double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+  };
+  // unit lower triangle: X[i][c] = [i == c] - sum_{c <= t < i} D[i][t] X[t][c]
+  for (int i = 0; i < B; ++i) {
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < B / 4; ++u) {
+      const int t = col + sub + 4 * u;
+      if (t < i) part = fma(D[i][t], X[t][col], part);
     }
+    part = quad_sum(part);
+    if (sub == 0) X[i][col] = (i < col) ? 0.0 : ((i == col) ? 1.0 : 0.0) - part;
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   for (int idx = tid; idx < B * B; idx += 256) linv[idx] = X[idx / B][idx % B];
   __syncthreads();
-  // inverse of the upper triangle, column c by back substitution
-  if (tid < B) {
-    const int c = tid;
-    for (int i = B - 1; i >= 0; --i) {
-      double x = (i == c) ? 1.0 : 0.0;
-      for (int t = i + 1; t <= c; ++t) x -= D[i][t] * X[t][c];
-      X[i][c] = (i > c) ? 0.0 : x / D[i][i];
+  // upper triangle: X[i][c] = ([i == c] - sum_{i < t <= c} D[i][t] X[t][c]) / D[i][i]
+  for (int i = B - 1; i >= 0; --i) {
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < B / 4; ++u) {
+      const int t = i + 1 + sub + 4 * u;
+      if (t <= col) part = fma(D[i][t], X[t][col], part);
     }
+    part = quad_sum(part);
+    if (sub == 0) X[i][col] = (i > col) ? 0.0 : (((i == col) ? 1.0 : 0.0) - part) / D[i][i];
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   for (int idx = tid; idx < B * B; idx += 256) uinv[idx] = X[idx / B][idx % B];
