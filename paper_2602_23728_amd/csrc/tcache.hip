@@ -95,8 +95,14 @@ __global__ __launch_bounds__(256) void tc_gamma(int n_modes, const double* __res
     for (int u = 0; u < U; ++u) {
       const long long k = base + 64 * u + lane;
       if (k < hi) {
-        ij[u] = pairs[k];
-        f[u] = factors[k];
+        // the entries stream through once per launch: non-temporal loads
+        // leave the caches to the population rows the entries gather
+        typedef unsigned nt_u2 __attribute__((ext_vector_type(2)));
+        typedef double nt_d2 __attribute__((ext_vector_type(2)));
+        const nt_u2 p2 = __builtin_nontemporal_load(reinterpret_cast<const nt_u2*>(pairs + k));
+        const nt_d2 f2 = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(factors + k));
+        ij[u] = make_uint2(p2.x, p2.y);
+        f[u] = make_double2(f2.x, f2.y);
       } else {
         ij[u] = make_uint2(0u, 0u);
         f[u] = make_double2(0.0, 0.0);
