@@ -193,13 +193,18 @@ __global__ __launch_bounds__(64) void bte_rows(
                 const size_t ox = (((size_t)q1 * NB3 + e_jc[e]) * NB3 + s1) * 2;
                 const size_t oy = (((size_t)q2 * NB3 + e_kc[e]) * NB3 + s2) * 2;
                 const double xr = evec[ox], xi = evec[ox + 1], yr = evec[oy], yi = evec[oy + 1];
-                const double zr = xr * yr - xi * yi, zi = xr * yi + xi * yr;
-                dr += a.x * zr - a.y * zi;
-                di += a.x * zi + a.y * zr;
+                const double zr = fma(xr, yr, -(xi * yi)), zi = fma(xr, yi, xi * yr);
+                // complex multiply-adds as fused multiply-adds into the sums
+                dr = fma(a.x, zr, dr);
+                dr = fma(-a.y, zi, dr);
+                di = fma(a.x, zi, di);
+                di = fma(a.y, zr, di);
               }
               const double2 f = ph[d];
-              vr += f.x * dr - f.y * di;
-              vi += f.x * di + f.y * dr;
+              vr = fma(f.x, dr, vr);
+              vr = fma(-f.y, di, vr);
+              vi = fma(f.x, di, vi);
+              vi = fma(f.y, dr, vi);
             }
             const double v2 = pref * (vr * vr + vi * vi);
             dp *= v2;
