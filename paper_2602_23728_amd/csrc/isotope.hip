@@ -12,12 +12,16 @@
 //
 //   iso_prep     per mode: (w, sigma) record (w NaN below nu_min), eta
 //                transposed to [q][mode][component], input checks
-//   iso_ranges   per (block of partner q-points, branch): the frequency range
-//                of its physical modes and their largest sigma
-//   iso_kernel   one wave per four modes of a branch at consecutive q-points
-//                (they share each partner's loads): the (block, branch) tiles
-//                whose range can meet the cut (range table in LDS), lanes
-//                over the block's q-points, exact FP64 cut per mode and
+//   iso_sort     per branch the q-points in order of frequency (one
+//                workgroup per branch, bitonic sort in LDS; larger meshes
+//                keep the flat order)
+//   iso_ranges   per (tile of partners in that order, branch): the frequency
+//                range of its physical modes and their largest sigma
+//   iso_kernel   one wave per four modes of a branch adjacent in that order
+//                (nearly equal frequencies: they share each partner's loads):
+//                per partner branch the run of tiles whose range can meet the
+//                cut (found by binary search in the range table, in LDS),
+//                lanes over the tile's partners, exact FP64 cut per mode and
 //                partner, overlap and smearing in FP64, per-lane sums in tile
 //                order, fixed wave reduction per mode
 #include <algorithm>
@@ -63,15 +67,62 @@ __global__ void iso_prep(IsoParams p, const double* __restrict__ omega, const do
   if (w < 0.0 && (-w / kTwoPi) >= p.nu_min) raise_flag(flags, kFlagImaginary);
 }
 
-// range[(b * nb3 + s')] = (lowest w, highest w, largest sigma) of the physical
-// modes (q', s') with q' in tile b; an empty tile gets (+inf, -inf, 0).
-__global__ void iso_ranges(IsoParams p, const double2* __restrict__ rec, double* __restrict__ range) {
+// perm[s][i] = the i-th q-point of branch s in order of frequency: physical
+// modes ascending (keys: the FP32 rounding of w, whose bits order like the
+// values for w > 0, then q), the others last.  One workgroup per branch,
+// bitonic sort of n2 = 2^k >= nq 64-bit keys in LDS; with sorted == 0 (too
+// large a mesh for the LDS) the flat order.
+__global__ __launch_bounds__(1024) void iso_sort(IsoParams p, int sorted, const double2* __restrict__ rec,
+                                                 int32_t* __restrict__ perm) {
+  extern __shared__ unsigned long long keys[];
+  const int s = blockIdx.x;
+  int32_t* out = perm + (size_t)s * p.nq;
+  if (!sorted) {
+    for (int i = threadIdx.x; i < p.nq; i += blockDim.x) out[i] = i;
+    return;
+  }
+  int n2 = 1;
+  while (n2 < p.nq) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    unsigned long long k = ~0ull;
+    if (i < p.nq) {
+      const double w = rec[(size_t)i * p.nb3 + s].x;
+      const unsigned hi = (w == w && w > 0.0) ? __float_as_uint((float)w) : 0xffffffffu;
+      k = ((unsigned long long)hi << 32) | (unsigned)i;
+    }
+    keys[i] = k;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const unsigned long long a = keys[i], b = keys[j];
+          if ((a > b) == ((i & size) == 0)) {
+            keys[i] = b;
+            keys[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < p.nq; i += blockDim.x) out[i] = (int32_t)(keys[i] & 0xffffffffull);
+}
+
+// range[(s' * nblk + b)] = (lowest w, highest w, largest sigma) of the
+// physical modes of branch s' in tile b of its order; an empty tile gets
+// (+inf, -inf, 0).  Tiles run in frequency order, so lowest w does not
+// decrease with b.
+__global__ void iso_ranges(IsoParams p, const int32_t* __restrict__ perm,
+                           const double2* __restrict__ rec, double* __restrict__ range) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= p.nblk * p.nb3) return;
-  const int b = k / p.nb3, s = k - b * p.nb3;
+  const int s = k / p.nblk, b = k - s * p.nblk;
   double lo = INFINITY, hi = -INFINITY, smax = 0.0;
-  const int q_end = min(p.nq, (b + 1) * p.blk);
-  for (int q = b * p.blk; q < q_end; ++q) {
+  const int i_end = min(p.nq, (b + 1) * p.blk);
+  for (int i = b * p.blk; i < i_end; ++i) {
+    const int q = perm[(size_t)s * p.nq + i];
     const double2 r = rec[(size_t)q * p.nb3 + s];
     if (r.x == r.x) {  // physical (not NaN)
       lo = fmin(lo, r.x);
@@ -84,6 +135,16 @@ __global__ void iso_ranges(IsoParams p, const double2* __restrict__ rec, double*
   range[3 * (size_t)k + 2] = smax;
 }
 
+// After the table: range[3 nblk nb3 + s'] = the largest sigma' over the tiles
+// of branch s' (one thread per branch).
+__global__ void iso_branch_smax(IsoParams p, double* __restrict__ range) {
+  const int s = threadIdx.x;
+  if (s >= p.nb3) return;
+  double m = 0.0;
+  for (int b = 0; b < p.nblk; ++b) m = fmax(m, range[3 * ((size_t)s * p.nblk + b) + 2]);
+  range[3 * (size_t)p.nblk * p.nb3 + s] = m;
+}
+
 // Modes per wave: MPW modes of one branch at consecutive q-points (nearly the
 // same frequency, so nearly the same live tiles and passing partners) share
 // every partner's record and eigenvector load.
@@ -94,27 +155,31 @@ __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __
                                                   const double2* __restrict__ inv,
                                                   const double2* __restrict__ etaT,
                                                   const double* __restrict__ range,
+                                                  const int32_t* __restrict__ perm,
                                                   int accumulate, double* __restrict__ gamma) {
   constexpr int NB = NB3 / 3;
   constexpr int MPW = kIsoMpw;
-  extern __shared__ double rng_lds[];  // the range table, [nblk][NB3][3]
+  extern __shared__ double rng_lds[];  // the range table, [NB3][nblk][3], then [NB3] largest sigma'
   __shared__ double2 e0s[4][MPW][NB3];  // each wave's modes' eigenvectors
-  const int n_rng = p.nblk * NB3 * 3;
+  const int n_rng = p.nblk * NB3 * 3 + NB3;
   for (int k = threadIdx.x; k < n_rng; k += blockDim.x) rng_lds[k] = range[k];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // wave -> (branch s, first q): waves of one branch are consecutive, so
-  // neighbouring workgroups also scan similar tiles
+  // wave -> (branch s, first position in the branch's frequency order):
+  // waves of one branch are consecutive, so neighbouring workgroups also scan
+  // similar tiles
   const int groups = (p.nq + MPW - 1) / MPW;
   const int gid = blockIdx.x * 4 + wv;
   const bool active = gid < NB3 * groups;
   const int s = active ? gid / groups : 0;
-  const int q0 = active ? (gid - s * groups) * MPW : 0;
+  const int i0 = active ? (gid - s * groups) * MPW : 0;
   double w[MPW];
   bool live_m[MPW];
+  int qm[MPW];
 #pragma unroll
   for (int k = 0; k < MPW; ++k) {
-    const int q = q0 + k;
-    const bool in = active && q < p.nq;
+    const bool in = active && i0 + k < p.nq;
+    const int q = in ? perm[(size_t)s * p.nq + i0 + k] : 0;
+    qm[k] = q;
     const double2 r = in ? rec[(size_t)q * NB3 + s] : make_double2(__builtin_nan(""), 0.0);
     w[k] = r.x;
     live_m[k] = in && (r.x == r.x);
@@ -129,17 +194,46 @@ __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __
 #pragma unroll
   for (int k = 0; k < MPW; ++k) any_live |= live_m[k];
   if (any_live) {
-    for (int b = 0; b < p.nblk; ++b) {
-      for (int s1 = 0; s1 < NB3; ++s1) {
-        const double* r = rng_lds + 3 * (b * NB3 + s1);
+    double wlo = INFINITY, whi = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < MPW; ++k)
+      if (live_m[k]) {
+        wlo = fmin(wlo, w[k]);
+        whi = fmax(whi, w[k]);
+      }
+    for (int s1 = 0; s1 < NB3; ++s1) {
+      const double* rs = rng_lds + 3 * (size_t)s1 * p.nblk;
+      // the tiles that can hold a partner within 2 sigma' of [wlo, whi] form
+      // a run: the first has its highest w at least wlo - 2 sigma'_max of the
+      // branch (binary search; the highest w rises with b over the non-empty
+      // tiles, which come first), and the run ends at the first tile whose
+      // lowest w lies past whi + 2 sigma'_max (lowest w never falls)
+      // (the order follows the FP32 rounding of w: a tile's highest or lowest
+      // w may exceed a later tile's by one FP32 ulp, 1.2e-7 w; both bounds
+      // carry twice that)
+      const double reach_max = 2.0 * rng_lds[3 * p.nblk * NB3 + s1] * (1.0 + 1e-12);
+      const double t_lo = wlo - reach_max - 2.4e-7 * fabs(wlo);
+      const double t_hi = whi + reach_max + 2.4e-7 * fabs(whi);
+      int lo_b = 0, hi_b = p.nblk;
+      while (lo_b < hi_b) {
+        const int mid = (lo_b + hi_b) >> 1;
+        const double h = rs[3 * mid + 1];
+        // an empty tile (h = -inf) sits after every non-empty one: count it as high
+        if (h >= t_lo || !(h > -INFINITY)) hi_b = mid;
+        else lo_b = mid + 1;
+      }
+      for (int b = lo_b; b < p.nblk; ++b) {
+        const double* r = rs + 3 * b;
+        if (!(r[0] <= t_hi)) break;  // lowest w past reach (or an empty tile)
         const double reach = 2.0 * r[2] * (1.0 + 1e-12);
         // the tile can hold a partner with |w - w'| < 2 sigma' only if w lies
-        // within reach of its range (an empty tile fails every test)
+        // within reach of its range
         bool tile = false;
 #pragma unroll
         for (int k = 0; k < MPW; ++k) tile |= live_m[k] && w[k] > r[0] - reach && w[k] < r[1] + reach;
         if (!tile) continue;
-        for (int q1 = b * p.blk + lane; q1 < min(p.nq, (b + 1) * p.blk); q1 += 64) {
+        for (int i1 = b * p.blk + lane; i1 < min(p.nq, (b + 1) * p.blk); i1 += 64) {
+          const int q1 = perm[(size_t)s1 * p.nq + i1];
           const int m1 = q1 * NB3 + s1;
           const double2 o = rec[m1];
           bool pass[MPW];
@@ -190,8 +284,8 @@ __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __
 #pragma unroll
   for (int k = 0; k < MPW; ++k) {
     const double v = wave_sum_fixed(acc[k]);
-    const int q = q0 + k;
-    if (lane == 0 && q < p.nq) {
+    const int q = qm[k];
+    if (lane == 0 && active && i0 + k < p.nq) {
       const size_t m = (size_t)q * NB3 + s;
       if (live_m[k]) {
         const double gi = p.scale * w[k] * w[k] * v;
@@ -205,7 +299,7 @@ __global__ __launch_bounds__(256) void iso_kernel(IsoParams p, const double2* __
 
 struct IsoWs {
   int blk, nblk;
-  size_t off_rec, off_inv, off_eta, off_range, total;
+  size_t off_rec, off_inv, off_eta, off_range, off_perm, total;
 };
 
 static IsoWs iso_ws(long nq, int nb3) {
@@ -224,7 +318,8 @@ static IsoWs iso_ws(long nq, int nb3) {
   w.off_rec = take(sizeof(double2) * nq * nb3);
   w.off_inv = take(sizeof(double2) * nq * nb3);
   w.off_eta = take(sizeof(double2) * nq * nb3 * nb3);
-  w.off_range = take(sizeof(double) * 3 * (size_t)w.nblk * nb3);
+  w.off_range = take(sizeof(double) * (3 * (size_t)w.nblk * nb3 + nb3));
+  w.off_perm = take(sizeof(int32_t) * (size_t)nq * nb3);
   w.total = o;
   return w;
 }
@@ -290,18 +385,29 @@ extern "C" int kaldo_isotope_linewidths(const kaldo_crystal* c, const int32_t* m
   auto* inv = reinterpret_cast<double2*>(ws + w.off_inv);
   auto* eta = reinterpret_cast<double2*>(ws + w.off_eta);
   auto* range = reinterpret_cast<double*>(ws + w.off_range);
+  auto* perm = reinterpret_cast<int32_t*>(ws + w.off_perm);
   const int n_modes = (int)nq * c->nb3;
   KALDO_LAUNCH("iso_prep", iso_prep, dim3((n_modes + 255) / 256), dim3(256), 0, st, p, omega, vel,
                evec, rec, inv, eta, c->d_flags);
+  // the frequency order of every branch, when its sort keys fit the LDS
+  int dev = 0, lds_max = 0;
+  KALDO_HIP(hipGetDevice(&dev));
+  KALDO_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  size_t n2 = 1;
+  while ((long)n2 < nq) n2 <<= 1;
+  const int sorted = n2 * sizeof(unsigned long long) <= (size_t)lds_max ? 1 : 0;
+  KALDO_LAUNCH("iso_sort", iso_sort, dim3(c->nb3), dim3(1024), sorted ? n2 * sizeof(unsigned long long) : 0,
+               st, p, sorted, rec, perm);
   KALDO_LAUNCH("iso_ranges", iso_ranges, dim3((p.nblk * p.nb3 + 255) / 256), dim3(256), 0, st, p,
-               rec, range);
-  const size_t lds = sizeof(double) * 3 * (size_t)p.nblk * p.nb3;
+               perm, rec, range);
+  KALDO_LAUNCH("iso_branch_smax", iso_branch_smax, dim3(1), dim3(64), 0, st, p, range);
+  const size_t lds = sizeof(double) * (3 * (size_t)p.nblk * p.nb3 + p.nb3);
   const long n_waves = (long)c->nb3 * ((nq + kIsoMpw - 1) / kIsoMpw);
   const dim3 grid((unsigned)((n_waves + 3) / 4));
 #define KALDO_ISO_CASE(NB3V)                                                                   \
   case NB3V:                                                                                   \
     KALDO_LAUNCH("iso_kernel", iso_kernel<NB3V>, grid, dim3(256), lds, st, p, rec, inv, eta, range, \
-                 accumulate, gamma);                                                           \
+                 perm, accumulate, gamma);                                                     \
     break;
   switch (c->nb3) {
     KALDO_ISO_CASE(3)
