@@ -31,7 +31,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 
 constexpr int kMT = 128;   // output tile edge
-constexpr int kMBatch = 256;  // modes per launch
+constexpr int kMBatch = 512;  // modes per launch
 
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
@@ -68,23 +68,38 @@ __global__ void gm_prep_e(int n, const double* __restrict__ E, float* __restrict
 // A_mu values in FP32 for modes m0 .. m0 + nb - 1, in the ELL layout the
 // SpMM reads with coalesced loads: the value of slot t of row b for mode j
 // is avE[((t * kMBatch / 4 + j / 4) * np + b) * 4 + j % 4] (zero for the
-// padding slots and for rows b >= n).
-__global__ void gm_avals(int n, int np, int max_row, int m0, int nb, const int32_t* __restrict__ row_ptr,
-                         const int32_t* __restrict__ t_ptr, const int32_t* __restrict__ t_a,
-                         const double* __restrict__ t_coef, const double* __restrict__ E,
-                         float* __restrict__ avE) {
-  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (long)max_row * np * kMBatch) return;
-  const int j = k % kMBatch;
-  const long tb = k / kMBatch;
-  const int b = tb % np, t = tb / np;
-  double s = 0.0;
-  if (j < nb && b < n) {
-    const int e = row_ptr[b] + t;
-    if (e < row_ptr[b + 1])
-      for (int u = t_ptr[e]; u < t_ptr[e + 1]; ++u) s += t_coef[u] * E[(size_t)t_a[u] * n + m0 + j];
+// padding slots and for rows b >= n).  A workgroup takes slot t, 16 rows and
+// 256 modes: the sums run with the modes across the threads (coalesced
+// reads of E's rows), the tile is transposed through LDS, and each group of
+// four modes is written as one run of 16 rows x 4 values.
+constexpr int kAvRows = 16;
+__global__ __launch_bounds__(256) void gm_avals(int n, int np, int max_row, int m0, int nb,
+                                                const int32_t* __restrict__ row_ptr,
+                                                const int32_t* __restrict__ t_ptr,
+                                                const int32_t* __restrict__ t_a,
+                                                const double* __restrict__ t_coef,
+                                                const double* __restrict__ E,
+                                                float* __restrict__ avE) {
+  __shared__ float tile[kAvRows][256 + 1];
+  const int t = blockIdx.x, b0 = blockIdx.y * kAvRows, jh = blockIdx.z * 256;
+  const int tid = threadIdx.x;
+  const int j = jh + tid;  // this thread's mode in the batch
+  for (int rb = 0; rb < kAvRows; ++rb) {
+    const int b = b0 + rb;
+    double s = 0.0;
+    if (j < nb && b < n) {
+      const int e = row_ptr[b] + t;
+      if (e < row_ptr[b + 1])
+        for (int u = t_ptr[e]; u < t_ptr[e + 1]; ++u) s += t_coef[u] * E[(size_t)t_a[u] * n + m0 + j];
+    }
+    tile[rb][tid] = (float)s;
   }
-  avE[(((size_t)t * (kMBatch / 4) + j / 4) * np + b) * 4 + j % 4] = (float)s;
+  __syncthreads();
+  // 64 groups of four modes, each a run of kAvRows x 4 floats
+  for (int idx = tid; idx < 64 * kAvRows * 4; idx += 256) {
+    const int jq = idx / (kAvRows * 4), w = idx % (kAvRows * 4), rb = w / 4, r = w % 4;
+    avE[(((size_t)t * (kMBatch / 4) + jh / 4 + jq) * np + b0 + rb) * 4 + r] = tile[rb][4 * jq + r];
+  }
 }
 
 // WT[j][c'][b] = sum_{k in row b} av[j][k] E[col_k][c'] for a tile of
@@ -655,11 +670,11 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
                evec, e32);
   for (int m0 = 0; m0 < n; m0 += kMBatch) {
     const int nb = std::min(kMBatch, n - m0);
-    const long na = (long)c->gamma.max_row * np * kMBatch;
-    if (na > 0)
-      KALDO_LAUNCH("gm_avals", gm_avals, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, n, np,
-                   c->gamma.max_row, m0, nb, c->gamma.row_ptr, c->gamma.t_ptr, c->gamma.t_a,
-                   c->gamma.t_coef, evec, av);
+    static_assert(kMBatch % 256 == 0, "whole 256-mode halves per batch");
+    if (c->gamma.max_row > 0)
+      KALDO_LAUNCH("gm_avals", gm_avals, dim3((unsigned)c->gamma.max_row, (unsigned)(np / kAvRows),
+                   kMBatch / 256), dim3(256), 0, st, n, np, c->gamma.max_row, m0, nb,
+                   c->gamma.row_ptr, c->gamma.t_ptr, c->gamma.t_a, c->gamma.t_coef, evec, av);
     KALDO_LAUNCH("gm_need", gm_need, dim3((nb * nt + 255) / 256), dim3(256), 0, st, p, nt, m0, nb, omega,
                  phys, sel, brange, need);
     const size_t spmm_lds = (size_t)c->gamma.max_u * kSpmmLds * sizeof(float);
