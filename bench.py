@@ -433,6 +433,46 @@ def tsweep_leg(K, torch, cfg, model, c, steps, warmup, n_temps=16, direct_gamma=
     return res
 
 
+def peaks_leg(torch):
+    """Rates re-measured on this device, beside the datasheet peaks the
+    roofline objects use: a 1 GiB device-to-device copy (HBM read + write
+    bytes per second) and plain library matrix products (torch.matmul on
+    contiguous square operands) in FP64, FP32 and BF16."""
+    out = {}
+    x = torch.empty(256 << 20, dtype=torch.float32, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_copy_GBps"] = 2 * x.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    for name, dt, n in (("fp64", torch.float64, 8192), ("fp32", torch.float32, 8192),
+                        ("bf16", torch.bfloat16, 16384)):
+        a = torch.rand(n, n, dtype=torch.float32, device="cuda").to(dt).contiguous()
+        b = torch.rand(n, n, dtype=torch.float32, device="cuda").to(dt).contiguous()
+        for _ in range(2):
+            torch.matmul(a, b)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            torch.matmul(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{name}_gemm_TFLOPs"] = 2.0 * n ** 3 * 3 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+        del a, b
+    out["datasheet"] = {"hbm_GBps": 8000.0, "fp64_TFLOPs": FP64_PEAK, "fp32_TFLOPs": FP32_PEAK,
+                        "bf16_TFLOPs": BF16_PEAK}
+    log("peaks: " + ", ".join(f"{k} {v:.1f}" for k, v in out.items() if not isinstance(v, dict)))
+    return out
+
+
 def qhgk_leg(K, torch, steps, warmup):
     """QHGK conductivity: the 512-atom glass (Eq. qhgk: host FP64
     eigensolver once as set-up, Gamma from the FP32 projection, then the QHGK
@@ -808,6 +848,7 @@ def main():
                                        max(3, a.steps // 4), 2)
         extras["bte_c2"] = bte_leg(K, torch, 3, 1)
         extras["qhgk"] = qhgk_leg(K, torch, max(3, a.steps // 4), 1)
+        extras["peaks"] = peaks_leg(torch)
         extras["isotope"] = isotope_leg(K, torch, cfg, model, c, max(3, a.steps // 4), 1,
                                         gamma_anh=bufs["gam"])
         extras["wedge"] = {"C2": wedge_leg(K, torch, "C2", K.FP64, max(3, a.steps // 4), 1),
