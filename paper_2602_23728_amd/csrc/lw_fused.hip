@@ -132,6 +132,11 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
       wq_abs_max = fmaxf(wq_abs_max, fabsf((float)w));
       live |= (phys[q * NB3 + s] && sel[q * NB3 + s]) ? (1u << s) : 0u;
     }
+    // FP32 frequencies of the live branches, +inf for the others (they then
+    // fail every band test of the sweep)
+    float wql[NB3];
+#pragma unroll
+    for (int s = 0; s < NB3; ++s) wql[s] = (live >> s & 1u) ? wqf[s] : __builtin_inff();
     if (tid < NB3) wq64[tid] = omega[q * NB3 + tid];
     if (tid < NB3) wqs[tid] = (float)omega[q * NB3 + tid];
     if constexpr (kRecord) {
@@ -338,16 +343,27 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
           // -|cp| on mirrored entries and cp otherwise.  The decay |x-| is the
           // same FP32 number for both orderings.  Live branches of q have w
           // >= 2 pi nu_min > 0; the others drop out through `live`.
+          // The common path asks only whether any live branch is near: the
+          // smallest |x| of each process over the branches against its edge
+          // (a minimum is exact, so the answer is that of the per-branch
+          // tests; a NaN x leaves the minimum at +inf or NaN, which fail).
           const float cpe = dbl ? -fabsf(cp) : cp;
-          unsigned cand = 0;
+          float xp[NB3], xm[NB3];
+          float mp = __builtin_inff(), mm = __builtin_inff();
 #pragma unroll
           for (int s = 0; s < NB3; ++s) {
-            const float apr = fabsf(wqf[s] + cpe), am = fabsf(wqf[s] + cm);
-            cand |= (apr < bp.hi || am < bm.hi) ? (1u << s) : 0u;
+            xp[s] = wql[s] + cpe;
+            xm[s] = wql[s] + cm;
+            mp = fminf(mp, fabsf(xp[s]));
+            mm = fminf(mm, fabsf(xm[s]));
           }
-          cand &= live;
           unsigned b = 0;
-          if (cand) {
+          if (mp < bp.hi || mm < bm.hi) {
+            unsigned cand = 0;
+#pragma unroll
+            for (int s = 0; s < NB3; ++s)
+              cand |= (fabsf(xp[s]) < bp.hi || fabsf(xm[s]) < bm.hi) ? (1u << s) : 0u;
+            cand &= live;
             // the rare candidates: which process is near (as the tests above),
             // certain passes in FP32, the band members take the exact FP64 test
             unsigned amb = 0, amb_p = 0, amb_r = 0, amb_m = 0;
