@@ -349,75 +349,95 @@ __global__ __launch_bounds__(256) void lu_diag(long n, int k, double* __restrict
                                                double* __restrict__ linv,
                                                double* __restrict__ uinv,
                                                int32_t* __restrict__ flags) {
+  // Thread (ty, tx) = (tid / 16, tid % 16) keeps in registers the 16
+  // elements of rows ty + 16 a and columns tx + 16 b (a, b < 4) of the block
+  // D, of X_L = L^-1 and of X_U = U^-1: the strided split keeps every thread
+  // busy as the active corner shrinks.  Step j publishes through LDS the
+  // rows and columns it needs (two buffers by step parity, so one barrier
+  // per step); then, with r = 1 / D[j][j] and l_i = D[i][j] r:
+  //   factorisation        D[i][c] -= l_i D[j][c]          (i, c > j), D[i][j] = l_i
+  //   unit lower inverse   X_L[i][:] -= l_i X_L[j][:]      (i > j; row j of X_L is final)
+  //   upper inverse        X_U[:][j] *= r, then X_U[:][c] -= X_U[:][j] U[j][c]   (c > j)
+  // Row j of D is row j of U from step j on, and column j of X_U has then
+  // taken every earlier step, so all three run in the same 64 steps.
   constexpr int B = kLuB;
-  __shared__ double D[B][B + 1];
-  __shared__ double X[B][B + 1];
-  const int tid = threadIdx.x;
+  static_assert(B == 64, "16 x 16 threads, 4 x 4 elements each");
+  __shared__ double pub_row[2][B];    // row j of D
+  __shared__ double pub_col[2][B];    // column j of D
+  __shared__ double pub_xrow[2][B];   // row j of X_L
+  __shared__ double pub_xucol[2][B];  // column j of X_U
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   const long r0 = (long)k * B;
-  for (int idx = tid; idx < B * B; idx += 256) {
-    const int i = idx / B, j = idx % B;
-    const long gi = r0 + i, gj = r0 + j;
-    D[i][j] = (gi < n && gj < n) ? mat[gi * n + gj] : (i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  for (int j = 0; j < B; ++j) {
-    const double piv = D[j][j];
-    if (tid == 0 && !(fabs(piv) > 1e-300)) raise_flag(flags, kFlagSingular);
-    for (int i = j + 1 + tid; i < B; i += 256) D[i][j] /= piv;
-    __syncthreads();
-    for (int idx = tid; idx < (B - j - 1) * (B - j - 1); idx += 256) {
-      const int i = j + 1 + idx / (B - j - 1), c = j + 1 + idx % (B - j - 1);
-      D[i][c] -= D[i][j] * D[j][c];
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < B * B; idx += 256) {
-    const int i = idx / B, j = idx % B;
-    const long gi = r0 + i, gj = r0 + j;
-    if (gi < n && gj < n) mat[gi * n + gj] = D[i][j];
-  }
-  // The two triangular inverses, column c by substitution, four threads per
-  // column (one wave holds a column's four: its stores are seen by its own
-  // later loads in order, so the steps need no barrier).  Each thread sums
-  // every fourth term of a step's dot product, its loads all issued before
-  // the products; the partial sums are added in a fixed order (the lane
-  // exchanges pair the same lanes every time).
-  static_assert(B * 4 == 256, "four threads per column");
-  const int col = tid >> 2, sub = tid & 3;
-  auto quad_sum = [&](double v) {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    return v;
-  };
-  // unit lower triangle: X[i][c] = [i == c] - sum_{c <= t < i} D[i][t] X[t][c]
-  for (int i = 0; i < B; ++i) {
-    double part = 0.0;
+  double d[4][4], xl[4][4], xu[4][4];
 #pragma unroll
-    for (int u = 0; u < B / 4; ++u) {
-      const int t = col + sub + 4 * u;
-      if (t < i) part = fma(D[i][t], X[t][col], part);
-    }
-    part = quad_sum(part);
-    if (sub == 0) X[i][col] = (i < col) ? 0.0 : ((i == col) ? 1.0 : 0.0) - part;
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  for (int idx = tid; idx < B * B; idx += 256) linv[idx] = X[idx / B][idx % B];
-  __syncthreads();
-  // upper triangle: X[i][c] = ([i == c] - sum_{i < t <= c} D[i][t] X[t][c]) / D[i][i]
-  for (int i = B - 1; i >= 0; --i) {
-    double part = 0.0;
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int u = 0; u < B / 4; ++u) {
-      const int t = i + 1 + sub + 4 * u;
-      if (t <= col) part = fma(D[i][t], X[t][col], part);
+    for (int b = 0; b < 4; ++b) {
+      const int i = ty + 16 * a, c = tx + 16 * b;
+      const long gi = r0 + i, gc = r0 + c;
+      d[a][b] = (gi < n && gc < n) ? mat[gi * n + gc] : (i == c ? 1.0 : 0.0);
+      xl[a][b] = xu[a][b] = (i == c) ? 1.0 : 0.0;
     }
-    part = quad_sum(part);
-    if (sub == 0) X[i][col] = (i > col) ? 0.0 : (((i == col) ? 1.0 : 0.0) - part) / D[i][i];
-    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int ja = 0; ja < 4; ++ja) {
+    for (int jy = 0; jy < 16; ++jy) {
+      const int j = 16 * ja + jy, pb = j & 1;
+      if (ty == jy) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          pub_row[pb][tx + 16 * b] = d[ja][b];
+          pub_xrow[pb][tx + 16 * b] = xl[ja][b];
+        }
+      }
+      if (tx == jy) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          pub_col[pb][ty + 16 * a] = d[a][ja];
+          pub_xucol[pb][ty + 16 * a] = xu[a][ja];
+        }
+      }
+      __syncthreads();
+      const double piv = pub_row[pb][j];
+      if (tid == 0 && !(fabs(piv) > 1e-300)) raise_flag(flags, kFlagSingular);
+      const double r = 1.0 / piv;
+      double uc[4], xc[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        uc[b] = pub_row[pb][tx + 16 * b];
+        xc[b] = pub_xrow[pb][tx + 16 * b];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = ty + 16 * a;
+        const double xj = pub_xucol[pb][i] * r;
+        const double li = pub_col[pb][i] * r;
+        const bool below = i > j;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int c = tx + 16 * b;
+          if (c > j) {
+            if (below) d[a][b] = fma(-li, uc[b], d[a][b]);
+            xu[a][b] = fma(-xj, uc[b], xu[a][b]);
+          }
+          if (b == ja && c == j) {
+            if (below) d[a][b] = li;
+            xu[a][b] = xj;
+          }
+          if (below) xl[a][b] = fma(-li, xc[b], xl[a][b]);
+        }
+      }
+    }
   }
-  __syncthreads();
-  for (int idx = tid; idx < B * B; idx += 256) uinv[idx] = X[idx / B][idx % B];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ty + 16 * a, c = tx + 16 * b;
+      const long gi = r0 + i, gc = r0 + c;
+      if (gi < n && gc < n) mat[gi * n + gc] = d[a][b];
+      linv[i * B + c] = xl[a][b];
+      uinv[i * B + c] = xu[a][b];
+    }
 }
 
 // Panels of step k: row blocks A_kj <- Linv A_kj (j > k, first nb - k - 1
