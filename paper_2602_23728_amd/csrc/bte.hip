@@ -440,6 +440,36 @@ __global__ __launch_bounds__(256) void lu_diag(long n, int k, double* __restrict
     }
 }
 
+// 64 x 64 x 64 product P Q from two LDS blocks, four waves of 32 x 32 on
+// v_mfma_f64_16x16x4f64; wave wv holds rows wm = 32 (wv / 2) and columns
+// wn = 32 (wv % 2) of the result in acc[a][b] (16 x 16 tiles).
+struct BlockProduct {
+  int wm, wn, lr, lg;
+  d4 acc[2][2];
+  __device__ void run(const double (*P)[kLuB + 1], const double (*Q)[kLuB + 1], int tid) {
+    const int lane = tid & 63, wv = tid >> 6;
+    wm = (wv >> 1) * 32;
+    wn = (wv & 1) * 32;
+    lr = lane & 15;
+    lg = lane >> 4;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < kLuB; kk += 4) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const double av = P[wm + 16 * a + lr][kk + lg];  // A[row = lane % 16][k = lane / 16]
+          const double bv = Q[kk + lg][wn + 16 * b + lr];  // B[k = lane / 16][col = lane % 16]
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+  // FP64 16 x 16 accumulator: item r of lane l is row 4 r + l / 16, column l % 16
+  __device__ int row(int a, int r) const { return wm + 16 * a + 4 * r + lg; }
+  __device__ int col(int b) const { return wn + 16 * b + lr; }
+};
+
 // Panels of step k: row blocks A_kj <- Linv A_kj (j > k, first nb - k - 1
 // workgroups), column blocks A_ik <- A_ik Uinv (i > k, the rest).
 __global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, double* __restrict__ mat,
@@ -460,32 +490,30 @@ __global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, double* 
     T[i][j] = row ? linv[idx] : uinv[idx];
   }
   __syncthreads();
-  double out[16];
-  for (int r = 0; r < 16; ++r) {
-    const int idx = tid + 256 * r, i = idx / B, j = idx % B;
-    double s = 0.0;
-    if (row)
-      for (int t = 0; t < B; ++t) s += T[i][t] * M[t][j];
-    else
-      for (int t = 0; t < B; ++t) s += M[i][t] * T[t][j];
-    out[r] = s;
-  }
-  for (int r = 0; r < 16; ++r) {
-    const int idx = tid + 256 * r, i = idx / B, j = idx % B;
-    const long gi = bi * B + i, gj = bj * B + j;
-    if (gi < n && gj < n) mat[gi * n + gj] = out[r];
-  }
+  BlockProduct bp;
+  if (row)
+    bp.run(T, M, tid);
+  else
+    bp.run(M, T, tid);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long gi = bi * B + bp.row(a, r), gj = bj * B + bp.col(b);
+        if (gi < n && gj < n) mat[gi * n + gj] = bp.acc[a][b][r];
+      }
 }
 
 // Update of step k on a rectangle of blocks: A_ij -= A_ik A_kj for i in [i0,
-// i0 + ni), j in [j0, j0 + nj), one 64 x 64 block per workgroup, four waves
-// of 32 x 32 on v_mfma_f64_16x16x4f64.
+// i0 + ni), j in [j0, j0 + nj), one 64 x 64 block per workgroup.
 __global__ __launch_bounds__(256) void lu_update(long n, int k, int i0, int j0, int nj,
                                                  double* __restrict__ mat) {
   constexpr int B = kLuB;
   __shared__ double L[B][B + 1];
   __shared__ double U[B][B + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   const long bi = i0 + blockIdx.x / nj, bj = j0 + blockIdx.x % nj;
   for (int idx = tid; idx < B * B; idx += 256) {
     const int i = idx / B, j = idx % B;
@@ -495,30 +523,16 @@ __global__ __launch_bounds__(256) void lu_update(long n, int k, int i0, int j0, 
     U[i][j] = (ui < n && uj < n) ? mat[ui * n + uj] : 0.0;
   }
   __syncthreads();
-  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
-  const int lr = lane & 15, lg = lane >> 4;
-  d4 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int kk = 0; kk < B; kk += 4) {
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const double av = L[wm + 16 * a + lr][kk + lg];  // A[row = lane % 16][k = lane / 16]
-        const double bv = U[kk + lg][wn + 16 * b + lr];  // B[k = lane / 16][col = lane % 16]
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[a][b], 0, 0, 0);
-      }
-  }
+  BlockProduct bp;
+  bp.run(L, U, tid);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // FP64 16x16 accumulator: item r of lane l is row 4 r + l / 16, column l % 16
-        const long gi = bi * B + wm + 16 * a + 4 * r + lg, gj = bj * B + wn + 16 * b + lr;
-        if (gi < n && gj < n) mat[gi * n + gj] -= acc[a][b][r];
+        const long gi = bi * B + bp.row(a, r), gj = bj * B + bp.col(b);
+        if (gi < n && gj < n) mat[gi * n + gj] -= bp.acc[a][b][r];
       }
 }
 
