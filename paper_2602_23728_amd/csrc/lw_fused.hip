@@ -230,36 +230,58 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         // costs a multiply, a fused one and an add per component), and no
         // x (x) y table (nine complex values a block would have to keep or
         // recompute)
+        // One block's term f_blk x_jb^T A~_blk y_kb into (vr, vi).  The FP64
+        // Gamma pass loads the three values of a row of the block together
+        // and fetches each block's phase one block ahead, so that the
+        // latencies fall under arithmetic; the FP32 form and the record pass
+        // have no registers left for either.
+        constexpr bool kAhead = sizeof(T) == 8 && MODE == kModeGamma;
+        auto block_term = [&](const C* ab, const C f, int jb, int kb) {
+          T ur = 0, ui = 0;
+#pragma unroll
+          for (int be = 0; be < 3; ++be) {
+            C a[3];
+            if constexpr (kAhead) {
+#pragma unroll
+              for (int ga = 0; ga < 3; ++ga) a[ga] = ab[(be * 3 + ga) * NB3];
+            }
+            T tr = 0, ti = 0;
+#pragma unroll
+            for (int ga = 0; ga < 3; ++ga) {
+              if constexpr (!kAhead) a[ga] = ab[(be * 3 + ga) * NB3];
+              const C v = y[3 * kb + ga];
+              tr = fma(a[ga].x, v.x, tr);
+              tr = fma(-a[ga].y, v.y, tr);
+              ti = fma(a[ga].x, v.y, ti);
+              ti = fma(a[ga].y, v.x, ti);
+            }
+            const C u = x[3 * jb + be];
+            ur = fma(u.x, tr, ur);
+            ur = fma(-u.y, ti, ur);
+            ui = fma(u.x, ti, ui);
+            ui = fma(u.y, tr, ui);
+          }
+          vr = fma(f.x, ur, vr);
+          vr = fma(-f.y, ui, vr);
+          vi = fma(f.x, ui, vi);
+          vi = fma(f.y, ur, vi);
+        };
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) {
 #pragma unroll
           for (int kb = 0; kb < NB; ++kb) {
             const int b_lo = pair_ptr[jb * NB + kb], b_hi = pair_ptr[jb * NB + kb + 1];
-            for (int blk = b_lo; blk < b_hi; ++blk) {
-              const C* ab = at + (size_t)blk * 9 * NB3 + s;
-              T ur = 0, ui = 0;
-#pragma unroll
-              for (int be = 0; be < 3; ++be) {
-                T tr = 0, ti = 0;
-#pragma unroll
-                for (int ga = 0; ga < 3; ++ga) {
-                  const C a = ab[(be * 3 + ga) * NB3], v = y[3 * kb + ga];
-                  tr = fma(a.x, v.x, tr);
-                  tr = fma(-a.y, v.y, tr);
-                  ti = fma(a.x, v.y, ti);
-                  ti = fma(a.y, v.x, ti);
-                }
-                const C u = x[3 * jb + be];
-                ur = fma(u.x, tr, ur);
-                ur = fma(-u.y, ti, ur);
-                ui = fma(u.x, ti, ui);
-                ui = fma(u.y, tr, ui);
+            if constexpr (kAhead) {
+              C f_next = Cx<T>::make((T)0, (T)0);
+              if (b_lo < b_hi) f_next = ph[blk_d[b_lo]];
+              for (int blk = b_lo; blk < b_hi; ++blk) {
+                const C f = f_next;
+                if (blk + 1 < b_hi) f_next = ph[blk_d[blk + 1]];
+                block_term(at + (size_t)blk * 9 * NB3 + s, f, jb, kb);
               }
-              const C f = ph[blk_d[blk]];
-              vr = fma(f.x, ur, vr);
-              vr = fma(-f.y, ui, vr);
-              vi = fma(f.x, ui, vi);
-              vi = fma(f.y, ur, vi);
+            } else {
+              for (int blk = b_lo; blk < b_hi; ++blk)
+                block_term(at + (size_t)blk * 9 * NB3 + s, ph[blk_d[blk]], jb, kb);
             }
           }
         }
