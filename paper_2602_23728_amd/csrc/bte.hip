@@ -22,16 +22,17 @@
 // Kernels:
 //   bte_tr_map     time-reversal partner of every mode (largest overlap)
 //   bte_zero       clears the n x n matrix
-//   bte_rows<NB3>  one workgroup (one wave) per q: A~_q (FP64, LDS), then the
-//                  partners q1 in rounds of 64 (one per lane): exact FP64 cut,
-//                  vertex of the passing candidates, per-lane sums per column
-//                  kind in LDS, written in three passes whose columns are a
+//   bte_rows<NB3>  one workgroup (one wave) per q: A~_q (FP64, LDS, by atom
+//                  block), then the partners q1 in rounds of 64 (one per
+//                  lane): exact FP64 cut, the passing candidates queued in LDS
+//                  and their vertices computed by all lanes, per-lane sums per
+//                  column kind in LDS, written in three passes whose columns are a
 //                  bijection of q1 (no two lanes of a pass touch one element),
 //                  Gamma0 reduced in a fixed order and added to the diagonal
 //   bte_gmax, bte_decouple   the RTA selection
 //   lu_diag, lu_panels, lu_update, lu_gemm   blocked LU without pivoting
-//                  (64 x 64 blocks, panels of four; the updates on the FP64
-//                  matrix cores)
+//                  (64 x 64 blocks, panels of eight; the panels and updates
+//                  on the FP64 matrix cores)
 //   lu_tri, lu_rupdate   the two triangular sweeps for the 3 RHS
 //   bte_gemv, bte_sc_init, bte_sc_update   the iteration of Eq. sc_iter
 //   bte_kappa      Eq. kappa_general, fixed-order reduction
@@ -101,21 +102,28 @@ __device__ __forceinline__ void process_rates(const LwParams& p, double w, doubl
 
 // ------------------------------------------------------------------ rows
 
+constexpr int kRowQueue = 256;  // passing candidates a wave queues before projecting them
+
 template <int NB3>
 __global__ __launch_bounds__(64) void bte_rows(
     LwParams p, int n_rep, const int32_t* __restrict__ rep, const double* __restrict__ omega,
     const double* __restrict__ vel, const double* __restrict__ occ,
     const uint8_t* __restrict__ phys, const double* __restrict__ evec,
-    const double2* __restrict__ phase_tab, const int32_t* __restrict__ d_ptr,
-    const int32_t* __restrict__ e_jc, const int32_t* __restrict__ e_kc,
-    const int32_t* __restrict__ t_ptr, const int32_t* __restrict__ t_i,
-    const int32_t* __restrict__ t_l2, const double* __restrict__ t_coef,
-    const int32_t* __restrict__ tr, double pref, double* __restrict__ mat,
-    double* __restrict__ gamma0) {
-  extern __shared__ double2 at[];  // [n_e][NB3]: A~_q, phases e^{+i q.R''} folded in
+    const double2* __restrict__ phase_tab, int n_blk, const int32_t* __restrict__ e_blk,
+    const int32_t* __restrict__ e_bg, const int32_t* __restrict__ blk_d,
+    const int32_t* __restrict__ pair_ptr, const int32_t* __restrict__ t_ptr,
+    const int32_t* __restrict__ t_i, const int32_t* __restrict__ t_l2,
+    const double* __restrict__ t_coef, const int32_t* __restrict__ tr, double pref,
+    double* __restrict__ mat, double* __restrict__ gamma0) {
+  // [n_blk][9][NB3]: A~_q by atom block (jb, kb, d) and Cartesian pair
+  // (beta, gamma), phases e^{+i q.R''} folded in
+  extern __shared__ double2 at[];
+  constexpr int NB = NB3 / 3;
   __shared__ double acc[3][NB3][NB3][64];  // [kind][s][s' or s''][lane]
   __shared__ double2 phq[64];
   __shared__ double red[NB3][64];
+  __shared__ int rq_code[kRowQueue];  // lane | s1 << 6 | s2 << 12 | s << 18
+  __shared__ double rq_dp[kRowQueue], rq_dm[kRowQueue], rq_v2[kRowQueue];
   const int lane = threadIdx.x;
   const int q = blockIdx.x;
   const int nq = p.nq;
@@ -137,6 +145,7 @@ __global__ __launch_bounds__(64) void bte_rows(
     sincospi(2.0 * f, &sn, &cs);
     phq[l] = make_double2(cs, sn);
   }
+  for (int k = lane; k < n_blk * 9 * NB3; k += 64) at[k] = make_double2(0.0, 0.0);
   __syncthreads();
   for (int k = lane; k < p.n_e * NB3; k += 64) {
     const int e = k / NB3, s = k % NB3;
@@ -149,74 +158,144 @@ __global__ __launch_bounds__(64) void bte_rows(
       re += c * (ex * f.x - ey * f.y);
       im += c * (ex * f.y + ey * f.x);
     }
-    at[k] = make_double2(re, im);
+    at[(e_blk[e] * 9 + e_bg[e]) * NB3 + s] = make_double2(re, im);
   }
   __syncthreads();
   double g0[NB3];
 #pragma unroll
   for (int s = 0; s < NB3; ++s) g0[s] = 0.0;
   const int t0 = (N0 - a0) % N0, t1 = (N1 - a1) % N1, t2 = (N2 - a2) % N2;
+  auto partner = [&](int q1) {
+    const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
+    return (wrap_sub(t0, b0, N0) * N1 + wrap_sub(t1, b1, N1)) * N2 + wrap_sub(t2, b2, N2);
+  };
+  // |V|^2 of one (q1, s1, q2, s2, s) with the prefactor:
+  // V = sum_blk e^{-i q1.R_d(blk)} sum_{beta gamma} A~[blk][beta gamma][s]
+  //     eta_{3 jb + beta}(q1, s1) eta_{3 kb + gamma}(q2, s2),
+  // the two eigenvector rows in registers, complex multiply-adds as fused
+  // multiply-adds into the sums
+  auto vertex2 = [&](int q1, int s1, int q2, int s2, int s) {
+    double2 x[NB3], y[NB3];
+#pragma unroll
+    for (int i = 0; i < NB3; ++i) {
+      const double* ex = evec + (((size_t)q1 * NB3 + i) * NB3 + s1) * 2;
+      const double* ey = evec + (((size_t)q2 * NB3 + i) * NB3 + s2) * 2;
+      x[i] = make_double2(ex[0], ex[1]);
+      y[i] = make_double2(ey[0], ey[1]);
+    }
+    const double2* ph = phase_tab + (size_t)q1 * p.n_d;
+    double vr = 0.0, vi = 0.0;
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+#pragma unroll
+      for (int kb = 0; kb < NB; ++kb) {
+        for (int blk = pair_ptr[jb * NB + kb]; blk < pair_ptr[jb * NB + kb + 1]; ++blk) {
+          const double2* ab = at + (size_t)blk * 9 * NB3 + s;
+          double ur = 0.0, ui = 0.0;
+#pragma unroll
+          for (int be = 0; be < 3; ++be) {
+            double tr_ = 0.0, ti = 0.0;
+#pragma unroll
+            for (int ga = 0; ga < 3; ++ga) {
+              const double2 a = ab[(be * 3 + ga) * NB3], v = y[3 * kb + ga];
+              tr_ = fma(a.x, v.x, tr_);
+              tr_ = fma(-a.y, v.y, tr_);
+              ti = fma(a.x, v.y, ti);
+              ti = fma(a.y, v.x, ti);
+            }
+            const double2 u = x[3 * jb + be];
+            ur = fma(u.x, tr_, ur);
+            ur = fma(-u.y, ti, ur);
+            ui = fma(u.x, ti, ui);
+            ui = fma(u.y, tr_, ui);
+          }
+          const double2 f = ph[blk_d[blk]];
+          vr = fma(f.x, ur, vr);
+          vr = fma(-f.y, ui, vr);
+          vi = fma(f.x, ui, vi);
+          vi = fma(f.y, ur, vi);
+        }
+      }
+    }
+    return pref * (vr * vr + vi * vi);
+  };
+  // A round takes 64 partners q1, one per lane.  Each lane classifies its
+  // (s1, s2, s) candidates in that order; the passing ones go to a queue in
+  // LDS (slots by ballot: candidate order, lanes ascending), whose vertices
+  // all 64 lanes then compute; each lane then takes its own entries back in
+  // queue order, so every sum sees the terms in the order of the loops.
+  const unsigned long long below = (1ull << lane) - 1ull;
   for (int base = 0; base < nq; base += 64) {
     const int q1 = base + lane;
     const bool ok = q1 < nq;
     for (int k = 0; k < 3; ++k)
       for (int s = 0; s < NB3; ++s)
         for (int u = 0; u < NB3; ++u) acc[k][s][u][lane] = 0.0;
-    int q2 = 0;
-    if (ok) {
-      const int b0 = q1 / (N1 * N2), b1 = (q1 / N2) % N1, b2 = q1 % N2;
-      q2 = (wrap_sub(t0, b0, N0) * N1 + wrap_sub(t1, b1, N1)) * N2 + wrap_sub(t2, b2, N2);
-      const double2* ph = phase_tab + (size_t)q1 * p.n_d;
-      for (int s1 = 0; s1 < NB3; ++s1) {
-        const int m1 = q1 * NB3 + s1;
-        if (!phys[m1]) continue;
-        const double w1 = omega[m1], n1 = occ[m1];
-        for (int s2 = 0; s2 < NB3; ++s2) {
-          const int m2 = q2 * NB3 + s2;
-          if (!phys[m2]) continue;
-          const double w2 = omega[m2], n2 = occ[m2];
-          double sp, sm;
+    const int q2 = ok ? partner(q1) : 0;
+    int qn = 0;  // entries in the queue (the same in every lane)
+    auto flush = [&]() {
+      __syncthreads();
+      for (int r = lane; r < qn; r += 64) {
+        const int code = rq_code[r];
+        const int o = code & 63, s1 = (code >> 6) & 63, s2 = (code >> 12) & 63, s = code >> 18;
+        const int e1 = base + o;
+        rq_v2[r] = vertex2(e1, s1, partner(e1), s2, s);
+      }
+      __syncthreads();
+      for (int r = 0; r < qn; ++r) {
+        const int code = rq_code[r];
+        if ((code & 63) != lane) continue;
+        const int s1 = (code >> 6) & 63, s2 = (code >> 12) & 63, s = code >> 18;
+        const double v2 = rq_v2[r];
+        const double w = omega[q * NB3 + s], w1 = omega[q1 * NB3 + s1], w2 = omega[q2 * NB3 + s2];
+        const double dp = rq_dp[r] * v2, dm = rq_dm[r] * v2;
+        g0[s] += dp + dm;
+        acc[0][s][s1][lane] += dp * (w1 / w);
+        acc[1][s][s1][lane] += dm * (w1 / w);
+        acc[2][s][s2][lane] += (dp + dm) * (w2 / w);
+      }
+      __syncthreads();
+      qn = 0;
+    };
+    for (int s1 = 0; s1 < NB3; ++s1) {
+      const int m1 = q1 * NB3 + s1;
+      const bool ok1 = ok && phys[m1];
+      const double w1 = ok1 ? omega[m1] : 0.0, n1 = ok1 ? occ[m1] : 0.0;
+      for (int s2 = 0; s2 < NB3; ++s2) {
+        const int m2 = q2 * NB3 + s2;
+        const bool ok2 = ok1 && phys[m2];
+        double w2 = 0.0, n2 = 0.0, sp = 1.0, sm = 1.0;
+        if (ok2) {
+          w2 = omega[m2];
+          n2 = occ[m2];
           widths(p, vel, m1, m2, sp, sm);
-          for (int s = 0; s < NB3; ++s) {
-            const int mu = q * NB3 + s;
-            if (!phys[mu]) continue;
+        }
+        for (int s = 0; s < NB3; ++s) {
+          const int mu = q * NB3 + s;
+          bool pass = false;
+          double dp = 0.0, dm = 0.0;
+          if (ok2 && phys[mu]) {
             const double w = omega[mu];
-            double dp, dm;
-            process_rates(p, w, w1, w2, n1, n2, sp, sm, dp, dm);
-            if (dp == 0.0 && dm == 0.0) continue;
-            // V = sum_d e^{-i q1.R_d} sum_{e in d} A~[e][s] eta_jc(q1, s1) eta_kc(q2, s2)
-            double vr = 0.0, vi = 0.0;
-            for (int d = 0; d < p.n_d; ++d) {
-              double dr = 0.0, di = 0.0;
-              for (int e = d_ptr[d]; e < d_ptr[d + 1]; ++e) {
-                const double2 a = at[e * NB3 + s];
-                const size_t ox = (((size_t)q1 * NB3 + e_jc[e]) * NB3 + s1) * 2;
-                const size_t oy = (((size_t)q2 * NB3 + e_kc[e]) * NB3 + s2) * 2;
-                const double xr = evec[ox], xi = evec[ox + 1], yr = evec[oy], yi = evec[oy + 1];
-                const double zr = fma(xr, yr, -(xi * yi)), zi = fma(xr, yi, xi * yr);
-                // complex multiply-adds as fused multiply-adds into the sums
-                dr = fma(a.x, zr, dr);
-                dr = fma(-a.y, zi, dr);
-                di = fma(a.x, zi, di);
-                di = fma(a.y, zr, di);
-              }
-              const double2 f = ph[d];
-              vr = fma(f.x, dr, vr);
-              vr = fma(-f.y, di, vr);
-              vi = fma(f.x, di, vi);
-              vi = fma(f.y, dr, vi);
+            // the cut first (most candidates fail it), then the rates
+            if (fabs((w + w1) - w2) < 2.0 * sp || fabs((w - w1) - w2) < 2.0 * sm) {
+              process_rates(p, w, w1, w2, n1, n2, sp, sm, dp, dm);
+              pass = !(dp == 0.0 && dm == 0.0);
             }
-            const double v2 = pref * (vr * vr + vi * vi);
-            dp *= v2;
-            dm *= v2;
-            g0[s] += dp + dm;
-            acc[0][s][s1][lane] += dp * (w1 / w);
-            acc[1][s][s1][lane] += dm * (w1 / w);
-            acc[2][s][s2][lane] += (dp + dm) * (w2 / w);
           }
+          const unsigned long long mask = __ballot(pass);
+          if (mask == 0ull) continue;
+          if (qn + __popcll(mask) > kRowQueue) flush();
+          if (pass) {
+            const int r = qn + __popcll(mask & below);
+            rq_code[r] = lane | (s1 << 6) | (s2 << 12) | (s << 18);
+            rq_dp[r] = dp;
+            rq_dm[r] = dm;
+          }
+          qn += __popcll(mask);
         }
       }
     }
+    flush();
     __syncthreads();
     // three passes; within each the columns of different lanes differ
     if (ok) {
@@ -778,7 +857,7 @@ static BteWs bte_ws(const kaldo_crystal* c, long nq) {
 
 static bool bte_supported(const kaldo_crystal* c) {
   if (c->nb3 != 3 && c->nb3 != 6) return false;
-  return (size_t)c->bloch.n_e * c->nb3 * 16 <= 64 * 1024 && c->n_rep <= 64;
+  return (size_t)c->bloch.n_blk * 9 * c->nb3 * 16 <= 64 * 1024 && c->n_rep <= 64;
 }
 
 __global__ void bte_prepare(int n_modes, const double* __restrict__ omega, double inv_kt_hbar,
@@ -850,17 +929,19 @@ extern "C" int kaldo_scattering_matrix(const kaldo_crystal* c, const int32_t* me
   const size_t n2 = (size_t)n * n;
   KALDO_LAUNCH("bte_zero", bte_zero, dim3((unsigned)std::min<size_t>((n2 + 255) / 256, 1u << 20)),
                dim3(256), 0, st, n2, matrix);
-  const size_t lds = (size_t)c->bloch.n_e * nb3 * sizeof(double2);
+  const size_t lds = (size_t)c->bloch.n_blk * 9 * nb3 * sizeof(double2);
   const double pref = 2.0 * kPrefactor / (double)nq;
   const Fc3Bloch& bl = c->bloch;
   if (nb3 == 6)
     KALDO_LAUNCH("bte_rows", bte_rows<6>, dim3((unsigned)nq), dim3(64), lds, st, p, c->n_rep,
-                 c->d_rep, omega, vel, occ, phys, evec, phase, bl.d_ptr, bl.e_jc, bl.e_kc,
-                 bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix, gamma0);
+                 c->d_rep, omega, vel, occ, phys, evec, phase, bl.n_blk, bl.e_blk, bl.e_bg,
+                 bl.blk_d, bl.pair_ptr, bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix,
+                 gamma0);
   else
     KALDO_LAUNCH("bte_rows", bte_rows<3>, dim3((unsigned)nq), dim3(64), lds, st, p, c->n_rep,
-                 c->d_rep, omega, vel, occ, phys, evec, phase, bl.d_ptr, bl.e_jc, bl.e_kc,
-                 bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix, gamma0);
+                 c->d_rep, omega, vel, occ, phys, evec, phase, bl.n_blk, bl.e_blk, bl.e_bg,
+                 bl.blk_d, bl.pair_ptr, bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix,
+                 gamma0);
   KALDO_LAUNCH("bte_gmax", bte_gmax, dim3(1), dim3(1024), 0, st, n, gamma0, gmax);
   KALDO_LAUNCH("bte_decouple", bte_decouple, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                n, omega, gamma0, gmax, b->nu_min_thz, matrix);
