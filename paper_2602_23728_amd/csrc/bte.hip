@@ -29,7 +29,7 @@
 //                  column kind in LDS, written in three passes whose columns are a
 //                  bijection of q1 (no two lanes of a pass touch one element),
 //                  Gamma0 reduced in a fixed order and added to the diagonal
-//   bte_gmax, bte_decouple   the RTA selection
+//   bte_gmax, bte_flags, bte_decouple   the RTA selection
 //   lu_diag, lu_panels, lu_update, lu_gemm   blocked LU without pivoting
 //                  (64 x 64 blocks, panels of eight; the panels and updates
 //                  on the FP64 matrix cores)
@@ -364,18 +364,28 @@ __device__ __forceinline__ bool bte_active(double w, double g, double gmax, doub
   return (w / kTwoPi >= nu_min) && (g > kGammaFloorRel * gmax) && (g > 0.0);
 }
 
-// Modes without RTA conductivity: zero row and column, unit diagonal.
-__global__ void bte_decouple(long n, const double* __restrict__ omega,
-                             const double* __restrict__ g0, const double* __restrict__ gmax,
-                             double nu_min, double* __restrict__ mat) {
+// Which modes keep their RTA conductivity (1) or are decoupled (0).
+__global__ void bte_flags(long n, const double* __restrict__ omega, const double* __restrict__ g0,
+                          const double* __restrict__ gmax, double nu_min,
+                          uint8_t* __restrict__ act) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (bte_active(omega[i], g0[i], *gmax, nu_min)) return;
-  for (long j = 0; j < n; ++j) {
-    mat[i * n + j] = 0.0;
-    mat[j * n + i] = 0.0;
+  if (i < n) act[i] = bte_active(omega[i], g0[i], *gmax, nu_min) ? 1 : 0;
+}
+
+// Decoupled modes: zero row and column, unit diagonal.  One workgroup per
+// row j, its threads along the row: a decoupled row is written whole, the
+// row of a kept mode only at the decoupled columns (coalesced either way).
+__global__ __launch_bounds__(256) void bte_decouple(long n, const uint8_t* __restrict__ act,
+                                                    double* __restrict__ mat) {
+  const long j = blockIdx.x;
+  if (j >= n) return;
+  double* row = mat + j * n;
+  if (!act[j]) {
+    for (long i = threadIdx.x; i < n; i += 256) row[i] = (i == j) ? 1.0 : 0.0;
+  } else {
+    for (long i = threadIdx.x; i < n; i += 256)
+      if (!act[i]) row[i] = 0.0;
   }
-  mat[i * n + i] = 1.0;
 }
 
 // Right-hand side: v on active modes, 0 elsewhere; rhs[i][3].
@@ -825,7 +835,7 @@ __global__ void bte_sc_update(long n, const double* __restrict__ rhs,
 // ------------------------------------------------------------------ host
 
 struct BteWs {
-  size_t off_occ, off_phys, off_tr, off_phase, off_gmax, off_rhs, off_lam, off_y, off_y2,
+  size_t off_occ, off_phys, off_act, off_tr, off_phase, off_gmax, off_rhs, off_lam, off_y, off_y2,
       off_linv, off_uinv, off_kappa, total;
 };
 
@@ -841,6 +851,7 @@ static BteWs bte_ws(const kaldo_crystal* c, long nq) {
   };
   w.off_occ = take(8 * n);
   w.off_phys = take(n);
+  w.off_act = take(n);
   w.off_tr = take(4 * n);
   w.off_phase = take(16 * nq * (size_t)std::max(1, c->bloch.n_d));
   w.off_gmax = take(8);
@@ -915,6 +926,7 @@ extern "C" int kaldo_scattering_matrix(const kaldo_crystal* c, const int32_t* me
   const long n = nq * nb3;
   double* occ = reinterpret_cast<double*>(ws + w.off_occ);
   uint8_t* phys = ws + w.off_phys;
+  uint8_t* act = ws + w.off_act;
   int32_t* tr = reinterpret_cast<int32_t*>(ws + w.off_tr);
   double2* phase = reinterpret_cast<double2*>(ws + w.off_phase);
   double* gmax = reinterpret_cast<double*>(ws + w.off_gmax);
@@ -943,8 +955,9 @@ extern "C" int kaldo_scattering_matrix(const kaldo_crystal* c, const int32_t* me
                  bl.blk_d, bl.pair_ptr, bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix,
                  gamma0);
   KALDO_LAUNCH("bte_gmax", bte_gmax, dim3(1), dim3(1024), 0, st, n, gamma0, gmax);
-  KALDO_LAUNCH("bte_decouple", bte_decouple, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-               n, omega, gamma0, gmax, b->nu_min_thz, matrix);
+  KALDO_LAUNCH("bte_flags", bte_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+               omega, gamma0, gmax, b->nu_min_thz, act);
+  KALDO_LAUNCH("bte_decouple", bte_decouple, dim3((unsigned)n), dim3(256), 0, st, n, act, matrix);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
 }
