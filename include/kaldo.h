@@ -302,8 +302,13 @@ int kaldo_scattering_matrix(const kaldo_crystal* c, const int32_t* mesh, const d
  * Angstrom) by a blocked LU factorisation without pivoting (64 x 64 blocks,
  * trailing updates on the FP64 matrix cores), then
  * kappa_ab = 1/(N_q V) sum c v_a lambda_b (device double[9], W/(m K)).
- * `matrix` is overwritten by its LU factors.  A zero pivot sets the handle's
- * status (kaldo_device_status -> KALDO_ENUMERIC).  Enqueued; returns at once. */
+ * The decoupled modes (see above: lambda = 0) are left out of the
+ * factorisation, which runs on the block of the coupled ones.  `matrix` is
+ * overwritten: in each coupled row the coupled columns are moved to the
+ * front and the coupled block's LU factors stored there; the decoupled rows
+ * are untouched.  A zero pivot sets the handle's status (kaldo_device_status
+ * -> KALDO_ENUMERIC).  Synchronises `stream` once (the number of coupled modes
+ * sizes the factorisation); the rest is enqueued. */
 int kaldo_bte_solve(const kaldo_crystal* c, const int32_t* mesh, const double* omega,
                     const double* vel, const double* gamma0, double temperature,
                     double nu_min_thz, double* matrix, void* workspace, size_t workspace_bytes,

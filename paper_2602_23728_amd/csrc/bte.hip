@@ -389,6 +389,65 @@ __global__ __launch_bounds__(256) void bte_decouple(long n, const uint8_t* __res
 }
 
 // Right-hand side: v on active modes, 0 elsewhere; rhs[i][3].
+// The coupled modes in order: rows[a] = the a-th mode with act = 1, *count =
+// their number.  One workgroup; each thread counts a contiguous run of
+// modes, a block-wide scan places the runs.
+__global__ __launch_bounds__(1024) void bte_compact_index(long n, const uint8_t* __restrict__ act,
+                                                          int32_t* __restrict__ rows,
+                                                          int32_t* __restrict__ count) {
+  __shared__ int sums[1024];
+  const int tid = threadIdx.x;
+  const long per = (n + 1023) / 1024;
+  const long lo = tid * per < n ? tid * per : n, hi = lo + per < n ? lo + per : n;
+  int c = 0;
+  for (long i = lo; i < hi; ++i) c += act[i];
+  sums[tid] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = tid >= off ? sums[tid - off] : 0;
+    __syncthreads();
+    sums[tid] += v;
+    __syncthreads();
+  }
+  int r = sums[tid] - c;
+  for (long i = lo; i < hi; ++i)
+    if (act[i]) rows[r++] = (int32_t)i;
+  if (tid == 1023) *count = sums[1023];
+}
+
+// Moves the coupled columns of a coupled row to its front: row rows[a]
+// becomes (A[rows[a]][rows[0]], ..., A[rows[a]][rows[na - 1]], ...).  One
+// workgroup per row, in slices of 256 columns: a slice's values are all read
+// before any is written, and its targets lie before the sources of every
+// later slice (rows[b] >= b).
+__global__ __launch_bounds__(256) void bte_compact_cols(long na, long ld,
+                                                        const int32_t* __restrict__ rows,
+                                                        double* __restrict__ mat) {
+  const long a = blockIdx.x;
+  if (a >= na) return;
+  double* row = mat + (long)rows[a] * ld;
+  for (long b0 = 0; b0 < na; b0 += 256) {
+    const long b = b0 + threadIdx.x;
+    const double v = b < na ? row[rows[b]] : 0.0;
+    __syncthreads();
+    if (b < na) row[b] = v;
+    __syncthreads();
+  }
+}
+
+// dst[a] = src[rows[a]] (three components), and back: dst[rows[a]] = src[a]
+// over a zeroed dst.
+__global__ void bte_gather3(long na, const int32_t* __restrict__ rows,
+                            const double* __restrict__ src, double* __restrict__ dst) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < 3 * na) dst[k] = src[3 * (long)rows[k / 3] + k % 3];
+}
+__global__ void bte_scatter3(long na, const int32_t* __restrict__ rows,
+                             const double* __restrict__ src, double* __restrict__ dst) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < 3 * na) dst[3 * (long)rows[k / 3] + k % 3] = src[k];
+}
+
 __global__ void bte_rhs(long n, const double* __restrict__ omega, const double* __restrict__ vel,
                         const double* __restrict__ g0, const double* __restrict__ gmax,
                         double nu_min, double* __restrict__ rhs) {
@@ -434,7 +493,18 @@ __global__ __launch_bounds__(1024) void bte_kappa(long n, const double* __restri
 // Factor the diagonal block k (no pivoting) in LDS; write L\U back, and the
 // inverses of the unit lower L and of the upper U to linv/uinv [64][64].
 // Padding rows past n act as identity rows.
-__global__ __launch_bounds__(256) void lu_diag(long n, int k, double* __restrict__ mat,
+// The coupled block of the matrix as the LU sees it: element (i, j) of the
+// n x n coupled system sits at row rows[i] of the stored matrix (leading
+// dimension ld), column j (the coupled columns of each stored row are moved
+// to its front by bte_compact_cols).
+struct MatRows {
+  double* mat;
+  const int32_t* rows;
+  long ld;
+  __device__ double* row(long i) const { return mat + (long)rows[i] * ld; }
+};
+
+__global__ __launch_bounds__(256) void lu_diag(long n, int k, MatRows A,
                                                double* __restrict__ linv,
                                                double* __restrict__ uinv,
                                                int32_t* __restrict__ flags) {
@@ -464,7 +534,7 @@ __global__ __launch_bounds__(256) void lu_diag(long n, int k, double* __restrict
     for (int b = 0; b < 4; ++b) {
       const int i = ty + 16 * a, c = tx + 16 * b;
       const long gi = r0 + i, gc = r0 + c;
-      d[a][b] = (gi < n && gc < n) ? mat[gi * n + gc] : (i == c ? 1.0 : 0.0);
+      d[a][b] = (gi < n && gc < n) ? A.row(gi)[gc] : (i == c ? 1.0 : 0.0);
       xl[a][b] = xu[a][b] = (i == c) ? 1.0 : 0.0;
     }
 #pragma unroll
@@ -523,7 +593,7 @@ __global__ __launch_bounds__(256) void lu_diag(long n, int k, double* __restrict
     for (int b = 0; b < 4; ++b) {
       const int i = ty + 16 * a, c = tx + 16 * b;
       const long gi = r0 + i, gc = r0 + c;
-      if (gi < n && gc < n) mat[gi * n + gc] = d[a][b];
+      if (gi < n && gc < n) A.row(gi)[gc] = d[a][b];
       linv[i * B + c] = xl[a][b];
       uinv[i * B + c] = xu[a][b];
     }
@@ -561,7 +631,7 @@ struct BlockProduct {
 
 // Panels of step k: row blocks A_kj <- Linv A_kj (j > k, first nb - k - 1
 // workgroups), column blocks A_ik <- A_ik Uinv (i > k, the rest).
-__global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, double* __restrict__ mat,
+__global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, MatRows A,
                                                  const double* __restrict__ linv,
                                                  const double* __restrict__ uinv) {
   constexpr int B = kLuB;
@@ -575,7 +645,7 @@ __global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, double* 
   for (int idx = tid; idx < B * B; idx += 256) {
     const int i = idx / B, j = idx % B;
     const long gi = bi * B + i, gj = bj * B + j;
-    M[i][j] = (gi < n && gj < n) ? mat[gi * n + gj] : 0.0;
+    M[i][j] = (gi < n && gj < n) ? A.row(gi)[gj] : 0.0;
     T[i][j] = row ? linv[idx] : uinv[idx];
   }
   __syncthreads();
@@ -591,14 +661,14 @@ __global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, double* 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const long gi = bi * B + bp.row(a, r), gj = bj * B + bp.col(b);
-        if (gi < n && gj < n) mat[gi * n + gj] = bp.acc[a][b][r];
+        if (gi < n && gj < n) A.row(gi)[gj] = bp.acc[a][b][r];
       }
 }
 
 // Update of step k on a rectangle of blocks: A_ij -= A_ik A_kj for i in [i0,
 // i0 + ni), j in [j0, j0 + nj), one 64 x 64 block per workgroup.
 __global__ __launch_bounds__(256) void lu_update(long n, int k, int i0, int j0, int nj,
-                                                 double* __restrict__ mat) {
+                                                 MatRows A) {
   constexpr int B = kLuB;
   __shared__ double L[B][B + 1];
   __shared__ double U[B][B + 1];
@@ -607,9 +677,9 @@ __global__ __launch_bounds__(256) void lu_update(long n, int k, int i0, int j0, 
   for (int idx = tid; idx < B * B; idx += 256) {
     const int i = idx / B, j = idx % B;
     const long li = bi * B + i, lj = (long)k * B + j;
-    L[i][j] = (li < n && lj < n) ? mat[li * n + lj] : 0.0;
+    L[i][j] = (li < n && lj < n) ? A.row(li)[lj] : 0.0;
     const long ui = (long)k * B + i, uj = bj * B + j;
-    U[i][j] = (ui < n && uj < n) ? mat[ui * n + uj] : 0.0;
+    U[i][j] = (ui < n && uj < n) ? A.row(ui)[uj] : 0.0;
   }
   __syncthreads();
   BlockProduct bp;
@@ -621,7 +691,7 @@ __global__ __launch_bounds__(256) void lu_update(long n, int k, int i0, int j0, 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const long gi = bi * B + bp.row(a, r), gj = bj * B + bp.col(b);
-        if (gi < n && gj < n) mat[gi * n + gj] -= bp.acc[a][b][r];
+        if (gi < n && gj < n) A.row(gi)[gj] -= bp.acc[a][b][r];
       }
 }
 
@@ -638,7 +708,7 @@ constexpr int kLgK = 16;   // K slice
 constexpr int kLgLd = kLgT + 2;  // LDS row stride (doubles)
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void lu_gemm(long n, long r0, long kc, int kw, int ntl,
-                                               double* __restrict__ mat) {
+                                               MatRows A) {
   __shared__ double As[2][kLgK][kLgLd];  // [k][row]
   __shared__ double Bs[2][kLgK][kLgLd];  // [k][col]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -649,7 +719,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int ar = tid >> 1, ak = 8 * (tid & 1);
   const int bk = tid >> 4, bc = 8 * (tid & 15);
   const long ga = row0 + ar, gbc = col0 + bc;
-  const double* arow = mat + (ga < n ? ga : 0) * n;  // row ga (a valid row when ga >= n)
+  const double* arow = A.row(ga < n ? ga : 0);  // row ga (a valid row when ga >= n)
   double pa[8], pb[8];
   // slice k0: eight consecutive elements per operand and thread, from one
   // base address (constant offsets)
@@ -659,7 +729,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
     for (int t = 0; t < 8; ++t) pa[t] = (ga < n && ka + t < n) ? a[t] : 0.0;
     const long kb = k0 + bk;
-    const double* b = mat + (kb < n ? kb : 0) * n + gbc;
+    const double* b = A.row(kb < n ? kb : 0) + gbc;
 #pragma unroll
     for (int t = 0; t < 8; ++t) pb[t] = (kb < n && gbc + t < n) ? b[t] : 0.0;
   };
@@ -709,7 +779,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       for (int r = 0; r < 4; ++r) {
         // item r of lane l is row 4 r + l / 16, column l % 16
         const long gi = row0 + wm + 16 * a + 4 * r + lg, gj = col0 + wn + 16 * b + lr;
-        if (gi < n && gj < n) mat[gi * n + gj] -= acc[a][b][r];
+        if (gi < n && gj < n) A.row(gi)[gj] -= acc[a][b][r];
       }
 }
 
@@ -741,7 +811,7 @@ __global__ __launch_bounds__(256) void lu_tri(long n, int k, const double* __res
 }
 
 template <bool FORWARD>
-__global__ __launch_bounds__(256) void lu_rupdate(long n, int k, const double* __restrict__ mat,
+__global__ __launch_bounds__(256) void lu_rupdate(long n, int k, MatRows A,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ r) {
   constexpr int B = kLuB;
@@ -761,7 +831,7 @@ __global__ __launch_bounds__(256) void lu_rupdate(long n, int k, const double* _
     for (int t = sub; t < B; t += 4) {
       const long gc = (long)k * B + t;
       if (gc >= n) break;
-      const double a = mat[gi * n + gc];
+      const double a = A.row(gi)[gc];
       s0 += a * xk[t][0];
       s1 += a * xk[t][1];
       s2 += a * xk[t][2];
@@ -835,7 +905,8 @@ __global__ void bte_sc_update(long n, const double* __restrict__ rhs,
 // ------------------------------------------------------------------ host
 
 struct BteWs {
-  size_t off_occ, off_phys, off_act, off_tr, off_phase, off_gmax, off_rhs, off_lam, off_y, off_y2,
+  size_t off_occ, off_phys, off_act, off_rows, off_count, off_tr, off_phase, off_gmax, off_rhs,
+      off_lam, off_y, off_y2,
       off_linv, off_uinv, off_kappa, total;
 };
 
@@ -852,6 +923,8 @@ static BteWs bte_ws(const kaldo_crystal* c, long nq) {
   w.off_occ = take(8 * n);
   w.off_phys = take(n);
   w.off_act = take(n);
+  w.off_rows = take(4 * n);
+  w.off_count = take(4);
   w.off_tr = take(4 * n);
   w.off_phase = take(16 * nq * (size_t)std::max(1, c->bloch.n_d));
   w.off_gmax = take(8);
@@ -997,65 +1070,90 @@ extern "C" int kaldo_bte_solve(const kaldo_crystal* c, const int32_t* mesh, cons
                         workspace_bytes, w, nq, st);
   if (rc) return rc;
   auto* ws = static_cast<unsigned char*>(workspace);
-  const long n = nq * c->nb3;
-  const int nb = (int)((n + kLuB - 1) / kLuB);
+  const long n_all = nq * c->nb3;
   double* linv = reinterpret_cast<double*>(ws + w.off_linv);
   double* uinv = reinterpret_cast<double*>(ws + w.off_uinv);
   double* rhs = reinterpret_cast<double*>(ws + w.off_rhs);
+  double* lam_c = reinterpret_cast<double*>(ws + w.off_lam);
   double* y = reinterpret_cast<double*>(ws + w.off_y);
   double* gmax = reinterpret_cast<double*>(ws + w.off_gmax);
+  uint8_t* act = ws + w.off_act;
+  int32_t* rows = reinterpret_cast<int32_t*>(ws + w.off_rows);
+  int32_t* count = reinterpret_cast<int32_t*>(ws + w.off_count);
   const size_t blk = (size_t)kLuB * kLuB;
-  // Blocked right-looking LU in panels of kLuPanel blocks: the steps inside
-  // a panel update only the panel's columns (every row below) and the
-  // panel's rows (every column to the right); the rest of the trailing
-  // matrix takes one rank-(64 kLuPanel) product per panel (lu_gemm).
-  for (int k0 = 0; k0 < nb; k0 += kLuPanel) {
-    const int k1 = std::min(nb, k0 + kLuPanel);
-    for (int k = k0; k < k1; ++k) {
-      KALDO_LAUNCH("lu_diag", lu_diag, dim3(1), dim3(256), 0, st, n, k, matrix, linv + k * blk,
-                   uinv + k * blk, c->d_flags);
-      const int m = nb - k - 1;
-      if (m == 0) continue;
-      KALDO_LAUNCH("lu_panels", lu_panels, dim3(2 * m), dim3(256), 0, st, n, nb, k, matrix,
-                   linv + k * blk, uinv + k * blk);
-      const int pw = k1 - k - 1;  // panel columns (and rows) still to factor
-      if (pw > 0) {
-        // the panel's columns, every row below k
-        KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(m * pw)), dim3(256), 0, st, n, k, k + 1,
-                     k + 1, pw, matrix);
-        // the panel's rows, the columns past the panel
-        if (nb - k1 > 0)
-          KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(pw * (nb - k1))), dim3(256), 0, st, n,
-                       k, k + 1, k1, nb - k1, matrix);
+  // The decoupled modes (unit diagonal, zero row and column, lambda = 0)
+  // drop out: the factorisation runs on the coupled block only, reached
+  // through the row map and with its columns moved to the front of each
+  // row.  The host learns the coupled count (one synchronisation).
+  KALDO_LAUNCH("bte_flags", bte_flags, dim3((unsigned)((n_all + 255) / 256)), dim3(256), 0, st,
+               n_all, omega, gamma0, gmax, nu_min_thz, act);
+  KALDO_LAUNCH("bte_compact_index", bte_compact_index, dim3(1), dim3(1024), 0, st, n_all, act,
+               rows, count);
+  int32_t n_coupled = 0;
+  KALDO_HIP(hipMemcpyAsync(&n_coupled, count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  KALDO_HIP(hipStreamSynchronize(st));
+  const long n = n_coupled;
+  const dim3 g3all((unsigned)((3 * n_all + 255) / 256));
+  KALDO_LAUNCH("bte_zero", bte_zero, g3all, dim3(256), 0, st, (size_t)(3 * n_all), lambda);
+  if (n > 0) {
+    const MatRows A{matrix, rows, n_all};
+    KALDO_LAUNCH("bte_compact_cols", bte_compact_cols, dim3((unsigned)n), dim3(256), 0, st, n,
+                 n_all, rows, matrix);
+    const int nb = (int)((n + kLuB - 1) / kLuB);
+    // Blocked right-looking LU in panels of kLuPanel blocks: the steps inside
+    // a panel update only the panel's columns (every row below) and the
+    // panel's rows (every column to the right); the rest of the trailing
+    // matrix takes one rank-(64 kLuPanel) product per panel (lu_gemm).
+    for (int k0 = 0; k0 < nb; k0 += kLuPanel) {
+      const int k1 = std::min(nb, k0 + kLuPanel);
+      for (int k = k0; k < k1; ++k) {
+        KALDO_LAUNCH("lu_diag", lu_diag, dim3(1), dim3(256), 0, st, n, k, A, linv + k * blk,
+                     uinv + k * blk, c->d_flags);
+        const int m = nb - k - 1;
+        if (m == 0) continue;
+        KALDO_LAUNCH("lu_panels", lu_panels, dim3(2 * m), dim3(256), 0, st, n, nb, k, A,
+                     linv + k * blk, uinv + k * blk);
+        const int pw = k1 - k - 1;  // panel columns (and rows) still to factor
+        if (pw > 0) {
+          // the panel's columns, every row below k
+          KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(m * pw)), dim3(256), 0, st, n, k,
+                       k + 1, k + 1, pw, A);
+          // the panel's rows, the columns past the panel
+          if (nb - k1 > 0)
+            KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(pw * (nb - k1))), dim3(256), 0,
+                         st, n, k, k + 1, k1, nb - k1, A);
+        }
+      }
+      if (k1 < nb) {
+        const long r0 = (long)k1 * kLuB;
+        const int ntl = (int)((n - r0 + kLgT - 1) / kLgT);
+        KALDO_LAUNCH("lu_gemm", lu_gemm, dim3((unsigned)(ntl * ntl)), dim3(256), 0, st, n, r0,
+                     (long)k0 * kLuB, (k1 - k0) * kLuB, ntl, A);
       }
     }
-    if (k1 < nb) {
-      const long r0 = (long)k1 * kLuB;
-      const int ntl = (int)((n - r0 + kLgT - 1) / kLgT);
-      KALDO_LAUNCH("lu_gemm", lu_gemm, dim3((unsigned)(ntl * ntl)), dim3(256), 0, st, n, r0,
-                   (long)k0 * kLuB, (k1 - k0) * kLuB, ntl, matrix);
+    // the coupled right-hand sides, then forward: y = L^-1 b, the residual in
+    // y2 (starting as b)
+    double* r = reinterpret_cast<double*>(ws + w.off_y2);
+    const dim3 g3((unsigned)((3 * n + 255) / 256));
+    KALDO_LAUNCH("bte_gather3", bte_gather3, g3, dim3(256), 0, st, n, rows, rhs, r);
+    for (int k = 0; k < nb; ++k) {
+      KALDO_LAUNCH("lu_tri", lu_tri, dim3(1), dim3(256), 0, st, n, k, linv + k * blk, r, y);
+      if (nb - k - 1 > 0)
+        KALDO_LAUNCH("lu_rupdate", lu_rupdate<true>, dim3(nb - k - 1), dim3(256), 0, st, n, k,
+                     A, y, r);
     }
-  }
-  // forward: y = L^-1 b, the residual in y2 (starting as b)
-  double* r = reinterpret_cast<double*>(ws + w.off_y2);
-  const dim3 g3((unsigned)((3 * n + 255) / 256));
-  KALDO_LAUNCH("bte_copy3", bte_copy3, g3, dim3(256), 0, st, n, rhs, r);
-  for (int k = 0; k < nb; ++k) {
-    KALDO_LAUNCH("lu_tri", lu_tri, dim3(1), dim3(256), 0, st, n, k, linv + k * blk, r, y);
-    if (nb - k - 1 > 0)
-      KALDO_LAUNCH("lu_rupdate", lu_rupdate<true>, dim3(nb - k - 1), dim3(256), 0, st, n, k,
-                   matrix, y, r);
-  }
-  // backward: lambda = U^-1 y, the residual in y2 (starting as y)
-  KALDO_LAUNCH("bte_copy3", bte_copy3, g3, dim3(256), 0, st, n, y, r);
-  for (int k = nb - 1; k >= 0; --k) {
-    KALDO_LAUNCH("lu_tri", lu_tri, dim3(1), dim3(256), 0, st, n, k, uinv + k * blk, r, lambda);
-    if (k > 0)
-      KALDO_LAUNCH("lu_rupdate", lu_rupdate<false>, dim3(k), dim3(256), 0, st, n, k, matrix,
-                   lambda, r);
+    // backward: lambda = U^-1 y, the residual in y2 (starting as y)
+    KALDO_LAUNCH("bte_copy3", bte_copy3, g3, dim3(256), 0, st, n, y, r);
+    for (int k = nb - 1; k >= 0; --k) {
+      KALDO_LAUNCH("lu_tri", lu_tri, dim3(1), dim3(256), 0, st, n, k, uinv + k * blk, r, lam_c);
+      if (k > 0)
+        KALDO_LAUNCH("lu_rupdate", lu_rupdate<false>, dim3(k), dim3(256), 0, st, n, k, A, lam_c,
+                     r);
+    }
+    KALDO_LAUNCH("bte_scatter3", bte_scatter3, g3, dim3(256), 0, st, n, rows, lam_c, lambda);
   }
   const double scale = kKappaUnit / ((double)nq * c->volume);
-  KALDO_LAUNCH("bte_kappa", bte_kappa, dim3(1), dim3(1024), 0, st, n, omega, vel, lambda, gamma0,
+  KALDO_LAUNCH("bte_kappa", bte_kappa, dim3(1), dim3(1024), 0, st, n_all, omega, vel, lambda, gamma0,
                gmax, kHbar / (kKb * temperature), nu_min_thz, scale, kappa);
   KALDO_HIP(hipGetLastError());
   return KALDO_OK;
