@@ -102,10 +102,11 @@ __device__ __forceinline__ void process_rates(const LwParams& p, double w, doubl
 
 // ------------------------------------------------------------------ rows
 
-constexpr int kRowQueue = 256;  // passing candidates a wave queues before projecting them
+constexpr int kRowWaves = 3;    // waves per row workgroup, each over a third of the branches s
+constexpr int kRowQueue = 128;  // passing candidates a wave queues before projecting them
 
 template <int NB3>
-__global__ __launch_bounds__(64) void bte_rows(
+__global__ __launch_bounds__(64 * kRowWaves) void bte_rows(
     LwParams p, int n_rep, const int32_t* __restrict__ rep, const double* __restrict__ omega,
     const double* __restrict__ vel, const double* __restrict__ occ,
     const uint8_t* __restrict__ phys, const double* __restrict__ evec,
@@ -119,12 +120,19 @@ __global__ __launch_bounds__(64) void bte_rows(
   // (beta, gamma), phases e^{+i q.R''} folded in
   extern __shared__ double2 at[];
   constexpr int NB = NB3 / 3;
+  static_assert(NB3 % kRowWaves == 0, "the branches of q split evenly over the waves");
+  constexpr int SPW = NB3 / kRowWaves;  // branches s per wave
+  constexpr int BS = 64 * kRowWaves;
   __shared__ double acc[3][NB3][NB3][64];  // [kind][s][s' or s''][lane]
   __shared__ double2 phq[64];
   __shared__ double red[NB3][64];
-  __shared__ int rq_code[kRowQueue];  // lane | s1 << 6 | s2 << 12 | s << 18
-  __shared__ double rq_dp[kRowQueue], rq_dm[kRowQueue], rq_v2[kRowQueue];
-  const int lane = threadIdx.x;
+  __shared__ int rq_code_w[kRowWaves][kRowQueue];  // lane | s1 << 6 | s2 << 12 | s << 18
+  __shared__ double rq_dp_w[kRowWaves][kRowQueue], rq_dm_w[kRowWaves][kRowQueue],
+      rq_v2_w[kRowWaves][kRowQueue];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int s_lo = wv * SPW;  // this wave's branches of q: [s_lo, s_lo + SPW)
+  int* rq_code = rq_code_w[wv];
+  double *rq_dp = rq_dp_w[wv], *rq_dm = rq_dm_w[wv], *rq_v2 = rq_v2_w[wv];
   const int q = blockIdx.x;
   const int nq = p.nq;
   const size_t n = (size_t)nq * NB3;
@@ -133,10 +141,10 @@ __global__ __launch_bounds__(64) void bte_rows(
   bool any = false;
   for (int s = 0; s < NB3; ++s) any = any || phys[q * NB3 + s];
   if (!any) {
-    if (lane < NB3) gamma0[q * NB3 + lane] = 0.0;
+    if (tid < NB3) gamma0[q * NB3 + tid] = 0.0;
     return;
   }
-  for (int l = lane; l < n_rep; l += 64) {
+  for (int l = tid; l < n_rep; l += BS) {
     const int32_t* r = rep + 3 * l;
     const int m0 = ((a0 * r[0]) % N0 + N0) % N0, m1 = ((a1 * r[1]) % N1 + N1) % N1,
               m2 = ((a2 * r[2]) % N2 + N2) % N2;
@@ -145,9 +153,9 @@ __global__ __launch_bounds__(64) void bte_rows(
     sincospi(2.0 * f, &sn, &cs);
     phq[l] = make_double2(cs, sn);
   }
-  for (int k = lane; k < n_blk * 9 * NB3; k += 64) at[k] = make_double2(0.0, 0.0);
+  for (int k = tid; k < n_blk * 9 * NB3; k += BS) at[k] = make_double2(0.0, 0.0);
   __syncthreads();
-  for (int k = lane; k < p.n_e * NB3; k += 64) {
+  for (int k = tid; k < p.n_e * NB3; k += BS) {
     const int e = k / NB3, s = k % NB3;
     double re = 0.0, im = 0.0;
     for (int t = t_ptr[e]; t < t_ptr[e + 1]; ++t) {
@@ -219,29 +227,37 @@ __global__ __launch_bounds__(64) void bte_rows(
     }
     return pref * (vr * vr + vi * vi);
   };
-  // A round takes 64 partners q1, one per lane.  Each lane classifies its
-  // (s1, s2, s) candidates in that order; the passing ones go to a queue in
-  // LDS (slots by ballot: candidate order, lanes ascending), whose vertices
-  // all 64 lanes then compute; each lane then takes its own entries back in
-  // queue order, so every sum sees the terms in the order of the loops.
+  // A round takes 64 partners q1, one per lane of every wave; wave w takes
+  // the branches s of q in [w SPW, (w + 1) SPW).  Each lane classifies its
+  // (s1, s2, s) candidates in that order; the passing ones go to its wave's
+  // queue in LDS (slots by ballot: candidate order, lanes ascending), whose
+  // vertices all 64 lanes of the wave then compute; each lane then takes its
+  // own entries back in queue order, so every sum sees the terms in the order
+  // of the loops.  A wave's queue is its own: a wave-level fence and barrier
+  // order its steps.
   const unsigned long long below = (1ull << lane) - 1ull;
+  auto wave_sync = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  };
   for (int base = 0; base < nq; base += 64) {
     const int q1 = base + lane;
     const bool ok = q1 < nq;
     for (int k = 0; k < 3; ++k)
-      for (int s = 0; s < NB3; ++s)
+      for (int s = s_lo; s < s_lo + SPW; ++s)
         for (int u = 0; u < NB3; ++u) acc[k][s][u][lane] = 0.0;
     const int q2 = ok ? partner(q1) : 0;
     int qn = 0;  // entries in the queue (the same in every lane)
     auto flush = [&]() {
-      __syncthreads();
+      wave_sync();
       for (int r = lane; r < qn; r += 64) {
         const int code = rq_code[r];
         const int o = code & 63, s1 = (code >> 6) & 63, s2 = (code >> 12) & 63, s = code >> 18;
         const int e1 = base + o;
         rq_v2[r] = vertex2(e1, s1, partner(e1), s2, s);
       }
-      __syncthreads();
+      wave_sync();
       for (int r = 0; r < qn; ++r) {
         const int code = rq_code[r];
         if ((code & 63) != lane) continue;
@@ -254,7 +270,7 @@ __global__ __launch_bounds__(64) void bte_rows(
         acc[1][s][s1][lane] += dm * (w1 / w);
         acc[2][s][s2][lane] += (dp + dm) * (w2 / w);
       }
-      __syncthreads();
+      wave_sync();
       qn = 0;
     };
     for (int s1 = 0; s1 < NB3; ++s1) {
@@ -270,7 +286,7 @@ __global__ __launch_bounds__(64) void bte_rows(
           n2 = occ[m2];
           widths(p, vel, m1, m2, sp, sm);
         }
-        for (int s = 0; s < NB3; ++s) {
+        for (int s = s_lo; s < s_lo + SPW; ++s) {
           const int mu = q * NB3 + s;
           bool pass = false;
           double dp = 0.0, dm = 0.0;
@@ -299,7 +315,7 @@ __global__ __launch_bounds__(64) void bte_rows(
     __syncthreads();
     // three passes; within each the columns of different lanes differ
     if (ok) {
-      for (int s = 0; s < NB3; ++s) {
+      for (int s = s_lo; s < s_lo + SPW; ++s) {
         double* row = mat + (size_t)(q * NB3 + s) * n;
         for (int u = 0; u < NB3; ++u) {
           const double x = acc[0][s][u][lane];
@@ -309,7 +325,7 @@ __global__ __launch_bounds__(64) void bte_rows(
     }
     __syncthreads();
     if (ok) {
-      for (int s = 0; s < NB3; ++s) {
+      for (int s = s_lo; s < s_lo + SPW; ++s) {
         double* row = mat + (size_t)(q * NB3 + s) * n;
         for (int u = 0; u < NB3; ++u) {
           const double x = acc[1][s][u][lane];
@@ -319,7 +335,7 @@ __global__ __launch_bounds__(64) void bte_rows(
     }
     __syncthreads();
     if (ok) {
-      for (int s = 0; s < NB3; ++s) {
+      for (int s = s_lo; s < s_lo + SPW; ++s) {
         double* row = mat + (size_t)(q * NB3 + s) * n;
         for (int u = 0; u < NB3; ++u) {
           const double x = acc[2][s][u][lane];
@@ -330,16 +346,16 @@ __global__ __launch_bounds__(64) void bte_rows(
     __syncthreads();
   }
   // Gamma0: fixed-order tree over the lanes, then onto the diagonal
-  for (int s = 0; s < NB3; ++s) red[s][lane] = g0[s];
+  for (int s = s_lo; s < s_lo + SPW; ++s) red[s][lane] = g0[s];
   __syncthreads();
   for (int w = 32; w > 0; w >>= 1) {
     if (lane < w)
-      for (int s = 0; s < NB3; ++s) red[s][lane] += red[s][lane + w];
+      for (int s = s_lo; s < s_lo + SPW; ++s) red[s][lane] += red[s][lane + w];
     __syncthreads();
   }
-  if (lane < NB3) {
-    const int mu = q * NB3 + lane;
-    const double g = phys[mu] ? red[lane][0] : 0.0;
+  if (lane < SPW) {
+    const int s = s_lo + lane, mu = q * NB3 + s;
+    const double g = phys[mu] ? red[s][0] : 0.0;
     gamma0[mu] = g;
     mat[(size_t)mu * n + mu] += g;
   }
@@ -1018,12 +1034,12 @@ extern "C" int kaldo_scattering_matrix(const kaldo_crystal* c, const int32_t* me
   const double pref = 2.0 * kPrefactor / (double)nq;
   const Fc3Bloch& bl = c->bloch;
   if (nb3 == 6)
-    KALDO_LAUNCH("bte_rows", bte_rows<6>, dim3((unsigned)nq), dim3(64), lds, st, p, c->n_rep,
+    KALDO_LAUNCH("bte_rows", bte_rows<6>, dim3((unsigned)nq), dim3(64 * kRowWaves), lds, st, p, c->n_rep,
                  c->d_rep, omega, vel, occ, phys, evec, phase, bl.n_blk, bl.e_blk, bl.e_bg,
                  bl.blk_d, bl.pair_ptr, bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix,
                  gamma0);
   else
-    KALDO_LAUNCH("bte_rows", bte_rows<3>, dim3((unsigned)nq), dim3(64), lds, st, p, c->n_rep,
+    KALDO_LAUNCH("bte_rows", bte_rows<3>, dim3((unsigned)nq), dim3(64 * kRowWaves), lds, st, p, c->n_rep,
                  c->d_rep, omega, vel, occ, phys, evec, phase, bl.n_blk, bl.e_blk, bl.e_bg,
                  bl.blk_d, bl.pair_ptr, bl.t_ptr, bl.t_i, bl.t_l2, bl.t_coef, tr, pref, matrix,
                  gamma0);
