@@ -88,6 +88,51 @@ def test_direct_inversion_matches_oracle(name):
     c.close()
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_direct_inversion_with_a_raised_floor(name):
+    """The solve leaves out every mode below its own nu_min: with the floor
+    at the 40th percentile of the frequencies a scattered subset of modes
+    drops out of the factorisation, whose solution must still be the
+    oracle's on the remaining modes (and zero on the others)."""
+    mk, mesh = CASES[name]
+    m = mk()
+    nq = int(np.prod(mesh))
+    c = K.Crystal.from_model(m)
+    om, ev, ve = oph.phonons(m, mesh)
+    mat, g0 = K.scattering_matrix(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT)
+    nu = om.ravel() / (2 * np.pi)
+    floor = float(np.percentile(nu[nu > 0], 40))
+    lam, kap = K.bte_solve(c, mesh, dev(om), dev(ve), g0, 300.0, floor, mat)
+    lam, kap = host(lam), host(kap)
+    c.device_status()
+    og0, og1, _, _ = oracle_matrix(m, mesh, om, ev, ve, B_ADAPT)
+    act = obte.active_modes(om, og0, floor)
+    assert 0 < act.sum() < act.size
+    olam = obte.solve_inverse(og0, og1, ve, act)
+    ok = obte.kappa_from_lambda(om, ve, olam, 300.0, m.volume, nq, act)
+    assert np.all(lam.reshape(-1, 3)[~act.ravel()] == 0.0)
+    assert np.max(np.abs(lam - olam)) <= 1e-8 * np.abs(olam).max()
+    assert np.max(np.abs(kap - ok)) <= 1e-8 * abs(np.trace(ok) / 3)
+    c.close()
+
+
+def test_direct_inversion_with_every_mode_decoupled():
+    """A floor above every frequency leaves nothing to factorise: lambda and
+    kappa are zero and the matrix is not touched."""
+    mk, mesh = CASES["diamond"]
+    m = mk()
+    c = K.Crystal.from_model(m)
+    om, ev, ve = oph.phonons(m, mesh)
+    mat, g0 = K.scattering_matrix(c, mesh, dev(om), dev(ev), dev(ve), 300.0, B_ADAPT)
+    before = host(mat).copy()
+    lam, kap = K.bte_solve(c, mesh, dev(om), dev(ve), g0, 300.0, 1e6, mat)
+    lam, kap = host(lam), host(kap)
+    c.device_status()
+    assert np.all(lam == 0.0) and np.all(kap == 0.0)
+    assert np.array_equal(host(mat), before)
+    c.close()
+
+
 def test_self_consistent_iteration_matches_oracle():
     mk, mesh = CASES["random"]
     m = mk()
