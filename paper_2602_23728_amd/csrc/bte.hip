@@ -33,7 +33,7 @@
 //   lu_diag, lu_panels, lu_update, lu_gemm   blocked LU without pivoting
 //                  (64 x 64 blocks, panels of eight; the panels and updates
 //                  on the FP64 matrix cores)
-//   lu_tri, lu_rupdate   the two triangular sweeps for the 3 RHS
+//   lu_step<FORWARD>   the two triangular sweeps for the 3 RHS, one launch per block
 //   bte_gemv, bte_sc_init, bte_sc_update   the iteration of Eq. sc_iter
 //   bte_kappa      Eq. kappa_general, fixed-order reduction
 // Every reduction and every sequence of additions into one matrix element
@@ -681,15 +681,19 @@ __global__ __launch_bounds__(256) void lu_panels(long n, int nb, int k, MatRows 
       }
 }
 
-// Update of step k on a rectangle of blocks: A_ij -= A_ik A_kj for i in [i0,
-// i0 + ni), j in [j0, j0 + nj), one 64 x 64 block per workgroup.
-__global__ __launch_bounds__(256) void lu_update(long n, int k, int i0, int j0, int nj,
-                                                 MatRows A) {
+// Update of step k on two rectangles of blocks: A_ij -= A_ik A_kj for i in
+// [i0, i0 + ni), j in [j0, j0 + nj) (the first n1 workgroups), then for i in
+// [i0b, ...), j in [j0b, j0b + njb); one 64 x 64 block per workgroup.  The
+// rectangles are disjoint and read only row and column k.
+__global__ __launch_bounds__(256) void lu_update(long n, int k, int i0, int j0, int nj, int n1,
+                                                 int i0b, int j0b, int njb, MatRows A) {
   constexpr int B = kLuB;
   __shared__ double L[B][B + 1];
   __shared__ double U[B][B + 1];
   const int tid = threadIdx.x;
-  const long bi = i0 + blockIdx.x / nj, bj = j0 + blockIdx.x % nj;
+  const int wb = (int)blockIdx.x;
+  const long bi = wb < n1 ? i0 + wb / nj : i0b + (wb - n1) / njb,
+             bj = wb < n1 ? j0 + wb % nj : j0b + (wb - n1) % njb;
   for (int idx = tid; idx < B * B; idx += 256) {
     const int i = idx / B, j = idx % B;
     const long li = bi * B + i, lj = (long)k * B + j;
@@ -800,17 +804,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 }
 
 // Triangular sweeps with 3 right-hand sides, right-looking: the residual r
-// starts as the right-hand side; step k solves block k, x_k = Tinv_k r_k
-// (lu_tri, one workgroup), then removes its contribution from the blocks
-// still to solve, r_i -= A_ik x_k (lu_rupdate, one workgroup per block:
-// i > k forward with the L blocks, i < k backward with the U blocks).  Every
-// r_i is updated in the order of k: the sums are fixed-order.
-__global__ __launch_bounds__(256) void lu_tri(long n, int k, const double* __restrict__ tinv,
-                                              const double* __restrict__ r,
-                                              double* __restrict__ x) {
+// starts as the right-hand side; step k solves block k, x_k = Tinv_k r_k,
+// and removes its contribution from the blocks still to solve, r_i -= A_ik
+// x_k (i > k forward with the L blocks, i < k backward with the U blocks),
+// in one launch: every workgroup forms x_k in LDS, workgroup 0 stores it and
+// each other one updates one block.  Every r_i is updated in the order of k:
+// the sums are fixed-order.
+template <bool FORWARD>
+__global__ __launch_bounds__(256) void lu_step(long n, int k, const double* __restrict__ tinv,
+                                               MatRows A, double* __restrict__ x,
+                                               double* __restrict__ r) {
   constexpr int B = kLuB;
   __shared__ double rk[B][3];
-  const int tid = threadIdx.x;
+  __shared__ double xk[B][3];
+  __shared__ double part[4][B][3];
+  const int tid = threadIdx.x, row = tid >> 2, sub = tid & 3;
   if (tid < B * 3) {
     const int i = tid / 3, c = tid % 3;
     const long g = (long)k * B + i;
@@ -821,26 +829,18 @@ __global__ __launch_bounds__(256) void lu_tri(long n, int k, const double* __res
     const int i = tid / 3, c = tid % 3;
     double s = 0.0;
     for (int t = 0; t < B; ++t) s += tinv[i * B + t] * rk[t][c];
-    const long g = (long)k * B + i;
-    if (g < n) x[3 * g + c] = s;
-  }
-}
-
-template <bool FORWARD>
-__global__ __launch_bounds__(256) void lu_rupdate(long n, int k, MatRows A,
-                                                  const double* __restrict__ x,
-                                                  double* __restrict__ r) {
-  constexpr int B = kLuB;
-  __shared__ double xk[B][3];
-  __shared__ double part[4][B][3];
-  const int tid = threadIdx.x, row = tid >> 2, sub = tid & 3;
-  const long bi = FORWARD ? k + 1 + (long)blockIdx.x : (long)blockIdx.x;
-  if (tid < B * 3) {
-    const int i = tid / 3, c = tid % 3;
-    const long g = (long)k * B + i;
-    xk[i][c] = g < n ? x[3 * g + c] : 0.0;
+    xk[i][c] = s;
   }
   __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid < B * 3) {
+      const int i = tid / 3, c = tid % 3;
+      const long g = (long)k * B + i;
+      if (g < n) x[3 * g + c] = xk[i][c];
+    }
+    return;
+  }
+  const long bi = FORWARD ? k + (long)blockIdx.x : (long)blockIdx.x - 1;
   const long gi = bi * B + row;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   if (gi < n)
@@ -1131,13 +1131,11 @@ extern "C" int kaldo_bte_solve(const kaldo_crystal* c, const int32_t* mesh, cons
                      linv + k * blk, uinv + k * blk);
         const int pw = k1 - k - 1;  // panel columns (and rows) still to factor
         if (pw > 0) {
-          // the panel's columns, every row below k
-          KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(m * pw)), dim3(256), 0, st, n, k,
-                       k + 1, k + 1, pw, A);
-          // the panel's rows, the columns past the panel
-          if (nb - k1 > 0)
-            KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(pw * (nb - k1))), dim3(256), 0,
-                         st, n, k, k + 1, k1, nb - k1, A);
+          // the panel's columns, every row below k; then the panel's rows,
+          // the columns past the panel
+          const int nr = nb - k1 > 0 ? pw * (nb - k1) : 0;
+          KALDO_LAUNCH("lu_update", lu_update, dim3((unsigned)(m * pw + nr)), dim3(256), 0, st, n,
+                       k, k + 1, k + 1, pw, m * pw, k + 1, k1, nb - k1 > 0 ? nb - k1 : 1, A);
         }
       }
       if (k1 < nb) {
@@ -1152,20 +1150,14 @@ extern "C" int kaldo_bte_solve(const kaldo_crystal* c, const int32_t* mesh, cons
     double* r = reinterpret_cast<double*>(ws + w.off_y2);
     const dim3 g3((unsigned)((3 * n + 255) / 256));
     KALDO_LAUNCH("bte_gather3", bte_gather3, g3, dim3(256), 0, st, n, rows, rhs, r);
-    for (int k = 0; k < nb; ++k) {
-      KALDO_LAUNCH("lu_tri", lu_tri, dim3(1), dim3(256), 0, st, n, k, linv + k * blk, r, y);
-      if (nb - k - 1 > 0)
-        KALDO_LAUNCH("lu_rupdate", lu_rupdate<true>, dim3(nb - k - 1), dim3(256), 0, st, n, k,
-                     A, y, r);
-    }
+    for (int k = 0; k < nb; ++k)
+      KALDO_LAUNCH("lu_step", lu_step<true>, dim3(nb - k), dim3(256), 0, st, n, k, linv + k * blk,
+                   A, y, r);
     // backward: lambda = U^-1 y, the residual in y2 (starting as y)
     KALDO_LAUNCH("bte_copy3", bte_copy3, g3, dim3(256), 0, st, n, y, r);
-    for (int k = nb - 1; k >= 0; --k) {
-      KALDO_LAUNCH("lu_tri", lu_tri, dim3(1), dim3(256), 0, st, n, k, uinv + k * blk, r, lam_c);
-      if (k > 0)
-        KALDO_LAUNCH("lu_rupdate", lu_rupdate<false>, dim3(k), dim3(256), 0, st, n, k, A, lam_c,
-                     r);
-    }
+    for (int k = nb - 1; k >= 0; --k)
+      KALDO_LAUNCH("lu_step", lu_step<false>, dim3(k + 1), dim3(256), 0, st, n, k, uinv + k * blk,
+                   A, lam_c, r);
     KALDO_LAUNCH("bte_scatter3", bte_scatter3, g3, dim3(256), 0, st, n, rows, lam_c, lambda);
   }
   const double scale = kKappaUnit / ((double)nq * c->volume);
