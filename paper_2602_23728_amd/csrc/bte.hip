@@ -22,17 +22,22 @@
 // Kernels:
 //   bte_tr_map     time-reversal partner of every mode (largest overlap)
 //   bte_zero       clears the n x n matrix
-//   bte_rows<NB3>  one workgroup (one wave) per q: A~_q (FP64, LDS, by atom
-//                  block), then the partners q1 in rounds of 64 (one per
-//                  lane): exact FP64 cut, the passing candidates queued in LDS
-//                  and their vertices computed by all lanes, per-lane sums per
-//                  column kind in LDS, written in three passes whose columns are a
-//                  bijection of q1 (no two lanes of a pass touch one element),
-//                  Gamma0 reduced in a fixed order and added to the diagonal
+//   bte_rows<NB3>  one workgroup per q, three waves each over a third of
+//                  the branches of q: A~_q (FP64, LDS, by atom block), then
+//                  the partners q1 in rounds of 64 (one per lane): exact FP64
+//                  cut, the passing candidates queued in the wave's LDS queue
+//                  and their vertices computed by all its lanes, per-lane sums
+//                  per column kind in LDS, written in three passes whose
+//                  columns are a bijection of q1 (no two lanes of a pass touch
+//                  one element), Gamma0 reduced in a fixed order and added to
+//                  the diagonal
 //   bte_gmax, bte_flags, bte_decouple   the RTA selection
-//   lu_diag, lu_panels, lu_update, lu_gemm   blocked LU without pivoting
-//                  (64 x 64 blocks, panels of eight; the panels and updates
-//                  on the FP64 matrix cores)
+//   bte_compact_index, bte_compact_cols, bte_gather3, bte_scatter3   the
+//                  solve's restriction to the coupled modes (row map, coupled
+//                  columns moved to the front of each coupled row)
+//   lu_diag, lu_panels, lu_update, lu_gemm   blocked LU without pivoting of
+//                  the coupled block (64 x 64 blocks, panels of eight; the
+//                  panels and updates on the FP64 matrix cores)
 //   lu_step<FORWARD>   the two triangular sweeps for the 3 RHS, one launch per block
 //   bte_gemv, bte_sc_init, bte_sc_update   the iteration of Eq. sc_iter
 //   bte_kappa      Eq. kappa_general, fixed-order reduction
