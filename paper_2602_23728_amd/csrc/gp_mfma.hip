@@ -177,16 +177,20 @@ __device__ __forceinline__ GmTileInfo gm_tile(int t, int nt, bool sym) {
 
 // Compacted list of the live (mode, tile) pairs of a batch, in (mode, tile)
 // order: list[k] = jb * n_tri + t.  One workgroup, fixed-order scan.
-__global__ __launch_bounds__(1024) void gm_live_list(LwParams p, int nt, int n_tri, int m0, int nb,
+__global__ __launch_bounds__(1024) void gm_live_list(LwParams p, int nt, int n_tri, int n,
                                                      const double* __restrict__ omega,
                                                      const uint8_t* __restrict__ phys,
                                                      const uint8_t* __restrict__ sel,
                                                      const double* __restrict__ brange,
-                                                     int32_t* __restrict__ list,
-                                                     int32_t* __restrict__ count) {
+                                                     int32_t* __restrict__ lists) {
+  // one workgroup per batch of kMBatch modes; batch b's list starts at
+  // lists + b (kMBatch n_tri + 1), its count is the region's last entry
   __shared__ int wave_tot[16];
   __shared__ int carry;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = (int)blockIdx.x * kMBatch, nb = min(kMBatch, n - m0);
+  int32_t* list = lists + (size_t)blockIdx.x * ((size_t)kMBatch * n_tri + 1);
+  int32_t* count = list + (size_t)kMBatch * n_tri;
   if (tid == 0) carry = 0;
   __syncthreads();
   const int total = nb * n_tri;
@@ -618,7 +622,7 @@ size_t gm_workspace_bytes(const kaldo_crystal* c, int prec) {
   take(n * n_tri * 8);                     // partials
   take(nt * 2 * 8);                        // block frequency ranges
   take((size_t)kMBatch * nt);              // W column blocks needed per mode
-  take((size_t)kMBatch * n_tri * 4 + 4);   // live (mode, tile) list and its count
+  take((n + kMBatch - 1) / kMBatch * ((size_t)kMBatch * n_tri + 1) * 4);  // live lists and counts
   return o;
 }
 
@@ -657,8 +661,9 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
   double* partial = reinterpret_cast<double*>(take((size_t)n * n_tri * 8));
   double* brange = reinterpret_cast<double*>(take((size_t)nt * 2 * 8));
   uint8_t* need = reinterpret_cast<uint8_t*>(take((size_t)kMBatch * nt));
-  int32_t* live_list = reinterpret_cast<int32_t*>(take((size_t)kMBatch * n_tri * 4 + 4));
-  int32_t* live_count = live_list + (size_t)kMBatch * n_tri;
+  const int n_batch = (n + kMBatch - 1) / kMBatch;
+  const size_t live_stride = (size_t)kMBatch * n_tri + 1;
+  int32_t* live_lists = reinterpret_cast<int32_t*>(take((size_t)n_batch * live_stride * 4));
   const long n_part = (long)n * n_tri;
   KALDO_LAUNCH("gm_zero", gm_zero, dim3((unsigned)((n_part + 255) / 256)), dim3(256), 0, st, n_part, partial);
   const long nn = (long)np * np;
@@ -668,8 +673,13 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
                et32, eth, etl, flags);
   KALDO_LAUNCH("gm_prep_e", gm_prep_e, dim3((unsigned)(((long)n * n + 255) / 256)), dim3(256), 0, st, n,
                evec, e32);
+  // the live (mode, tile) lists of every batch at once, one workgroup each
+  KALDO_LAUNCH("gm_live_list", gm_live_list, dim3((unsigned)n_batch), dim3(1024), 0, st, p, nt, n_tri,
+               n, omega, phys, sel, brange, live_lists);
   for (int m0 = 0; m0 < n; m0 += kMBatch) {
     const int nb = std::min(kMBatch, n - m0);
+    int32_t* live_list = live_lists + (size_t)(m0 / kMBatch) * live_stride;
+    int32_t* live_count = live_list + (size_t)kMBatch * n_tri;
     static_assert(kMBatch % 256 == 0, "whole 256-mode halves per batch");
     if (c->gamma.max_row > 0)
       KALDO_LAUNCH("gm_avals", gm_avals, dim3((unsigned)c->gamma.max_row, (unsigned)(np / kAvRows),
@@ -681,8 +691,6 @@ int run_gm(const kaldo_crystal* c, const LwParams& p, const double* omega, const
     KALDO_LAUNCH("gm_spmm", gm_spmm, dim3(np / kSpmmRows, np / kSpmmCols, (nb + kSpmmModes - 1) / kSpmmModes),
                  dim3(256), spmm_lds, st, n, np, nb, c->gamma.n_rtiles, c->gamma.max_row,
                  c->gamma.col_ell, c->gamma.tile_u_ptr, c->gamma.tile_u, av, e32, wt32, wth, wtl, nt, need);
-    KALDO_LAUNCH("gm_live_list", gm_live_list, dim3(1), dim3(1024), 0, st, p, nt, n_tri, m0, nb, omega,
-                 phys, sel, brange, live_list, live_count);
     if (split)
       KALDO_LAUNCH("gm_gemm_bf16x3", gm_gemm<true>, dim3(n_tri * nb), dim3(256), 0, st, p, n, np,
                    m0, n_tri, et32, eth, etl, wt32, wth, wtl, omega, occ, phys, live_list,
