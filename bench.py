@@ -224,21 +224,37 @@ def crystal_step(K, torch, c, cfg, prec):
     return step, dict(om=om, ev=ev, ve=ve, gam=gam, kap=kap)
 
 
-def timed(K, torch, step, steps, warmup, name):
+def timed(K, torch, step, steps, warmup, name, plain=False):
+    """Wall time per step over `steps` steps after `warmup`, and the library's
+    per-kernel HIP-event times.  By default the kernels are timed in the same
+    steps (the headline: its roofline divides by the kernel's average over the
+    timed region).  With plain=True the steps are timed without the
+    per-kernel events (two event records per launch cost several microseconds
+    of GPU time each, which matters for the launch-heavy legs) and the kernel
+    times come from a second pass of as many steps."""
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     log(f"{name}: warmup done ({warmup} steps), timing {steps} steps")
-    K.lib().kaldo_profile_begin()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+
+    def run():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    if plain:
+        elapsed = run()
+        K.lib().kaldo_profile_begin()
+        run()
+    else:
+        K.lib().kaldo_profile_begin()
+        elapsed = run()
     prof = profile_read(K)
     ms = 1e3 * elapsed / steps
-    log(f"{name}: {ms:.3f} ms/step; kernels: " +
+    log(f"{name}: {ms:.3f} ms/step{' (kernels from a profiled pass)' if plain else ''}; kernels: " +
         ", ".join(f"{k} {v[1] / v[0]:.3f} ms" for k, v in prof.items()))
     return ms, prof
 
@@ -296,7 +312,7 @@ def gamma_point_leg(a, K, torch, cfg, model, steps, warmup):
         def step():
             K.linewidths_gamma(c, om, E, cfg.temperature, cfg.broadening, prec, workspace=ws,
                                out=gam)
-        ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} {name}")
+        ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} {name}", plain=True)
         per = {k: v[1] / steps for k, v in prof.items()}
         gemm = sum(v for k, v in per.items() if k.startswith("gm_gemm"))
         proj = gemm + sum(v for k, v in per.items() if k in ("gm_avals", "gm_spmm", "gm_fused"))
@@ -341,7 +357,7 @@ def bte_leg(K, torch, steps, warmup):
         state["lk"] = K.bte_solve(c, mesh, om, ve, g0, cfg.temperature,
                                   cfg.broadening.nu_min_thz, mat, workspace=ws)
 
-    ms, prof = timed(K, torch, step, steps, warmup, "C2 full BTE")
+    ms, prof = timed(K, torch, step, steps, warmup, "C2 full BTE", plain=True)
     c.device_status()
     per = {k: v[1] / steps for k, v in prof.items()}
     solve_side = ("bte_compact_index", "bte_compact_cols", "bte_gather3", "bte_scatter3",
@@ -397,7 +413,7 @@ def tsweep_leg(K, torch, cfg, model, c, steps, warmup, n_temps=16, direct_gamma=
 
     def step():
         K.tcache_gamma(c, cache, om, b.nu_min_thz, temps, workspace=gws, out=out)
-    ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} sweep of {n_temps} T")
+    ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} sweep of {n_temps} T", plain=True)
     c.device_status()
     launches, total = prof["tc_gamma"]
     avg = total / launches
@@ -435,7 +451,7 @@ def tsweep_leg(K, torch, cfg, model, c, steps, warmup, n_temps=16, direct_gamma=
         K.tcache_gamma(c, wc, om, b.nu_min_thz, temps, workspace=gws, out=g_ir)
         for k in range(n_temps):
             K.star_map(mesh, c.nb3, w.ir_dev, om, g_ir[k], out=g_full[k])
-    wms, _ = timed(K, torch, wstep, steps, warmup, f"{cfg.name} wedge sweep of {n_temps} T")
+    wms, _ = timed(K, torch, wstep, steps, warmup, f"{cfg.name} wedge sweep of {n_temps} T", plain=True)
     c.device_status()
     res["wedge"] = dict(irreducible_q=int(w.n_ir), entries=wc.n_entries, build_ms=wbuild * 1e3,
                         ms_per_step=wms, ms_per_temperature=wms / n_temps)
@@ -504,7 +520,7 @@ def qhgk_leg(K, torch, steps, warmup):
     def step():
         res["k"] = K.qhgk_gamma(cg, m4.frac, om, E, G, c4.temperature, c4.broadening.nu_min_thz,
                                 workspace=ws)
-    ms, prof = timed(K, torch, step, steps, warmup, "C4 QHGK")
+    ms, prof = timed(K, torch, step, steps, warmup, "C4 QHGK", plain=True)
     cg.device_status()
     n3 = len(om_h)
     # executed matrix-core work: the tiles on and above the diagonal (the
@@ -531,7 +547,7 @@ def qhgk_leg(K, torch, steps, warmup):
     def step3():
         res["ki"] = K.qhgk_crystal(cc, c3.mesh, m3.frac, om3, ev3, G3, c3.temperature,
                                    c3.broadening.nu_min_thz)
-    ms3, prof3 = timed(K, torch, step3, steps, warmup, "C3 interband")
+    ms3, prof3 = timed(K, torch, step3, steps, warmup, "C3 interband", plain=True)
     cc.device_status()
     out["perovskite_interband"] = dict(
         ms_per_step=ms3, kappa_rta_trace_over_3=float(torch.trace(kr).item() / 3),
@@ -558,7 +574,7 @@ def isotope_leg(K, torch, cfg, model, c, steps, warmup, gamma_anh=None):
 
     def step():
         K.isotope_linewidths(c, mesh, om, ev, ve, g, b, out=out, workspace=ws)
-    ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} isotope")
+    ms, prof = timed(K, torch, step, steps, warmup, f"{cfg.name} isotope", plain=True)
     c.device_status()
     w = om.cpu().numpy().reshape(-1)
     v = ve.cpu().numpy().reshape(-1, 3)
@@ -620,8 +636,8 @@ def wedge_leg(K, torch, name, prec, steps, warmup):
         K.linewidths(c, mesh, om, ev, ve, cfg.temperature, cfg.broadening, prec, subset=sub,
                      workspace=ws, out=g_ir)
         K.star_map(mesh, c.nb3, w.ir_dev, om, g_ir, out=g_w)
-    ms_f, _ = timed(K, torch, s_full, steps, warmup, f"{name} full mesh")
-    ms_w, _ = timed(K, torch, s_wedge, steps, warmup, f"{name} wedge")
+    ms_f, _ = timed(K, torch, s_full, steps, warmup, f"{name} full mesh", plain=True)
+    ms_w, _ = timed(K, torch, s_wedge, steps, warmup, f"{name} wedge", plain=True)
     kf = K.kappa_rta(c, mesh, om, ve, full, cfg.temperature, cfg.broadening.nu_min_thz).cpu().numpy()
     kw = K.kappa_rta(c, mesh, om, ve, g_w, cfg.temperature, cfg.broadening.nu_min_thz).cpu().numpy()
     c.device_status()
@@ -687,11 +703,11 @@ def bench_learned(a, cfg, model, c, K, torch):
         state["res"] = res
         state["k"] = kap.clone()
 
-    ms_full, p_full = timed(K, torch, full, a.steps, a.warmup, "plain-full")
+    ms_full, p_full = timed(K, torch, full, a.steps, a.warmup, "plain-full", plain=True)
     k_full = state["k"].cpu().numpy()
-    ms_ibz, p_ibz = timed(K, torch, ibz, a.steps, a.warmup, "plain-wedge")
+    ms_ibz, p_ibz = timed(K, torch, ibz, a.steps, a.warmup, "plain-wedge", plain=True)
     k_ibz = state["k"].cpu().numpy()
-    ms_lrn, p_lrn = timed(K, torch, learned, a.steps, a.warmup, "learned")
+    ms_lrn, p_lrn = timed(K, torch, learned, a.steps, a.warmup, "learned", plain=True)
     k_lrn = state["k"].cpu().numpy()
     res = state["res"]
 
@@ -826,7 +842,7 @@ def main():
     if not a.no_extras:
         if prec != K.FP32:
             step32, b32 = crystal_step(K, torch, c, cfg, K.FP32)
-            ms32, prof32 = timed(K, torch, step32, a.steps, a.warmup, f"{cfg.name} fp32")
+            ms32, prof32 = timed(K, torch, step32, a.steps, a.warmup, f"{cfg.name} fp32", plain=True)
             k32 = b32["kap"].cpu().numpy()
             extras["fp32"] = dict(ms_per_step=ms32, modes_per_s=n_modes / (ms32 * 1e-3),
                                   speedup_vs_headline=ms_per_step / ms32,
@@ -842,7 +858,7 @@ def main():
         ks = {}
         for name, p in (("fp32", K.FP32), ("bf16x3", K.BF16X3)):
             s3, b3 = crystal_step(K, torch, cc3, c3, p)
-            ms3, pr3 = timed(K, torch, s3, max(3, a.steps // 4), 2, f"C3 {name}")
+            ms3, pr3 = timed(K, torch, s3, max(3, a.steps // 4), 2, f"C3 {name}", plain=True)
             ks[name] = b3["kap"].cpu().numpy()
             leg[name] = dict(ms_per_step=ms3, modes_per_s=n3 / (ms3 * 1e-3),
                              kernels_ms={k: v[1] / v[0] for k, v in pr3.items()})

@@ -264,8 +264,13 @@ class Crystal:
         _check(lib().kaldo_device_status(self.handle, _stream()))
 
     def __del__(self):
-        if sys.is_finalizing():
-            return  # the atexit hook has closed it, or the runtime is going away
+        if not getattr(self, "handle", None):
+            return  # closed already
+        # during interpreter shutdown module globals may already be None: the
+        # atexit hook has closed every handle by then, so do nothing
+        _sys = sys
+        if _sys is None or _sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
