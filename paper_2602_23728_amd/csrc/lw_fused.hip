@@ -8,7 +8,8 @@
 //  1. A~_q (the FC3 COO contracted on its home-cell index with eta(q), with
 //     the phase e^{+i q.R''} folded in) built in FP64 and stored in LDS in an
 //     atom-block layout [block (jb, kb, d)][beta gamma][s].
-//  2. The (q1, s') candidates are swept in chunks, one per thread: for every
+//  2. The (q1, s') candidates are swept in rounds, one per thread (the FP64
+//     pass: a partner q1 per thread, swept once per s'): for every
 //     s'' and s the energy cut |x+-| < 2 sigma+- of the oracle, with
 //     x+ = (w + w1) - w2, x- = (w - w1) - w2, decides (pre-classified in FP32
 //     against a conservative band from the FP32 mode copies; band members
@@ -48,6 +49,16 @@ constexpr int kFusedCap = 2048;
 template <int NB, typename T>
 constexpr int fused_waves_per_eu() {
   return (NB <= 2 && sizeof(T) == 4) ? 4 : (NB <= 2 ? 3 : 1);
+}
+
+// Whether the sweep runs in blocks of partners, each swept once per branch
+// s' (the FP64 linewidth pass), or in rounds of (q1, s') items (the FP32
+// forms, and the temperature cache's count and record passes, which must
+// split their work items alike; its FP64 record pass spills 19 registers
+// with partner blocks against 2).
+template <typename T, int MODE>
+constexpr bool fused_partner_blocks() {
+  return sizeof(T) == 8 && MODE == kModeGamma;
 }
 
 // Gamma of the selected modes: the chunk sums of their q in chunk order.
@@ -319,25 +330,44 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     // comparison through their NaN frequency)
     int fill = 0;
     const Partners prt(p.half != 0, a0, a1, a2, N0, N1, N2);
-    // this work item's share: a contiguous range of whole sweep rounds
-    const int n_all = prt.n * NB3;
+    // this work item's share: a contiguous range of whole sweep rounds.  The
+    // FP64 linewidth pass (kBlk) sweeps blocks of BS partners: a thread
+    // decodes its partner once per block (run-time divisions and range
+    // tests, paid per wave whatever the number of lanes that need them) and
+    // sweeps it once per branch s', a round being one (block, s') pair (the
+    // round's body below keeps the indentation of the item form).  The FP32
+    // forms (four waves per SIMD) and the cache passes have no registers for
+    // that and sweep (q1, s') items, a round being BS consecutive items.
+    constexpr bool kBlk = fused_partner_blocks<T, MODE>();
+    const int n_all = kBlk ? prt.n : prt.n * NB3;
     const int per = ((n_all + n_chunk - 1) / n_chunk + BS - 1) / BS * BS;
     const int i_lo = min(n_all, chunk * per), n_items = min(n_all, i_lo + per);
     for (int base = i_lo; base < n_items; base += BS) {
       const int item = base + tid;
+      const bool have = item < n_items;
+      int q1 = 0, q2_blk = 0, dbl = 0, s1_item = 0;
+      if (have) {
+        const int qi = kBlk ? item : item / NB3;
+        s1_item = kBlk ? 0 : item - qi * NB3;
+        int b0, b1, b2;
+        dbl = prt.get(qi, N1, N2, b0, b1, b2);
+        q1 = (b0 * N1 + b1) * N2 + b2;
+        q2_blk = (wrap_sub(prt.h[0].t, b0, N0) * N1 + wrap_sub(prt.h[1].t, b1, N1)) * N2 +
+             wrap_sub(prt.h[2].t, b2, N2);
+      }
+#pragma unroll 1
+    for (int sr = 0; sr < (kBlk ? NB3 : 1); ++sr) {
+      const int s1 = kBlk ? sr : s1_item;
+      // q2 as seen by this round: an empty register barrier keeps the
+      // compiler from hoisting the partner's per-branch addresses (six 64-bit
+      // pointers of the rare exact path) out of the s' loop, where they spill
+      int q2 = q2_blk;
+      if constexpr (kBlk) asm volatile("" : "+v"(q2));
       unsigned bits[NB3];
 #pragma unroll
       for (int k = 0; k < NB3; ++k) bits[k] = 0;
       int count = 0;
-      int q1 = 0, q2 = 0, s1 = 0, dbl = 0;
-      if (item < n_items) {
-        const int qi = item / NB3;
-        s1 = item - qi * NB3;
-        int b0, b1, b2;
-        dbl = prt.get(qi, N1, N2, b0, b1, b2);
-        q1 = (b0 * N1 + b1) * N2 + b2;
-        q2 = (wrap_sub(prt.h[0].t, b0, N0) * N1 + wrap_sub(prt.h[1].t, b1, N1)) * N2 +
-             wrap_sub(prt.h[2].t, b2, N2);
+      if (have) {
         const int m1 = q1 * NB3 + s1;
         const float4 f1 = modef[m1];
         // the partner's mode copies one branch ahead, so that each load is
@@ -552,6 +582,7 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
         for (int s = 0; s < NB3; ++s) run[s] += s_tot[s];
       }
     }
+    }
 
     if constexpr (MODE == kModeCount) {
       // 4c. entries per branch of this work item (integer sums: any order)
@@ -710,9 +741,11 @@ static int launch_fused_impl(const kaldo_crystal* c, const LwParams& p, const do
   // bits of Gamma, the same on every device).
   const long upper = n_subset > 0 ? std::min<long>(nq, n_subset) : nq;
   const long guess = n_subset > 0 ? std::max<long>(1, n_subset / c->nb3) : nq;
-  // and no chunk shorter than one sweep round (a q sweeps about N_q 3N_b / 2 items)
+  // and no chunk shorter than one sweep round (a q sweeps about N_q / 2
+  // partners, N_q 3N_b / 2 items)
+  const long per_q = fused_partner_blocks<T, MODE>() ? (long)nq : (long)nq * c->nb3;
   const int max_chunks =
-      (int)std::max<long>(1, std::min<long>(kFusedMaxChunks, (long)nq * c->nb3 / (2 * kFusedThreads)));
+      (int)std::max<long>(1, std::min<long>(kFusedMaxChunks, per_q / (2 * kFusedThreads)));
   const int n_chunk =
       std::min(fused_chunks((int)std::min<long>(guess, 1l << 30), kWorkItems), max_chunks);
 #define KALDO_FUSED_CASE(NBV)                                                                    \
