@@ -14,10 +14,11 @@
 //     x+ = (w + w1) - w2, x- = (w - w1) - w2, decides (pre-classified in FP32
 //     against a conservative band from the FP32 mode copies; band members
 //     take the FP64 test); the passing (q1, q2, s, s', s'') are compacted in
-//     a fixed order (block-wide exclusive scan) into an LDS queue.  When Phi3 is symmetric in its last two slots
-//     the ordered pair (q1 s', q2 s'') and its mirror (q2 s'', q1 s') have
-//     the same V, so only q1 <_lex q2 is swept (and q1 == q2 once) and an
-//     entry carries the terms of both orderings, each with its own cut.
+//     a fixed order (block-wide exclusive scan) into an LDS queue.  When Phi3
+//     is symmetric in its last two slots the ordered pair (q1 s', q2 s'')
+//     and its mirror (q2 s'', q1 s') have the same V, so only q1 <_lex q2 is
+//     swept (and q1 == q2 once) and an entry carries the terms of both
+//     orderings, each with its own cut.
 //  3. When the queue is full (and at the end) every thread projects queue
 //     entries: V = sum_blocks e^{-i q1.R_d} sum_{beta,gamma}
 //     A~[blk][beta gamma][s] eta_{3jb+beta}(q1,s') eta_{3kb+gamma}(q2,s''),
@@ -334,10 +335,9 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
     // FP64 linewidth pass (kBlk) sweeps blocks of BS partners: a thread
     // decodes its partner once per block (run-time divisions and range
     // tests, paid per wave whatever the number of lanes that need them) and
-    // sweeps it once per branch s', a round being one (block, s') pair (the
-    // round's body below keeps the indentation of the item form).  The FP32
-    // forms (four waves per SIMD) and the cache passes have no registers for
-    // that and sweep (q1, s') items, a round being BS consecutive items.
+    // sweeps it once per branch s', a round being one (block, s') pair.  The
+    // FP32 forms (four waves per SIMD) and the cache passes have no registers
+    // for that and sweep (q1, s') items, a round being BS consecutive items.
     constexpr bool kBlk = fused_partner_blocks<T, MODE>();
     const int n_all = kBlk ? prt.n : prt.n * NB3;
     const int per = ((n_all + n_chunk - 1) / n_chunk + BS - 1) / BS * BS;
@@ -356,232 +356,232 @@ __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<NB, T>()))) void lw_fused(
              wrap_sub(prt.h[2].t, b2, N2);
       }
 #pragma unroll 1
-    for (int sr = 0; sr < (kBlk ? NB3 : 1); ++sr) {
-      const int s1 = kBlk ? sr : s1_item;
-      // q2 as seen by this round: an empty register barrier keeps the
-      // compiler from hoisting the partner's per-branch addresses (six 64-bit
-      // pointers of the rare exact path) out of the s' loop, where they spill
-      int q2 = q2_blk;
-      if constexpr (kBlk) asm volatile("" : "+v"(q2));
-      unsigned bits[NB3];
+      for (int sr = 0; sr < (kBlk ? NB3 : 1); ++sr) {
+        const int s1 = kBlk ? sr : s1_item;
+        // q2 as seen by this round: an empty register barrier keeps the
+        // compiler from hoisting the partner's per-branch addresses (six 64-bit
+        // pointers of the rare exact path) out of the s' loop, where they spill
+        int q2 = q2_blk;
+        if constexpr (kBlk) asm volatile("" : "+v"(q2));
+        unsigned bits[NB3];
 #pragma unroll
-      for (int k = 0; k < NB3; ++k) bits[k] = 0;
-      int count = 0;
-      if (have) {
-        const int m1 = q1 * NB3 + s1;
-        const float4 f1 = modef[m1];
-        // the partner's mode copies one branch ahead, so that each load is
-        // in flight while the previous branch is classified
-        const float4* f2p = modef + (size_t)q2 * NB3;
-        float4 f2n = f2p[0];
+        for (int k = 0; k < NB3; ++k) bits[k] = 0;
+        int count = 0;
+        if (have) {
+          const int m1 = q1 * NB3 + s1;
+          const float4 f1 = modef[m1];
+          // the partner's mode copies one branch ahead, so that each load is
+          // in flight while the previous branch is classified
+          const float4* f2p = modef + (size_t)q2 * NB3;
+          float4 f2n = f2p[0];
 #pragma unroll
-        for (int s2 = 0; s2 < NB3; ++s2) {
-          const int m2 = q2 * NB3 + s2;
-          // FP32 classification from the mode copies (a mode below the floor
-          // carries a NaN frequency and fails every comparison)
-          const float4 f2 = f2n;
-          if (s2 + 1 < NB3) f2n = f2p[s2 + 1];
-          float s2p, s2m, e_sig;
-          widths2_f(p, f1, f2, s2p, s2m, e_sig);
-          const float scl = wq_abs_max + fabsf(f1.w) + fabsf(f2.w);
-          const Band bp = make_band_f(s2p, scl, e_sig), bm = make_band_f(s2m, scl, e_sig);
-          const float cp = f1.w - f2.w, cm = -f1.w - f2.w;
-          // The upper band edge for all branches first (branch-free): a
-          // candidate is any process with |x| < hi.  The coalescence |x+| =
-          // |w + cp| and that of the mirrored ordering, |w - cp| (= (w + w2) -
-          // w1), share the edge bp.hi, and for w >= 0 the smaller of the two
-          // is |w - |cp||, bitwise in FP32 (w + cp and w - cp round
-          // monotonically); so one test per branch covers both, with cpe =
-          // -|cp| on mirrored entries and cp otherwise.  The decay |x-| is the
-          // same FP32 number for both orderings.  Live branches of q have w
-          // >= 2 pi nu_min > 0; the others drop out through `live`.
-          // The common path asks only whether any live branch is near: the
-          // smallest |x| of each process over the branches against its edge
-          // (a minimum is exact, so the answer is that of the per-branch
-          // tests; a NaN x leaves the minimum at +inf or NaN, which fail).
-          const float cpe = dbl ? -fabsf(cp) : cp;
-          float xp[NB3], xm[NB3];
-          float mp = __builtin_inff(), mm = __builtin_inff();
+          for (int s2 = 0; s2 < NB3; ++s2) {
+            const int m2 = q2 * NB3 + s2;
+            // FP32 classification from the mode copies (a mode below the floor
+            // carries a NaN frequency and fails every comparison)
+            const float4 f2 = f2n;
+            if (s2 + 1 < NB3) f2n = f2p[s2 + 1];
+            float s2p, s2m, e_sig;
+            widths2_f(p, f1, f2, s2p, s2m, e_sig);
+            const float scl = wq_abs_max + fabsf(f1.w) + fabsf(f2.w);
+            const Band bp = make_band_f(s2p, scl, e_sig), bm = make_band_f(s2m, scl, e_sig);
+            const float cp = f1.w - f2.w, cm = -f1.w - f2.w;
+            // The upper band edge for all branches first (branch-free): a
+            // candidate is any process with |x| < hi.  The coalescence |x+| =
+            // |w + cp| and that of the mirrored ordering, |w - cp| (= (w + w2) -
+            // w1), share the edge bp.hi, and for w >= 0 the smaller of the two
+            // is |w - |cp||, bitwise in FP32 (w + cp and w - cp round
+            // monotonically); so one test per branch covers both, with cpe =
+            // -|cp| on mirrored entries and cp otherwise.  The decay |x-| is the
+            // same FP32 number for both orderings.  Live branches of q have w
+            // >= 2 pi nu_min > 0; the others drop out through `live`.
+            // The common path asks only whether any live branch is near: the
+            // smallest |x| of each process over the branches against its edge
+            // (a minimum is exact, so the answer is that of the per-branch
+            // tests; a NaN x leaves the minimum at +inf or NaN, which fail).
+            const float cpe = dbl ? -fabsf(cp) : cp;
+            float xp[NB3], xm[NB3];
+            float mp = __builtin_inff(), mm = __builtin_inff();
 #pragma unroll
-          for (int s = 0; s < NB3; ++s) {
-            xp[s] = wql[s] + cpe;
-            xm[s] = wql[s] + cm;
-            mp = fminf(mp, fabsf(xp[s]));
-            mm = fminf(mm, fabsf(xm[s]));
-          }
-          unsigned b = 0;
-          if (mp < bp.hi || mm < bm.hi) {
-            unsigned cand = 0;
-#pragma unroll
-            for (int s = 0; s < NB3; ++s)
-              cand |= (fabsf(xp[s]) < bp.hi || fabsf(xm[s]) < bm.hi) ? (1u << s) : 0u;
-            cand &= live;
-            // the rare candidates: which process is near (as the tests above),
-            // certain passes in FP32, the band members take the exact FP64 test
-            unsigned amb = 0, amb_p = 0, amb_r = 0, amb_m = 0;
-            for (unsigned c = cand; c; c &= c - 1) {
-              const int s = __ffs(c) - 1;
-              const float w = wqs[s];
-              const float ap = fabsf(w + cp), ar = fabsf(w - cp), am = fabsf(w + cm);
-              const bool hp = ap < bp.hi, hr = dbl && ar < bp.hi, hm = am < bm.hi;
-              amb_p |= hp ? (1u << s) : 0u;
-              amb_r |= hr ? (1u << s) : 0u;
-              amb_m |= hm ? (1u << s) : 0u;
-              const bool sure = (hp && ap < bp.lo) || (hm && am < bm.lo) || (hr && ar < bp.lo);
-              b |= sure ? (1u << s) : 0u;
-              amb |= sure ? 0u : (1u << s);
+            for (int s = 0; s < NB3; ++s) {
+              xp[s] = wql[s] + cpe;
+              xm[s] = wql[s] + cm;
+              mp = fminf(mp, fabsf(xp[s]));
+              mm = fminf(mm, fabsf(xm[s]));
             }
-            if (amb) {
-              const double w1 = omega[m1], w2 = omega[m2];
-              double s2p64, s2m64, Sp, Sm;
-              widths2(p, vel + 3 * (size_t)m1, vel + 3 * (size_t)m2, s2p64, s2m64, Sp, Sm);
-              while (amb) {
-                const int s = __ffs(amb) - 1;
-                amb &= amb - 1;
-                const bool bm_ = amb_m >> s & 1u;
-                bool pass = ((amb_p >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, true)) ||
-                            (bm_ && exact_pass(p, wq64[s], w1, w2, Sp, Sm, false));
-                if (dbl && !pass)
-                  pass = ((amb_r >> s & 1u) && exact_pass(p, wq64[s], w2, w1, Sp, Sm, true)) ||
-                         (bm_ && exact_pass(p, wq64[s], w2, w1, Sp, Sm, false));
-                b |= pass ? (1u << s) : 0u;
+            unsigned b = 0;
+            if (mp < bp.hi || mm < bm.hi) {
+              unsigned cand = 0;
+#pragma unroll
+              for (int s = 0; s < NB3; ++s)
+                cand |= (fabsf(xp[s]) < bp.hi || fabsf(xm[s]) < bm.hi) ? (1u << s) : 0u;
+              cand &= live;
+              // the rare candidates: which process is near (as the tests above),
+              // certain passes in FP32, the band members take the exact FP64 test
+              unsigned amb = 0, amb_p = 0, amb_r = 0, amb_m = 0;
+              for (unsigned c = cand; c; c &= c - 1) {
+                const int s = __ffs(c) - 1;
+                const float w = wqs[s];
+                const float ap = fabsf(w + cp), ar = fabsf(w - cp), am = fabsf(w + cm);
+                const bool hp = ap < bp.hi, hr = dbl && ar < bp.hi, hm = am < bm.hi;
+                amb_p |= hp ? (1u << s) : 0u;
+                amb_r |= hr ? (1u << s) : 0u;
+                amb_m |= hm ? (1u << s) : 0u;
+                const bool sure = (hp && ap < bp.lo) || (hm && am < bm.lo) || (hr && ar < bp.lo);
+                b |= sure ? (1u << s) : 0u;
+                amb |= sure ? 0u : (1u << s);
+              }
+              if (amb) {
+                const double w1 = omega[m1], w2 = omega[m2];
+                double s2p64, s2m64, Sp, Sm;
+                widths2(p, vel + 3 * (size_t)m1, vel + 3 * (size_t)m2, s2p64, s2m64, Sp, Sm);
+                while (amb) {
+                  const int s = __ffs(amb) - 1;
+                  amb &= amb - 1;
+                  const bool bm_ = amb_m >> s & 1u;
+                  bool pass = ((amb_p >> s & 1u) && exact_pass(p, wq64[s], w1, w2, Sp, Sm, true)) ||
+                              (bm_ && exact_pass(p, wq64[s], w1, w2, Sp, Sm, false));
+                  if (dbl && !pass)
+                    pass = ((amb_r >> s & 1u) && exact_pass(p, wq64[s], w2, w1, Sp, Sm, true)) ||
+                           (bm_ && exact_pass(p, wq64[s], w2, w1, Sp, Sm, false));
+                  b |= pass ? (1u << s) : 0u;
+                }
               }
             }
-          }
-          b &= live;
-          bits[s2] = b;
-          count += __popc(b);
-        }
-      }
-      if constexpr (MODE == kModeCount) {
-#pragma unroll
-        for (int s2 = 0; s2 < NB3; ++s2)
-#pragma unroll
-          for (int s = 0; s < NB3; ++s) cnt[s] += (int)((bits[s2] >> s) & 1u);
-        continue;  // no queue: the round ends here (no barrier was passed)
-      }
-      // record pass: per-branch counts of this thread, packed two per int
-      // (a round holds at most BS * NB3 < 2^16 entries of one branch)
-      int pk[NPK], pk_incl[NPK];
-      if constexpr (kRecord) {
-#pragma unroll
-        for (int k = 0; k < NPK; ++k) pk[k] = 0;
-#pragma unroll
-        for (int s2 = 0; s2 < NB3; ++s2)
-#pragma unroll
-          for (int s = 0; s < NB3; ++s) pk[s >> 1] += (int)((bits[s2] >> s) & 1u) << ((s & 1) * 16);
-#pragma unroll
-        for (int k = 0; k < NPK; ++k) {
-          int v = pk[k];
-#pragma unroll
-          for (int off = 1; off < 64; off <<= 1) {
-            const int t = __shfl_up(v, off, 64);
-            if (lane >= off) v += t;
-          }
-          pk_incl[k] = v;
-          if (lane == 63) wave_tot_s[wv][k] = v;
-        }
-      }
-      // block-wide exclusive scan of count (fixed order)
-      int incl = count;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int v = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += v;
-      }
-      if (lane == 63) wave_tot[wv] = incl;
-      __syncthreads();
-      int wave_off = 0, total = 0;
-#pragma unroll
-      for (int k = 0; k < BS / 64; ++k) {
-        const int t = wave_tot[k];
-        wave_off += (k < wv) ? t : 0;
-        total += t;
-      }
-      const int my_off = wave_off + incl - count;
-      // record pass: this thread's first rank per branch within the round and
-      // the round's total per branch
-      int s_off[NB3], s_tot[NB3];
-      if constexpr (kRecord) {
-#pragma unroll
-        for (int k = 0; k < NPK; ++k) {
-          int off = 0, tot = 0;
-#pragma unroll
-          for (int w = 0; w < BS / 64; ++w) {
-            const int t = wave_tot_s[w][k];
-            off += (w < wv) ? t : 0;
-            tot += t;
-          }
-          const int ex = off + pk_incl[k] - pk[k];
-          s_off[2 * k] = ex & 0xffff;
-          s_tot[2 * k] = tot & 0xffff;
-          if (2 * k + 1 < NB3) {
-            s_off[2 * k + 1] = (int)((unsigned)ex >> 16);
-            s_tot[2 * k + 1] = (int)((unsigned)tot >> 16);
+            b &= live;
+            bits[s2] = b;
+            count += __popc(b);
           }
         }
-      }
-      __syncthreads();
-      int written = 0;
-      while (written < total) {
-        const int take = min(CAP - fill, total - written);
-        if (count > 0 && my_off < written + take && my_off + count > written) {
-          int rank = my_off;
-          if constexpr (kRecord) {
-            // the order of the loop below (s'' ascending, then s ascending),
-            // with static indices into the per-branch counters
-            int loc[NB3];
+        if constexpr (MODE == kModeCount) {
 #pragma unroll
-            for (int s = 0; s < NB3; ++s) loc[s] = 0;
+          for (int s2 = 0; s2 < NB3; ++s2)
 #pragma unroll
-            for (int s2 = 0; s2 < NB3; ++s2) {
+            for (int s = 0; s < NB3; ++s) cnt[s] += (int)((bits[s2] >> s) & 1u);
+          continue;  // no queue: the round ends here (no barrier was passed)
+        }
+        // record pass: per-branch counts of this thread, packed two per int
+        // (a round holds at most BS * NB3 < 2^16 entries of one branch)
+        int pk[NPK], pk_incl[NPK];
+        if constexpr (kRecord) {
 #pragma unroll
-              for (int s = 0; s < NB3; ++s) {
-                if ((bits[s2] >> s) & 1u) {
+          for (int k = 0; k < NPK; ++k) pk[k] = 0;
+#pragma unroll
+          for (int s2 = 0; s2 < NB3; ++s2)
+#pragma unroll
+            for (int s = 0; s < NB3; ++s) pk[s >> 1] += (int)((bits[s2] >> s) & 1u) << ((s & 1) * 16);
+#pragma unroll
+          for (int k = 0; k < NPK; ++k) {
+            int v = pk[k];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+              const int t = __shfl_up(v, off, 64);
+              if (lane >= off) v += t;
+            }
+            pk_incl[k] = v;
+            if (lane == 63) wave_tot_s[wv][k] = v;
+          }
+        }
+        // block-wide exclusive scan of count (fixed order)
+        int incl = count;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int v = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += v;
+        }
+        if (lane == 63) wave_tot[wv] = incl;
+        __syncthreads();
+        int wave_off = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < BS / 64; ++k) {
+          const int t = wave_tot[k];
+          wave_off += (k < wv) ? t : 0;
+          total += t;
+        }
+        const int my_off = wave_off + incl - count;
+        // record pass: this thread's first rank per branch within the round and
+        // the round's total per branch
+        int s_off[NB3], s_tot[NB3];
+        if constexpr (kRecord) {
+#pragma unroll
+          for (int k = 0; k < NPK; ++k) {
+            int off = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < BS / 64; ++w) {
+              const int t = wave_tot_s[w][k];
+              off += (w < wv) ? t : 0;
+              tot += t;
+            }
+            const int ex = off + pk_incl[k] - pk[k];
+            s_off[2 * k] = ex & 0xffff;
+            s_tot[2 * k] = tot & 0xffff;
+            if (2 * k + 1 < NB3) {
+              s_off[2 * k + 1] = (int)((unsigned)ex >> 16);
+              s_tot[2 * k + 1] = (int)((unsigned)tot >> 16);
+            }
+          }
+        }
+        __syncthreads();
+        int written = 0;
+        while (written < total) {
+          const int take = min(CAP - fill, total - written);
+          if (count > 0 && my_off < written + take && my_off + count > written) {
+            int rank = my_off;
+            if constexpr (kRecord) {
+              // the order of the loop below (s'' ascending, then s ascending),
+              // with static indices into the per-branch counters
+              int loc[NB3];
+#pragma unroll
+              for (int s = 0; s < NB3; ++s) loc[s] = 0;
+#pragma unroll
+              for (int s2 = 0; s2 < NB3; ++s2) {
+#pragma unroll
+                for (int s = 0; s < NB3; ++s) {
+                  if ((bits[s2] >> s) & 1u) {
+                    if (rank >= written && rank < written + take) {
+                      const int slot = fill + rank - written;
+                      rq_q1[slot] = q1;
+                      rq_q2[slot] = q2;
+                      rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (dbl << 24);
+                      rq_dst[slot] = run[s] + s_off[s] + loc[s];
+                    }
+                    ++loc[s];
+                    ++rank;
+                  }
+                }
+              }
+            } else {
+#pragma unroll
+              for (int s2 = 0; s2 < NB3; ++s2) {
+                unsigned b = bits[s2];
+                while (b) {
+                  const int s = __ffs(b) - 1;
+                  b &= b - 1;
                   if (rank >= written && rank < written + take) {
                     const int slot = fill + rank - written;
                     rq_q1[slot] = q1;
                     rq_q2[slot] = q2;
                     rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (dbl << 24);
-                    rq_dst[slot] = run[s] + s_off[s] + loc[s];
                   }
-                  ++loc[s];
                   ++rank;
                 }
               }
             }
-          } else {
-#pragma unroll
-            for (int s2 = 0; s2 < NB3; ++s2) {
-              unsigned b = bits[s2];
-              while (b) {
-                const int s = __ffs(b) - 1;
-                b &= b - 1;
-                if (rank >= written && rank < written + take) {
-                  const int slot = fill + rank - written;
-                  rq_q1[slot] = q1;
-                  rq_q2[slot] = q2;
-                  rq_code[slot] = s | (s1 << 8) | (s2 << 16) | (dbl << 24);
-                }
-                ++rank;
-              }
-            }
+          }
+          fill += take;
+          written += take;
+          __syncthreads();
+          if (fill == CAP) {
+            process(fill);
+            fill = 0;
+            __syncthreads();
           }
         }
-        fill += take;
-        written += take;
-        __syncthreads();
-        if (fill == CAP) {
-          process(fill);
-          fill = 0;
-          __syncthreads();
+        if constexpr (kRecord) {
+#pragma unroll
+          for (int s = 0; s < NB3; ++s) run[s] += s_tot[s];
         }
       }
-      if constexpr (kRecord) {
-#pragma unroll
-        for (int s = 0; s < NB3; ++s) run[s] += s_tot[s];
-      }
-    }
     }
 
     if constexpr (MODE == kModeCount) {
